@@ -1,0 +1,176 @@
+/* exm: MI355X-native differentiable UV-PBR render pass (Stage II of ExMesh++).
+ *
+ * The pass renders a fixed mesh-UV carrier with optimisable UV-space PBR maps and an
+ * equirectangular environment map (UV-PBR Asset Decomposition section):
+ *   raster G-buffer -> bilinear UV queries (Eq. 10-11) -> GGX/Lambert shading under env
+ *   importance sampling with shadow rays (Eq. 12-17) -> one-bounce diffuse indirect (Eq. 18-19)
+ *   -> hand-written adjoint scatter into the maps and the env map.
+ *
+ * Conventions for every call:
+ *  - Array pointers are DEVICE pointers owned by the caller, except those marked _host.
+ *  - Calls only enqueue work on `stream` and return; results are valid after the stream
+ *    synchronises. The library allocates no device memory except inside exm_build_bvh.
+ *  - Gradient outputs ACCUMULATE (+=); the caller zeroes them.
+ *  - Shapes, null pointers, sizes and host-readable values are validated before any launch;
+ *    a failed check returns EXM_E_INVAL and enqueues nothing. A HIP launch or runtime error
+ *    returns EXM_E_HIP. exm_last_error() gives a thread-local message for the last non-OK
+ *    status of the calling thread.
+ *  - All views of one call share H and W. At most 64 direct samples per pixel (one u64 of
+ *    visibility bits) and at most 64 secondary light samples (N_b * N_s <= 64).
+ *  - Random numbers: Philox4x32-10 keyed by (seed_lo ^ seed_hi, iteration_lo) with counter
+ *    (pixel = y*W + x, view_id, sample, stream); stream 0 = direct sample, 1 = secondary
+ *    direction, 2+j = light sample of secondary ray j. Results are independent of how views
+ *    are batched into calls.
+ */
+#ifndef EXM_H
+#define EXM_H
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EXM_OK = 0,
+  EXM_E_INVAL = -1,       /* bad argument; nothing was enqueued */
+  EXM_E_HIP = -2,         /* HIP runtime / launch error */
+  EXM_E_NOMEM = -3,       /* allocation failed (exm_build_bvh only) */
+  EXM_E_UNSUPPORTED = -4, /* no gfx950 device / feature */
+} exm_status;
+
+/* Thread-local text of the last non-OK status returned on this thread. */
+const char* exm_last_error(void);
+
+/* Shading flags (exm_params.flags). METALLIC_OFF fixes m = 0 (dielectric model; UV-PBR Asset
+ * Decomposition section, and the Implementation details of the Experiments). DIFFUSE_ONLY /
+ * SPECULAR_ONLY drop f_s / f_d of Eq. 13 (tests). NO_VIS sets Vis = 1 (tests). */
+enum {
+  EXM_METALLIC_OFF = 1u << 0,
+  EXM_DIFFUSE_ONLY = 1u << 1,
+  EXM_SPECULAR_ONLY = 1u << 2,
+  EXM_NO_VIS = 1u << 3,
+};
+
+/* Fixed mesh-UV carrier M = (V, F), UV set U and face-corner UV index Phi (UV-PBR Asset
+ * Decomposition section). Counter-clockwise triangles are front facing. */
+typedef struct {
+  int32_t nV, nF, nUV;
+  const float* pos;      /* [nV,3] */
+  const int32_t* tri;    /* [nF,3] vertex indices */
+  const float* uv;       /* [nUV,2] (u, v), row 0 of a map is v in [0, 1/Ht) */
+  const int32_t* tri_uv; /* [nF,3] UV indices (Phi) */
+  double* vnrm;          /* [nV,3] unit vertex normals (FP64), written by exm_mesh_prepare */
+  float* ftan;           /* [nF,4] face tangent xyz + handedness, written by exm_mesh_prepare */
+} exm_mesh;
+
+/* One view. Host memory; clip = mvp * [p, 1] (row-major, OpenGL clip space, y up);
+ * view_id is the RNG counter word of the view (a request id when serving). */
+typedef struct {
+  double mvp[16];
+  double eye[3];
+  int32_t H, W;
+  int32_t view_id;
+} exm_camera;
+
+/* Packed UV-space material maps {A, R, M_met, N}: [Ht,Wt,8] float =
+ * (a.r, a.g, a.b, roughness, metallic, n.x, n.y, n.z); n is the tangent-space normal. */
+typedef struct {
+  int32_t Ht, Wt;
+  const float* tex;
+} exm_material;
+
+/* Learnable lat-long environment map E ([He,We,3], E >= 0; row 0 at theta = 0, +Y up,
+ * phi from +X toward +Z) and its importance-sampling tables from exm_build_env_sampler. */
+typedef struct {
+  int32_t He, We;
+  const float* env;
+  const uint64_t* cdf_row; /* [He] */
+  const uint64_t* cdf_col; /* [He,We] */
+  const float* pdf;        /* [He,We] solid-angle density of the texel */
+} exm_env;
+
+/* Estimator parameters. N_d direct env samples (Eq. 17), N_b secondary rays (Eq. 19), N_s
+ * light samples per secondary hit (Eq. 18); hyperparameter table defaults are 8 / 16 / 4.
+ * f_diel = F_dielectric of Eq. 16 (0.04), eps = epsilon of Eq. 15 (1e-6), tmin = ray start
+ * distance (world units) for shadow and secondary rays. */
+typedef struct {
+  int32_t N_d, N_b, N_s;
+  uint64_t seed, iteration;
+  float f_diel, eps, tmin;
+  uint32_t flags;
+} exm_params;
+
+/* One secondary-ray record per (pixel, j): triangle id (-1: miss or back face) and
+ * barycentrics (b1, b2) of the hit. */
+typedef struct {
+  int32_t tri;
+  float b1, b2;
+} exm_sec_rec;
+
+typedef struct exm_bvh exm_bvh; /* opaque; device resident; owned by the library */
+
+/* Area-weighted vertex normals and per-face UV tangent frames of the carrier (tangent frame
+ * "interpolated on the current face", Attribute Query). Writes m->vnrm and m->ftan. */
+exm_status exm_mesh_prepare(const exm_mesh* m, hipStream_t stream);
+
+/* Binned-SAH BVH over the fixed triangles, built on the host and uploaded on `stream`
+ * (ray queries for visibility and secondary hits: Direct Illumination, One-Bounce Indirect
+ * Illumination). Host inputs; *out receives a handle. Returns EXM_E_NOMEM if device memory
+ * runs out. exm_free_bvh waits for the stream work that uses the BVH to be done by the caller. */
+exm_status exm_build_bvh(const float* pos_host, int32_t nV, const int32_t* tri_host, int32_t nF,
+                         exm_bvh** out, hipStream_t stream);
+exm_status exm_free_bvh(exm_bvh* bvh);
+/* Device bytes held by the BVH (for admission by HBM footprint). 0 for NULL. */
+size_t exm_bvh_device_bytes(const exm_bvh* bvh);
+
+/* Importance-sampling distribution over env texels proportional to luminance times texel
+ * solid angle (Direct Illumination). Integer tables: q_ij = max(1, floor(w_ij / max w *
+ * 2^20)); cdf_row = inclusive prefix of row totals; cdf_col = inclusive prefix inside a row;
+ * pdf_ij = q_ij / (Q Omega_i). Needs He >= 1, 2 <= We, He*We <= 2^24; uses no workspace. */
+exm_status exm_build_env_sampler(const float* env, int32_t He, int32_t We, uint64_t* cdf_row,
+                                 uint64_t* cdf_col, float* pdf, hipStream_t stream);
+
+/* G-buffer (Attribute Query: face f and barycentrics b of the visible point): per pixel the
+ * closest triangle under a top-left fill rule at the pixel centre, id -1 for background, and
+ * perspective-correct barycentrics (b1, b2). tri_id [nViews,H,W] int32, bary [nViews,H,W,2]
+ * float (8-byte aligned; also used as the depth buffer during the call). */
+exm_status exm_raster_gbuffer(const exm_mesh* m, const exm_camera* cams_host, int32_t nViews,
+                              int32_t* tri_id, float* bary, hipStream_t stream);
+
+/* Direct light, Eq. 17: L_dir [nViews,H,W,3] float (overwritten) and vis [nViews,H,W] u64,
+ * bit k = sample k had n_s . w > 0 and was unoccluded. Needs exm_mesh_prepare. */
+exm_status exm_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat,
+                         const exm_env* env, const exm_camera* cams_host, int32_t nViews,
+                         const int32_t* tri_id, const float* bary, const exm_params* p,
+                         float* L_dir, uint64_t* vis, hipStream_t stream);
+
+/* One-bounce diffuse indirect, Eq. 18-19: L_ind [nViews,H,W,3] (overwritten), sec_rec
+ * [nViews,H,W,N_b], sec_vis [nViews,H,W] u64 (bit j*N_s+s). */
+exm_status exm_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat,
+                              const exm_env* env, const exm_camera* cams_host, int32_t nViews,
+                              const int32_t* tri_id, const float* bary, const exm_params* p,
+                              float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis,
+                              hipStream_t stream);
+
+/* Adjoint of the direct pass for upstream dI [nViews,H,W,3]: dtex [Ht,Wt,8] += d/dtex,
+ * denv [He,We,3] += d/dE (double). Discrete choices (ids, texel picks, vis bits) and the
+ * sampling pdf are held fixed. */
+exm_status exm_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env,
+                         const exm_camera* cams_host, int32_t nViews, const int32_t* tri_id,
+                         const float* bary, const exm_params* p, const float* dI,
+                         const uint64_t* vis, float* dtex, double* denv, hipStream_t stream);
+
+/* Adjoint of the indirect pass for upstream lambda_ind * dI (Eq. 20): into the materials at
+ * the primary and the secondary points and into E at the secondary light samples. */
+exm_status exm_trace_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env,
+                         const exm_camera* cams_host, int32_t nViews, const int32_t* tri_id,
+                         const float* bary, const exm_params* p, float lambda_ind,
+                         const float* dI, const exm_sec_rec* sec_rec, const uint64_t* sec_vis,
+                         float* dtex, double* denv, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -81,6 +81,7 @@ def lib() -> C.CDLL:
         L.ora_trace_any.argtypes = [vp, vp, i32, vp, vp, dbl, vp, vp]
         L.ora_ray_margins.argtypes = [vp, vp, vp, dbl, i32, dbl, vp, vp, vp]
         L.ora_raster.argtypes = [vp, vp, vp, vp]
+        L.ora_sample_rays.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, vp, i32, vp, vp, vp, vp, vp]
         L.ora_coverage_count.argtypes = [vp, vp, vp]
         L.ora_env_tables.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.ora_env_sample.argtypes = [vp, C.c_uint64, dbl, dbl, vp, vp, vp, vp]
@@ -262,6 +263,27 @@ def ray_margins(m: OracleMesh, o, d, tmin, skip, tol):
     lib().ora_ray_margins(m.ref, _p(o), _p(d), float(tmin), int(skip), float(tol), C.byref(nh),
                           C.byref(mx), C.byref(mn))
     return nh.value, mx.value, mn.value
+
+
+def sample_rays(m: OracleMesh, cam, tables: EnvTables, tex, env, pix, idx, stream: int, N_d: int = 0,
+                N_b: int = 0, N_s: int = 0, seed: int = 3, iteration: int = 0, tmin: float = 0.0, flags: int = 0,
+                view_id: int = 0):
+    """The oracle's ray (origin, direction, cosine argument, skipped triangle) of each listed
+    (pixel, sample index) of `stream`; valid = False where the ray does not exist."""
+    tex = np.ascontiguousarray(tex, dtype=np.float64)
+    env = np.ascontiguousarray(env, dtype=np.float64)
+    th = Theta(tex.shape[0], tex.shape[1], _p(tex), None, env.shape[0], env.shape[1], _p(env), None)
+    p = Params(N_d, N_b, N_s, seed, iteration, 0.04, 1e-6, tmin, flags)
+    c = camera(cam, view_id)
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    n = pix.shape[0]
+    o, d, cc = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros(n)
+    sk = np.zeros(n, dtype=np.int32)
+    val = np.zeros(n, dtype=np.uint8)
+    lib().ora_sample_rays(m.ref, m.bvh, C.byref(c), C.byref(th), tables.ref, C.byref(p), n, _p(pix), _p(idx),
+                          int(stream), _p(o), _p(d), _p(cc), _p(sk), _p(val))
+    return o, d, cc, sk, val.astype(bool)
 
 
 class RenderResult(dict):

@@ -895,6 +895,67 @@ void ora_ray_margins(const ora_mesh* m, const double o_[3], const double d_[3], 
   *min_margin = mn;
 }
 
+void ora_sample_rays(const ora_mesh* m, const ora_bvh* b, const ora_camera* cam, const ora_params_theta* th,
+                     const ora_tables* tab, const ora_params* p, int32_t n, const int64_t* pix, const int32_t* idx,
+                     int32_t stream, double* o, double* d, double* c, int32_t* skip, uint8_t* valid) {
+  Scene S{m, b, th, tab, p, {}};
+  S.attr.vnrm.resize(3 * (size_t)m->nV);
+  S.attr.ftan.resize(4 * (size_t)m->nF);
+  vertex_normals(m, S.attr.vnrm.data());
+  face_tangents(m, S.attr.ftan.data());
+  const size_t HW = (size_t)cam->H * cam->W;
+  std::vector<int32_t> ids(HW);
+  std::vector<double> bary(3 * HW);
+  ora_raster(m, cam, ids.data(), bary.data());
+  const uint32_t view = (uint32_t)cam->view_id;
+  for (int32_t i = 0; i < n; ++i) {
+    valid[i] = 0;
+    const int64_t q = pix[i];
+    const int32_t f = ids[q];
+    if (f < 0) continue;
+    Attr<double> A = query<double>(S, f, &bary[3 * q]);
+    D3 org = A.x, dir{0, 0, 0};
+    double cc = 0;
+    int32_t sk = f;
+    if (stream == 0) {
+      Draw dr = draw(p, (uint32_t)q, view, (uint32_t)idx[i], 0u);
+      EnvSample es = env_sample(tab, dr.x, dr.u2, dr.u3);
+      dir = es.dir;
+      cc = dot(A.ns, dir);
+    } else {
+      const int32_t j = stream == 1 ? idx[i] : stream - 2;
+      D3 b1, b2;
+      onb(A.ng, &b1, &b2);
+      Draw dr = draw(p, (uint32_t)q, view, (uint32_t)j, 1u);
+      double rr = std::sqrt(dr.u2), phi = 2.0 * kPi * dr.u3;
+      double lz = std::sqrt(std::max(0.0, 1.0 - dr.u2));
+      D3 w = (mul(rr * std::cos(phi), b1) + mul(rr * std::sin(phi), b2)) + mul(lz, A.ng);
+      if (stream == 1) {
+        dir = w;
+        cc = dot(A.ng, w);
+      } else {
+        Hit h = closest(m, b, A.x, w, p->tmin, f);
+        if (h.id < 0) continue;
+        D3 q0 = vtx(m, m->tri[3 * h.id]), q1 = vtx(m, m->tri[3 * h.id + 1]), q2 = vtx(m, m->tri[3 * h.id + 2]);
+        if (!(dot(w, cross(q1 - q0, q2 - q0)) < 0.0)) continue;
+        double by[3] = {1.0 - h.b1 - h.b2, h.b1, h.b2};
+        Attr<double> Y = query<double>(S, h.id, by);
+        Draw ds = draw(p, (uint32_t)q, view, (uint32_t)idx[i], (uint32_t)stream);
+        EnvSample es = env_sample(tab, ds.x, ds.u2, ds.u3);
+        org = Y.x;
+        dir = es.dir;
+        cc = dot(Y.ns, dir);
+        sk = h.id;
+      }
+    }
+    o[3 * i] = org.x; o[3 * i + 1] = org.y; o[3 * i + 2] = org.z;
+    d[3 * i] = dir.x; d[3 * i + 1] = dir.y; d[3 * i + 2] = dir.z;
+    c[i] = cc;
+    skip[i] = sk;
+    valid[i] = 1;
+  }
+}
+
 int32_t ora_render(const ora_mesh* m, const ora_bvh* b, const ora_camera* cam, const ora_params_theta* th,
                    const ora_tables* tab, const ora_params* p, int32_t n_pix, const int64_t* pix, ora_out* out,
                    int32_t n_threads) {

@@ -127,6 +127,16 @@ void ora_ray_margins(const ora_mesh* m, const double o[3], const double d[3], do
                      int32_t skip, double tol, int32_t* n_hits, double* max_hit_margin,
                      double* min_margin);
 
+/* The oracle's own ray of one estimator sample, for flip accounting: for pixel pix[i] and
+ * index idx[i] of stream `stream` (0 = direct sample k, 1 = secondary direction j,
+ * 2+j = light sample idx of secondary ray j): origin, direction, the clamped cosine's
+ * argument (n_s.w for 0 and 2+j, n_g.w for 1) and the triangle the ray skips.
+ * valid[i] = 0 when the ray does not exist (background pixel, or no valid secondary hit). */
+void ora_sample_rays(const ora_mesh* m, const ora_bvh* b, const ora_camera* cam, const ora_params_theta* th,
+                     const ora_tables* tab, const ora_params* p, int32_t n, const int64_t* pix,
+                     const int32_t* idx, int32_t stream, double* o, double* d, double* c, int32_t* skip,
+                     uint8_t* valid);
+
 /* ---- the render pass, for a list of pixels of one view ---- */
 int32_t ora_render(const ora_mesh* m, const ora_bvh* b, const ora_camera* cam,
                    const ora_params_theta* th, const ora_tables* tab, const ora_params* p,

@@ -1,0 +1,242 @@
+"""ctypes binding of libexm.so: the C ABI of include/exm.h under the same names.
+
+Argument marshalling only: tensors become device pointers, the current torch stream becomes
+the HIP stream; every step of the render pass runs in the library's HIP kernels. There is
+no fallback: if libexm.so is missing or fails to load, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libexm.so")
+
+EXM_OK = 0
+EXM_E_INVAL = -1
+EXM_E_HIP = -2
+EXM_E_NOMEM = -3
+EXM_E_UNSUPPORTED = -4
+
+EXM_METALLIC_OFF = 1 << 0
+EXM_DIFFUSE_ONLY = 1 << 1
+EXM_SPECULAR_ONLY = 1 << 2
+EXM_NO_VIS = 1 << 3
+
+
+class ExmError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where} failed with status {status}: {msg}")
+        self.status = status
+
+
+class exm_mesh(C.Structure):
+    _fields_ = [("nV", C.c_int32), ("nF", C.c_int32), ("nUV", C.c_int32), ("pos", C.c_void_p),
+                ("tri", C.c_void_p), ("uv", C.c_void_p), ("tri_uv", C.c_void_p), ("vnrm", C.c_void_p),
+                ("ftan", C.c_void_p)]
+
+
+class exm_camera(C.Structure):
+    _fields_ = [("mvp", C.c_double * 16), ("eye", C.c_double * 3), ("H", C.c_int32), ("W", C.c_int32),
+                ("view_id", C.c_int32)]
+
+
+class exm_material(C.Structure):
+    _fields_ = [("Ht", C.c_int32), ("Wt", C.c_int32), ("tex", C.c_void_p)]
+
+
+class exm_env(C.Structure):
+    _fields_ = [("He", C.c_int32), ("We", C.c_int32), ("env", C.c_void_p), ("cdf_row", C.c_void_p),
+                ("cdf_col", C.c_void_p), ("pdf", C.c_void_p)]
+
+
+class exm_params(C.Structure):
+    _fields_ = [("N_d", C.c_int32), ("N_b", C.c_int32), ("N_s", C.c_int32), ("seed", C.c_uint64),
+                ("iteration", C.c_uint64), ("f_diel", C.c_float), ("eps", C.c_float), ("tmin", C.c_float),
+                ("flags", C.c_uint32)]
+
+
+SEC_REC_BYTES = 12  # exm_sec_rec {int32 tri; float b1, b2}
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2608_24109_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, st = C.c_void_p, C.c_int32, C.c_int
+    sig = {
+        "exm_last_error": (C.c_char_p, []),
+        "exm_mesh_prepare": (st, [vp, vp]),
+        "exm_build_bvh": (st, [vp, i32, vp, i32, C.POINTER(vp), vp]),
+        "exm_free_bvh": (st, [vp]),
+        "exm_bvh_device_bytes": (C.c_size_t, [vp]),
+        "exm_build_env_sampler": (st, [vp, i32, i32, vp, vp, vp, vp]),
+        "exm_raster_gbuffer": (st, [vp, vp, i32, vp, vp, vp]),
+        "exm_shade_fwd": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]),
+        "exm_trace_indirect": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]),
+        "exm_shade_bwd": (st, [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "exm_trace_bwd": (st, [vp, vp, vp, vp, i32, vp, vp, vp, C.c_float, vp, vp, vp, vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return lib.exm_last_error().decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != EXM_OK:
+        raise ExmError(status, where, last_error())
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _need(t, dtype, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name}: expected contiguous {dtype} {tuple(shape)}, got {t.dtype} {tuple(t.shape)}")
+
+
+def cameras(cams, view_ids=None) -> C.Array:
+    """Host array of exm_camera from objects with .mvp (4x4), .eye (3), .H, .W."""
+    arr = (exm_camera * len(cams))()
+    for i, c in enumerate(cams):
+        m = np.asarray(c.mvp, dtype=np.float64).ravel()
+        for k in range(16):
+            arr[i].mvp[k] = float(m[k])
+        for k in range(3):
+            arr[i].eye[k] = float(c.eye[k])
+        arr[i].H, arr[i].W = int(c.H), int(c.W)
+        arr[i].view_id = int(view_ids[i] if view_ids is not None else getattr(c, "view_id", i))
+    return arr
+
+
+def params(N_d: int, N_b: int = 0, N_s: int = 0, seed: int = 3, iteration: int = 0, f_diel: float = 0.04,
+           eps: float = 1e-6, tmin: float = 0.0, flags: int = 0) -> exm_params:
+    return exm_params(N_d, N_b, N_s, seed, iteration, f_diel, eps, tmin, flags)
+
+
+# ------------------------------------------------------------------------------------------
+# the C ABI under the same names
+# ------------------------------------------------------------------------------------------
+
+def exm_mesh_prepare(mesh: exm_mesh, stream=None) -> None:
+    _check(lib.exm_mesh_prepare(C.byref(mesh), _stream(stream)), "exm_mesh_prepare")
+
+
+class Bvh:
+    """Owner of a device-resident BVH handle."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    @property
+    def device_bytes(self) -> int:
+        return int(lib.exm_bvh_device_bytes(self.handle))
+
+    def free(self) -> None:
+        if self.handle:
+            _check(lib.exm_free_bvh(self.handle), "exm_free_bvh")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def exm_build_bvh(pos: np.ndarray, tri: np.ndarray, stream=None) -> Bvh:
+    pos = np.ascontiguousarray(pos, dtype=np.float32)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    out = C.c_void_p()
+    _check(lib.exm_build_bvh(pos.ctypes.data, pos.shape[0], tri.ctypes.data, tri.shape[0], C.byref(out),
+                             _stream(stream)), "exm_build_bvh")
+    return Bvh(out.value)
+
+
+def exm_build_env_sampler(env, cdf_row, cdf_col, pdf, stream=None) -> None:
+    import torch
+    He, We = env.shape[0], env.shape[1]
+    _need(env, torch.float32, (He, We, 3), "env")
+    _need(cdf_row, torch.uint64, (He,), "cdf_row")
+    _need(cdf_col, torch.uint64, (He, We), "cdf_col")
+    _need(pdf, torch.float32, (He, We), "pdf")
+    _check(lib.exm_build_env_sampler(_ptr(env), He, We, _ptr(cdf_row), _ptr(cdf_col), _ptr(pdf), _stream(stream)),
+           "exm_build_env_sampler")
+
+
+def exm_raster_gbuffer(mesh: exm_mesh, cams, tri_id, bary, stream=None) -> None:
+    import torch
+    n, H, W = len(cams), cams[0].H, cams[0].W
+    _need(tri_id, torch.int32, (n, H, W), "tri_id")
+    _need(bary, torch.float32, (n, H, W, 2), "bary")
+    _check(lib.exm_raster_gbuffer(C.byref(mesh), cams, n, _ptr(tri_id), _ptr(bary), _stream(stream)),
+           "exm_raster_gbuffer")
+
+
+def exm_shade_fwd(mesh, bvh: Bvh, mat: exm_material, env: exm_env, cams, tri_id, bary, p: exm_params, L_dir,
+                  vis, stream=None) -> None:
+    import torch
+    n, H, W = len(cams), cams[0].H, cams[0].W
+    _need(L_dir, torch.float32, (n, H, W, 3), "L_dir")
+    _need(vis, torch.uint64, (n, H, W), "vis")
+    _check(lib.exm_shade_fwd(C.byref(mesh), bvh.handle, C.byref(mat), C.byref(env), cams, n, _ptr(tri_id),
+                             _ptr(bary), C.byref(p), _ptr(L_dir), _ptr(vis), _stream(stream)), "exm_shade_fwd")
+
+
+def exm_trace_indirect(mesh, bvh: Bvh, mat, env, cams, tri_id, bary, p: exm_params, L_ind, sec_rec, sec_vis,
+                       stream=None) -> None:
+    import torch
+    n, H, W = len(cams), cams[0].H, cams[0].W
+    _need(L_ind, torch.float32, (n, H, W, 3), "L_ind")
+    _need(sec_rec, torch.int32, (n, H, W, max(p.N_b, 1), 3), "sec_rec")
+    _need(sec_vis, torch.uint64, (n, H, W), "sec_vis")
+    _check(lib.exm_trace_indirect(C.byref(mesh), bvh.handle, C.byref(mat), C.byref(env), cams, n, _ptr(tri_id),
+                                  _ptr(bary), C.byref(p), _ptr(L_ind), _ptr(sec_rec), _ptr(sec_vis),
+                                  _stream(stream)), "exm_trace_indirect")
+
+
+def exm_shade_bwd(mesh, mat, env, cams, tri_id, bary, p: exm_params, dI, vis, dtex, denv, stream=None) -> None:
+    import torch
+    n, H, W = len(cams), cams[0].H, cams[0].W
+    _need(dI, torch.float32, (n, H, W, 3), "dI")
+    _need(dtex, torch.float32, (mat.Ht, mat.Wt, 8), "dtex")
+    _need(denv, torch.float64, (env.He, env.We, 3), "denv")
+    _check(lib.exm_shade_bwd(C.byref(mesh), C.byref(mat), C.byref(env), cams, n, _ptr(tri_id), _ptr(bary),
+                             C.byref(p), _ptr(dI), _ptr(vis), _ptr(dtex), _ptr(denv), _stream(stream)),
+           "exm_shade_bwd")
+
+
+def exm_trace_bwd(mesh, mat, env, cams, tri_id, bary, p: exm_params, lambda_ind: float, dI, sec_rec, sec_vis,
+                  dtex, denv, stream=None) -> None:
+    import torch
+    n, H, W = len(cams), cams[0].H, cams[0].W
+    _need(dI, torch.float32, (n, H, W, 3), "dI")
+    _need(dtex, torch.float32, (mat.Ht, mat.Wt, 8), "dtex")
+    _need(denv, torch.float64, (env.He, env.We, 3), "denv")
+    _check(lib.exm_trace_bwd(C.byref(mesh), C.byref(mat), C.byref(env), cams, n, _ptr(tri_id), _ptr(bary),
+                             C.byref(p), float(lambda_ind), _ptr(dI), _ptr(sec_rec), _ptr(sec_vis), _ptr(dtex),
+                             _ptr(denv), _stream(stream)), "exm_trace_bwd")

@@ -1,0 +1,335 @@
+// C ABI of the render pass: argument validation (before any launch), error state, view
+// chunking, and BVH ownership. Every entry point returns an exm_status and only enqueues
+// work on the caller's stream.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "exm_internal.h"
+
+namespace exm {
+
+namespace {
+thread_local std::string g_last_error;
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// gfx950 check, cached per device
+std::mutex g_dev_mu;
+std::vector<int> g_dev_ok;  // -1 unknown, 0 no, 1 yes
+
+exm_status check_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return fail(EXM_E_HIP, "no current HIP device");
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  if ((int)g_dev_ok.size() <= dev) g_dev_ok.resize(dev + 1, -1);
+  if (g_dev_ok[dev] < 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(EXM_E_HIP, "hipGetDeviceProperties failed");
+    g_dev_ok[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+  }
+  if (!g_dev_ok[dev]) return fail(EXM_E_UNSUPPORTED, "device is not gfx950 (MI355X)");
+  return EXM_OK;
+}
+
+exm_status check_mesh(const exm_mesh* m, bool need_prepared) {
+  if (!m) return fail(EXM_E_INVAL, "mesh is NULL");
+  if (m->nV <= 0 || m->nF < 0 || m->nUV <= 0) return fail(EXM_E_INVAL, "mesh sizes must be nV > 0, nF >= 0, nUV > 0");
+  if (m->nF >= (1 << 27)) return fail(EXM_E_INVAL, "mesh has too many triangles (limit 2^27 - 1)");
+  // per-face arrays may be NULL for a mesh without triangles
+  if (!m->pos || !m->uv || (m->nF > 0 && (!m->tri || !m->tri_uv)))
+    return fail(EXM_E_INVAL, "mesh array pointer is NULL");
+  if (need_prepared) {
+    if (!m->vnrm || (m->nF > 0 && !m->ftan)) return fail(EXM_E_INVAL, "mesh vnrm/ftan are NULL (run exm_mesh_prepare)");
+    if (!aligned(m->ftan, 16) || !aligned(m->vnrm, 8)) return fail(EXM_E_INVAL, "mesh ftan must be 16-byte and vnrm 8-byte aligned");
+  }
+  return EXM_OK;
+}
+
+exm_status check_cams(const exm_camera* c, int32_t n) {
+  if (!c) return fail(EXM_E_INVAL, "cameras are NULL");
+  if (n <= 0) return fail(EXM_E_INVAL, "nViews must be > 0");
+  for (int32_t i = 0; i < n; ++i) {
+    if (c[i].H != c[0].H || c[i].W != c[0].W) return fail(EXM_E_INVAL, "all views of a call must share H and W");
+    for (int k = 0; k < 16; ++k)
+      if (!std::isfinite(c[i].mvp[k])) return fail(EXM_E_INVAL, "camera matrix is not finite");
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(c[i].eye[k])) return fail(EXM_E_INVAL, "camera eye is not finite");
+  }
+  if (c[0].H <= 0 || c[0].W <= 0) return fail(EXM_E_INVAL, "H and W must be > 0");
+  if ((int64_t)c[0].H * c[0].W * n >= ((int64_t)1 << 31))
+    return fail(EXM_E_INVAL, "nViews * H * W must be < 2^31");
+  return EXM_OK;
+}
+
+exm_status check_material(const exm_material* t) {
+  if (!t || !t->tex) return fail(EXM_E_INVAL, "material is NULL");
+  if (t->Ht <= 0 || t->Wt <= 0 || (int64_t)t->Ht * t->Wt >= ((int64_t)1 << 31))
+    return fail(EXM_E_INVAL, "material map size must be > 0 and Ht*Wt < 2^31");
+  if (!aligned(t->tex, 16)) return fail(EXM_E_INVAL, "material map must be 16-byte aligned");
+  return EXM_OK;
+}
+
+exm_status check_env_dims(int32_t He, int32_t We) {
+  if (He < 1 || We < 2 || (int64_t)He * We > ((int64_t)1 << 24))
+    return fail(EXM_E_INVAL, "env size must satisfy He >= 1, We >= 2, He*We <= 2^24");
+  return EXM_OK;
+}
+
+exm_status check_env(const exm_env* e) {
+  if (!e || !e->env || !e->cdf_row || !e->cdf_col || !e->pdf) return fail(EXM_E_INVAL, "env or its tables are NULL");
+  return check_env_dims(e->He, e->We);
+}
+
+exm_status check_params(const exm_params* p, bool indirect) {
+  if (!p) return fail(EXM_E_INVAL, "params are NULL");
+  if (p->N_d < 0 || p->N_d > 64) return fail(EXM_E_INVAL, "N_d must be in [0, 64]");
+  if (indirect) {
+    if (p->N_b < 0 || p->N_b > 64 || p->N_s < 0 || (int64_t)p->N_b * p->N_s > 64)
+      return fail(EXM_E_INVAL, "N_b, N_s must be >= 0 with N_b <= 64 and N_b * N_s <= 64");
+  }
+  if (!std::isfinite(p->tmin) || p->tmin < 0.f) return fail(EXM_E_INVAL, "tmin must be finite and >= 0");
+  if (!std::isfinite(p->eps) || p->eps < 0.f) return fail(EXM_E_INVAL, "eps must be finite and >= 0");
+  if (!std::isfinite(p->f_diel)) return fail(EXM_E_INVAL, "f_diel must be finite");
+  if (p->flags & ~0xFu) return fail(EXM_E_INVAL, "unknown flag bits");
+  return EXM_OK;
+}
+
+exm_status check_gbuffer(const int32_t* tri_id, const float* bary) {
+  if (!tri_id || !bary) return fail(EXM_E_INVAL, "G-buffer pointer is NULL");
+  if (!aligned(bary, 8)) return fail(EXM_E_INVAL, "bary must be 8-byte aligned");
+  return EXM_OK;
+}
+
+ShadeViews shade_views(const exm_camera* c, int32_t first, int32_t n) {
+  ShadeViews v;
+  std::memset(&v, 0, sizeof(v));
+  v.n = n;
+  v.H = c[0].H;
+  v.W = c[0].W;
+  for (int32_t i = 0; i < n; ++i) {
+    v.view_id[i] = c[first + i].view_id;
+    for (int k = 0; k < 3; ++k) v.eye[i][k] = (float)c[first + i].eye[k];
+  }
+  return v;
+}
+
+#define EXM_TRY(x)                        \
+  do {                                    \
+    exm_status _s = (x);                  \
+    if (_s != EXM_OK) return _s;          \
+  } while (0)
+
+}  // namespace
+
+exm_status fail(exm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+exm_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(EXM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return EXM_OK;
+}
+
+}  // namespace exm
+
+using namespace exm;
+
+extern "C" {
+
+const char* exm_last_error(void) { return g_last_error.c_str(); }
+
+exm_status exm_mesh_prepare(const exm_mesh* m, hipStream_t stream) {
+  EXM_TRY(check_mesh(m, true));
+  EXM_TRY(check_device());
+  hipError_t e = launch_mesh_prepare(m, stream);
+  if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_mesh_prepare: ") + hipGetErrorString(e));
+  return EXM_OK;
+}
+
+exm_status exm_build_bvh(const float* pos_host, int32_t nV, const int32_t* tri_host, int32_t nF, exm_bvh** out,
+                         hipStream_t stream) {
+  if (!out) return fail(EXM_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!pos_host || (nF > 0 && !tri_host)) return fail(EXM_E_INVAL, "host mesh arrays are NULL");
+  if (nV <= 0 || nF < 0 || nF >= (1 << 27)) return fail(EXM_E_INVAL, "bad mesh sizes");
+  for (int64_t i = 0; i < 3 * (int64_t)nF; ++i)
+    if (tri_host[i] < 0 || tri_host[i] >= nV) return fail(EXM_E_INVAL, "triangle vertex index out of range");
+  for (int64_t i = 0; i < 3 * (int64_t)nV; ++i)
+    if (!std::isfinite(pos_host[i])) return fail(EXM_E_INVAL, "vertex position is not finite");
+  EXM_TRY(check_device());
+  HostBvh hb{};
+  std::string err;
+  if (!build_bvh_host(pos_host, nV, tri_host, nF, &hb, &err)) return fail(EXM_E_NOMEM, err);
+  exm_bvh* b = new exm_bvh;
+  b->n_nodes = hb.n_nodes;
+  b->n_tris = hb.n_tris;
+  b->root_is_leaf = hb.root_is_leaf;
+  b->depth = hb.depth;
+  const size_t nb = sizeof(BvhNode) * (size_t)std::max(1, hb.n_nodes);
+  const size_t tb = sizeof(BvhTri) * (size_t)std::max(1, hb.n_tris);
+  if (hipMalloc(&b->nodes, nb) != hipSuccess || hipMalloc(&b->tris, tb) != hipSuccess) {
+    if (b->nodes) (void)hipFree(b->nodes);
+    free_bvh_host(&hb);
+    delete b;
+    (void)hipGetLastError();
+    return fail(EXM_E_NOMEM, "hipMalloc of the BVH failed");
+  }
+  b->bytes = nb + tb;
+  // synchronous copies: the host arrays are freed right after
+  hipError_t e1 = hipMemcpyAsync(b->nodes, hb.nodes, sizeof(BvhNode) * (size_t)hb.n_nodes, hipMemcpyHostToDevice, stream);
+  hipError_t e2 = hipMemcpyAsync(b->tris, hb.tris, sizeof(BvhTri) * (size_t)hb.n_tris, hipMemcpyHostToDevice, stream);
+  hipError_t e3 = hipStreamSynchronize(stream);
+  free_bvh_host(&hb);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+    (void)hipFree(b->nodes);
+    (void)hipFree(b->tris);
+    delete b;
+    return fail(EXM_E_HIP, "BVH upload failed");
+  }
+  *out = b;
+  return EXM_OK;
+}
+
+exm_status exm_free_bvh(exm_bvh* b) {
+  if (!b) return EXM_OK;
+  hipError_t e1 = hipFree(b->nodes), e2 = hipFree(b->tris);
+  delete b;
+  if (e1 != hipSuccess || e2 != hipSuccess) return fail(EXM_E_HIP, "hipFree of the BVH failed");
+  return EXM_OK;
+}
+
+size_t exm_bvh_device_bytes(const exm_bvh* b) { return b ? b->bytes : 0; }
+
+exm_status exm_build_env_sampler(const float* env, int32_t He, int32_t We, uint64_t* cdf_row, uint64_t* cdf_col,
+                                 float* pdf, hipStream_t stream) {
+  if (!env || !cdf_row || !cdf_col || !pdf) return fail(EXM_E_INVAL, "env sampler pointer is NULL");
+  EXM_TRY(check_env_dims(He, We));
+  if (!aligned(pdf, 8) || !aligned(cdf_row, 8) || !aligned(cdf_col, 8))
+    return fail(EXM_E_INVAL, "env tables must be 8-byte aligned");
+  EXM_TRY(check_device());
+  hipError_t e = launch_env_sampler(env, He, We, cdf_row, cdf_col, pdf, stream);
+  if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_build_env_sampler: ") + hipGetErrorString(e));
+  return EXM_OK;
+}
+
+exm_status exm_raster_gbuffer(const exm_mesh* m, const exm_camera* cams, int32_t nViews, int32_t* tri_id, float* bary,
+                              hipStream_t stream) {
+  EXM_TRY(check_mesh(m, false));
+  EXM_TRY(check_cams(cams, nViews));
+  EXM_TRY(check_gbuffer(tri_id, bary));
+  EXM_TRY(check_device());
+  const int64_t HW = (int64_t)cams[0].H * cams[0].W;
+  for (int32_t v0 = 0; v0 < nViews; v0 += kViewsPerLaunch) {
+    RasterViews rv;
+    std::memset(&rv, 0, sizeof(rv));
+    rv.n = std::min(kViewsPerLaunch, nViews - v0);
+    rv.H = cams[0].H;
+    rv.W = cams[0].W;
+    for (int32_t i = 0; i < rv.n; ++i) std::memcpy(rv.mvp[i], cams[v0 + i].mvp, sizeof(double) * 16);
+    hipError_t e = launch_raster(m, rv, tri_id + v0 * HW, bary + 2 * v0 * HW, stream);
+    if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_raster_gbuffer: ") + hipGetErrorString(e));
+  }
+  return EXM_OK;
+}
+
+exm_status exm_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
+                         const exm_camera* cams, int32_t nViews, const int32_t* tri_id, const float* bary,
+                         const exm_params* p, float* L_dir, uint64_t* vis, hipStream_t stream) {
+  EXM_TRY(check_mesh(m, true));
+  if (!bvh) return fail(EXM_E_INVAL, "bvh is NULL");
+  EXM_TRY(check_material(mat));
+  EXM_TRY(check_env(env));
+  EXM_TRY(check_cams(cams, nViews));
+  EXM_TRY(check_gbuffer(tri_id, bary));
+  EXM_TRY(check_params(p, false));
+  if (!L_dir || !vis) return fail(EXM_E_INVAL, "output pointer is NULL");
+  EXM_TRY(check_device());
+  const int64_t HW = (int64_t)cams[0].H * cams[0].W;
+  for (int32_t v0 = 0; v0 < nViews; v0 += kViewsPerLaunch) {
+    const int32_t n = std::min(kViewsPerLaunch, nViews - v0);
+    hipError_t e = launch_shade_fwd(m, bvh, mat, env, shade_views(cams, v0, n), tri_id + v0 * HW, bary + 2 * v0 * HW, p,
+                                    L_dir + 3 * v0 * HW, vis + v0 * HW, stream);
+    if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_shade_fwd: ") + hipGetErrorString(e));
+  }
+  return EXM_OK;
+}
+
+exm_status exm_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
+                              const exm_camera* cams, int32_t nViews, const int32_t* tri_id, const float* bary,
+                              const exm_params* p, float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis,
+                              hipStream_t stream) {
+  EXM_TRY(check_mesh(m, true));
+  if (!bvh) return fail(EXM_E_INVAL, "bvh is NULL");
+  EXM_TRY(check_material(mat));
+  EXM_TRY(check_env(env));
+  EXM_TRY(check_cams(cams, nViews));
+  EXM_TRY(check_gbuffer(tri_id, bary));
+  EXM_TRY(check_params(p, true));
+  if (!L_ind || !sec_vis || (!sec_rec && p->N_b > 0)) return fail(EXM_E_INVAL, "output pointer is NULL");
+  EXM_TRY(check_device());
+  const int64_t HW = (int64_t)cams[0].H * cams[0].W;
+  for (int32_t v0 = 0; v0 < nViews; v0 += kViewsPerLaunch) {
+    const int32_t n = std::min(kViewsPerLaunch, nViews - v0);
+    hipError_t e = launch_trace_indirect(m, bvh, mat, env, shade_views(cams, v0, n), tri_id + v0 * HW,
+                                         bary + 2 * v0 * HW, p, L_ind + 3 * v0 * HW,
+                                         sec_rec ? sec_rec + v0 * HW * p->N_b : nullptr, sec_vis + v0 * HW, stream);
+    if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_trace_indirect: ") + hipGetErrorString(e));
+  }
+  return EXM_OK;
+}
+
+exm_status exm_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const exm_camera* cams,
+                         int32_t nViews, const int32_t* tri_id, const float* bary, const exm_params* p, const float* dI,
+                         const uint64_t* vis, float* dtex, double* denv, hipStream_t stream) {
+  EXM_TRY(check_mesh(m, true));
+  EXM_TRY(check_material(mat));
+  EXM_TRY(check_env(env));
+  EXM_TRY(check_cams(cams, nViews));
+  EXM_TRY(check_gbuffer(tri_id, bary));
+  EXM_TRY(check_params(p, false));
+  if (!dI || !vis || !dtex || !denv) return fail(EXM_E_INVAL, "gradient pointer is NULL");
+  EXM_TRY(check_device());
+  const int64_t HW = (int64_t)cams[0].H * cams[0].W;
+  for (int32_t v0 = 0; v0 < nViews; v0 += kViewsPerLaunch) {
+    const int32_t n = std::min(kViewsPerLaunch, nViews - v0);
+    hipError_t e = launch_shade_bwd(m, mat, env, shade_views(cams, v0, n), tri_id + v0 * HW, bary + 2 * v0 * HW, p,
+                                    dI + 3 * v0 * HW, vis + v0 * HW, dtex, denv, stream);
+    if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_shade_bwd: ") + hipGetErrorString(e));
+  }
+  return EXM_OK;
+}
+
+exm_status exm_trace_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const exm_camera* cams,
+                         int32_t nViews, const int32_t* tri_id, const float* bary, const exm_params* p,
+                         float lambda_ind, const float* dI, const exm_sec_rec* sec_rec, const uint64_t* sec_vis,
+                         float* dtex, double* denv, hipStream_t stream) {
+  EXM_TRY(check_mesh(m, true));
+  EXM_TRY(check_material(mat));
+  EXM_TRY(check_env(env));
+  EXM_TRY(check_cams(cams, nViews));
+  EXM_TRY(check_gbuffer(tri_id, bary));
+  EXM_TRY(check_params(p, true));
+  if (!std::isfinite(lambda_ind)) return fail(EXM_E_INVAL, "lambda_ind must be finite");
+  if (!dI || !sec_vis || !dtex || !denv || (!sec_rec && p->N_b > 0)) return fail(EXM_E_INVAL, "pointer is NULL");
+  EXM_TRY(check_device());
+  const int64_t HW = (int64_t)cams[0].H * cams[0].W;
+  for (int32_t v0 = 0; v0 < nViews; v0 += kViewsPerLaunch) {
+    const int32_t n = std::min(kViewsPerLaunch, nViews - v0);
+    hipError_t e = launch_trace_bwd(m, mat, env, shade_views(cams, v0, n), tri_id + v0 * HW, bary + 2 * v0 * HW, p,
+                                    lambda_ind, dI + 3 * v0 * HW, sec_rec ? sec_rec + v0 * HW * p->N_b : nullptr,
+                                    sec_vis + v0 * HW, dtex, denv, stream);
+    if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_trace_bwd: ") + hipGetErrorString(e));
+  }
+  return EXM_OK;
+}
+
+}  // extern "C"

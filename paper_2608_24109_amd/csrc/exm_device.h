@@ -1,0 +1,446 @@
+// Device-side building blocks of the render pass (gfx950, wave64).
+//
+// Shared by the forward and adjoint kernels so that both take every discrete decision
+// (texel picks, ray directions, bilinear taps) from the same arithmetic.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "exm_internal.h"
+
+namespace exm {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kInvPi = 0.318309886183790671538f;
+
+// ------------------------------------------------------------------------------------------
+// small vector helpers
+// ------------------------------------------------------------------------------------------
+struct f3 {
+  float x, y, z;
+};
+__device__ __forceinline__ f3 mk(float x, float y, float z) { return {x, y, z}; }
+__device__ __forceinline__ f3 operator+(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ f3 operator-(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ f3 operator*(float s, f3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ f3 cross(f3 a, f3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ float len(f3 a) { return sqrtf(dot(a, a)); }
+__device__ __forceinline__ f3 normalize(f3 a) { return (1.0f / len(a)) * a; }
+__device__ __forceinline__ f3 ld3(const float* p, int64_t i) { return {p[3 * i], p[3 * i + 1], p[3 * i + 2]}; }
+__device__ __forceinline__ f3 ld3d(const double* p, int64_t i) {
+  return {(float)p[3 * i], (float)p[3 * i + 1], (float)p[3 * i + 2]};
+}
+
+// ------------------------------------------------------------------------------------------
+// Philox4x32-10 counter-based generator (Salmon et al., SC'11)
+// ------------------------------------------------------------------------------------------
+struct Draw {
+  uint64_t x;  // 64-bit word for the integer CDF target
+  float u2, u3;
+};
+
+__device__ __forceinline__ Draw philox_draw(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
+                                            uint32_t c2, uint32_t c3) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  Draw d;
+  d.x = ((uint64_t)c0 << 32) | c1;
+  d.u2 = (float)(c2 >> 8) * (1.0f / 16777216.0f);
+  d.u3 = (float)(c3 >> 8) * (1.0f / 16777216.0f);
+  return d;
+}
+
+struct RngKey {
+  uint32_t k0, k1;
+};
+__host__ __device__ inline RngKey make_key(uint64_t seed, uint64_t iteration) {
+  return {(uint32_t)seed ^ (uint32_t)(seed >> 32), (uint32_t)iteration};
+}
+
+// ------------------------------------------------------------------------------------------
+// env importance sampling: integer CDF inversion, then uniform in solid angle in the texel
+// ------------------------------------------------------------------------------------------
+struct EnvView {
+  int32_t He, We;
+  const float* env;
+  const uint64_t* cdf_row;
+  const uint64_t* cdf_col;
+  const float* pdf;
+};
+
+struct EnvSample {
+  int32_t texel;
+  f3 dir;
+  float inv_pdf;
+};
+
+// first index in [0, n) with a[i] > t (a is non-decreasing, a[n-1] > t)
+__device__ __forceinline__ int32_t upper_bound_u64(const uint64_t* a, int32_t n, uint64_t t) {
+  int32_t lo = 0, cnt = n;
+  while (cnt > 0) {
+    int32_t step = cnt >> 1;
+    if (a[lo + step] <= t) {
+      lo += step + 1;
+      cnt -= step + 1;
+    } else {
+      cnt = step;
+    }
+  }
+  return lo;
+}
+
+__device__ __forceinline__ EnvSample env_sample(const EnvView& e, const Draw& d) {
+  const uint64_t Q = e.cdf_row[e.He - 1];
+  const uint64_t target = __umul64hi(d.x, Q);
+  // target < Q whenever the tables are well formed; the clamps only keep a malformed table
+  // (e.g. built from a NaN map) inside the arrays
+  const int32_t row = min(upper_bound_u64(e.cdf_row, e.He, target), e.He - 1);
+  const uint64_t rem = target - (row > 0 ? e.cdf_row[row - 1] : 0ull);
+  const int32_t col = min(upper_bound_u64(e.cdf_col + (int64_t)row * e.We, e.We, rem), e.We - 1);
+  EnvSample s;
+  s.texel = row * e.We + col;
+  // theta in [row, row+1] * pi/He with cos(theta) uniform; the complement 1 -/+ cos(theta) is
+  // formed from half-angle sines so that sin(theta) keeps full precision at both poles
+  const float inv2He = 0.5f / (float)e.He;
+  const float dlt = 2.0f * sinpif((float)(2 * row + 1) * inv2He) * sinpif(inv2He);  // c_i - c_{i+1}
+  float ct, st2;
+  if (2 * row < e.He) {
+    const float sa = sinpif((float)row * inv2He);
+    const float omc = 2.0f * sa * sa + d.u3 * dlt;  // 1 - cos(theta)
+    ct = 1.0f - omc;
+    st2 = omc * (2.0f - omc);
+  } else {
+    const float sb = sinpif((float)(e.He - row - 1) * inv2He);
+    const float opc = 2.0f * sb * sb + (1.0f - d.u3) * dlt;  // 1 + cos(theta)
+    ct = opc - 1.0f;
+    st2 = opc * (2.0f - opc);
+  }
+  const float st = sqrtf(fmaxf(st2, 0.0f));
+  // phi = 2 pi (col + u2) / We by angle addition (keeps u2's resolution at large col)
+  float sj, cj, sd, cd;
+  sincospif(2.0f * (float)col / (float)e.We, &sj, &cj);
+  sincospif(2.0f * d.u2 / (float)e.We, &sd, &cd);
+  const float cphi = cj * cd - sj * sd, sphi = sj * cd + cj * sd;
+  s.dir = mk(st * cphi, ct, st * sphi);
+  s.inv_pdf = 1.0f / e.pdf[s.texel];
+  return s;
+}
+
+// ------------------------------------------------------------------------------------------
+// attribute query at a surface point (Attribute Query, Eq. 10-11)
+// ------------------------------------------------------------------------------------------
+struct MeshView {
+  int32_t nV, nF;
+  const float* pos;
+  const int32_t* tri;
+  const float* uv;
+  const int32_t* tri_uv;
+  const double* vnrm;
+  const float* ftan;
+};
+
+struct TexView {
+  int32_t Ht, Wt;
+  const float* tex;
+};
+
+struct Surf {
+  f3 x, ng;
+  f3 T, B;       // Gram-Schmidt tangent frame (valid if map_ok)
+  f3 ns;         // shading normal
+  float vlen;    // |q.x T + q.y B + q.z n_g| (map_ok only)
+  bool map_ok;   // normal map applied (otherwise n_s = n_g)
+  int32_t tap[4];
+  float w[4];
+  float a[3], r, m, q[3];
+};
+
+// Texel-space position in FP64: with i.i.d. texel values the material is sensitive to the
+// sample position at the scale of one texel, and a float u (ulp 6e-8) would already move it by
+// 1e-4 texel on a 2048^2 map.
+__device__ __forceinline__ void bilinear_taps(const TexView& t, double u, double v, int32_t tap[4], float w[4]) {
+  u = fmin(1.0, fmax(0.0, u));
+  v = fmin(1.0, fmax(0.0, v));
+  const double s = u * (double)t.Wt - 0.5, tt = v * (double)t.Ht - 0.5;
+  const double s0 = floor(s), t0 = floor(tt);
+  const float fs = (float)(s - s0), ft = (float)(tt - t0);
+  const int32_t i0 = (int32_t)s0, j0 = (int32_t)t0;
+  const int32_t ia = min(t.Wt - 1, max(0, i0)), ib = min(t.Wt - 1, max(0, i0 + 1));
+  const int32_t ja = min(t.Ht - 1, max(0, j0)), jb = min(t.Ht - 1, max(0, j0 + 1));
+  tap[0] = ja * t.Wt + ia;
+  tap[1] = ja * t.Wt + ib;
+  tap[2] = jb * t.Wt + ia;
+  tap[3] = jb * t.Wt + ib;
+  w[0] = (1.0f - fs) * (1.0f - ft);
+  w[1] = fs * (1.0f - ft);
+  w[2] = (1.0f - fs) * ft;
+  w[3] = fs * ft;
+}
+
+__device__ __forceinline__ Surf query(const MeshView& M, const TexView& T, int32_t f, float b1, float b2,
+                                      uint32_t flags) {
+  Surf S;
+  const float b0 = 1.0f - b1 - b2;
+  const int32_t v0 = M.tri[3 * f], v1 = M.tri[3 * f + 1], v2 = M.tri[3 * f + 2];
+  const f3 P0 = ld3(M.pos, v0), P1 = ld3(M.pos, v1), P2 = ld3(M.pos, v2);
+  S.x = (b0 * P0 + b1 * P1) + b2 * P2;
+  const f3 N0 = ld3d(M.vnrm, v0), N1 = ld3d(M.vnrm, v1), N2 = ld3d(M.vnrm, v2);
+  S.ng = normalize((b0 * N0 + b1 * N1) + b2 * N2);
+  const int32_t t0 = M.tri_uv[3 * f], t1 = M.tri_uv[3 * f + 1], t2 = M.tri_uv[3 * f + 2];
+  const double d1 = b1, d2 = b2, d0 = 1.0 - d1 - d2;
+  const double u = (d0 * M.uv[2 * t0] + d1 * M.uv[2 * t1]) + d2 * M.uv[2 * t2];
+  const double v = (d0 * M.uv[2 * t0 + 1] + d1 * M.uv[2 * t1 + 1]) + d2 * M.uv[2 * t2 + 1];
+  bilinear_taps(T, u, v, S.tap, S.w);
+  float ch[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) ch[c] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float4* tp = reinterpret_cast<const float4*>(T.tex + (int64_t)S.tap[k] * 8);
+    const float4 lo = tp[0], hi = tp[1];
+    ch[0] += S.w[k] * lo.x;
+    ch[1] += S.w[k] * lo.y;
+    ch[2] += S.w[k] * lo.z;
+    ch[3] += S.w[k] * lo.w;
+    ch[4] += S.w[k] * hi.x;
+    ch[5] += S.w[k] * hi.y;
+    ch[6] += S.w[k] * hi.z;
+    ch[7] += S.w[k] * hi.w;
+  }
+  S.a[0] = ch[0];
+  S.a[1] = ch[1];
+  S.a[2] = ch[2];
+  S.r = ch[3];
+  S.m = (flags & EXM_METALLIC_OFF) ? 0.0f : ch[4];
+  S.q[0] = ch[5];
+  S.q[1] = ch[6];
+  S.q[2] = ch[7];
+  const float4 ft = reinterpret_cast<const float4*>(M.ftan)[f];
+  const f3 Tf = mk(ft.x, ft.y, ft.z);
+  f3 Tp = Tf - dot(S.ng, Tf) * S.ng;
+  const float lt = len(Tp);
+  S.map_ok = false;
+  S.ns = S.ng;
+  S.vlen = 1.0f;
+  S.T = S.B = mk(0, 0, 0);
+  if (lt >= 1e-12f) {
+    Tp = (1.0f / lt) * Tp;
+    const f3 Bp = ft.w * cross(S.ng, Tp);
+    const f3 vv = (S.q[0] * Tp + S.q[1] * Bp) + S.q[2] * S.ng;
+    const float lv = len(vv);
+    if (lv >= 1e-12f) {
+      S.map_ok = true;
+      S.T = Tp;
+      S.B = Bp;
+      S.vlen = lv;
+      S.ns = (1.0f / lv) * vv;
+    }
+  }
+  return S;
+}
+
+// ------------------------------------------------------------------------------------------
+// metallic-roughness BRDF (Eq. 13-16): GGX D with sin^2 = |n x h|^2, separable Smith-GGX G,
+// Schlick F, alpha = r^2
+// ------------------------------------------------------------------------------------------
+struct Spec {
+  bool on;               // f_s evaluated (n.wi > 0, n.wo > 0, |wi + wo| > 0)
+  f3 h;
+  float ci, co, alpha2;  // n.wi, n.wo, alpha^2
+  float chh, d;          // n.h, sin^2 + alpha^2 cos^2
+  float D, G1i, G1o, si, so;  // D, G1(wi), G1(wo), sqrt terms of G1
+  float den, x5;          // 4 ci co + eps, (1 - wi.h)^5
+  bool alpha_clamped;
+};
+
+__device__ __forceinline__ Spec spec_terms(f3 n, f3 wi, f3 wo, float ci, float r, float eps) {
+  Spec s;
+  s.on = false;
+  const f3 hs = wi + wo;
+  const float hl = len(hs);
+  s.co = dot(n, wo);
+  s.ci = ci;
+  if (!(hl >= 1e-12f) || !(s.co > 0.0f) || !(ci > 0.0f)) return s;
+  s.on = true;
+  s.h = (1.0f / hl) * hs;
+  const float alpha = r * r;
+  s.alpha2 = alpha * alpha;
+  s.alpha_clamped = s.alpha2 < 1e-12f;
+  if (s.alpha_clamped) s.alpha2 = 1e-12f;
+  s.chh = dot(n, s.h);
+  const f3 nx = cross(n, s.h);
+  s.d = dot(nx, nx) + s.alpha2 * s.chh * s.chh;
+  s.D = s.alpha2 / (kPi * s.d * s.d);
+  s.si = sqrtf(s.alpha2 + (1.0f - s.alpha2) * ci * ci);
+  s.so = sqrtf(s.alpha2 + (1.0f - s.alpha2) * s.co * s.co);
+  s.G1i = 2.0f * ci / (ci + s.si);
+  s.G1o = 2.0f * s.co / (s.co + s.so);
+  const float x = 1.0f - fmaxf(dot(wi, s.h), 0.0f);
+  const float x2 = x * x;
+  s.x5 = x2 * x2 * x;
+  s.den = 4.0f * ci * s.co + eps;
+  return s;
+}
+
+// ------------------------------------------------------------------------------------------
+// BVH (binned SAH, 64-byte nodes) and ray queries
+// ------------------------------------------------------------------------------------------
+struct BvhView {
+  const BvhNode* nodes;
+  const BvhTri* tris;
+  int32_t root_is_leaf;
+};
+
+// ray precomputation for the watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013)
+struct Ray {
+  f3 o, d, inv;
+  int kx, ky, kz;
+  float Sx, Sy, Sz;
+};
+
+__device__ __forceinline__ float comp(f3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+
+__device__ __forceinline__ Ray make_ray(f3 o, f3 d) {
+  Ray r;
+  r.o = o;
+  r.d = d;
+  r.inv = mk(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
+  const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+  r.kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+  r.kx = r.kz == 2 ? 0 : r.kz + 1;
+  r.ky = r.kx == 2 ? 0 : r.kx + 1;
+  if (comp(d, r.kz) < 0.0f) {
+    int t = r.kx;
+    r.kx = r.ky;
+    r.ky = t;
+  }
+  const float dz = comp(d, r.kz);
+  r.Sx = comp(d, r.kx) / dz;
+  r.Sy = comp(d, r.ky) / dz;
+  r.Sz = 1.0f / dz;
+  return r;
+}
+
+// returns true on hit with t in [tmin, tmax]; writes t and barycentrics (b1, b2)
+__device__ __forceinline__ bool tri_hit(const Ray& r, const BvhTri& T, float tmin, float tmax, float* t_out,
+                                        float* b1, float* b2) {
+  const f3 A = mk(T.v0[0], T.v0[1], T.v0[2]) - r.o;
+  const f3 B = mk(T.v1[0], T.v1[1], T.v1[2]) - r.o;
+  const f3 C = mk(T.v2[0], T.v2[1], T.v2[2]) - r.o;
+  const float Az0 = comp(A, r.kz), Bz0 = comp(B, r.kz), Cz0 = comp(C, r.kz);
+  const float Ax = comp(A, r.kx) - r.Sx * Az0, Ay = comp(A, r.ky) - r.Sy * Az0;
+  const float Bx = comp(B, r.kx) - r.Sx * Bz0, By = comp(B, r.ky) - r.Sy * Bz0;
+  const float Cx = comp(C, r.kx) - r.Sx * Cz0, Cy = comp(C, r.ky) - r.Sy * Cz0;
+  float U = Cx * By - Cy * Bx;
+  float V = Ax * Cy - Ay * Cx;
+  float W = Bx * Ay - By * Ax;
+  if (U == 0.0f || V == 0.0f || W == 0.0f) {  // edge case: redo in double for watertightness
+    U = (float)((double)Cx * By - (double)Cy * Bx);
+    V = (float)((double)Ax * Cy - (double)Ay * Cx);
+    W = (float)((double)Bx * Ay - (double)By * Ax);
+  }
+  if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+  const float det = U + V + W;
+  if (det == 0.0f) return false;
+  const float Tn = U * (r.Sz * Az0) + V * (r.Sz * Bz0) + W * (r.Sz * Cz0);
+  const float inv = 1.0f / det;
+  const float t = Tn * inv;
+  if (!(t >= tmin && t <= tmax)) return false;
+  *t_out = t;
+  *b1 = V * inv;
+  *b2 = W * inv;
+  return true;
+}
+
+// slab test of one child box; returns entry distance or +inf
+__device__ __forceinline__ float box_enter(const float* lo, const float* hi, const Ray& r, float tmax) {
+  const float tx0 = (lo[0] - r.o.x) * r.inv.x, tx1 = (hi[0] - r.o.x) * r.inv.x;
+  const float ty0 = (lo[1] - r.o.y) * r.inv.y, ty1 = (hi[1] - r.o.y) * r.inv.y;
+  const float tz0 = (lo[2] - r.o.z) * r.inv.z, tz1 = (hi[2] - r.o.z) * r.inv.z;
+  const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+  const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax));
+  // conservative by a few ulps so rays grazing a box face are not lost
+  return tn <= tf * 1.00000024f ? tn : __builtin_huge_valf();
+}
+
+struct HitRec {
+  int32_t id;  // original triangle id, -1 = miss
+  float t, b1, b2;
+};
+
+// Stack of node references in LDS: stack[slot * stride + lane_slot]
+template <bool ANY>
+__device__ __forceinline__ HitRec trace(const BvhView& B, const Ray& r, float tmin, int32_t skip, int32_t* stack,
+                                        int stride) {
+  HitRec h;
+  h.id = -1;
+  h.t = __builtin_huge_valf();
+  h.b1 = h.b2 = 0.0f;
+  int sp = 0;
+  int32_t ref = B.root_is_leaf ? B.nodes[0].c0 : 0;
+  const int32_t kEmpty = (int32_t)0x80000000;
+  // the builder bounds the depth by kMaxDepth < kStack; the visit cap only guarantees that a
+  // corrupted structure cannot keep a wave alive
+  for (int visits = 0; visits < (1 << 22); ++visits) {
+    if (ref >= 0) {
+      const BvhNode& N = B.nodes[ref];
+      const float4 a = reinterpret_cast<const float4*>(&N)[0];
+      const float4 b = reinterpret_cast<const float4*>(&N)[1];
+      const float4 c = reinterpret_cast<const float4*>(&N)[2];
+      const int4 e = reinterpret_cast<const int4*>(&N)[3];
+      const float lo0[3] = {a.x, a.y, a.z}, hi0[3] = {a.w, b.x, b.y};
+      const float lo1[3] = {b.z, b.w, c.x}, hi1[3] = {c.y, c.z, c.w};
+      const float t0 = box_enter(lo0, hi0, r, h.t);
+      const float t1 = box_enter(lo1, hi1, r, h.t);
+      const bool h0 = t0 != __builtin_huge_valf(), h1 = t1 != __builtin_huge_valf();
+      if (h0 && h1) {
+        const bool first0 = t0 <= t1;
+        ref = first0 ? e.x : e.y;
+        if (sp < kStack) stack[(sp++) * stride] = first0 ? e.y : e.x;
+        continue;
+      }
+      if (h0 || h1) {
+        ref = h0 ? e.x : e.y;
+        continue;
+      }
+    } else if (ref != kEmpty) {
+      const uint32_t v = ~(uint32_t)ref;
+      const int32_t first = (int32_t)(v >> 4), cnt = (int32_t)(v & 15u);
+      for (int32_t i = first; i < first + cnt; ++i) {
+        const BvhTri T = B.tris[i];
+        if (T.id == skip) continue;
+        float t, b1, b2;
+        if (tri_hit(r, T, tmin, h.t, &t, &b1, &b2)) {
+          if (ANY) {
+            h.id = T.id;
+            return h;
+          }
+          if (t < h.t || (t == h.t && T.id < h.id)) {
+            h.id = T.id;
+            h.t = t;
+            h.b1 = b1;
+            h.b2 = b2;
+          }
+        }
+      }
+    }
+    if (sp == 0) break;
+    ref = stack[(--sp) * stride];
+  }
+  return h;
+}
+
+}  // namespace exm

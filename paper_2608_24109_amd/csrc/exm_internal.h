@@ -1,0 +1,93 @@
+// Internal declarations shared by the host ABI layer and the kernel files.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/exm.h"
+
+namespace exm {
+
+// 64-byte BVH2 node: boxes of both children and their references.
+//   ref >= 0              internal node index
+//   ref <  0, != INT_MIN  leaf: v = ~ref, triangles [v >> 4, (v >> 4) + (v & 15))
+//   ref == INT_MIN        empty
+struct alignas(64) BvhNode {
+  float lo0[3], hi0[3];
+  float lo1[3], hi1[3];
+  int32_t c0, c1;
+  int32_t pad[2];
+};
+static_assert(sizeof(BvhNode) == 64, "node layout");
+
+// 48-byte triangle record in leaf order (vertices copied, original id kept)
+struct alignas(16) BvhTri {
+  float v0[3], v1[3], v2[3];
+  int32_t id;
+  int32_t pad[2];
+};
+static_assert(sizeof(BvhTri) == 48, "triangle layout");
+
+constexpr int kMaxDepth = 30;  // builder guarantee; traversal stack holds <= kMaxDepth refs
+constexpr int kStack = 32;
+
+// Views per launch: camera data travels in kernel arguments.
+constexpr int kViewsPerLaunch = 8;
+
+struct RasterViews {
+  int32_t n, H, W;
+  double mvp[kViewsPerLaunch][16];
+};
+
+struct ShadeViews {
+  int32_t n, H, W;
+  int32_t view_id[kViewsPerLaunch];
+  float eye[kViewsPerLaunch][3];
+};
+
+}  // namespace exm
+
+struct exm_bvh {
+  exm::BvhNode* nodes = nullptr;
+  exm::BvhTri* tris = nullptr;
+  int32_t n_nodes = 0, n_tris = 0;
+  int32_t root_is_leaf = 0;
+  int32_t depth = 0;
+  size_t bytes = 0;
+};
+
+namespace exm {
+
+// error reporting (thread-local last error)
+exm_status fail(exm_status s, const std::string& msg);
+exm_status check_launch(const char* what);
+
+// host launchers (defined in the .hip files); arguments already validated
+hipError_t launch_mesh_prepare(const exm_mesh* m, hipStream_t s);
+hipError_t launch_env_sampler(const float* env, int32_t He, int32_t We, uint64_t* cdf_row, uint64_t* cdf_col,
+                              float* pdf, hipStream_t s);
+hipError_t launch_raster(const exm_mesh* m, const RasterViews& v, int32_t* tri_id, float* bary, hipStream_t s);
+hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
+                            const ShadeViews& v, const int32_t* tri_id, const float* bary, const exm_params* p,
+                            float* L_dir, uint64_t* vis, hipStream_t s);
+hipError_t launch_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const ShadeViews& v,
+                            const int32_t* tri_id, const float* bary, const exm_params* p, const float* dI,
+                            const uint64_t* vis, float* dtex, double* denv, hipStream_t s);
+hipError_t launch_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
+                                 const ShadeViews& v, const int32_t* tri_id, const float* bary, const exm_params* p,
+                                 float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis, hipStream_t s);
+hipError_t launch_trace_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const ShadeViews& v,
+                            const int32_t* tri_id, const float* bary, const exm_params* p, float lambda_ind,
+                            const float* dI, const exm_sec_rec* sec_rec, const uint64_t* sec_vis, float* dtex,
+                            double* denv, hipStream_t s);
+
+// host SAH builder (bvh_build.cpp): fills node/triangle arrays in host memory
+struct HostBvh {
+  BvhNode* nodes;
+  BvhTri* tris;
+  int32_t n_nodes, n_tris, root_is_leaf, depth;
+};
+bool build_bvh_host(const float* pos, int32_t nV, const int32_t* tri, int32_t nF, HostBvh* out, std::string* err);
+void free_bvh_host(HostBvh* b);
+
+}  // namespace exm

@@ -1,0 +1,138 @@
+"""The Stage-II render pass over the C ABI, and its autograd form.
+
+render_forward:  env tables -> G-buffer -> direct (Eq. 17) -> indirect (Eq. 18-19)
+render_backward: adjoints of the direct and indirect passes into the maps and the env map
+RenderPBR:       torch.autograd.Function; I = L_dir + lambda_ind * L_ind (Eq. 20); with
+                 checkpoint=True the G-buffer is not kept between forward and backward but
+                 rasterised again in backward (only the visibility bits and secondary-hit
+                 records are stored).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+from .scene import DeviceEnv, DeviceMaterial, DeviceMesh
+
+
+@dataclass
+class PassParams:
+    N_d: int = 8          # direct env samples (hyperparameter table default)
+    N_b: int = 0          # secondary rays (0: direct only)
+    N_s: int = 4          # light samples per secondary hit
+    seed: int = 3
+    iteration: int = 0
+    tmin: float = 0.0
+    flags: int = 0
+    f_diel: float = 0.04  # F_dielectric of Eq. 16
+    eps: float = 1e-6     # epsilon of Eq. 15
+
+    def c(self) -> L.exm_params:
+        return L.params(self.N_d, self.N_b, self.N_s if self.N_b > 0 else 0, self.seed, self.iteration,
+                        self.f_diel, self.eps, self.tmin, self.flags)
+
+
+class PassBuffers:
+    """Per-view outputs of one forward pass (device tensors)."""
+
+    def __init__(self, n: int, H: int, W: int, N_b: int, device="cuda", gbuffer: bool = True):
+        self.n, self.H, self.W, self.N_b = n, H, W, N_b
+        self.tri_id = torch.empty((n, H, W), dtype=torch.int32, device=device) if gbuffer else None
+        self.bary = torch.empty((n, H, W, 2), dtype=torch.float32, device=device) if gbuffer else None
+        self.L_dir = torch.empty((n, H, W, 3), dtype=torch.float32, device=device)
+        self.vis = torch.empty((n, H, W), dtype=torch.uint64, device=device)
+        self.L_ind = torch.empty((n, H, W, 3), dtype=torch.float32, device=device) if N_b > 0 else None
+        self.sec_rec = torch.empty((n, H, W, max(N_b, 1), 3), dtype=torch.int32, device=device) if N_b > 0 else None
+        self.sec_vis = torch.empty((n, H, W), dtype=torch.uint64, device=device) if N_b > 0 else None
+
+    def ensure_gbuffer(self, device="cuda"):
+        if self.tri_id is None:
+            self.tri_id = torch.empty((self.n, self.H, self.W), dtype=torch.int32, device=device)
+            self.bary = torch.empty((self.n, self.H, self.W, 2), dtype=torch.float32, device=device)
+
+    def drop_gbuffer(self):
+        self.tri_id = None
+        self.bary = None
+
+
+def raster(mesh: DeviceMesh, cams_c, bufs: PassBuffers, stream=None) -> None:
+    bufs.ensure_gbuffer()
+    L.exm_raster_gbuffer(mesh.s, cams_c, bufs.tri_id, bufs.bary, stream)
+
+
+def render_forward(mesh: DeviceMesh, mat: DeviceMaterial, env: DeviceEnv, cams_c, p: PassParams,
+                   bufs: PassBuffers, stream=None, rebuild_tables: bool = True, do_raster: bool = True) -> None:
+    pc = p.c()
+    if rebuild_tables:
+        env.update(stream=stream)
+    if do_raster:
+        raster(mesh, cams_c, bufs, stream)
+    L.exm_shade_fwd(mesh.s, mesh.bvh, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, bufs.L_dir, bufs.vis,
+                    stream)
+    if p.N_b > 0:
+        L.exm_trace_indirect(mesh.s, mesh.bvh, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, bufs.L_ind,
+                             bufs.sec_rec, bufs.sec_vis, stream)
+
+
+def render_backward(mesh: DeviceMesh, mat: DeviceMaterial, env: DeviceEnv, cams_c, p: PassParams,
+                    bufs: PassBuffers, dI: torch.Tensor, lambda_ind: float, dtex: torch.Tensor,
+                    denv: torch.Tensor, stream=None) -> None:
+    pc = p.c()
+    L.exm_shade_bwd(mesh.s, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, dI, bufs.vis, dtex, denv, stream)
+    if p.N_b > 0 and lambda_ind != 0.0:
+        L.exm_trace_bwd(mesh.s, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, lambda_ind, dI, bufs.sec_rec,
+                        bufs.sec_vis, dtex, denv, stream)
+
+
+class RenderPBR(torch.autograd.Function):
+    """I = L_dir + lambda_ind L_ind for the views `cams`, differentiable w.r.t. the packed
+    material map `tex` [Ht,Wt,8] and the env map `env` [He,We,3].
+
+    The maps passed in must be the tensors that `mat` and `env_dev` point to (the kernels read
+    them through the device structs). Views are processed in chunks of `chunk` views; with
+    checkpoint=True each chunk's G-buffer is freed after the forward and rasterised again in
+    backward.
+    """
+
+    @staticmethod
+    def forward(ctx, tex, env, mesh, mat, env_dev, cams, p: PassParams, lambda_ind: float = 1.0,
+                checkpoint: bool = False, chunk: int = 8):
+        if tex.data_ptr() != mat.tex.data_ptr() or env.data_ptr() != env_dev.env.data_ptr():
+            raise ValueError("tex/env must be the tensors bound to the device material/env")
+        env_dev.update()
+        H, W = cams[0].H, cams[0].W
+        out = torch.empty((len(cams), H, W, 3), dtype=torch.float32, device=tex.device)
+        chunks = []
+        for v0 in range(0, len(cams), chunk):
+            cs = cams[v0:v0 + chunk]
+            cc = L.cameras(cs, [getattr(c, "view_id", v0 + i) for i, c in enumerate(cs)])
+            bufs = PassBuffers(len(cs), H, W, p.N_b, device=tex.device)
+            render_forward(mesh, mat, env_dev, cc, p, bufs, rebuild_tables=False)
+            o = out[v0:v0 + len(cs)]
+            if p.N_b > 0:
+                torch.add(bufs.L_dir, bufs.L_ind, alpha=lambda_ind, out=o)
+            else:
+                o.copy_(bufs.L_dir)
+            bufs.L_dir = bufs.L_ind = None
+            if checkpoint:
+                bufs.drop_gbuffer()
+            chunks.append((cc, bufs))
+        ctx.state = (mesh, mat, env_dev, chunks, p, lambda_ind, chunk)
+        return out
+
+    @staticmethod
+    def backward(ctx, dI):
+        mesh, mat, env_dev, chunks, p, lambda_ind, chunk = ctx.state
+        dI = dI.contiguous().float()
+        dtex = torch.zeros_like(mat.tex)
+        denv = torch.zeros(env_dev.env.shape, dtype=torch.float64, device=dI.device)
+        for k, (cc, bufs) in enumerate(chunks):
+            if bufs.tri_id is None:
+                raster(mesh, cc, bufs)
+            g = dI[k * chunk:k * chunk + bufs.n]
+            render_backward(mesh, mat, env_dev, cc, p, bufs, g, lambda_ind, dtex, denv)
+            bufs.drop_gbuffer()
+        ctx.state = None
+        return dtex, denv.to(torch.float32), None, None, None, None, None, None, None, None

@@ -1,0 +1,131 @@
+"""The C-ABI library on the CPU: it loads, exports every entry point include/exm.h declares,
+and rejects invalid arguments with EXM_E_INVAL before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2608_24109_amd import _lib
+    return _lib
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "exm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(exm_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(L.lib, n), n
+
+
+def _mesh(L, nV=3, nF=1, nUV=3, ptr=0x1000):
+    return L.exm_mesh(nV, nF, nUV, ptr, ptr, ptr, ptr, ptr, ptr)
+
+
+def _cams(L, n=1, H=8, W=8):
+    from paper_2608_24109_amd import inputs as I
+    return L.cameras(I.ring_cameras(n, 3.0, H, W))
+
+
+def _status(L, fn, *args):
+    s = fn(*args)
+    return s, L.last_error()
+
+
+def test_raster_validation(L):
+    f = L.lib.exm_raster_gbuffer
+    m = _mesh(L)
+    cams = _cams(L)
+    assert _status(L, f, None, cams, 1, 0x1000, 0x1000, None)[0] == L.EXM_E_INVAL
+    assert _status(L, f, C.byref(m), None, 1, 0x1000, 0x1000, None)[0] == L.EXM_E_INVAL
+    assert _status(L, f, C.byref(m), cams, 0, 0x1000, 0x1000, None)[0] == L.EXM_E_INVAL
+    s, msg = _status(L, f, C.byref(m), cams, 1, 0x1000, 0x1004, None)
+    assert s == L.EXM_E_INVAL and "aligned" in msg
+    bad = _mesh(L, nV=0)
+    assert _status(L, f, C.byref(bad), cams, 1, 0x1000, 0x1000, None)[0] == L.EXM_E_INVAL
+    two = _cams(L, 2)
+    two[1].H = 9
+    s, msg = _status(L, f, C.byref(m), two, 2, 0x1000, 0x1000, None)
+    assert s == L.EXM_E_INVAL and "share H and W" in msg
+    nan = _cams(L)
+    nan[0].mvp[5] = float("nan")
+    assert _status(L, f, C.byref(m), nan, 1, 0x1000, 0x1000, None)[0] == L.EXM_E_INVAL
+    huge = _cams(L, 1, H=65536, W=65536)
+    assert _status(L, f, C.byref(m), huge, 1, 0x1000, 0x1000, None)[0] == L.EXM_E_INVAL
+
+
+def test_shade_validation(L):
+    m = _mesh(L)
+    cams = _cams(L)
+    mat = L.exm_material(4, 4, 0x1000)
+    env = L.exm_env(4, 8, 0x1000, 0x1000, 0x1000, 0x1000)
+    f = L.lib.exm_shade_fwd
+    bvh = 0x2000
+
+    def call(p=None, **kw):
+        a = dict(m=C.byref(m), bvh=bvh, mat=C.byref(mat), env=C.byref(env), cams=cams, n=1, tri=0x1000,
+                 bary=0x1000, p=C.byref(p if p is not None else L.params(8)), L=0x1000, vis=0x1000,
+                 stream=None)
+        a.update(kw)
+        return _status(L, f, *a.values())
+
+    assert call(L.params(65))[0] == L.EXM_E_INVAL
+    assert call(L.params(-1))[0] == L.EXM_E_INVAL
+    assert call(L.params(8, tmin=float("inf")))[0] == L.EXM_E_INVAL
+    assert call(L.params(8, flags=1 << 7))[0] == L.EXM_E_INVAL
+    assert call(bvh=None)[0] == L.EXM_E_INVAL
+    assert call(L=None)[0] == L.EXM_E_INVAL
+    mis = L.exm_material(4, 4, 0x1004)
+    assert call(mat=C.byref(mis))[0] == L.EXM_E_INVAL
+    e1 = L.exm_env(4, 1, 0x1000, 0x1000, 0x1000, 0x1000)
+    assert call(env=C.byref(e1))[0] == L.EXM_E_INVAL
+    unprep = L.exm_mesh(3, 1, 3, 0x1000, 0x1000, 0x1000, 0x1000, None, None)
+    s, msg = call(m=C.byref(unprep))
+    assert s == L.EXM_E_INVAL and "exm_mesh_prepare" in msg
+
+
+def test_indirect_and_backward_validation(L):
+    m = _mesh(L)
+    cams = _cams(L)
+    mat = L.exm_material(4, 4, 0x1000)
+    env = L.exm_env(4, 8, 0x1000, 0x1000, 0x1000, 0x1000)
+    p = L.params(8, N_b=16, N_s=8)  # 128 light-sample bits do not fit one u64
+    s = L.lib.exm_trace_indirect(C.byref(m), 0x2000, C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000,
+                                 C.byref(p), 0x1000, 0x1000, 0x1000, None)
+    assert s == L.EXM_E_INVAL
+    p = L.params(8, N_b=4, N_s=4)
+    s = L.lib.exm_trace_bwd(C.byref(m), C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000, C.byref(p),
+                            float("nan"), 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, None)
+    assert s == L.EXM_E_INVAL
+    s = L.lib.exm_shade_bwd(C.byref(m), C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000, C.byref(p),
+                            0x1000, 0x1000, None, 0x1000, None)
+    assert s == L.EXM_E_INVAL
+
+
+def test_env_sampler_and_bvh_validation(L):
+    f = L.lib.exm_build_env_sampler
+    assert f(0x1000, 0, 8, 0x1000, 0x1000, 0x1000, None) == L.EXM_E_INVAL
+    assert f(0x1000, 4, 1, 0x1000, 0x1000, 0x1000, None) == L.EXM_E_INVAL
+    assert f(0x1000, 4096, 8192, 0x1000, 0x1000, 0x1000, None) == L.EXM_E_INVAL
+    assert f(0x1000, 4, 8, 0x1000, 0x1000, 0x1004, None) == L.EXM_E_INVAL
+    pos = np.zeros((3, 3), np.float32)
+    tri = np.array([[0, 1, 3]], np.int32)
+    out = C.c_void_p()
+    s = L.lib.exm_build_bvh(pos.ctypes.data, 3, tri.ctypes.data, 1, C.byref(out), None)
+    assert s == L.EXM_E_INVAL and "out of range" in L.last_error() and not out.value
+    pos[1, 2] = np.inf
+    tri[0, 2] = 2
+    assert L.lib.exm_build_bvh(pos.ctypes.data, 3, tri.ctypes.data, 1, C.byref(out), None) == L.EXM_E_INVAL
+    assert L.lib.exm_free_bvh(None) == L.EXM_OK
+    assert L.lib.exm_bvh_device_bytes(None) == 0

@@ -1,0 +1,412 @@
+"""HIP path vs FP64 oracle on the same seeded inputs (every call goes through the C ABI).
+
+Bars: triangle ids and coverage bit-exact; env tables integer-equal; radiance within
+1e-4 relative (+1e-7 of the frame maximum) on every pixel without a flipped discrete decision,
+flips rare and each explained by the oracle's margins; gradients within 1e-3 relative of the
+oracle's forward-mode derivative."""
+import math
+import sys
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from paper_2608_24109_amd import inputs as I
+
+from parity import (EDGE_TOL, bits_set, explain_flips, flipped_pairs, radiance_close)
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2608_24109_amd import _lib
+    return _lib
+
+
+class Dev:
+    """A scene on the device and on the oracle side."""
+
+    def __init__(self, sc: I.Scene):
+        from paper_2608_24109_amd.scene import DeviceEnv, DeviceMaterial, DeviceMesh
+        self.sc = sc
+        self.mesh = DeviceMesh(sc.pos, sc.tri, sc.uv, sc.tri_uv)
+        self.mat = DeviceMaterial(sc.tex)
+        self.env = DeviceEnv(sc.env)
+        self.om = O.OracleMesh(sc.pos, sc.tri, sc.uv, sc.tri_uv)
+        self.tab = O.EnvTables(sc.env)
+        self.diag = I.aabb_diagonal(sc.pos)
+
+    def params(self, N_d=None, N_b=None, N_s=None, flags=0):
+        from paper_2608_24109_amd.render import PassParams
+        return PassParams(N_d=self.sc.N_d if N_d is None else N_d, N_b=self.sc.N_b if N_b is None else N_b,
+                          N_s=self.sc.N_s if N_s is None else N_s, seed=self.sc.seed, tmin=self.sc.tmin, flags=flags)
+
+    def forward(self, cams, p, view_ids=None):
+        from paper_2608_24109_amd import _lib as L
+        from paper_2608_24109_amd.render import PassBuffers, render_forward
+        cc = L.cameras(cams, view_ids if view_ids is not None else list(range(len(cams))))
+        b = PassBuffers(len(cams), cams[0].H, cams[0].W, p.N_b)
+        render_forward(self.mesh, self.mat, self.env, cc, p, b)
+        torch.cuda.synchronize()
+        return cc, b
+
+    def oracle(self, cam, p, view_id=0, pix=None, tex_dot=None, env_dot=None):
+        return O.render(self.om, cam, self.tab, self.sc.tex, self.sc.env, N_d=p.N_d, N_b=p.N_b,
+                        N_s=p.N_s if p.N_b > 0 else 0, seed=p.seed, tmin=p.tmin, flags=p.flags, view_id=view_id,
+                        pix=pix, tex_dot=tex_dot, env_dot=env_dot)
+
+
+@pytest.fixture(scope="module")
+def small():
+    log("[setup] small: icosphere 1280 tris, 128^2")
+    return Dev(I.config("small"))
+
+
+@pytest.fixture(scope="module")
+def small_tori():
+    log("[setup] small tori (concave): 2 x 48 x 20 quads, 96^2")
+    pos, tri = I.interlocking_tori(48, 20)
+    cams = I.ring_cameras(2, 4.5, 96, 96)
+    return Dev(I.make_scene("small_tori", pos, tri, 128, 128, 32, 64, 1.0, cams, N_d=16, N_b=4, N_s=4))
+
+
+# ------------------------------------------------------------------------------------------
+# env tables
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("He,We,sigma", [(32, 64, 1.0), (512, 1024, 1.5), (7, 13, 2.0)])
+def test_env_tables_integer_equal(lib, He, We, sigma):
+    from paper_2608_24109_amd.scene import DeviceEnv
+    env = I.env_map(He, We, sigma, seed=2)
+    log(f"[env tables] {He}x{We}")
+    d = DeviceEnv(env)
+    torch.cuda.synchronize()
+    t = O.EnvTables(env)
+    cr = d.cdf_row.cpu().numpy()
+    cc = d.cdf_col.cpu().numpy()
+    # integer tables: equal, except where the oracle's scaled weight is within 1e-6 of an
+    # integer step (a last-ulp difference of cos() between the two libms can move it)
+    x = t.w / t.w.max() * 2 ** 20
+    near = np.abs(x - np.round(x)) < 1e-6
+    q_gpu = np.diff(np.concatenate([np.zeros((He, 1), np.uint64), cc], 1), axis=1)
+    bad = q_gpu != t.q
+    assert not (bad & ~near).any()
+    if not bad.any():
+        assert np.array_equal(cr, t.cdf_row) and np.array_equal(cc, t.cdf_col)
+    pdf = d.pdf.cpu().numpy()
+    assert np.allclose(pdf, t.pdf, rtol=2e-7, atol=0)
+
+
+# ------------------------------------------------------------------------------------------
+# raster
+# ------------------------------------------------------------------------------------------
+
+def _raster_gpu(dev, cams):
+    from paper_2608_24109_amd import _lib as L
+    from paper_2608_24109_amd.render import PassBuffers, raster
+    cc = L.cameras(cams)
+    b = PassBuffers(len(cams), cams[0].H, cams[0].W, 0)
+    raster(dev.mesh, cc, b)
+    torch.cuda.synchronize()
+    return b.tri_id.cpu().numpy(), b.bary.cpu().numpy()
+
+
+def _check_raster(dev, cams, ids, bary, views):
+    for v in views:
+        oi, ob = O.raster(dev.om, cams[v])
+        assert np.array_equal(ids[v], oi), f"view {v}: {np.sum(ids[v] != oi)} id mismatches"
+        cov = oi >= 0
+        assert np.abs(bary[v][cov] - ob[cov][:, 1:]).max() <= 1e-6
+        assert np.all(bary[v][~cov] == 0)
+
+
+def test_raster_small_bit_exact(small):
+    sc = small.sc
+    log("[raster] small 128^2")
+    ids, bary = _raster_gpu(small, sc.cams)
+    _check_raster(small, sc.cams, ids, bary, [0])
+
+
+def test_raster_ragged_and_chunked(small):
+    """37x53 views (no size is a tile multiple), 11 views (two launches of <= 8 views)."""
+    cams = I.ring_cameras(11, 3.0, 37, 53)
+    log("[raster] small 11 views 37x53")
+    ids, bary = _raster_gpu(small, cams)
+    _check_raster(small, cams, ids, bary, range(11))
+
+
+def test_raster_triangle_order_and_large_triangles(lib):
+    """Screen-filling grid with big triangles (wave-cooperative path) and a permuted copy."""
+    pos, tri = I.quad_mesh(np.array([[-1.3, -1.3, 0], [1.3, -1.3, 0], [1.3, 1.3, 0], [-1.3, 1.3, 0]]), 3, 2)
+    rng = np.random.default_rng(1)
+    flip = rng.random(tri.shape[0]) < 0.5
+    tri[flip, 1], tri[flip, 2] = tri[flip, 2].copy(), tri[flip, 1].copy()
+    cam = I.Camera(mvp=np.eye(4), eye=np.array([0, 0, 10.0]), H=70, W=90)
+    sc = I.make_scene("grid", pos, tri, 16, 16, 8, 16, 1.0, [cam], N_d=4)
+    log("[raster] big-triangle grid 70x90")
+    dev = Dev(sc)
+    ids, bary = _raster_gpu(dev, [cam])
+    _check_raster(dev, [cam], ids, bary, [0])
+    cnt = O.coverage_count(dev.om, cam)
+    assert cnt.min() == 1 and cnt.max() == 1 and (ids[0] >= 0).all()
+    perm = rng.permutation(tri.shape[0])
+    sc2 = I.make_scene("grid_perm", pos, tri[perm], 16, 16, 8, 16, 1.0, [cam], N_d=4)
+    ids2, _ = _raster_gpu(Dev(sc2), [cam])
+    assert np.array_equal(perm[ids2[0]], ids[0])
+
+
+def test_raster_empty_mesh_is_background(lib):
+    from paper_2608_24109_amd.scene import DeviceMesh
+    from paper_2608_24109_amd.render import PassBuffers, raster
+    pos = np.zeros((3, 3), np.float32)
+    tri = np.zeros((0, 3), np.int32)
+    uv = np.zeros((1, 2), np.float32)
+    log("[raster] empty mesh")
+    m = DeviceMesh(pos, tri, uv, np.zeros((0, 3), np.int32))
+    cams = I.ring_cameras(1, 3.0, 16, 24)
+    b = PassBuffers(1, 16, 24, 0)
+    raster(m, lib.cameras(cams), b)
+    torch.cuda.synchronize()
+    assert (b.tri_id.cpu().numpy() == -1).all() and (b.bary.cpu().numpy() == 0).all()
+
+
+@pytest.mark.parametrize("name", ["sphere", "tori"])
+def test_raster_full_size_bit_exact(lib, name):
+    """Full workload (8 views of 1024^2 in the benchmark's launch), every pixel of two views."""
+    sc = I.config(name)
+    sc.tex = np.zeros((1, 1, 8), np.float32)
+    from paper_2608_24109_amd.scene import DeviceMesh
+    log(f"[raster] {name} {sc.nF} tris, 8 x 1024^2")
+    mesh = DeviceMesh(sc.pos, sc.tri, sc.uv, sc.tri_uv, with_bvh=False)
+    om = O.OracleMesh(sc.pos, sc.tri, sc.uv, sc.tri_uv, with_bvh=False)
+    from paper_2608_24109_amd.render import PassBuffers, raster
+    b = PassBuffers(8, 1024, 1024, 0)
+    raster(mesh, lib.cameras(sc.cams), b)
+    torch.cuda.synchronize()
+    ids = b.tri_id.cpu().numpy()
+    bary = b.bary.cpu().numpy()
+    for v in (0, 5):
+        oi, ob = O.raster(om, sc.cams[v])
+        assert np.array_equal(ids[v], oi), f"{np.sum(ids[v] != oi)} mismatches"
+        cov = oi >= 0
+        assert np.abs(bary[v][cov] - ob[cov][:, 1:]).max() <= 1e-6
+    log(f"[raster] {name} covered fraction {np.mean(ids >= 0):.4f}")
+
+
+# ------------------------------------------------------------------------------------------
+# direct and indirect radiance
+# ------------------------------------------------------------------------------------------
+
+def _compare_view(dev, cam, p, bufs, v, view_id, pix=None, max_flip_frac=1e-5):
+    """Compare view v of the GPU buffers with the oracle on `pix` (None = all pixels)."""
+    sc = dev.sc
+    H, W = cam.H, cam.W
+    t0 = time.time()
+    r = dev.oracle(cam, p, view_id=view_id, pix=pix)
+    sel = np.arange(H * W) if pix is None else np.asarray(pix)
+    ids = bufs.tri_id[v].cpu().numpy().reshape(-1)[sel]
+    assert np.array_equal(ids, r.tri_id)
+    Ld = bufs.L_dir[v].cpu().numpy().reshape(-1, 3)[sel]
+    vis = bufs.vis[v].cpu().numpy().reshape(-1)[sel]
+    kw = dict(N_d=p.N_d, N_b=p.N_b, N_s=p.N_s, seed=p.seed, tmin=p.tmin, flags=p.flags, view_id=view_id)
+    rows, ks = flipped_pairs(vis, r.vis, max(p.N_d, 1))
+    gbit = (vis[rows] >> ks.astype(np.uint64)) & np.uint64(1)
+    ok = explain_flips(dev.om, cam, dev.tab, sc.tex, sc.env, sel[rows], ks, 0, gbit.astype(bool), dev.diag, **kw)
+    n_rays = int(np.sum(ids >= 0)) * p.N_d
+    assert ok.all(), f"unexplained direct flips: {list(zip(sel[rows][~ok], ks[~ok]))[:10]}"
+    bad = np.zeros(len(sel), dtype=bool)
+    bad[rows] = True
+    n_flips = len(rows)
+    if p.N_b > 0:
+        rec = bufs.sec_rec[v].cpu().numpy().reshape(-1, p.N_b, 3)[sel]
+        st = rec[..., 0]
+        sb = rec[..., 1:].copy().view(np.float32)
+        sv = bufs.sec_vis[v].cpu().numpy().reshape(-1)[sel]
+        Li = bufs.L_ind[v].cpu().numpy().reshape(-1, 3)[sel]
+        srow, sj = np.nonzero(st != r.sec_tri)
+        okj = explain_flips(dev.om, cam, dev.tab, sc.tex, sc.env, sel[srow], sj.astype(np.int32), 1,
+                            np.zeros(len(srow), bool), dev.diag, **kw)
+        assert okj.all(), f"unexplained secondary-hit flips {list(zip(sel[srow][~okj], sj[~okj]))[:10]}"
+        same = st == r.sec_tri
+        assert np.abs(sb[same & (st >= 0)] - r.sec_bary[same & (st >= 0)]).max(initial=0) < 1e-4
+        bad[srow] = True
+        n_flips += len(srow)
+        # light-sample bits, on secondary rays whose hit agrees
+        xr, xb = flipped_pairs(sv, r.sec_vis, p.N_b * p.N_s)
+        keep = same[xr, xb // p.N_s]
+        xr, xb = xr[keep], xb[keep]
+        for j in np.unique(xb // p.N_s):
+            m = xb // p.N_s == j
+            g = ((sv[xr[m]] >> xb[m].astype(np.uint64)) & np.uint64(1)).astype(bool)
+            okl = explain_flips(dev.om, cam, dev.tab, sc.tex, sc.env, sel[xr[m]], (xb[m] % p.N_s).astype(np.int32),
+                                2 + int(j), g, dev.diag, **kw)
+            assert okl.all(), "unexplained light-sample flips"
+        bad[xr] = True
+        n_flips += len(xr)
+        n_rays += int(np.sum(st >= 0)) * p.N_s + int(np.sum(ids >= 0)) * p.N_b
+        okI, worstI, dI_ = radiance_close(Li, r.L_ind, ~bad)
+        assert okI, f"L_ind worst excess {worstI}: {dI_}"
+    okD, worstD, dD_ = radiance_close(Ld, r.L_dir, ~bad)
+    assert okD, f"L_dir worst excess {worstD}: {dD_}"
+    log(f"  view {v}: {len(sel)} px, {n_rays} rays, {n_flips} flips (all explained), "
+        f"worst L_dir excess {worstD:.3f}, oracle {time.time() - t0:.1f}s")
+    assert n_flips <= max(4, max_flip_frac * n_rays)
+    return n_flips, n_rays
+
+
+@pytest.mark.parametrize("flags,N_d", [(0, 16), (1, 64), (2, 16), (4, 16), (8, 16), (0, 1), (0, 0)])
+def test_direct_small_full_frame(small, flags, N_d):
+    sc = small.sc
+    p = small.params(N_d=N_d, flags=flags)
+    log(f"[direct] small flags={flags} N_d={N_d}")
+    _, b = small.forward(sc.cams, p)
+    _compare_view(small, sc.cams[0], p, b, 0, 0)
+
+
+def test_indirect_small_tori_full_frame(small_tori):
+    sc = small_tori.sc
+    p = small_tori.params()
+    log("[indirect] small tori 2 x 96^2")
+    _, b = small_tori.forward(sc.cams, p)
+    Li = b.L_ind.cpu().numpy()
+    assert (Li > 0).mean() > 0.05  # interreflection actually happens
+    for v in range(2):
+        _compare_view(small_tori, sc.cams[v], p, b, v, v)
+
+
+def test_ragged_views_direct(small):
+    cams = I.ring_cameras(3, 3.0, 37, 53)
+    p = small.params()
+    log("[direct] small 3 x 37x53")
+    _, b = small.forward(cams, p, view_ids=[5, 6, 7])
+    for v in range(3):
+        _compare_view(small, cams[v], p, b, v, 5 + v)
+
+
+@pytest.mark.parametrize("name", ["sphere", "tori"])
+def test_full_size_sampled_pixels(name):
+    """The benchmark workload (8 views of 1024^2 in one call), 1024 seeded pixels of two views
+    checked against the oracle one by one."""
+    sc = I.config(name)
+    log(f"[full] {name}: building device scene")
+    dev = Dev(sc)
+    p = dev.params()
+    t0 = time.time()
+    _, b = dev.forward(sc.cams, p)
+    log(f"[full] {name}: GPU forward {time.time() - t0:.2f}s incl. launch")
+    rng = np.random.default_rng(11)
+    for v in (0, 3):
+        ids = b.tri_id[v].cpu().numpy().reshape(-1)
+        cov = np.nonzero(ids >= 0)[0]
+        pix = np.sort(rng.choice(cov, 1024, replace=False))
+        _compare_view(dev, sc.cams[v], p, b, v, v, pix=pix)
+
+
+def test_determinism_and_view_batching(small_tori):
+    sc = small_tori.sc
+    p = small_tori.params()
+    log("[determinism] small tori")
+    _, b1 = small_tori.forward(sc.cams, p)
+    _, b2 = small_tori.forward(sc.cams, p)
+    for k in ("tri_id", "bary", "L_dir", "vis", "L_ind", "sec_rec", "sec_vis"):
+        assert torch.equal(getattr(b1, k), getattr(b2, k)), k
+    _, s1 = small_tori.forward(sc.cams[1:2], p, view_ids=[1])
+    assert torch.equal(s1.L_dir[0], b1.L_dir[1]) and torch.equal(s1.L_ind[0], b1.L_ind[1])
+
+
+# ------------------------------------------------------------------------------------------
+# gradients (adjoint vs forward-mode derivative of the oracle)
+# ------------------------------------------------------------------------------------------
+
+def _gpu_grad(dev, cams, p, g, lam=1.0):
+    from paper_2608_24109_amd import _lib as L
+    from paper_2608_24109_amd.render import PassBuffers, render_backward, render_forward
+    cc = L.cameras(cams, list(range(len(cams))))
+    b = PassBuffers(len(cams), cams[0].H, cams[0].W, p.N_b)
+    render_forward(dev.mesh, dev.mat, dev.env, cc, p, b)
+    dtex = torch.zeros_like(dev.mat.tex)
+    denv = torch.zeros(dev.env.env.shape, dtype=torch.float64, device="cuda")
+    render_backward(dev.mesh, dev.mat, dev.env, cc, p, b, torch.from_numpy(g).cuda(), lam, dtex, denv)
+    torch.cuda.synchronize()
+    return b, dtex.cpu().numpy().astype(np.float64), denv.cpu().numpy()
+
+
+def _flip_free_upstream(dev, cams, p, b, g):
+    """Zero the upstream gradient on pixels whose discrete decisions differ from the oracle's,
+    so both sides differentiate the same estimator."""
+    g = g.copy()
+    for v, cam in enumerate(cams):
+        r = dev.oracle(cam, p, view_id=v)
+        bad = b.vis[v].cpu().numpy().reshape(-1) != r.vis
+        if p.N_b > 0:
+            st = b.sec_rec[v].cpu().numpy().reshape(-1, p.N_b, 3)[..., 0]
+            bad |= (st != r.sec_tri).any(1) | (b.sec_vis[v].cpu().numpy().reshape(-1) != r.sec_vis)
+        g[v].reshape(-1, 3)[bad] = 0.0
+    return g
+
+
+def _jvp(dev, cams, p, g, lam, tex_dot=None, env_dot=None):
+    tot = 0.0
+    for v, cam in enumerate(cams):
+        r = dev.oracle(cam, p, view_id=v, tex_dot=tex_dot, env_dot=env_dot)
+        gv = g[v].reshape(-1, 3).astype(np.float64)
+        tot += float(np.sum(gv * r.dL_dir)) + (lam * float(np.sum(gv * r.dL_ind)) if p.N_b > 0 else 0.0)
+    return tot
+
+
+def _check_grads(dev, cams, p, lam=1.0, n_texels=64, n_dirs=4, seed=0):
+    sc = dev.sc
+    g = I.upstream_grad(len(cams), cams[0].H, cams[0].W, seed=4 + seed)
+    b, _, _ = _gpu_grad(dev, cams, p, g, lam)
+    g = _flip_free_upstream(dev, cams, p, b, g)
+    _, dtex, denv = _gpu_grad(dev, cams, p, g, lam)
+    rng = np.random.default_rng(seed)
+    # random directions over all texels and env texels: sum of dtex * v vs the oracle's JVP
+    for _ in range(n_dirs):
+        v = rng.normal(size=sc.tex.shape)
+        u = rng.normal(size=sc.env.shape)
+        jt = _jvp(dev, cams, p, g, lam, tex_dot=v)
+        je = _jvp(dev, cams, p, g, lam, env_dot=u)
+        gt = float(np.sum(dtex * v))
+        ge = float(np.sum(denv * u))
+        log(f"  JVP tex {jt:.6e} vs {gt:.6e}; env {je:.6e} vs {ge:.6e}")
+        assert abs(gt - jt) <= 1e-3 * abs(jt) + 1e-6 * np.abs(dtex).max() * np.sqrt(dtex.size)
+        assert abs(ge - je) <= 1e-3 * abs(je) + 1e-6 * np.abs(denv).max() * np.sqrt(denv.size)
+    # single texel-channels with the largest gradients plus random touched ones
+    flat = np.abs(dtex).reshape(-1)
+    touched = np.nonzero(flat > 0)[0]
+    pick = np.concatenate([np.argsort(flat)[-n_texels // 2:], rng.choice(touched, n_texels // 2, replace=False)])
+    gmax = flat.max()
+    for i in pick:
+        v = np.zeros(sc.tex.size)
+        v[i] = 1.0
+        ref = _jvp(dev, cams, p, g, lam, tex_dot=v.reshape(sc.tex.shape))
+        got = dtex.reshape(-1)[i]
+        assert abs(got - ref) <= 1e-3 * abs(ref) + 1e-6 * gmax, (i // 8, i % 8, got, ref)
+    eflat = np.abs(denv).reshape(-1)
+    for i in np.argsort(eflat)[-8:]:
+        u = np.zeros(sc.env.size)
+        u[i] = 1.0
+        ref = _jvp(dev, cams, p, g, lam, env_dot=u.reshape(sc.env.shape))
+        got = denv.reshape(-1)[i]
+        assert abs(got - ref) <= 1e-3 * abs(ref) + 1e-6 * eflat.max(), (i, got, ref)
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_gradients_direct_small(small, flags):
+    log(f"[grad] small direct flags={flags}")
+    _check_grads(small, small.sc.cams, small.params(flags=flags), n_texels=32)
+
+
+def test_gradients_indirect_small_tori(small_tori):
+    log("[grad] small tori direct + indirect, lambda 0.7")
+    _check_grads(small_tori, small_tori.sc.cams[:1], small_tori.params(), lam=0.7, n_texels=32, n_dirs=3)
