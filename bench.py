@@ -1,0 +1,282 @@
+"""Benchmark of the Stage-II UV-PBR render pass on one MI355X.
+
+One step = one pass of the whole hot path over the workload's views: env sampling tables,
+G-buffer raster, direct shading (+ one-bounce indirect where the workload has it), gradient
+buffers cleared, then the direct (+ indirect) adjoint into the UV maps and the env map.
+Inputs are resident in HBM before timing starts.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere|tori|small]
+
+Prints one JSON line. The metric is forward+backward Mpixels/s at 1024^2 (all pixels of the
+step counted, background included); per-kernel times come from HIP events recorded on the
+stream the kernels are launched on.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
+FP32_LANE_PEAK_T = 39.32    # 256 CU x 64 lanes x 2.4 GHz, non-packed FP32 instructions per second (1e12)
+
+METRIC = "fwd+bwd Mpixels/s and indirect Mrays/s at 1024²; relight p50/p99 ms"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sphere", choices=["sphere", "tori", "small"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-pixels", type=int, default=262144, help="oracle sample size (pixels of one view)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="before timing, copy a buffer of this many MiB once (HBM counter calibration)")
+    ap.add_argument("--no-extras", dest="extras", action="store_false",
+                    help="skip the tori workload (indirect Mrays/s)")
+    return ap.parse_args()
+
+
+class Timer:
+    """Per-ABI-call HIP event pairs on the current (launch) stream."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.ev = {}
+
+    def __call__(self, name, fn):
+        t = self.torch.cuda
+        a, b = t.Event(enable_timing=True), t.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        self.ev.setdefault(name, []).append((a, b))
+
+    def mean_ms(self):
+        return {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in self.ev.items()}
+
+
+def run_gpu(workload: str, steps: int, warmup: int):
+    import torch
+
+    from paper_2608_24109_amd import _lib as L
+    from paper_2608_24109_amd import inputs as I
+    from paper_2608_24109_amd.render import PassBuffers, PassParams, raster
+    from paper_2608_24109_amd.scene import DeviceEnv, DeviceMaterial, DeviceMesh
+
+    sc = I.config(workload)
+    mesh = DeviceMesh(sc.pos, sc.tri, sc.uv, sc.tri_uv)
+    mat = DeviceMaterial(sc.tex)
+    env = DeviceEnv(sc.env)
+    V, H, W = len(sc.cams), sc.cams[0].H, sc.cams[0].W
+    p = PassParams(N_d=sc.N_d, N_b=sc.N_b, N_s=sc.N_s, seed=sc.seed, tmin=sc.tmin)
+    pc = p.c()
+    cc = L.cameras(sc.cams, list(range(V)))
+    bufs = PassBuffers(V, H, W, p.N_b)
+    dI = torch.from_numpy(I.upstream_grad(V, H, W)).cuda()
+    dtex = torch.zeros_like(mat.tex)
+    denv = torch.zeros(env.env.shape, dtype=torch.float64, device="cuda")
+    lam = 1.0
+    torch.cuda.synchronize()
+
+    def step(tm):
+        tm("build_env_sampler", lambda: L.exm_build_env_sampler(env.env, env.cdf_row, env.cdf_col, env.pdf))
+        tm("raster_gbuffer", lambda: raster(mesh, cc, bufs))
+        tm("shade_fwd", lambda: L.exm_shade_fwd(mesh.s, mesh.bvh, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc,
+                                                bufs.L_dir, bufs.vis))
+        if p.N_b > 0:
+            tm("trace_indirect", lambda: L.exm_trace_indirect(mesh.s, mesh.bvh, mat.s, env.s, cc, bufs.tri_id,
+                                                              bufs.bary, pc, bufs.L_ind, bufs.sec_rec, bufs.sec_vis))
+            tm("compose", lambda: torch.add(bufs.L_dir, bufs.L_ind, alpha=lam))
+        tm("zero_grads", lambda: (dtex.zero_(), denv.zero_()))
+        tm("shade_bwd", lambda: L.exm_shade_bwd(mesh.s, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc, dI, bufs.vis,
+                                                dtex, denv))
+        if p.N_b > 0:
+            tm("trace_bwd", lambda: L.exm_trace_bwd(mesh.s, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc, lam, dI,
+                                                    bufs.sec_rec, bufs.sec_vis, dtex, denv))
+
+    warm = Timer(torch)
+    for _ in range(warmup):
+        step(warm)
+    torch.cuda.synchronize()
+    tm = Timer(torch)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(tm)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = tm.mean_ms()
+
+    # work counts of the workload, from the counting variants (outside the timed region)
+    c_dir = torch.zeros(4, dtype=torch.uint64, device="cuda")
+    L.exm_shade_fwd_counted(mesh.s, mesh.bvh, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc, bufs.L_dir, bufs.vis,
+                            c_dir)
+    c_ind = torch.zeros(6, dtype=torch.uint64, device="cuda")
+    if p.N_b > 0:
+        L.exm_trace_indirect_counted(mesh.s, mesh.bvh, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc, bufs.L_ind,
+                                     bufs.sec_rec, bufs.sec_vis, c_ind)
+    torch.cuda.synchronize()
+    cd = [int(x) for x in c_dir.cpu().numpy()]
+    ci = [int(x) for x in c_ind.cpu().numpy()]
+    ids = bufs.tri_id.cpu().numpy()
+    covered = int((ids >= 0).sum())
+    vis = bufs.vis.cpu().numpy().reshape(-1)
+    set_bits = int(np.unpackbits(vis.view(np.uint8)).sum())
+    stats = dict(views=V, H=H, W=W, pixels=V * H * W, covered=covered, tris=int(sc.nF),
+                 texels=int(sc.tex.shape[0] * sc.tex.shape[1]), He=int(sc.env.shape[0]), We=int(sc.env.shape[1]),
+                 samples=cd[3], shadow_rays=cd[0], shadow_nodes=cd[1], shadow_tris=cd[2], unoccluded=set_bits)
+    if p.N_b > 0:
+        sv = bufs.sec_vis.cpu().numpy().reshape(-1)
+        stats.update(sec_rays=ci[0], sec_nodes=ci[1], sec_tris=ci[2], sec_shadow_rays=ci[3], sec_shadow_nodes=ci[4],
+                     sec_shadow_tris=ci[5], sec_hits=int((bufs.sec_rec.cpu().numpy()[..., 0] >= 0).sum()),
+                     sec_unoccluded=int(np.unpackbits(sv.view(np.uint8)).sum()))
+    return sc, p, wall, kern, stats, (mesh, mat, env, bufs)
+
+
+def cpu_baseline(sc, p, n_pix: int, view: int = 0):
+    """The FP64 oracle as it stands, on a seeded sample of `n_pix` pixels of one view (all pixels
+    eligible, background included): forward value pass plus one forward-mode derivative pass
+    (its gradient), extrapolated to the step's pixels."""
+    import oracle as O
+    om = O.OracleMesh(sc.pos, sc.tri, sc.uv, sc.tri_uv)
+    tab = O.EnvTables(sc.env)
+    cam = sc.cams[view]
+    HW = cam.H * cam.W
+    rng = np.random.default_rng(123)
+    pix = np.sort(rng.choice(HW, n_pix, replace=False))
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    O.raster(om, cam, view_id=view)
+    t_raster = time.perf_counter() - t0
+    tex_dot = np.zeros_like(sc.tex, dtype=np.float64)
+    tex_dot[..., 0] = 1.0
+    t0 = time.perf_counter()
+    O.render(om, cam, tab, sc.tex, sc.env, N_d=p.N_d, N_b=p.N_b, N_s=p.N_s, seed=p.seed, tmin=p.tmin, pix=pix,
+             view_id=view, n_threads=cores)
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.render(om, cam, tab, sc.tex, sc.env, N_d=p.N_d, N_b=p.N_b, N_s=p.N_s, seed=p.seed, tmin=p.tmin, pix=pix,
+             view_id=view, tex_dot=tex_dot, n_threads=cores)
+    t_jvp = time.perf_counter() - t0
+    # each render call includes one full-view raster; per-pixel shading cost extrapolates
+    per_px = (t_fwd - t_raster) / n_pix + (t_jvp - t_raster) / n_pix
+    t_view = 2 * t_raster + per_px * HW
+    return {"value": HW / t_view / 1e6, "unit": "Mpixels/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_pix} seeded pixels of view {view} of the {sc.name} workload ({HW} px/view), FP64 "
+                      f"forward + one forward-mode derivative pass, per-pixel time extrapolated to the full "
+                      f"view plus two full-view rasters; measured {t_fwd + t_jvp + t_raster:.1f} s"}
+
+
+# Algorithmic bytes: what the method itself must read or write per unit, times the units of one
+# launch. Per covered pixel the attribute query reads 3 vertices (12 B position + 24 B FP64
+# normal), the triangle's vertex and UV indices (12 + 12 B), 3 UVs (24 B), the face tangent
+# (16 B) and 4 bilinear taps of 8 floats (128 B): 300 B. Each env sample reads its texel's pdf
+# (4 B) and the CDF entries a binary search visits (ceil(log2(He+1)) + ceil(log2(We+1)) u64),
+# and an unoccluded one the texel's radiance (12 B). Each traced ray reads the nodes it visits
+# (64 B) and the triangles it tests (48 B).
+SURF_BYTES = 3 * (12 + 24) + 12 + 12 + 24 + 16 + 4 * 32
+
+
+def algorithmic_bytes(kernel: str, st: dict, p) -> float:
+    P, C = st["pixels"], st["covered"]
+    cdf = 8 * (math.ceil(math.log2(st["He"] + 1)) + math.ceil(math.log2(st["We"] + 1)))
+    if kernel == "raster_gbuffer":  # G-buffer out, 8 B depth key in/out, mesh per view
+        return (12.0 + 16.0) * P + st["views"] * 24.0 * st["tris"]
+    if kernel == "build_env_sampler":
+        return st["He"] * st["We"] * (12 + 8 + 4) + 8.0 * st["He"]
+    if kernel == "shade_fwd":
+        return (32.0 * P + SURF_BYTES * C + (4 + cdf) * st["samples"] + 12.0 * st["unoccluded"]
+                + 64.0 * st["shadow_nodes"] + 48.0 * st["shadow_tris"])
+    if kernel == "shade_bwd":  # + 4 taps x 8 channel atomics (8 B RMW) + 3 FP64 env atomics (16 B RMW)
+        return (32.0 * P + (SURF_BYTES + 256.0) * C + (4 + cdf + 12 + 48) * st["unoccluded"])
+    if kernel == "trace_indirect":
+        return (12.0 * P + 20.0 * C + st["sec_rays"] * 12.0 + st["sec_hits"] * SURF_BYTES
+                + (4 + cdf) * st["sec_shadow_rays"] + 12.0 * st["sec_unoccluded"]
+                + 64.0 * (st["sec_nodes"] + st["sec_shadow_nodes"]) + 48.0 * (st["sec_tris"] + st["sec_shadow_tris"]))
+    if kernel == "trace_bwd":
+        return (44.0 * P + (SURF_BYTES + 224.0) * C + st["sec_hits"] * (SURF_BYTES + 224.0)
+                + (4 + cdf + 12 + 48) * st["sec_unoccluded"])
+    return float("nan")
+
+
+def pmc_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc summary, if it was taken
+    on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        from paper_2608_24109_amd.profiling import source_digest
+        d = json.load(open(path))
+        k = d["kernels"].get(kernel)
+        if k is None or d.get("source_sha") != source_digest():
+            return None
+        return k["fetch_bytes"] + k["write_bytes"]
+    except Exception:
+        return None
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU: the render pass would shard views across GPUs "
+                                   "with one all-reduce of the gradient maps, which is not built; run --gpus 1"}))
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if a.calib_copy_mb:
+        src = torch.ones(a.calib_copy_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    sc, p, wall, kern, stats, _ = run_gpu(a.workload, a.steps, a.warmup)
+    ms_step = wall / a.steps * 1e3
+    value = stats["pixels"] / (ms_step * 1e-3) / 1e6
+    dom = max((k for k in kern if k not in ("compose", "zero_grads")), key=lambda k: kern[k])
+    alg = algorithmic_bytes(dom, stats, p)
+    achieved = alg / (kern[dom] * 1e-3) / 1e9
+    traffic = pmc_traffic(dom, a.workload)
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Mpixels/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{sc.name}: {stats['tris']} tris, {stats['views']} views {stats['H']}x{stats['W']}, "
+                               f"{sc.tex.shape[0]}^2 maps, {sc.env.shape[0]}x{sc.env.shape[1]} env, N_d={p.N_d}"
+                               + (f", N_b={p.N_b}, N_s={p.N_s}" if p.N_b else "") + ", fwd+bwd",
+                   "global_batch": stats["views"], "seq_len": stats["H"] * stats["W"], "parallelism": "none"},
+        "kernels_ms": {k: round(v, 4) for k, v in kern.items()},
+        "covered_fraction": round(stats["covered"] / stats["pixels"], 4),
+        "direct_shadow_Mrays_s": round(stats["shadow_rays"] / (kern["shade_fwd"] * 1e-3) / 1e6, 1),
+        "nodes_per_shadow_ray": round(stats["shadow_nodes"] / max(stats["shadow_rays"], 1), 2),
+        "tris_per_shadow_ray": round(stats["shadow_tris"] / max(stats["shadow_rays"], 1), 2),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": None if traffic is None else round(traffic)},
+        "algorithmic_GBps": {k: round(algorithmic_bytes(k, stats, p) / (kern[k] * 1e-3) / 1e9, 1)
+                             for k in kern if not math.isnan(algorithmic_bytes(k, stats, p))},
+    }
+    if a.extras:
+        sc2, p2, wall2, kern2, st2, _ = run_gpu("tori", max(2, a.steps // 3), 1)
+        rays = st2["sec_rays"] + st2["sec_shadow_rays"]
+        out["indirect"] = {
+            "workload": "tori: 1M tris, 8 views 1024x1024, 2048^2 maps, N_d=64, N_b=4, N_s=4, fwd+bwd",
+            "indirect_Mrays_s": round(rays / (kern2["trace_indirect"] * 1e-3) / 1e6, 1),
+            "fwd_bwd_Mpixels_s": round(st2["pixels"] / (wall2 / max(2, a.steps // 3)) / 1e6, 3),
+            "kernels_ms": {k: round(v, 3) for k, v in kern2.items()}}
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(sc, p, a.cpu_pixels)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -154,6 +154,24 @@ exm_status exm_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_m
                               float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis,
                               hipStream_t stream);
 
+/* Measurement variants: the same work and outputs as exm_shade_fwd / exm_trace_indirect, plus
+ * work counts accumulated (+=) into the caller's device array `counters` (u64):
+ *   exm_shade_fwd_counted      [4]: shadow rays traced, BVH nodes visited, triangles tested,
+ *                                   env samples drawn
+ *   exm_trace_indirect_counted [6]: secondary rays, their node visits and triangle tests,
+ *                                   secondary light shadow rays, their node visits and tests
+ * The counts are the traversal work of the ray queries (Direct Illumination visibility,
+ * One-Bounce Indirect Illumination secondary hits) on this BVH. */
+exm_status exm_shade_fwd_counted(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat,
+                                 const exm_env* env, const exm_camera* cams_host, int32_t nViews,
+                                 const int32_t* tri_id, const float* bary, const exm_params* p,
+                                 float* L_dir, uint64_t* vis, uint64_t* counters, hipStream_t stream);
+exm_status exm_trace_indirect_counted(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat,
+                                      const exm_env* env, const exm_camera* cams_host, int32_t nViews,
+                                      const int32_t* tri_id, const float* bary, const exm_params* p,
+                                      float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis,
+                                      uint64_t* counters, hipStream_t stream);
+
 /* Adjoint of the direct pass for upstream dI [nViews,H,W,3]: dtex [Ht,Wt,8] += d/dtex,
  * denv [He,We,3] += d/dE (double). Discrete choices (ids, texel picks, vis bits) and the
  * sampling pdf are held fixed. */

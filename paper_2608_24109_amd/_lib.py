@@ -76,6 +76,8 @@ def _load() -> C.CDLL:
         "exm_raster_gbuffer": (st, [vp, vp, i32, vp, vp, vp]),
         "exm_shade_fwd": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]),
         "exm_trace_indirect": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]),
+        "exm_shade_fwd_counted": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]),
+        "exm_trace_indirect_counted": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
         "exm_shade_bwd": (st, [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
         "exm_trace_bwd": (st, [vp, vp, vp, vp, i32, vp, vp, vp, C.c_float, vp, vp, vp, vp, vp, vp]),
     }
@@ -217,6 +219,25 @@ def exm_trace_indirect(mesh, bvh: Bvh, mat, env, cams, tri_id, bary, p: exm_para
     _check(lib.exm_trace_indirect(C.byref(mesh), bvh.handle, C.byref(mat), C.byref(env), cams, n, _ptr(tri_id),
                                   _ptr(bary), C.byref(p), _ptr(L_ind), _ptr(sec_rec), _ptr(sec_vis),
                                   _stream(stream)), "exm_trace_indirect")
+
+
+def exm_shade_fwd_counted(mesh, bvh: Bvh, mat, env, cams, tri_id, bary, p: exm_params, L_dir, vis, counters,
+                          stream=None) -> None:
+    import torch
+    _need(counters, torch.uint64, (4,), "counters")
+    _check(lib.exm_shade_fwd_counted(C.byref(mesh), bvh.handle, C.byref(mat), C.byref(env), cams, len(cams),
+                                     _ptr(tri_id), _ptr(bary), C.byref(p), _ptr(L_dir), _ptr(vis), _ptr(counters),
+                                     _stream(stream)), "exm_shade_fwd_counted")
+
+
+def exm_trace_indirect_counted(mesh, bvh: Bvh, mat, env, cams, tri_id, bary, p: exm_params, L_ind, sec_rec,
+                               sec_vis, counters, stream=None) -> None:
+    import torch
+    _need(counters, torch.uint64, (6,), "counters")
+    _check(lib.exm_trace_indirect_counted(C.byref(mesh), bvh.handle, C.byref(mat), C.byref(env), cams, len(cams),
+                                          _ptr(tri_id), _ptr(bary), C.byref(p), _ptr(L_ind), _ptr(sec_rec),
+                                          _ptr(sec_vis), _ptr(counters), _stream(stream)),
+           "exm_trace_indirect_counted")
 
 
 def exm_shade_bwd(mesh, mat, env, cams, tri_id, bary, p: exm_params, dI, vis, dtex, denv, stream=None) -> None:

@@ -241,9 +241,10 @@ exm_status exm_raster_gbuffer(const exm_mesh* m, const exm_camera* cams, int32_t
   return EXM_OK;
 }
 
-exm_status exm_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
-                         const exm_camera* cams, int32_t nViews, const int32_t* tri_id, const float* bary,
-                         const exm_params* p, float* L_dir, uint64_t* vis, hipStream_t stream) {
+static exm_status shade_fwd_impl(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
+                                 const exm_camera* cams, int32_t nViews, const int32_t* tri_id, const float* bary,
+                                 const exm_params* p, float* L_dir, uint64_t* vis, uint64_t* counters,
+                                 hipStream_t stream) {
   EXM_TRY(check_mesh(m, true));
   if (!bvh) return fail(EXM_E_INVAL, "bvh is NULL");
   EXM_TRY(check_material(mat));
@@ -257,16 +258,18 @@ exm_status exm_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_materi
   for (int32_t v0 = 0; v0 < nViews; v0 += kViewsPerLaunch) {
     const int32_t n = std::min(kViewsPerLaunch, nViews - v0);
     hipError_t e = launch_shade_fwd(m, bvh, mat, env, shade_views(cams, v0, n), tri_id + v0 * HW, bary + 2 * v0 * HW, p,
-                                    L_dir + 3 * v0 * HW, vis + v0 * HW, stream);
+                                    L_dir + 3 * v0 * HW, vis + v0 * HW,
+                                    reinterpret_cast<unsigned long long*>(counters), stream);
     if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_shade_fwd: ") + hipGetErrorString(e));
   }
   return EXM_OK;
 }
 
-exm_status exm_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
-                              const exm_camera* cams, int32_t nViews, const int32_t* tri_id, const float* bary,
-                              const exm_params* p, float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis,
-                              hipStream_t stream) {
+static exm_status trace_indirect_impl(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat,
+                                      const exm_env* env, const exm_camera* cams, int32_t nViews,
+                                      const int32_t* tri_id, const float* bary, const exm_params* p, float* L_ind,
+                                      exm_sec_rec* sec_rec, uint64_t* sec_vis, uint64_t* counters,
+                                      hipStream_t stream) {
   EXM_TRY(check_mesh(m, true));
   if (!bvh) return fail(EXM_E_INVAL, "bvh is NULL");
   EXM_TRY(check_material(mat));
@@ -281,10 +284,43 @@ exm_status exm_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_m
     const int32_t n = std::min(kViewsPerLaunch, nViews - v0);
     hipError_t e = launch_trace_indirect(m, bvh, mat, env, shade_views(cams, v0, n), tri_id + v0 * HW,
                                          bary + 2 * v0 * HW, p, L_ind + 3 * v0 * HW,
-                                         sec_rec ? sec_rec + v0 * HW * p->N_b : nullptr, sec_vis + v0 * HW, stream);
+                                         sec_rec ? sec_rec + v0 * HW * p->N_b : nullptr, sec_vis + v0 * HW,
+                                         reinterpret_cast<unsigned long long*>(counters), stream);
     if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_trace_indirect: ") + hipGetErrorString(e));
   }
   return EXM_OK;
+}
+
+exm_status exm_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
+                         const exm_camera* cams, int32_t nViews, const int32_t* tri_id, const float* bary,
+                         const exm_params* p, float* L_dir, uint64_t* vis, hipStream_t stream) {
+  return shade_fwd_impl(m, bvh, mat, env, cams, nViews, tri_id, bary, p, L_dir, vis, nullptr, stream);
+}
+
+exm_status exm_shade_fwd_counted(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
+                                 const exm_camera* cams, int32_t nViews, const int32_t* tri_id, const float* bary,
+                                 const exm_params* p, float* L_dir, uint64_t* vis, uint64_t* counters,
+                                 hipStream_t stream) {
+  if (!counters || !aligned(counters, 8)) return fail(EXM_E_INVAL, "counters must be an 8-byte aligned device array");
+  return shade_fwd_impl(m, bvh, mat, env, cams, nViews, tri_id, bary, p, L_dir, vis, counters, stream);
+}
+
+exm_status exm_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
+                              const exm_camera* cams, int32_t nViews, const int32_t* tri_id, const float* bary,
+                              const exm_params* p, float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis,
+                              hipStream_t stream) {
+  return trace_indirect_impl(m, bvh, mat, env, cams, nViews, tri_id, bary, p, L_ind, sec_rec, sec_vis, nullptr,
+                             stream);
+}
+
+exm_status exm_trace_indirect_counted(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat,
+                                      const exm_env* env, const exm_camera* cams, int32_t nViews,
+                                      const int32_t* tri_id, const float* bary, const exm_params* p, float* L_ind,
+                                      exm_sec_rec* sec_rec, uint64_t* sec_vis, uint64_t* counters,
+                                      hipStream_t stream) {
+  if (!counters || !aligned(counters, 8)) return fail(EXM_E_INVAL, "counters must be an 8-byte aligned device array");
+  return trace_indirect_impl(m, bvh, mat, env, cams, nViews, tri_id, bary, p, L_ind, sec_rec, sec_vis, counters,
+                             stream);
 }
 
 exm_status exm_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const exm_camera* cams,

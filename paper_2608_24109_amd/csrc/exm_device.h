@@ -381,10 +381,15 @@ struct HitRec {
   float t, b1, b2;
 };
 
+// work counters of the measurement variants (node visits, triangle tests)
+struct TraceCount {
+  uint32_t nodes = 0, tris = 0;
+};
+
 // Stack of node references in LDS: stack[slot * stride + lane_slot]
-template <bool ANY>
+template <bool ANY, bool COUNT = false>
 __device__ __forceinline__ HitRec trace(const BvhView& B, const Ray& r, float tmin, int32_t skip, int32_t* stack,
-                                        int stride) {
+                                        int stride, TraceCount* counts = nullptr) {
   HitRec h;
   h.id = -1;
   h.t = __builtin_huge_valf();
@@ -396,6 +401,7 @@ __device__ __forceinline__ HitRec trace(const BvhView& B, const Ray& r, float tm
   // corrupted structure cannot keep a wave alive
   for (int visits = 0; visits < (1 << 22); ++visits) {
     if (ref >= 0) {
+      if (COUNT) counts->nodes++;
       const BvhNode& N = B.nodes[ref];
       const float4 a = reinterpret_cast<const float4*>(&N)[0];
       const float4 b = reinterpret_cast<const float4*>(&N)[1];
@@ -421,6 +427,7 @@ __device__ __forceinline__ HitRec trace(const BvhView& B, const Ray& r, float tm
       const int32_t first = (int32_t)(v >> 4), cnt = (int32_t)(v & 15u);
       for (int32_t i = first; i < first + cnt; ++i) {
         const BvhTri T = B.tris[i];
+        if (COUNT) counts->tris++;
         if (T.id == skip) continue;
         float t, b1, b2;
         if (tri_hit(r, T, tmin, h.t, &t, &b1, &b2)) {

@@ -69,13 +69,14 @@ hipError_t launch_env_sampler(const float* env, int32_t He, int32_t We, uint64_t
 hipError_t launch_raster(const exm_mesh* m, const RasterViews& v, int32_t* tri_id, float* bary, hipStream_t s);
 hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                             const ShadeViews& v, const int32_t* tri_id, const float* bary, const exm_params* p,
-                            float* L_dir, uint64_t* vis, hipStream_t s);
+                            float* L_dir, uint64_t* vis, unsigned long long* counters, hipStream_t s);
 hipError_t launch_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const ShadeViews& v,
                             const int32_t* tri_id, const float* bary, const exm_params* p, const float* dI,
                             const uint64_t* vis, float* dtex, double* denv, hipStream_t s);
 hipError_t launch_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                                  const ShadeViews& v, const int32_t* tri_id, const float* bary, const exm_params* p,
-                                 float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis, hipStream_t s);
+                                 float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis, unsigned long long* counters,
+                                 hipStream_t s);
 hipError_t launch_trace_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const ShadeViews& v,
                             const int32_t* tri_id, const float* bary, const exm_params* p, float lambda_ind,
                             const float* dI, const exm_sec_rec* sec_rec, const uint64_t* sec_vis, float* dtex,

@@ -42,10 +42,14 @@ __device__ __forceinline__ void brdf_eval(const Surf& S, f3 wi, f3 wo, float ci,
   }
 }
 
+// COUNT: measurement variant that also accumulates [shadow rays, node visits, triangle tests,
+// samples drawn] into counters
+template <bool COUNT>
 __global__ __launch_bounds__(kThreads) void k_shade_fwd(MeshView M, TexView T, EnvView E, BvhView B, ShadeViews V,
                                                         const int32_t* __restrict__ tri_id,
                                                         const float* __restrict__ bary, KParams p,
-                                                        float* __restrict__ L_dir, uint64_t* __restrict__ vis) {
+                                                        float* __restrict__ L_dir, uint64_t* __restrict__ vis,
+                                                        unsigned long long* __restrict__ counters) {
   __shared__ int32_t stack[kStack * kThreads];
   const int64_t HW = (int64_t)V.H * V.W;
   const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -55,6 +59,8 @@ __global__ __launch_bounds__(kThreads) void k_shade_fwd(MeshView M, TexView T, E
   const int32_t f = tri_id[gid];
   float L[3] = {0.f, 0.f, 0.f};
   uint64_t bits = 0;
+  TraceCount tc;
+  uint32_t n_rays = 0;
   if (f >= 0) {
     const float2 b = reinterpret_cast<const float2*>(bary)[gid];
     const Surf S = query(M, T, f, b.x, b.y, p.flags);
@@ -67,7 +73,8 @@ __global__ __launch_bounds__(kThreads) void k_shade_fwd(MeshView M, TexView T, E
       if (!(c > 0.0f)) continue;
       if (!(p.flags & EXM_NO_VIS)) {
         const Ray r = make_ray(S.x, es.dir);
-        const HitRec h = trace<true>(B, r, p.tmin, f, stack + threadIdx.x, kThreads);
+        if (COUNT) ++n_rays;
+        const HitRec h = trace<true, COUNT>(B, r, p.tmin, f, stack + threadIdx.x, kThreads, &tc);
         if (h.id >= 0) continue;
       }
       bits |= 1ull << k;
@@ -88,6 +95,12 @@ __global__ __launch_bounds__(kThreads) void k_shade_fwd(MeshView M, TexView T, E
   L_dir[3 * gid + 1] = L[1];
   L_dir[3 * gid + 2] = L[2];
   vis[gid] = bits;
+  if (COUNT && f >= 0) {
+    atomicAdd(counters + 0, (unsigned long long)n_rays);
+    atomicAdd(counters + 1, (unsigned long long)tc.nodes);
+    atomicAdd(counters + 2, (unsigned long long)tc.tris);
+    atomicAdd(counters + 3, (unsigned long long)p.N_d);
+  }
 }
 
 // Accumulated adjoint of one surface point w.r.t. its material values and shading normal.
@@ -247,11 +260,16 @@ BvhView bvh_view(const exm_bvh* b) { return BvhView{b->nodes, b->tris, b->root_i
 
 hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                             const ShadeViews& v, const int32_t* tri_id, const float* bary, const exm_params* p,
-                            float* L_dir, uint64_t* vis, hipStream_t s) {
+                            float* L_dir, uint64_t* vis, unsigned long long* counters, hipStream_t s) {
   const int64_t n = (int64_t)v.n * v.H * v.W;
-  k_shade_fwd<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
-      mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), bvh_view(bvh), v, tri_id, bary, kparams(p),
-      L_dir, vis);
+  const unsigned nb = (unsigned)((n + kThreads - 1) / kThreads);
+  const TexView tv{mat->Ht, mat->Wt, mat->tex};
+  if (counters)
+    k_shade_fwd<true><<<nb, kThreads, 0, s>>>(mesh_view(m), tv, env_view(env), bvh_view(bvh), v, tri_id, bary,
+                                              kparams(p), L_dir, vis, counters);
+  else
+    k_shade_fwd<false><<<nb, kThreads, 0, s>>>(mesh_view(m), tv, env_view(env), bvh_view(bvh), v, tri_id, bary,
+                                               kparams(p), L_dir, vis, nullptr);
   return hipGetLastError();
 }
 

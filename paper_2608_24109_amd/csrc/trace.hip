@@ -106,11 +106,15 @@ __device__ __forceinline__ bool front_facing(const MeshView& M, int32_t f, f3 w)
   return dot(w, cross(P1 - P0, P2 - P0)) < 0.0f;
 }
 
+// COUNT: measurement variant that also accumulates [secondary rays, their node visits, their
+// triangle tests, light shadow rays, their node visits, their triangle tests] into counters
+template <bool COUNT>
 __global__ __launch_bounds__(kThreads) void k_trace_indirect(MeshView M, TexView T, EnvView E, BvhView B,
                                                              ShadeViews V, const int32_t* __restrict__ tri_id,
                                                              const float* __restrict__ bary, KParams p,
                                                              float* __restrict__ L_ind, exm_sec_rec* __restrict__ rec,
-                                                             uint64_t* __restrict__ sec_vis) {
+                                                             uint64_t* __restrict__ sec_vis,
+                                                             unsigned long long* __restrict__ counters) {
   __shared__ int32_t stack[kStack * kThreads];
   const int64_t HW = (int64_t)V.H * V.W;
   const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -121,6 +125,8 @@ __global__ __launch_bounds__(kThreads) void k_trace_indirect(MeshView M, TexView
   float L[3] = {0.f, 0.f, 0.f};
   uint64_t bits = 0;
   exm_sec_rec* myrec = rec + gid * p.N_b;
+  TraceCount tc_sec, tc_sh;
+  uint32_t n_sh = 0;
   if (f >= 0) {
     const float2 b = reinterpret_cast<const float2*>(bary)[gid];
     const Surf S = query(M, T, f, b.x, b.y, p.flags);
@@ -134,7 +140,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_indirect(MeshView M, TexView
       const SecRay sr = secondary_ray(M, f, b.x, b.y, d.u2, d.u3);
       const f3 w = sr.df;
       const float pb = sr.pb;
-      HitRec h = trace<false>(B, make_ray(sr.of, w), p.tmin, f, stack + threadIdx.x, kThreads);
+      HitRec h = trace<false, COUNT>(B, make_ray(sr.of, w), p.tmin, f, stack + threadIdx.x, kThreads, &tc_sec);
       if (h.id >= 0 && front_facing(M, h.id, w)) {
         refine_hit(M, h.id, sr, &h.b1, &h.b2);
         r = exm_sec_rec{h.id, h.b1, h.b2};
@@ -147,7 +153,9 @@ __global__ __launch_bounds__(kThreads) void k_trace_indirect(MeshView M, TexView
           const float c = dot(Y.ns, es.dir);
           if (!(c > 0.0f)) continue;
           if (!(p.flags & EXM_NO_VIS)) {
-            const HitRec hs = trace<true>(B, make_ray(Y.x, es.dir), p.tmin, h.id, stack + threadIdx.x, kThreads);
+            if (COUNT) ++n_sh;
+            const HitRec hs =
+                trace<true, COUNT>(B, make_ray(Y.x, es.dir), p.tmin, h.id, stack + threadIdx.x, kThreads, &tc_sh);
             if (hs.id >= 0) continue;
           }
           bits |= 1ull << (j * p.N_s + s);
@@ -176,6 +184,14 @@ __global__ __launch_bounds__(kThreads) void k_trace_indirect(MeshView M, TexView
   L_ind[3 * gid + 1] = L[1];
   L_ind[3 * gid + 2] = L[2];
   sec_vis[gid] = bits;
+  if (COUNT && f >= 0) {
+    atomicAdd(counters + 0, (unsigned long long)p.N_b);
+    atomicAdd(counters + 1, (unsigned long long)tc_sec.nodes);
+    atomicAdd(counters + 2, (unsigned long long)tc_sec.tris);
+    atomicAdd(counters + 3, (unsigned long long)n_sh);
+    atomicAdd(counters + 4, (unsigned long long)tc_sh.nodes);
+    atomicAdd(counters + 5, (unsigned long long)tc_sh.tris);
+  }
 }
 
 __device__ __forceinline__ void scatter7(const Surf& S, const float ga[3], float gm, const float gq[3],
@@ -316,11 +332,17 @@ KParams kparams(const exm_params* p) {
 
 hipError_t launch_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                                  const ShadeViews& v, const int32_t* tri_id, const float* bary, const exm_params* p,
-                                 float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis, hipStream_t s) {
+                                 float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis, unsigned long long* counters,
+                                 hipStream_t s) {
   const int64_t n = (int64_t)v.n * v.H * v.W;
-  k_trace_indirect<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
-      mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), bvh_view(bvh), v, tri_id, bary, kparams(p),
-      L_ind, sec_rec, sec_vis);
+  const unsigned nb = (unsigned)((n + kThreads - 1) / kThreads);
+  const TexView tv{mat->Ht, mat->Wt, mat->tex};
+  if (counters)
+    k_trace_indirect<true><<<nb, kThreads, 0, s>>>(mesh_view(m), tv, env_view(env), bvh_view(bvh), v, tri_id, bary,
+                                                   kparams(p), L_ind, sec_rec, sec_vis, counters);
+  else
+    k_trace_indirect<false><<<nb, kThreads, 0, s>>>(mesh_view(m), tv, env_view(env), bvh_view(bvh), v, tri_id, bary,
+                                                    kparams(p), L_ind, sec_rec, sec_vis, nullptr);
   return hipGetLastError();
 }
 

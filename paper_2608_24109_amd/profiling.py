@@ -1,0 +1,107 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+  python -m paper_2608_24109_amd.profiling stats <kernel_stats.csv> <out.md> "<command>"
+  python -m paper_2608_24109_amd.profiling pmc <fetch_counter_collection.csv> <write_counter_collection.csv>
+         <workload> <copy_bytes> <out.json> "<fetch command>" "<write command>"
+
+The PMC summary converts FETCH_SIZE / WRITE_SIZE (KiB per dispatch) to bytes per launch of each
+render-pass kernel, scaled by what the same counters read for a plain device copy of known size
+(the calibration kernel in the same run), and records a digest of the kernel sources so that a
+later change of the kernels invalidates it.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# ABI call -> kernel symbol fragment
+KERNELS = {
+    "shade_fwd": "k_shade_fwd<false>",
+    "shade_bwd": "k_shade_bwd",
+    "trace_indirect": "k_trace_indirect<false>",
+    "trace_bwd": "k_trace_bwd",
+    "raster": "k_raster",
+    "resolve": "k_resolve",
+}
+COPY_KERNEL = "copyBuffer"
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        if p.endswith((".hip", ".h", ".cpp")):
+            h.update(os.path.basename(p).encode())
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _name_matches(name: str, frag: str) -> bool:
+    if "<" in frag:
+        base, targ = frag.split("<", 1)
+        return base in name and ("<" + targ.rstrip(">")) in name.replace(" ", "")
+    return frag in name
+
+
+def stats_md(csv_path: str, out: str, command: str) -> None:
+    rows = list(csv.DictReader(open(csv_path)))
+    lines = [f"Command: `{command}`", "", "| kernel | calls | avg ms | total ms | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows:
+        name = r["Name"]
+        short = name.replace("exm::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        if len(short) > 70:
+            short = short[:67] + "..."
+        lines.append(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.4f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} |")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
+def _per_kernel(csv_path: str, counter: str):
+    acc = defaultdict(list)
+    for r in csv.DictReader(open(csv_path)):
+        if r.get("Counter_Name") != counter:
+            continue
+        acc[r["Kernel_Name"]].append(float(r["Counter_Value"]) * 1024.0)  # KiB -> bytes
+    return acc
+
+
+def pmc_json(fetch_csv: str, write_csv: str, workload: str, copy_bytes: float, out: str, cmd_f: str,
+             cmd_w: str) -> dict:
+    f = _per_kernel(fetch_csv, "FETCH_SIZE")
+    w = _per_kernel(write_csv, "WRITE_SIZE")
+
+    def avg(acc, frag):
+        vals = [v for n, vs in acc.items() if _name_matches(n, frag) for v in vs]
+        return sum(vals) / len(vals) if vals else None
+
+    # calibration: the largest copy dispatch is the known-size copy
+    cf = max((v for n, vs in f.items() if COPY_KERNEL in n for v in vs), default=None)
+    cw = max((v for n, vs in w.items() if COPY_KERNEL in n for v in vs), default=None)
+    kf = cf / copy_bytes if cf else 1.0
+    kw = cw / copy_bytes if cw else 1.0
+    res = {"workload": workload, "source_sha": source_digest(), "copy_bytes": copy_bytes,
+           "calibration": {"fetch_factor": kf, "write_factor": kw},
+           "commands": {"fetch": cmd_f, "write": cmd_w}, "kernels": {}}
+    for key, frag in KERNELS.items():
+        a, b = avg(f, frag), avg(w, frag)
+        if a is None or b is None:
+            continue
+        res["kernels"][key] = {"fetch_bytes": a / kf, "write_bytes": b / kw, "fetch_raw_kib": a / 1024,
+                               "write_raw_kib": b / 1024}
+    json.dump(res, open(out, "w"), indent=1)
+    return res
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats_md(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "pmc":
+        pmc_json(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]), sys.argv[6], sys.argv[7], sys.argv[8])
+    else:
+        raise SystemExit(__doc__)
