@@ -86,13 +86,14 @@ def run_gpu(workload: str, steps: int, warmup: int):
     dtex = torch.zeros_like(mat.tex)
     denv = torch.zeros(env.env.shape, dtype=torch.float64, device="cuda")
     lam = 1.0
+    ws_fwd = bufs.workspace(L.exm_shade_fwd_workspace_size(V, H, W, p.N_d))
     torch.cuda.synchronize()
 
     def step(tm):
         tm("build_env_sampler", lambda: L.exm_build_env_sampler(env.env, env.cdf_row, env.cdf_col, env.pdf))
         tm("raster_gbuffer", lambda: raster(mesh, cc, bufs))
         tm("shade_fwd", lambda: L.exm_shade_fwd(mesh.s, mesh.bvh, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc,
-                                                bufs.L_dir, bufs.vis))
+                                                bufs.L_dir, bufs.vis, ws_fwd))
         if p.N_b > 0:
             tm("trace_indirect", lambda: L.exm_trace_indirect(mesh.s, mesh.bvh, mat.s, env.s, cc, bufs.tri_id,
                                                               bufs.bary, pc, bufs.L_ind, bufs.sec_rec, bufs.sec_vis))
@@ -119,7 +120,7 @@ def run_gpu(workload: str, steps: int, warmup: int):
     # work counts of the workload, from the counting variants (outside the timed region)
     c_dir = torch.zeros(4, dtype=torch.uint64, device="cuda")
     L.exm_shade_fwd_counted(mesh.s, mesh.bvh, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc, bufs.L_dir, bufs.vis,
-                            c_dir)
+                            ws_fwd, c_dir)
     c_ind = torch.zeros(6, dtype=torch.uint64, device="cuda")
     if p.N_b > 0:
         L.exm_trace_indirect_counted(mesh.s, mesh.bvh, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc, bufs.L_ind,

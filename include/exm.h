@@ -9,7 +9,8 @@
  * Conventions for every call:
  *  - Array pointers are DEVICE pointers owned by the caller, except those marked _host.
  *  - Calls only enqueue work on `stream` and return; results are valid after the stream
- *    synchronises. The library allocates no device memory except inside exm_build_bvh.
+ *    synchronises. The library allocates no device memory except inside exm_build_bvh; passes
+ *    that buffer rays take a caller-owned workspace.
  *  - Gradient outputs ACCUMULATE (+=); the caller zeroes them.
  *  - Shapes, null pointers, sizes and host-readable values are validated before any launch;
  *    a failed check returns EXM_E_INVAL and enqueues nothing. A HIP launch or runtime error
@@ -140,11 +141,18 @@ exm_status exm_raster_gbuffer(const exm_mesh* m, const exm_camera* cams_host, in
                               int32_t* tri_id, float* bary, hipStream_t stream);
 
 /* Direct light, Eq. 17: L_dir [nViews,H,W,3] float (overwritten) and vis [nViews,H,W] u64,
- * bit k = sample k had n_s . w > 0 and was unoccluded. Needs exm_mesh_prepare. */
+ * bit k = sample k had n_s . w > 0 and was unoccluded. Needs exm_mesh_prepare.
+ * ws: caller-owned device workspace (256-byte aligned) holding the shadow rays of a chunk of
+ * pixels; exm_shade_fwd_workspace_size gives the bytes that hold one launch's pixels at once
+ * (at most 8 views per launch), any size >= exm_shade_fwd_workspace_min works by processing
+ * pixels in chunks. The workspace is scratch: its contents are undefined after the call, and
+ * calls sharing one workspace must be ordered on one stream. */
+size_t exm_shade_fwd_workspace_size(int32_t nViews, int32_t H, int32_t W, int32_t N_d);
+size_t exm_shade_fwd_workspace_min(int32_t N_d);
 exm_status exm_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat,
                          const exm_env* env, const exm_camera* cams_host, int32_t nViews,
                          const int32_t* tri_id, const float* bary, const exm_params* p,
-                         float* L_dir, uint64_t* vis, hipStream_t stream);
+                         float* L_dir, uint64_t* vis, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* One-bounce diffuse indirect, Eq. 18-19: L_ind [nViews,H,W,3] (overwritten), sec_rec
  * [nViews,H,W,N_b], sec_vis [nViews,H,W] u64 (bit j*N_s+s). */
@@ -165,7 +173,8 @@ exm_status exm_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_m
 exm_status exm_shade_fwd_counted(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat,
                                  const exm_env* env, const exm_camera* cams_host, int32_t nViews,
                                  const int32_t* tri_id, const float* bary, const exm_params* p,
-                                 float* L_dir, uint64_t* vis, uint64_t* counters, hipStream_t stream);
+                                 float* L_dir, uint64_t* vis, void* ws, size_t ws_bytes,
+                                 uint64_t* counters, hipStream_t stream);
 exm_status exm_trace_indirect_counted(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat,
                                       const exm_env* env, const exm_camera* cams_host, int32_t nViews,
                                       const int32_t* tri_id, const float* bary, const exm_params* p,

@@ -74,9 +74,11 @@ def _load() -> C.CDLL:
         "exm_bvh_device_bytes": (C.c_size_t, [vp]),
         "exm_build_env_sampler": (st, [vp, i32, i32, vp, vp, vp, vp]),
         "exm_raster_gbuffer": (st, [vp, vp, i32, vp, vp, vp]),
-        "exm_shade_fwd": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]),
+        "exm_shade_fwd_workspace_size": (C.c_size_t, [i32, i32, i32, i32]),
+        "exm_shade_fwd_workspace_min": (C.c_size_t, [i32]),
+        "exm_shade_fwd": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
         "exm_trace_indirect": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]),
-        "exm_shade_fwd_counted": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]),
+        "exm_shade_fwd_counted": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp, vp]),
         "exm_trace_indirect_counted": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
         "exm_shade_bwd": (st, [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
         "exm_trace_bwd": (st, [vp, vp, vp, vp, i32, vp, vp, vp, C.c_float, vp, vp, vp, vp, vp, vp]),
@@ -199,14 +201,29 @@ def exm_raster_gbuffer(mesh: exm_mesh, cams, tri_id, bary, stream=None) -> None:
            "exm_raster_gbuffer")
 
 
+def exm_shade_fwd_workspace_size(nViews: int, H: int, W: int, N_d: int) -> int:
+    return int(lib.exm_shade_fwd_workspace_size(nViews, H, W, N_d))
+
+
+def exm_shade_fwd_workspace_min(N_d: int) -> int:
+    return int(lib.exm_shade_fwd_workspace_min(N_d))
+
+
+def workspace(nbytes: int, device="cuda"):
+    """A device byte buffer for the ray workspaces (the caching allocator keeps it 256-B aligned)."""
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
 def exm_shade_fwd(mesh, bvh: Bvh, mat: exm_material, env: exm_env, cams, tri_id, bary, p: exm_params, L_dir,
-                  vis, stream=None) -> None:
+                  vis, ws, stream=None) -> None:
     import torch
     n, H, W = len(cams), cams[0].H, cams[0].W
     _need(L_dir, torch.float32, (n, H, W, 3), "L_dir")
     _need(vis, torch.uint64, (n, H, W), "vis")
     _check(lib.exm_shade_fwd(C.byref(mesh), bvh.handle, C.byref(mat), C.byref(env), cams, n, _ptr(tri_id),
-                             _ptr(bary), C.byref(p), _ptr(L_dir), _ptr(vis), _stream(stream)), "exm_shade_fwd")
+                             _ptr(bary), C.byref(p), _ptr(L_dir), _ptr(vis), _ptr(ws), ws.numel(), _stream(stream)),
+           "exm_shade_fwd")
 
 
 def exm_trace_indirect(mesh, bvh: Bvh, mat, env, cams, tri_id, bary, p: exm_params, L_ind, sec_rec, sec_vis,
@@ -221,13 +238,13 @@ def exm_trace_indirect(mesh, bvh: Bvh, mat, env, cams, tri_id, bary, p: exm_para
                                   _stream(stream)), "exm_trace_indirect")
 
 
-def exm_shade_fwd_counted(mesh, bvh: Bvh, mat, env, cams, tri_id, bary, p: exm_params, L_dir, vis, counters,
+def exm_shade_fwd_counted(mesh, bvh: Bvh, mat, env, cams, tri_id, bary, p: exm_params, L_dir, vis, ws, counters,
                           stream=None) -> None:
     import torch
     _need(counters, torch.uint64, (4,), "counters")
     _check(lib.exm_shade_fwd_counted(C.byref(mesh), bvh.handle, C.byref(mat), C.byref(env), cams, len(cams),
-                                     _ptr(tri_id), _ptr(bary), C.byref(p), _ptr(L_dir), _ptr(vis), _ptr(counters),
-                                     _stream(stream)), "exm_shade_fwd_counted")
+                                     _ptr(tri_id), _ptr(bary), C.byref(p), _ptr(L_dir), _ptr(vis), _ptr(ws),
+                                     ws.numel(), _ptr(counters), _stream(stream)), "exm_shade_fwd_counted")
 
 
 def exm_trace_indirect_counted(mesh, bvh: Bvh, mat, env, cams, tri_id, bary, p: exm_params, L_ind, sec_rec,

@@ -243,8 +243,8 @@ exm_status exm_raster_gbuffer(const exm_mesh* m, const exm_camera* cams, int32_t
 
 static exm_status shade_fwd_impl(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                                  const exm_camera* cams, int32_t nViews, const int32_t* tri_id, const float* bary,
-                                 const exm_params* p, float* L_dir, uint64_t* vis, uint64_t* counters,
-                                 hipStream_t stream) {
+                                 const exm_params* p, float* L_dir, uint64_t* vis, void* ws, size_t ws_bytes,
+                                 uint64_t* counters, hipStream_t stream) {
   EXM_TRY(check_mesh(m, true));
   if (!bvh) return fail(EXM_E_INVAL, "bvh is NULL");
   EXM_TRY(check_material(mat));
@@ -253,12 +253,14 @@ static exm_status shade_fwd_impl(const exm_mesh* m, const exm_bvh* bvh, const ex
   EXM_TRY(check_gbuffer(tri_id, bary));
   EXM_TRY(check_params(p, false));
   if (!L_dir || !vis) return fail(EXM_E_INVAL, "output pointer is NULL");
+  if (!ws || !aligned(ws, 256) || ws_bytes < shade_fwd_ws_min(p->N_d))
+    return fail(EXM_E_INVAL, "workspace must be 256-byte aligned and at least exm_shade_fwd_workspace_min bytes");
   EXM_TRY(check_device());
   const int64_t HW = (int64_t)cams[0].H * cams[0].W;
   for (int32_t v0 = 0; v0 < nViews; v0 += kViewsPerLaunch) {
     const int32_t n = std::min(kViewsPerLaunch, nViews - v0);
     hipError_t e = launch_shade_fwd(m, bvh, mat, env, shade_views(cams, v0, n), tri_id + v0 * HW, bary + 2 * v0 * HW, p,
-                                    L_dir + 3 * v0 * HW, vis + v0 * HW,
+                                    L_dir + 3 * v0 * HW, vis + v0 * HW, ws, ws_bytes,
                                     reinterpret_cast<unsigned long long*>(counters), stream);
     if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_shade_fwd: ") + hipGetErrorString(e));
   }
@@ -291,18 +293,26 @@ static exm_status trace_indirect_impl(const exm_mesh* m, const exm_bvh* bvh, con
   return EXM_OK;
 }
 
+size_t exm_shade_fwd_workspace_size(int32_t nViews, int32_t H, int32_t W, int32_t N_d) {
+  if (nViews <= 0 || H <= 0 || W <= 0 || N_d < 0 || N_d > 64) return 0;
+  return shade_fwd_ws_bytes((int64_t)std::min(nViews, kViewsPerLaunch) * H * W, N_d);
+}
+
+size_t exm_shade_fwd_workspace_min(int32_t N_d) { return (N_d < 0 || N_d > 64) ? 0 : shade_fwd_ws_min(N_d); }
+
 exm_status exm_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                          const exm_camera* cams, int32_t nViews, const int32_t* tri_id, const float* bary,
-                         const exm_params* p, float* L_dir, uint64_t* vis, hipStream_t stream) {
-  return shade_fwd_impl(m, bvh, mat, env, cams, nViews, tri_id, bary, p, L_dir, vis, nullptr, stream);
+                         const exm_params* p, float* L_dir, uint64_t* vis, void* ws, size_t ws_bytes,
+                         hipStream_t stream) {
+  return shade_fwd_impl(m, bvh, mat, env, cams, nViews, tri_id, bary, p, L_dir, vis, ws, ws_bytes, nullptr, stream);
 }
 
 exm_status exm_shade_fwd_counted(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                                  const exm_camera* cams, int32_t nViews, const int32_t* tri_id, const float* bary,
-                                 const exm_params* p, float* L_dir, uint64_t* vis, uint64_t* counters,
-                                 hipStream_t stream) {
+                                 const exm_params* p, float* L_dir, uint64_t* vis, void* ws, size_t ws_bytes,
+                                 uint64_t* counters, hipStream_t stream) {
   if (!counters || !aligned(counters, 8)) return fail(EXM_E_INVAL, "counters must be an 8-byte aligned device array");
-  return shade_fwd_impl(m, bvh, mat, env, cams, nViews, tri_id, bary, p, L_dir, vis, counters, stream);
+  return shade_fwd_impl(m, bvh, mat, env, cams, nViews, tri_id, bary, p, L_dir, vis, ws, ws_bytes, counters, stream);
 }
 
 exm_status exm_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,

@@ -386,66 +386,91 @@ struct TraceCount {
   uint32_t nodes = 0, tris = 0;
 };
 
-// Stack of node references in LDS: stack[slot * stride + lane_slot]
-template <bool ANY, bool COUNT = false>
-__device__ __forceinline__ HitRec trace(const BvhView& B, const Ray& r, float tmin, int32_t skip, int32_t* stack,
-                                        int stride, TraceCount* counts = nullptr) {
-  HitRec h;
+// Resumable traversal state: the current node reference and the depth of the lane's stack of
+// deferred node references (kept in LDS at stack[slot * stride]).
+struct TravState {
+  int32_t ref;
+  int32_t sp;
+  uint32_t steps;
+};
+
+constexpr int32_t kEmptyRef = (int32_t)0x80000000;
+constexpr uint32_t kMaxSteps = 1u << 22;  // the builder bounds the work far below this; the cap
+                                          // only keeps a corrupted structure from trapping a wave
+
+__device__ __forceinline__ void trav_begin(const BvhView& B, TravState& s, HitRec& h) {
+  s.ref = B.root_is_leaf ? B.nodes[0].c0 : 0;
+  s.sp = 0;
+  s.steps = 0;
   h.id = -1;
   h.t = __builtin_huge_valf();
   h.b1 = h.b2 = 0.0f;
-  int sp = 0;
-  int32_t ref = B.root_is_leaf ? B.nodes[0].c0 : 0;
-  const int32_t kEmpty = (int32_t)0x80000000;
-  // the builder bounds the depth by kMaxDepth < kStack; the visit cap only guarantees that a
-  // corrupted structure cannot keep a wave alive
-  for (int visits = 0; visits < (1 << 22); ++visits) {
-    if (ref >= 0) {
-      if (COUNT) counts->nodes++;
-      const BvhNode& N = B.nodes[ref];
-      const float4 a = reinterpret_cast<const float4*>(&N)[0];
-      const float4 b = reinterpret_cast<const float4*>(&N)[1];
-      const float4 c = reinterpret_cast<const float4*>(&N)[2];
-      const int4 e = reinterpret_cast<const int4*>(&N)[3];
-      const float lo0[3] = {a.x, a.y, a.z}, hi0[3] = {a.w, b.x, b.y};
-      const float lo1[3] = {b.z, b.w, c.x}, hi1[3] = {c.y, c.z, c.w};
-      const float t0 = box_enter(lo0, hi0, r, h.t);
-      const float t1 = box_enter(lo1, hi1, r, h.t);
-      const bool h0 = t0 != __builtin_huge_valf(), h1 = t1 != __builtin_huge_valf();
-      if (h0 && h1) {
-        const bool first0 = t0 <= t1;
-        ref = first0 ? e.x : e.y;
-        if (sp < kStack) stack[(sp++) * stride] = first0 ? e.y : e.x;
-        continue;
-      }
-      if (h0 || h1) {
-        ref = h0 ? e.x : e.y;
-        continue;
-      }
-    } else if (ref != kEmpty) {
-      const uint32_t v = ~(uint32_t)ref;
-      const int32_t first = (int32_t)(v >> 4), cnt = (int32_t)(v & 15u);
-      for (int32_t i = first; i < first + cnt; ++i) {
-        const BvhTri T = B.tris[i];
-        if (COUNT) counts->tris++;
-        if (T.id == skip) continue;
-        float t, b1, b2;
-        if (tri_hit(r, T, tmin, h.t, &t, &b1, &b2)) {
-          if (ANY) {
-            h.id = T.id;
-            return h;
-          }
-          if (t < h.t || (t == h.t && T.id < h.id)) {
-            h.id = T.id;
-            h.t = t;
-            h.b1 = b1;
-            h.b2 = b2;
-          }
+}
+
+// One traversal step: an internal node (both child boxes tested, near child next, far child
+// deferred) or a leaf (its triangles tested). Returns true when the query is finished: the
+// stack is empty, or ANY and a hit was found.
+template <bool ANY, bool COUNT>
+__device__ __forceinline__ bool trav_step(const BvhView& B, const Ray& r, float tmin, int32_t skip, int32_t* stack,
+                                          int stride, TravState& s, HitRec& h, TraceCount* counts) {
+  if (++s.steps > kMaxSteps) return true;
+  if (s.ref >= 0) {
+    if (COUNT) counts->nodes++;
+    const BvhNode& N = B.nodes[s.ref];
+    const float4 a = reinterpret_cast<const float4*>(&N)[0];
+    const float4 b = reinterpret_cast<const float4*>(&N)[1];
+    const float4 c = reinterpret_cast<const float4*>(&N)[2];
+    const int4 e = reinterpret_cast<const int4*>(&N)[3];
+    const float lo0[3] = {a.x, a.y, a.z}, hi0[3] = {a.w, b.x, b.y};
+    const float lo1[3] = {b.z, b.w, c.x}, hi1[3] = {c.y, c.z, c.w};
+    const float t0 = box_enter(lo0, hi0, r, h.t);
+    const float t1 = box_enter(lo1, hi1, r, h.t);
+    const bool h0 = t0 != __builtin_huge_valf(), h1 = t1 != __builtin_huge_valf();
+    if (h0 && h1) {
+      const bool first0 = t0 <= t1;
+      s.ref = first0 ? e.x : e.y;
+      if (s.sp < kStack) stack[(s.sp++) * stride] = first0 ? e.y : e.x;
+      return false;
+    }
+    if (h0 || h1) {
+      s.ref = h0 ? e.x : e.y;
+      return false;
+    }
+  } else if (s.ref != kEmptyRef) {
+    const uint32_t v = ~(uint32_t)s.ref;
+    const int32_t first = (int32_t)(v >> 4), cnt = (int32_t)(v & 15u);
+    for (int32_t i = first; i < first + cnt; ++i) {
+      const BvhTri T = B.tris[i];
+      if (COUNT) counts->tris++;
+      if (T.id == skip) continue;
+      float t, b1, b2;
+      if (tri_hit(r, T, tmin, h.t, &t, &b1, &b2)) {
+        if (ANY) {
+          h.id = T.id;
+          return true;
+        }
+        if (t < h.t || (t == h.t && T.id < h.id)) {
+          h.id = T.id;
+          h.t = t;
+          h.b1 = b1;
+          h.b2 = b2;
         }
       }
     }
-    if (sp == 0) break;
-    ref = stack[(--sp) * stride];
+  }
+  if (s.sp == 0) return true;
+  s.ref = stack[(--s.sp) * stride];
+  return false;
+}
+
+// Whole query in one call (ANY: first hit; else closest hit).
+template <bool ANY, bool COUNT = false>
+__device__ __forceinline__ HitRec trace(const BvhView& B, const Ray& r, float tmin, int32_t skip, int32_t* stack,
+                                        int stride, TraceCount* counts = nullptr) {
+  TravState s;
+  HitRec h;
+  trav_begin(B, s, h);
+  while (!trav_step<ANY, COUNT>(B, r, tmin, skip, stack, stride, s, h, counts)) {
   }
   return h;
 }

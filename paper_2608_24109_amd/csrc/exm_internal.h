@@ -69,7 +69,10 @@ hipError_t launch_env_sampler(const float* env, int32_t He, int32_t We, uint64_t
 hipError_t launch_raster(const exm_mesh* m, const RasterViews& v, int32_t* tri_id, float* bary, hipStream_t s);
 hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                             const ShadeViews& v, const int32_t* tri_id, const float* bary, const exm_params* p,
-                            float* L_dir, uint64_t* vis, unsigned long long* counters, hipStream_t s);
+                            float* L_dir, uint64_t* vis, void* ws, size_t ws_bytes, unsigned long long* counters,
+                            hipStream_t s);
+size_t shade_fwd_ws_bytes(int64_t n_pix, int32_t N_d);
+size_t shade_fwd_ws_min(int32_t N_d);
 hipError_t launch_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const ShadeViews& v,
                             const int32_t* tri_id, const float* bary, const exm_params* p, const float* dI,
                             const uint64_t* vis, float* dtex, double* denv, hipStream_t s);

@@ -1,0 +1,88 @@
+// Ray batches between the kernels that generate rays, the persistent traversal kernel and the
+// kernels that consume the results, plus the workspace layouts of the passes that use them.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "exm_device.h"
+
+namespace exm {
+
+// 32-byte ray record: origin, the triangle the ray leaves from (skipped), direction, t_min
+struct alignas(16) RayRec {
+  float o[3];
+  int32_t skip;
+  float d[3];
+  float tmin;
+};
+static_assert(sizeof(RayRec) == 32, "ray layout");
+
+// Region r holds count[r] rays at slots [r * region_stride, r * region_stride + count[r]).
+struct RayBatch {
+  const RayRec* rays;
+  const uint32_t* count;
+  int32_t n_regions;
+  int64_t region_stride;
+  uint32_t* region_counter;  // workspace word, reset by the launcher
+};
+
+int32_t ray_refill_threshold();
+// any-hit: out[slot] = 1 if something is hit at t >= tmin (the skipped triangle excepted)
+hipError_t launch_trace_any(const exm_bvh* bvh, const RayBatch& rb, uint8_t* out, unsigned long long* counters,
+                            hipStream_t s);
+// closest hit: out[slot] = {id (-1 miss), t, b1, b2}
+hipError_t launch_trace_closest(const exm_bvh* bvh, const RayBatch& rb, HitRec* out, unsigned long long* counters,
+                                hipStream_t s);
+
+// ---- workspace carving ----
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Direct pass over a chunk of P pixels (P a multiple of 64; one region per 64 pixels, N_d slots
+// per pixel): counter, per-region counts, per-pixel sample masks, rays, contributions, hits.
+struct DirectWs {
+  uint32_t* counter;
+  uint32_t* count;
+  uint64_t* mask;
+  RayRec* rays;
+  float* contrib;
+  uint8_t* hit;
+};
+
+inline size_t direct_ws_bytes(int64_t P, int32_t N_d) {
+  const int64_t slots = P * (int64_t)(N_d > 0 ? N_d : 1);
+  return 256 + align256((size_t)(P / 64) * 4) + align256((size_t)P * 8) + align256((size_t)slots * 32) +
+         align256((size_t)slots * 12) + align256((size_t)slots);
+}
+
+inline DirectWs direct_ws(void* ws, int64_t P, int32_t N_d) {
+  const int64_t slots = P * (int64_t)(N_d > 0 ? N_d : 1);
+  char* q = static_cast<char*>(ws);
+  DirectWs w;
+  w.counter = reinterpret_cast<uint32_t*>(q);
+  q += 256;
+  w.count = reinterpret_cast<uint32_t*>(q);
+  q += align256((size_t)(P / 64) * 4);
+  w.mask = reinterpret_cast<uint64_t*>(q);
+  q += align256((size_t)P * 8);
+  w.rays = reinterpret_cast<RayRec*>(q);
+  q += align256((size_t)slots * 32);
+  w.contrib = reinterpret_cast<float*>(q);
+  q += align256((size_t)slots * 12);
+  w.hit = reinterpret_cast<uint8_t*>(q);
+  return w;
+}
+
+// largest chunk (multiple of 64 pixels, at most max_px) that fits ws_bytes; 0 if none
+inline int64_t direct_chunk(size_t ws_bytes, int32_t N_d, int64_t max_px) {
+  int64_t lo = 0, hi = (max_px + 63) / 64;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (direct_ws_bytes(mid * 64, N_d) <= ws_bytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo * 64;
+}
+
+}  // namespace exm

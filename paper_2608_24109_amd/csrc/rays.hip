@@ -1,0 +1,146 @@
+// Batched ray queries on the BVH: any-hit (visibility) and closest-hit (secondary rays).
+//
+// Rays arrive in regions: region r holds count[r] rays at slots [r * region_stride, ...). The
+// kernel is persistent: a wave claims a whole region with one atomic, then its lanes take the
+// region's rays one at a time as they finish (wave-local bookkeeping through ballots, no
+// atomics), so a wave is held neither by its longest ray nor by idle lanes. Traversal yields
+// back to refilling when fewer than `refill` lanes are still traversing. Each lane keeps only a
+// ray and its traversal state, so the kernel stays small and many waves are resident to hide
+// the latency of node fetches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "exm_device.h"
+#include "exm_rays.h"
+
+namespace exm {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  const uint32_t lane = __lane_id();
+  return (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+}
+
+template <bool ANY, bool COUNT>
+__global__ __launch_bounds__(kThreads) void k_trace(BvhView B, RayBatch rb, int32_t refill, HitRec* __restrict__ out_hit,
+                                                    uint8_t* __restrict__ out_any,
+                                                    unsigned long long* __restrict__ counters) {
+  __shared__ int32_t stack_mem[kStack * kThreads];
+  int32_t* stack = stack_mem + threadIdx.x;
+  // wave-uniform region cursor
+  int32_t region = -1;
+  uint32_t next = 0, count = 0;
+  int64_t base = 0;
+  bool exhausted = false;
+  // lane state
+  bool have_ray = false;
+  int64_t slot = 0;
+  Ray ray;
+  float tmin = 0.0f;
+  int32_t skip = -1;
+  TravState ts;
+  HitRec h;
+  TraceCount tc;
+  uint32_t n_rays = 0;
+
+  while (true) {
+    uint64_t need = __ballot(!have_ray);
+    while (need != 0ull && !exhausted) {
+      if (next >= count) {
+        int32_t r = 0;
+        if (__lane_id() == 0) r = (int32_t)atomicAdd(rb.region_counter, 1u);
+        region = __shfl(r, 0, 64);
+        if (region >= rb.n_regions) {
+          exhausted = true;
+          break;
+        }
+        count = rb.count[region];
+        next = 0;
+        base = (int64_t)region * rb.region_stride;
+        continue;
+      }
+      const uint32_t avail = count - next;
+      const uint32_t rank = lanes_below(need);
+      if (!have_ray && rank < avail) {
+        slot = base + next + rank;
+        const RayRec R = rb.rays[slot];
+        ray = make_ray(mk(R.o[0], R.o[1], R.o[2]), mk(R.d[0], R.d[1], R.d[2]));
+        tmin = R.tmin;
+        skip = R.skip;
+        trav_begin(B, ts, h);
+        have_ray = true;
+        if (COUNT) ++n_rays;
+      }
+      next += min(avail, (uint32_t)__popcll(need));
+      need = __ballot(!have_ray);
+    }
+    if (__ballot(have_ray) == 0ull) break;
+    if (have_ray) {
+      while (true) {
+        if (trav_step<ANY, COUNT>(B, ray, tmin, skip, stack, kThreads, ts, h, &tc)) {
+          if (ANY)
+            out_any[slot] = h.id >= 0 ? 1 : 0;
+          else
+            out_hit[slot] = h;
+          have_ray = false;
+          break;
+        }
+        if (__popcll(__ballot(1)) < refill) break;
+      }
+    }
+  }
+  if (COUNT) {
+    atomicAdd(counters + 0, (unsigned long long)n_rays);
+    atomicAdd(counters + 1, (unsigned long long)tc.nodes);
+    atomicAdd(counters + 2, (unsigned long long)tc.tris);
+  }
+}
+
+__global__ void k_reset_counter(uint32_t* c) { *c = 0u; }
+
+template <bool ANY, bool COUNT>
+hipError_t launch_impl(const exm_bvh* bvh, const RayBatch& rb, HitRec* out_hit, uint8_t* out_any,
+                       unsigned long long* counters, hipStream_t s) {
+  if (rb.n_regions <= 0) return hipSuccess;
+  int dev = 0, cus = 256, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hipGetLastError();
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return hipGetLastError();
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_trace<ANY, COUNT>, kThreads, 0) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  const int64_t waves_needed = rb.n_regions;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((waves_needed + 3) / 4, (int64_t)cus * per_cu));
+  k_reset_counter<<<1, 1, 0, s>>>(rb.region_counter);
+  k_trace<ANY, COUNT><<<(unsigned)blocks, kThreads, 0, s>>>(BvhView{bvh->nodes, bvh->tris, bvh->root_is_leaf}, rb,
+                                                             ray_refill_threshold(), out_hit, out_any, counters);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int32_t ray_refill_threshold() {
+  static const int32_t v = [] {
+    const char* e = getenv("EXM_RAY_REFILL");
+    const int x = e ? atoi(e) : 0;
+    return (x >= 1 && x <= 64) ? x : 16;
+  }();
+  return v;
+}
+
+hipError_t launch_trace_any(const exm_bvh* bvh, const RayBatch& rb, uint8_t* out, unsigned long long* counters,
+                            hipStream_t s) {
+  return counters ? launch_impl<true, true>(bvh, rb, nullptr, out, counters, s)
+                  : launch_impl<true, false>(bvh, rb, nullptr, out, nullptr, s);
+}
+
+hipError_t launch_trace_closest(const exm_bvh* bvh, const RayBatch& rb, HitRec* out, unsigned long long* counters,
+                                hipStream_t s) {
+  return counters ? launch_impl<false, true>(bvh, rb, out, nullptr, counters, s)
+                  : launch_impl<false, false>(bvh, rb, out, nullptr, nullptr, s);
+}
+
+}  // namespace exm

@@ -3,6 +3,13 @@
 // Forward, per covered pixel: attribute query at the visible point (Eq. 10-11), then N_d
 // env samples drawn from the importance-sampling tables; a sample with n_s . w > 0 traces an
 // any-hit shadow ray and, if unoccluded, adds E f_r (n_s . w) / pdf (Eq. 13-16 for f_r).
+// It runs as three kernels per chunk of pixels:
+//   gen      one thread per pixel: attribute query, all N_d samples, and for each sample with
+//            n_s . w > 0 its shadow ray and its contribution E f_r c / pdf, written compactly
+//            into its wave's region of the workspace (slots from ballots, no atomics);
+//   trace    the persistent any-hit kernel over the regions (rays.hip);
+//   finalize one thread per pixel: the same ballots locate each sample's slot; unoccluded
+//            contributions are summed in sample order; visibility bits are written.
 // The visibility bits of all samples are stored so the adjoint never traces a ray.
 //
 // Adjoint, per covered pixel with upstream g = dLoss/dL_dir: the same samples again (same RNG
@@ -12,7 +19,11 @@
 // The pdf and every discrete choice are held fixed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdlib>
+
 #include "exm_device.h"
+#include "exm_rays.h"
 
 namespace exm {
 namespace {
@@ -42,65 +53,111 @@ __device__ __forceinline__ void brdf_eval(const Surf& S, f3 wi, f3 wo, float ci,
   }
 }
 
-// COUNT: measurement variant that also accumulates [shadow rays, node visits, triangle tests,
-// samples drawn] into counters
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return (uint32_t)__popcll(mask & ((1ull << __lane_id()) - 1ull));
+}
+
+// Chunk [p0, p0 + P) of the launch's pixels; P is a multiple of 64 and waves past it exit whole.
+// COUNT: also accumulates env samples drawn into counters[3].
 template <bool COUNT>
-__global__ __launch_bounds__(kThreads) void k_shade_fwd(MeshView M, TexView T, EnvView E, BvhView B, ShadeViews V,
-                                                        const int32_t* __restrict__ tri_id,
-                                                        const float* __restrict__ bary, KParams p,
-                                                        float* __restrict__ L_dir, uint64_t* __restrict__ vis,
-                                                        unsigned long long* __restrict__ counters) {
-  __shared__ int32_t stack[kStack * kThreads];
+__global__ __launch_bounds__(kThreads) void k_dir_gen(MeshView M, TexView T, EnvView E, ShadeViews V,
+                                                      const int32_t* __restrict__ tri_id,
+                                                      const float* __restrict__ bary, KParams p, int64_t p0,
+                                                      int64_t P, DirectWs ws, unsigned long long* __restrict__ counters) {
+  const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if ((local & ~(int64_t)63) >= P) return;  // whole waves only
   const int64_t HW = (int64_t)V.H * V.W;
-  const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (gid >= HW * V.n) return;
-  const int32_t view = (int32_t)(gid / HW);
-  const uint32_t pix = (uint32_t)(gid - view * HW);
-  const int32_t f = tri_id[gid];
-  float L[3] = {0.f, 0.f, 0.f};
-  uint64_t bits = 0;
-  TraceCount tc;
-  uint32_t n_rays = 0;
+  const int64_t gid = p0 + local;
+  const int64_t region = local >> 6;
+  const int32_t f = gid < HW * V.n ? tri_id[gid] : -1;
+  Surf S;
+  f3 wo = mk(0, 0, 0);
+  uint32_t pix = 0, vid = 0;
   if (f >= 0) {
+    const int32_t view = (int32_t)(gid / HW);
+    pix = (uint32_t)(gid - view * HW);
+    vid = (uint32_t)V.view_id[view];
     const float2 b = reinterpret_cast<const float2*>(bary)[gid];
-    const Surf S = query(M, T, f, b.x, b.y, p.flags);
-    const f3 wo = normalize(mk(V.eye[view][0], V.eye[view][1], V.eye[view][2]) - S.x);
-    const uint32_t vid = (uint32_t)V.view_id[view];
-    for (int k = 0; k < p.N_d; ++k) {
-      const Draw d = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)k, 0u);
-      const EnvSample es = env_sample(E, d);
-      const float c = dot(S.ns, es.dir);
-      if (!(c > 0.0f)) continue;
-      if (!(p.flags & EXM_NO_VIS)) {
-        const Ray r = make_ray(S.x, es.dir);
-        if (COUNT) ++n_rays;
-        const HitRec h = trace<true, COUNT>(B, r, p.tmin, f, stack + threadIdx.x, kThreads, &tc);
-        if (h.id >= 0) continue;
-      }
-      bits |= 1ull << k;
+    S = query(M, T, f, b.x, b.y, p.flags);
+    wo = normalize(mk(V.eye[view][0], V.eye[view][1], V.eye[view][2]) - S.x);
+  }
+  uint64_t mask = 0;
+  uint32_t running = 0;  // wave-uniform
+  const int64_t rbase = region * 64 * (int64_t)p.N_d;
+  for (int k = 0; k < p.N_d; ++k) {
+    bool need = false;
+    EnvSample es;
+    float c = 0.0f;
+    if (f >= 0) {
+      es = env_sample(E, philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)k, 0u));
+      c = dot(S.ns, es.dir);
+      need = c > 0.0f;
+    }
+    const uint64_t bal = __ballot(need);
+    if (need) {
+      const int64_t slot = rbase + running + lanes_below(bal);
+      RayRec R;
+      R.o[0] = S.x.x;
+      R.o[1] = S.x.y;
+      R.o[2] = S.x.z;
+      R.skip = f;
+      R.d[0] = es.dir.x;
+      R.d[1] = es.dir.y;
+      R.d[2] = es.dir.z;
+      R.tmin = p.tmin;
+      ws.rays[slot] = R;
       float fr[3];
       brdf_eval(S, es.dir, wo, c, p, fr);
       const float* e = E.env + 3 * (int64_t)es.texel;
       const float wgt = c * es.inv_pdf;
-      L[0] += e[0] * fr[0] * wgt;
-      L[1] += e[1] * fr[1] * wgt;
-      L[2] += e[2] * fr[2] * wgt;
+      ws.contrib[3 * slot] = e[0] * fr[0] * wgt;
+      ws.contrib[3 * slot + 1] = e[1] * fr[1] * wgt;
+      ws.contrib[3 * slot + 2] = e[2] * fr[2] * wgt;
+      mask |= 1ull << k;
     }
-    const float inv = p.N_d > 0 ? 1.0f / (float)p.N_d : 0.0f;
-    L[0] *= inv;
-    L[1] *= inv;
-    L[2] *= inv;
+    running += (uint32_t)__popcll(bal);
   }
-  L_dir[3 * gid] = L[0];
-  L_dir[3 * gid + 1] = L[1];
-  L_dir[3 * gid + 2] = L[2];
+  ws.mask[local] = mask;
+  const uint64_t covered = __ballot(f >= 0);
+  if (__lane_id() == 0) {
+    ws.count[region] = running;
+    if (COUNT) atomicAdd(counters + 3, (unsigned long long)__popcll(covered) * (unsigned long long)p.N_d);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_dir_finalize(ShadeViews V, KParams p, int64_t p0, int64_t P,
+                                                           DirectWs ws, float* __restrict__ L_dir,
+                                                           uint64_t* __restrict__ vis) {
+  const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if ((local & ~(int64_t)63) >= P) return;
+  const int64_t gid = p0 + local;
+  const bool valid = gid < (int64_t)V.H * V.W * V.n;
+  const uint64_t mask = ws.mask[local];
+  const bool novis = (p.flags & EXM_NO_VIS) != 0;
+  const int64_t rbase = (local >> 6) * 64 * (int64_t)p.N_d;
+  uint32_t running = 0;
+  float L[3] = {0.f, 0.f, 0.f};
+  uint64_t bits = 0;
+  for (int k = 0; k < p.N_d; ++k) {
+    const bool have = (mask >> k) & 1ull;
+    const uint64_t bal = __ballot(have);
+    if (have) {
+      const int64_t slot = rbase + running + lanes_below(bal);
+      if (novis || ws.hit[slot] == 0) {
+        bits |= 1ull << k;
+        L[0] += ws.contrib[3 * slot];
+        L[1] += ws.contrib[3 * slot + 1];
+        L[2] += ws.contrib[3 * slot + 2];
+      }
+    }
+    running += (uint32_t)__popcll(bal);
+  }
+  if (!valid) return;
+  const float inv = p.N_d > 0 ? 1.0f / (float)p.N_d : 0.0f;
+  L_dir[3 * gid] = L[0] * inv;
+  L_dir[3 * gid + 1] = L[1] * inv;
+  L_dir[3 * gid + 2] = L[2] * inv;
   vis[gid] = bits;
-  if (COUNT && f >= 0) {
-    atomicAdd(counters + 0, (unsigned long long)n_rays);
-    atomicAdd(counters + 1, (unsigned long long)tc.nodes);
-    atomicAdd(counters + 2, (unsigned long long)tc.tris);
-    atomicAdd(counters + 3, (unsigned long long)p.N_d);
-  }
 }
 
 // Accumulated adjoint of one surface point w.r.t. its material values and shading normal.
@@ -260,18 +317,36 @@ BvhView bvh_view(const exm_bvh* b) { return BvhView{b->nodes, b->tris, b->root_i
 
 hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                             const ShadeViews& v, const int32_t* tri_id, const float* bary, const exm_params* p,
-                            float* L_dir, uint64_t* vis, unsigned long long* counters, hipStream_t s) {
+                            float* L_dir, uint64_t* vis, void* ws_ptr, size_t ws_bytes, unsigned long long* counters,
+                            hipStream_t s) {
   const int64_t n = (int64_t)v.n * v.H * v.W;
-  const unsigned nb = (unsigned)((n + kThreads - 1) / kThreads);
+  const int64_t P = direct_chunk(ws_bytes, p->N_d, n);
+  if (P <= 0) return hipErrorInvalidValue;  // the ABI layer checks the size first
+  const KParams kp = kparams(p);
   const TexView tv{mat->Ht, mat->Wt, mat->tex};
-  if (counters)
-    k_shade_fwd<true><<<nb, kThreads, 0, s>>>(mesh_view(m), tv, env_view(env), bvh_view(bvh), v, tri_id, bary,
-                                              kparams(p), L_dir, vis, counters);
-  else
-    k_shade_fwd<false><<<nb, kThreads, 0, s>>>(mesh_view(m), tv, env_view(env), bvh_view(bvh), v, tri_id, bary,
-                                               kparams(p), L_dir, vis, nullptr);
+  const DirectWs ws = direct_ws(ws_ptr, P, p->N_d);
+  const bool trace = p->N_d > 0 && !(p->flags & EXM_NO_VIS);
+  for (int64_t p0 = 0; p0 < n; p0 += P) {
+    const int64_t Pc = std::min<int64_t>(P, ((n - p0) + 63) / 64 * 64);
+    const unsigned nb = (unsigned)((Pc + kThreads - 1) / kThreads);
+    if (counters)
+      k_dir_gen<true><<<nb, kThreads, 0, s>>>(mesh_view(m), tv, env_view(env), v, tri_id, bary, kp, p0, Pc, ws,
+                                             counters);
+    else
+      k_dir_gen<false><<<nb, kThreads, 0, s>>>(mesh_view(m), tv, env_view(env), v, tri_id, bary, kp, p0, Pc, ws,
+                                              nullptr);
+    if (trace) {
+      const RayBatch rb{ws.rays, ws.count, (int32_t)(Pc / 64), 64 * (int64_t)p->N_d, ws.counter};
+      const hipError_t e = launch_trace_any(bvh, rb, ws.hit, counters, s);
+      if (e != hipSuccess) return e;
+    }
+    k_dir_finalize<<<nb, kThreads, 0, s>>>(v, kp, p0, Pc, ws, L_dir, vis);
+  }
   return hipGetLastError();
 }
+
+size_t shade_fwd_ws_bytes(int64_t n_pix, int32_t N_d) { return direct_ws_bytes((n_pix + 63) / 64 * 64, N_d); }
+size_t shade_fwd_ws_min(int32_t N_d) { return direct_ws_bytes(64, N_d); }
 
 hipError_t launch_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const ShadeViews& v,
                             const int32_t* tri_id, const float* bary, const exm_params* p, const float* dI,

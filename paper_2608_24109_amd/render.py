@@ -34,11 +34,17 @@ class PassParams:
                         self.f_diel, self.eps, self.tmin, self.flags)
 
 
+# Upper bound of the ray workspace a pass allocates; larger passes run in pixel chunks.
+WORKSPACE_CAP = 4 << 30
+
+
 class PassBuffers:
-    """Per-view outputs of one forward pass (device tensors)."""
+    """Per-view outputs of one forward pass (device tensors) and its ray workspace."""
 
     def __init__(self, n: int, H: int, W: int, N_b: int, device="cuda", gbuffer: bool = True):
         self.n, self.H, self.W, self.N_b = n, H, W, N_b
+        self.device = device
+        self.ws = None
         self.tri_id = torch.empty((n, H, W), dtype=torch.int32, device=device) if gbuffer else None
         self.bary = torch.empty((n, H, W, 2), dtype=torch.float32, device=device) if gbuffer else None
         self.L_dir = torch.empty((n, H, W, 3), dtype=torch.float32, device=device)
@@ -46,6 +52,14 @@ class PassBuffers:
         self.L_ind = torch.empty((n, H, W, 3), dtype=torch.float32, device=device) if N_b > 0 else None
         self.sec_rec = torch.empty((n, H, W, max(N_b, 1), 3), dtype=torch.int32, device=device) if N_b > 0 else None
         self.sec_vis = torch.empty((n, H, W), dtype=torch.uint64, device=device) if N_b > 0 else None
+
+    def workspace(self, nbytes: int):
+        """The pass's ray workspace, grown to `nbytes` (capped at WORKSPACE_CAP) when needed."""
+        nbytes = min(int(nbytes), WORKSPACE_CAP)
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = None
+            self.ws = L.workspace(nbytes, self.device)
+        return self.ws
 
     def ensure_gbuffer(self, device="cuda"):
         if self.tri_id is None:
@@ -69,7 +83,9 @@ def render_forward(mesh: DeviceMesh, mat: DeviceMaterial, env: DeviceEnv, cams_c
         env.update(stream=stream)
     if do_raster:
         raster(mesh, cams_c, bufs, stream)
-    L.exm_shade_fwd(mesh.s, mesh.bvh, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, bufs.L_dir, bufs.vis,
+    ws = bufs.workspace(max(L.exm_shade_fwd_workspace_size(len(cams_c), bufs.H, bufs.W, p.N_d),
+                            L.exm_shade_fwd_workspace_min(p.N_d)))
+    L.exm_shade_fwd(mesh.s, mesh.bvh, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, bufs.L_dir, bufs.vis, ws,
                     stream)
     if p.N_b > 0:
         L.exm_trace_indirect(mesh.s, mesh.bvh, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, bufs.L_ind,
@@ -116,6 +132,7 @@ class RenderPBR(torch.autograd.Function):
             else:
                 o.copy_(bufs.L_dir)
             bufs.L_dir = bufs.L_ind = None
+            bufs.ws = None
             if checkpoint:
                 bufs.drop_gbuffer()
             chunks.append((cc, bufs))

@@ -76,7 +76,7 @@ def test_shade_validation(L):
     def call(p=None, **kw):
         a = dict(m=C.byref(m), bvh=bvh, mat=C.byref(mat), env=C.byref(env), cams=cams, n=1, tri=0x1000,
                  bary=0x1000, p=C.byref(p if p is not None else L.params(8)), L=0x1000, vis=0x1000,
-                 stream=None)
+                 ws=0x100000, ws_bytes=1 << 30, stream=None)
         a.update(kw)
         return _status(L, f, *a.values())
 
@@ -93,6 +93,18 @@ def test_shade_validation(L):
     unprep = L.exm_mesh(3, 1, 3, 0x1000, 0x1000, 0x1000, 0x1000, None, None)
     s, msg = call(m=C.byref(unprep))
     assert s == L.EXM_E_INVAL and "exm_mesh_prepare" in msg
+    s, msg = call(ws_bytes=L.exm_shade_fwd_workspace_min(8) - 1)
+    assert s == L.EXM_E_INVAL and "workspace" in msg
+    assert call(ws=0x100010)[0] == L.EXM_E_INVAL  # not 256-byte aligned
+    assert call(ws=None)[0] == L.EXM_E_INVAL
+
+
+def test_workspace_sizes(L):
+    assert L.exm_shade_fwd_workspace_min(64) < L.exm_shade_fwd_workspace_size(1, 128, 128, 64)
+    one = L.exm_shade_fwd_workspace_size(1, 1024, 1024, 64)
+    assert L.exm_shade_fwd_workspace_size(8, 1024, 1024, 64) > 7 * one
+    assert L.exm_shade_fwd_workspace_size(16, 1024, 1024, 64) == L.exm_shade_fwd_workspace_size(8, 1024, 1024, 64)
+    assert L.exm_shade_fwd_workspace_size(0, 8, 8, 8) == 0 and L.exm_shade_fwd_workspace_min(65) == 0
 
 
 def test_indirect_and_backward_validation(L):
