@@ -317,7 +317,9 @@ __device__ __forceinline__ Ray make_ray(f3 o, f3 d) {
   Ray r;
   r.o = o;
   r.d = d;
-  r.inv = mk(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
+  // hardware reciprocals (1 ulp): the slab test pads its interval by a few ulps, and the shear
+  // below only needs to be the same for every triangle a ray meets
+  r.inv = mk(__builtin_amdgcn_rcpf(d.x), __builtin_amdgcn_rcpf(d.y), __builtin_amdgcn_rcpf(d.z));
   const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
   r.kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
   r.kx = r.kz == 2 ? 0 : r.kz + 1;
@@ -328,9 +330,9 @@ __device__ __forceinline__ Ray make_ray(f3 o, f3 d) {
     r.ky = t;
   }
   const float dz = comp(d, r.kz);
-  r.Sx = comp(d, r.kx) / dz;
-  r.Sy = comp(d, r.ky) / dz;
-  r.Sz = 1.0f / dz;
+  r.Sz = __builtin_amdgcn_rcpf(dz);
+  r.Sx = comp(d, r.kx) * r.Sz;
+  r.Sy = comp(d, r.ky) * r.Sz;
   return r;
 }
 
@@ -356,7 +358,7 @@ __device__ __forceinline__ bool tri_hit(const Ray& r, const BvhTri& T, float tmi
   const float det = U + V + W;
   if (det == 0.0f) return false;
   const float Tn = U * (r.Sz * Az0) + V * (r.Sz * Bz0) + W * (r.Sz * Cz0);
-  const float inv = 1.0f / det;
+  const float inv = __builtin_amdgcn_rcpf(det);
   const float t = Tn * inv;
   if (!(t >= tmin && t <= tmax)) return false;
   *t_out = t;

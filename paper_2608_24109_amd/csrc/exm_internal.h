@@ -28,8 +28,8 @@ struct alignas(16) BvhTri {
 };
 static_assert(sizeof(BvhTri) == 48, "triangle layout");
 
-constexpr int kMaxDepth = 30;  // builder guarantee; traversal stack holds <= kMaxDepth refs
-constexpr int kStack = 32;
+constexpr int kMaxDepth = 24;  // builder guarantee; traversal stack holds <= kMaxDepth refs
+constexpr int kStack = 24;
 
 // Views per launch: camera data travels in kernel arguments.
 constexpr int kViewsPerLaunch = 8;

@@ -1,7 +1,7 @@
 """The host SAH builder's output satisfies what the device traversal relies on: a tree whose
 nodes are each reached once, every triangle in exactly one leaf, child boxes inside parent
-boxes and around their triangles, leaves of 1..15 triangles, depth <= 30 (the traversal
-stack holds 32 references)."""
+boxes and around their triangles, leaves of 1..15 triangles, depth <= 24 (the traversal
+stack holds 24 references)."""
 import ctypes as C
 import os
 import subprocess
@@ -54,7 +54,7 @@ def test_builder_invariants(checker, mesh):
         pos, tri = I.interlocking_tori(1000, 250)
     rc, st = run(checker, pos, tri)
     assert rc == 0, f"invariant {rc} broken; stats {st}"
-    assert st[1] <= 30 and st[2] <= 15
+    assert st[1] <= 24 and st[2] <= 15
     if mesh == "tori":
         assert st[0] < tri.shape[0]  # internal nodes
-        assert st[1] < 30
+        assert st[1] <= 24
