@@ -86,7 +86,8 @@ def run_gpu(workload: str, steps: int, warmup: int):
     dtex = torch.zeros_like(mat.tex)
     denv = torch.zeros(env.env.shape, dtype=torch.float64, device="cuda")
     lam = 1.0
-    ws_fwd = bufs.workspace(L.exm_shade_fwd_workspace_size(V, H, W, p.N_d))
+    ws_fwd = bufs.workspace(max(L.exm_shade_fwd_workspace_size(V, H, W, p.N_d),
+                                L.exm_trace_indirect_workspace_size(V, H, W, p.N_b, p.N_s) if p.N_b else 0))
     torch.cuda.synchronize()
 
     def step(tm):
@@ -96,7 +97,8 @@ def run_gpu(workload: str, steps: int, warmup: int):
                                                 bufs.L_dir, bufs.vis, ws_fwd))
         if p.N_b > 0:
             tm("trace_indirect", lambda: L.exm_trace_indirect(mesh.s, mesh.bvh, mat.s, env.s, cc, bufs.tri_id,
-                                                              bufs.bary, pc, bufs.L_ind, bufs.sec_rec, bufs.sec_vis))
+                                                              bufs.bary, pc, bufs.L_ind, bufs.sec_rec, bufs.sec_vis,
+                                                              ws_fwd))
             tm("compose", lambda: torch.add(bufs.L_dir, bufs.L_ind, alpha=lam))
         tm("zero_grads", lambda: (dtex.zero_(), denv.zero_()))
         tm("shade_bwd", lambda: L.exm_shade_bwd(mesh.s, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc, dI, bufs.vis,
@@ -124,7 +126,7 @@ def run_gpu(workload: str, steps: int, warmup: int):
     c_ind = torch.zeros(6, dtype=torch.uint64, device="cuda")
     if p.N_b > 0:
         L.exm_trace_indirect_counted(mesh.s, mesh.bvh, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc, bufs.L_ind,
-                                     bufs.sec_rec, bufs.sec_vis, c_ind)
+                                     bufs.sec_rec, bufs.sec_vis, ws_fwd, c_ind)
     torch.cuda.synchronize()
     cd = [int(x) for x in c_dir.cpu().numpy()]
     ci = [int(x) for x in c_ind.cpu().numpy()]

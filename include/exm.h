@@ -155,12 +155,16 @@ exm_status exm_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_materi
                          float* L_dir, uint64_t* vis, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* One-bounce diffuse indirect, Eq. 18-19: L_ind [nViews,H,W,3] (overwritten), sec_rec
- * [nViews,H,W,N_b], sec_vis [nViews,H,W] u64 (bit j*N_s+s). */
+ * [nViews,H,W,N_b], sec_vis [nViews,H,W] u64 (bit j*N_s+s). ws: ray workspace as for
+ * exm_shade_fwd, sized by exm_trace_indirect_workspace_size / _min. */
+size_t exm_trace_indirect_workspace_size(int32_t nViews, int32_t H, int32_t W, int32_t N_b,
+                                         int32_t N_s);
+size_t exm_trace_indirect_workspace_min(int32_t N_b, int32_t N_s);
 exm_status exm_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat,
                               const exm_env* env, const exm_camera* cams_host, int32_t nViews,
                               const int32_t* tri_id, const float* bary, const exm_params* p,
-                              float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis,
-                              hipStream_t stream);
+                              float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis, void* ws,
+                              size_t ws_bytes, hipStream_t stream);
 
 /* Measurement variants: the same work and outputs as exm_shade_fwd / exm_trace_indirect, plus
  * work counts accumulated (+=) into the caller's device array `counters` (u64):
@@ -178,8 +182,8 @@ exm_status exm_shade_fwd_counted(const exm_mesh* m, const exm_bvh* bvh, const ex
 exm_status exm_trace_indirect_counted(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat,
                                       const exm_env* env, const exm_camera* cams_host, int32_t nViews,
                                       const int32_t* tri_id, const float* bary, const exm_params* p,
-                                      float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis,
-                                      uint64_t* counters, hipStream_t stream);
+                                      float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis, void* ws,
+                                      size_t ws_bytes, uint64_t* counters, hipStream_t stream);
 
 /* Adjoint of the direct pass for upstream dI [nViews,H,W,3]: dtex [Ht,Wt,8] += d/dtex,
  * denv [He,We,3] += d/dE (double). Discrete choices (ids, texel picks, vis bits) and the

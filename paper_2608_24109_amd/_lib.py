@@ -77,9 +77,12 @@ def _load() -> C.CDLL:
         "exm_shade_fwd_workspace_size": (C.c_size_t, [i32, i32, i32, i32]),
         "exm_shade_fwd_workspace_min": (C.c_size_t, [i32]),
         "exm_shade_fwd": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
-        "exm_trace_indirect": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]),
+        "exm_trace_indirect_workspace_size": (C.c_size_t, [i32, i32, i32, i32, i32]),
+        "exm_trace_indirect_workspace_min": (C.c_size_t, [i32, i32]),
+        "exm_trace_indirect": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
         "exm_shade_fwd_counted": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp, vp]),
-        "exm_trace_indirect_counted": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "exm_trace_indirect_counted": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp,
+                                            vp]),
         "exm_shade_bwd": (st, [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
         "exm_trace_bwd": (st, [vp, vp, vp, vp, i32, vp, vp, vp, C.c_float, vp, vp, vp, vp, vp, vp]),
     }
@@ -226,7 +229,15 @@ def exm_shade_fwd(mesh, bvh: Bvh, mat: exm_material, env: exm_env, cams, tri_id,
            "exm_shade_fwd")
 
 
-def exm_trace_indirect(mesh, bvh: Bvh, mat, env, cams, tri_id, bary, p: exm_params, L_ind, sec_rec, sec_vis,
+def exm_trace_indirect_workspace_size(nViews: int, H: int, W: int, N_b: int, N_s: int) -> int:
+    return int(lib.exm_trace_indirect_workspace_size(nViews, H, W, N_b, N_s))
+
+
+def exm_trace_indirect_workspace_min(N_b: int, N_s: int) -> int:
+    return int(lib.exm_trace_indirect_workspace_min(N_b, N_s))
+
+
+def exm_trace_indirect(mesh, bvh: Bvh, mat, env, cams, tri_id, bary, p: exm_params, L_ind, sec_rec, sec_vis, ws,
                        stream=None) -> None:
     import torch
     n, H, W = len(cams), cams[0].H, cams[0].W
@@ -234,8 +245,8 @@ def exm_trace_indirect(mesh, bvh: Bvh, mat, env, cams, tri_id, bary, p: exm_para
     _need(sec_rec, torch.int32, (n, H, W, max(p.N_b, 1), 3), "sec_rec")
     _need(sec_vis, torch.uint64, (n, H, W), "sec_vis")
     _check(lib.exm_trace_indirect(C.byref(mesh), bvh.handle, C.byref(mat), C.byref(env), cams, n, _ptr(tri_id),
-                                  _ptr(bary), C.byref(p), _ptr(L_ind), _ptr(sec_rec), _ptr(sec_vis),
-                                  _stream(stream)), "exm_trace_indirect")
+                                  _ptr(bary), C.byref(p), _ptr(L_ind), _ptr(sec_rec), _ptr(sec_vis), _ptr(ws),
+                                  ws.numel(), _stream(stream)), "exm_trace_indirect")
 
 
 def exm_shade_fwd_counted(mesh, bvh: Bvh, mat, env, cams, tri_id, bary, p: exm_params, L_dir, vis, ws, counters,
@@ -248,12 +259,12 @@ def exm_shade_fwd_counted(mesh, bvh: Bvh, mat, env, cams, tri_id, bary, p: exm_p
 
 
 def exm_trace_indirect_counted(mesh, bvh: Bvh, mat, env, cams, tri_id, bary, p: exm_params, L_ind, sec_rec,
-                               sec_vis, counters, stream=None) -> None:
+                               sec_vis, ws, counters, stream=None) -> None:
     import torch
     _need(counters, torch.uint64, (6,), "counters")
     _check(lib.exm_trace_indirect_counted(C.byref(mesh), bvh.handle, C.byref(mat), C.byref(env), cams, len(cams),
                                           _ptr(tri_id), _ptr(bary), C.byref(p), _ptr(L_ind), _ptr(sec_rec),
-                                          _ptr(sec_vis), _ptr(counters), _stream(stream)),
+                                          _ptr(sec_vis), _ptr(ws), ws.numel(), _ptr(counters), _stream(stream)),
            "exm_trace_indirect_counted")
 
 

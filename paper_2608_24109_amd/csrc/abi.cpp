@@ -270,8 +270,8 @@ static exm_status shade_fwd_impl(const exm_mesh* m, const exm_bvh* bvh, const ex
 static exm_status trace_indirect_impl(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat,
                                       const exm_env* env, const exm_camera* cams, int32_t nViews,
                                       const int32_t* tri_id, const float* bary, const exm_params* p, float* L_ind,
-                                      exm_sec_rec* sec_rec, uint64_t* sec_vis, uint64_t* counters,
-                                      hipStream_t stream) {
+                                      exm_sec_rec* sec_rec, uint64_t* sec_vis, void* ws, size_t ws_bytes,
+                                      uint64_t* counters, hipStream_t stream) {
   EXM_TRY(check_mesh(m, true));
   if (!bvh) return fail(EXM_E_INVAL, "bvh is NULL");
   EXM_TRY(check_material(mat));
@@ -280,14 +280,16 @@ static exm_status trace_indirect_impl(const exm_mesh* m, const exm_bvh* bvh, con
   EXM_TRY(check_gbuffer(tri_id, bary));
   EXM_TRY(check_params(p, true));
   if (!L_ind || !sec_vis || (!sec_rec && p->N_b > 0)) return fail(EXM_E_INVAL, "output pointer is NULL");
+  if (!ws || !aligned(ws, 256) || ws_bytes < trace_indirect_ws_min(p->N_b, p->N_s))
+    return fail(EXM_E_INVAL, "workspace must be 256-byte aligned and at least exm_trace_indirect_workspace_min bytes");
   EXM_TRY(check_device());
   const int64_t HW = (int64_t)cams[0].H * cams[0].W;
   for (int32_t v0 = 0; v0 < nViews; v0 += kViewsPerLaunch) {
     const int32_t n = std::min(kViewsPerLaunch, nViews - v0);
     hipError_t e = launch_trace_indirect(m, bvh, mat, env, shade_views(cams, v0, n), tri_id + v0 * HW,
                                          bary + 2 * v0 * HW, p, L_ind + 3 * v0 * HW,
-                                         sec_rec ? sec_rec + v0 * HW * p->N_b : nullptr, sec_vis + v0 * HW,
-                                         reinterpret_cast<unsigned long long*>(counters), stream);
+                                         sec_rec ? sec_rec + v0 * HW * p->N_b : nullptr, sec_vis + v0 * HW, ws,
+                                         ws_bytes, reinterpret_cast<unsigned long long*>(counters), stream);
     if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_trace_indirect: ") + hipGetErrorString(e));
   }
   return EXM_OK;
@@ -315,22 +317,32 @@ exm_status exm_shade_fwd_counted(const exm_mesh* m, const exm_bvh* bvh, const ex
   return shade_fwd_impl(m, bvh, mat, env, cams, nViews, tri_id, bary, p, L_dir, vis, ws, ws_bytes, counters, stream);
 }
 
+size_t exm_trace_indirect_workspace_size(int32_t nViews, int32_t H, int32_t W, int32_t N_b, int32_t N_s) {
+  if (nViews <= 0 || H <= 0 || W <= 0 || N_b < 0 || N_s < 0 || (int64_t)N_b * N_s > 64 || N_b > 64) return 0;
+  return trace_indirect_ws_bytes((int64_t)std::min(nViews, kViewsPerLaunch) * H * W, N_b, N_s);
+}
+
+size_t exm_trace_indirect_workspace_min(int32_t N_b, int32_t N_s) {
+  if (N_b < 0 || N_s < 0 || (int64_t)N_b * N_s > 64 || N_b > 64) return 0;
+  return trace_indirect_ws_min(N_b, N_s);
+}
+
 exm_status exm_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                               const exm_camera* cams, int32_t nViews, const int32_t* tri_id, const float* bary,
-                              const exm_params* p, float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis,
-                              hipStream_t stream) {
-  return trace_indirect_impl(m, bvh, mat, env, cams, nViews, tri_id, bary, p, L_ind, sec_rec, sec_vis, nullptr,
-                             stream);
+                              const exm_params* p, float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis, void* ws,
+                              size_t ws_bytes, hipStream_t stream) {
+  return trace_indirect_impl(m, bvh, mat, env, cams, nViews, tri_id, bary, p, L_ind, sec_rec, sec_vis, ws, ws_bytes,
+                             nullptr, stream);
 }
 
 exm_status exm_trace_indirect_counted(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat,
                                       const exm_env* env, const exm_camera* cams, int32_t nViews,
                                       const int32_t* tri_id, const float* bary, const exm_params* p, float* L_ind,
-                                      exm_sec_rec* sec_rec, uint64_t* sec_vis, uint64_t* counters,
-                                      hipStream_t stream) {
+                                      exm_sec_rec* sec_rec, uint64_t* sec_vis, void* ws, size_t ws_bytes,
+                                      uint64_t* counters, hipStream_t stream) {
   if (!counters || !aligned(counters, 8)) return fail(EXM_E_INVAL, "counters must be an 8-byte aligned device array");
-  return trace_indirect_impl(m, bvh, mat, env, cams, nViews, tri_id, bary, p, L_ind, sec_rec, sec_vis, counters,
-                             stream);
+  return trace_indirect_impl(m, bvh, mat, env, cams, nViews, tri_id, bary, p, L_ind, sec_rec, sec_vis, ws, ws_bytes,
+                             counters, stream);
 }
 
 exm_status exm_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const exm_camera* cams,

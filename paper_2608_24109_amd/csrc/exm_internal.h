@@ -78,8 +78,10 @@ hipError_t launch_shade_bwd(const exm_mesh* m, const exm_material* mat, const ex
                             const uint64_t* vis, float* dtex, double* denv, hipStream_t s);
 hipError_t launch_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                                  const ShadeViews& v, const int32_t* tri_id, const float* bary, const exm_params* p,
-                                 float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis, unsigned long long* counters,
-                                 hipStream_t s);
+                                 float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis, void* ws, size_t ws_bytes,
+                                 unsigned long long* counters, hipStream_t s);
+size_t trace_indirect_ws_bytes(int64_t n_pix, int32_t N_b, int32_t N_s);
+size_t trace_indirect_ws_min(int32_t N_b, int32_t N_s);
 hipError_t launch_trace_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const ShadeViews& v,
                             const int32_t* tri_id, const float* bary, const exm_params* p, float lambda_ind,
                             const float* dI, const exm_sec_rec* sec_rec, const uint64_t* sec_vis, float* dtex,

@@ -85,4 +85,61 @@ inline int64_t direct_chunk(size_t ws_bytes, int32_t N_d, int64_t max_px) {
   return lo * 64;
 }
 
+// Indirect pass over a chunk of P pixels (P a multiple of 64): secondary rays (N_b per pixel)
+// with their closest hits, then the light samples of valid hits (N_b * N_s per pixel) with
+// their shadow rays, contributions and hits.
+struct IndirectWs {
+  uint32_t* counter;
+  uint32_t* sec_count;
+  RayRec* sec_rays;
+  HitRec* sec_hits;
+  uint32_t* sh_count;
+  uint64_t* sh_mask;
+  RayRec* sh_rays;
+  float* sh_contrib;
+  uint8_t* sh_hit;
+};
+
+inline size_t indirect_ws_bytes(int64_t P, int32_t N_b, int32_t N_s) {
+  const int64_t s1 = P * (int64_t)(N_b > 0 ? N_b : 1), s2 = s1 * (N_s > 0 ? N_s : 1);
+  return 256 + 2 * align256((size_t)(P / 64) * 4) + align256((size_t)s1 * 32) + align256((size_t)s1 * 16) +
+         align256((size_t)P * 8) + align256((size_t)s2 * 32) + align256((size_t)s2 * 12) + align256((size_t)s2);
+}
+
+inline IndirectWs indirect_ws(void* ws, int64_t P, int32_t N_b, int32_t N_s) {
+  const int64_t s1 = P * (int64_t)(N_b > 0 ? N_b : 1), s2 = s1 * (N_s > 0 ? N_s : 1);
+  char* q = static_cast<char*>(ws);
+  IndirectWs w;
+  w.counter = reinterpret_cast<uint32_t*>(q);
+  q += 256;
+  w.sec_count = reinterpret_cast<uint32_t*>(q);
+  q += align256((size_t)(P / 64) * 4);
+  w.sh_count = reinterpret_cast<uint32_t*>(q);
+  q += align256((size_t)(P / 64) * 4);
+  w.sec_rays = reinterpret_cast<RayRec*>(q);
+  q += align256((size_t)s1 * 32);
+  w.sec_hits = reinterpret_cast<HitRec*>(q);
+  q += align256((size_t)s1 * 16);
+  w.sh_mask = reinterpret_cast<uint64_t*>(q);
+  q += align256((size_t)P * 8);
+  w.sh_rays = reinterpret_cast<RayRec*>(q);
+  q += align256((size_t)s2 * 32);
+  w.sh_contrib = reinterpret_cast<float*>(q);
+  q += align256((size_t)s2 * 12);
+  w.sh_hit = reinterpret_cast<uint8_t*>(q);
+  return w;
+}
+
+inline int64_t indirect_chunk(size_t ws_bytes, int32_t N_b, int32_t N_s, int64_t max_px) {
+  int64_t lo = 0, hi = (max_px + 63) / 64;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (indirect_ws_bytes(mid * 64, N_b, N_s) <= ws_bytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo * 64;
+}
+
 }  // namespace exm

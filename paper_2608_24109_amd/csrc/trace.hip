@@ -7,13 +7,21 @@
 // At a valid hit y: the same attribute query as for primary points, then N_s env samples with
 // shadow rays give the diffuse radiance L_sec(y) (Eq. 18, no specular term). Eq. 19 sums
 // 1_hit f_d(x) L_sec(y_j) max(n_s(x) . w_j, 0) / p_b over j and divides by N_b.
+// It runs per chunk of pixels as gen1 (secondary rays) -> closest-hit trace -> gen2 (hit
+// validity, FP64 refinement, query at y, light samples with their shadow rays and their whole
+// contribution f_d(x) f_d(y) E c / pdf * (n_s(x).w / p_b) / (N_b N_s)) -> any-hit trace ->
+// finalize (sum of the unoccluded contributions in (j, s) order). Ray slots come from wave
+// ballots as in the direct pass.
 // The hit records and the light-sample visibility bits are stored for the adjoint.
 //
 // Adjoint, for upstream G = lambda_ind dLoss/dI: gradients to a, m, n_s at x (through f_d(x)
 // and the cosine) and at each y_j (through f_d(y) and n_s(y)), and to E at the light samples.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "exm_device.h"
+#include "exm_rays.h"
 
 namespace exm {
 
@@ -106,92 +114,169 @@ __device__ __forceinline__ bool front_facing(const MeshView& M, int32_t f, f3 w)
   return dot(w, cross(P1 - P0, P2 - P0)) < 0.0f;
 }
 
-// COUNT: measurement variant that also accumulates [secondary rays, their node visits, their
-// triangle tests, light shadow rays, their node visits, their triangle tests] into counters
-template <bool COUNT>
-__global__ __launch_bounds__(kThreads) void k_trace_indirect(MeshView M, TexView T, EnvView E, BvhView B,
-                                                             ShadeViews V, const int32_t* __restrict__ tri_id,
-                                                             const float* __restrict__ bary, KParams p,
-                                                             float* __restrict__ L_ind, exm_sec_rec* __restrict__ rec,
-                                                             uint64_t* __restrict__ sec_vis,
-                                                             unsigned long long* __restrict__ counters) {
-  __shared__ int32_t stack[kStack * kThreads];
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return (uint32_t)__popcll(mask & ((1ull << __lane_id()) - 1ull));
+}
+
+__global__ __launch_bounds__(kThreads) void k_ind_gen1(MeshView M, ShadeViews V, const int32_t* __restrict__ tri_id,
+                                                       const float* __restrict__ bary, KParams p, int64_t p0,
+                                                       int64_t P, IndirectWs ws) {
+  const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if ((local & ~(int64_t)63) >= P) return;  // whole waves only
   const int64_t HW = (int64_t)V.H * V.W;
-  const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (gid >= HW * V.n) return;
-  const int32_t view = (int32_t)(gid / HW);
-  const uint32_t pix = (uint32_t)(gid - view * HW);
-  const int32_t f = tri_id[gid];
-  float L[3] = {0.f, 0.f, 0.f};
-  uint64_t bits = 0;
-  exm_sec_rec* myrec = rec + gid * p.N_b;
-  TraceCount tc_sec, tc_sh;
-  uint32_t n_sh = 0;
+  const int64_t gid = p0 + local;
+  const int32_t f = gid < HW * V.n ? tri_id[gid] : -1;
+  const int64_t region = local >> 6;
+  const int64_t rbase = region * 64 * (int64_t)p.N_b;
+  const uint64_t bal = __ballot(f >= 0);
+  const uint32_t below = lanes_below(bal), n_cov = (uint32_t)__popcll(bal);
   if (f >= 0) {
+    const int32_t view = (int32_t)(gid / HW);
+    const uint32_t pix = (uint32_t)(gid - view * HW), vid = (uint32_t)V.view_id[view];
     const float2 b = reinterpret_cast<const float2*>(bary)[gid];
-    const Surf S = query(M, T, f, b.x, b.y, p.flags);
-    const uint32_t vid = (uint32_t)V.view_id[view];
-    const bool diff = !(p.flags & EXM_SPECULAR_ONLY);
-    const float kdx = diff ? (1.0f - S.m) * kInvPi : 0.0f;
-    const float invNs = p.N_s > 0 ? 1.0f / (float)p.N_s : 0.0f;
     for (int j = 0; j < p.N_b; ++j) {
-      exm_sec_rec r{-1, 0.f, 0.f};
       const Draw d = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)j, 1u);
       const SecRay sr = secondary_ray(M, f, b.x, b.y, d.u2, d.u3);
-      const f3 w = sr.df;
-      const float pb = sr.pb;
-      HitRec h = trace<false, COUNT>(B, make_ray(sr.of, w), p.tmin, f, stack + threadIdx.x, kThreads, &tc_sec);
-      if (h.id >= 0 && front_facing(M, h.id, w)) {
+      RayRec R;
+      R.o[0] = sr.of.x;
+      R.o[1] = sr.of.y;
+      R.o[2] = sr.of.z;
+      R.skip = f;
+      R.d[0] = sr.df.x;
+      R.d[1] = sr.df.y;
+      R.d[2] = sr.df.z;
+      R.tmin = p.tmin;
+      ws.sec_rays[rbase + (int64_t)j * n_cov + below] = R;
+    }
+  }
+  if (__lane_id() == 0) ws.sec_count[region] = n_cov * (uint32_t)p.N_b;
+}
+
+__global__ __launch_bounds__(kThreads) void k_ind_gen2(MeshView M, TexView T, EnvView E, ShadeViews V,
+                                                       const int32_t* __restrict__ tri_id,
+                                                       const float* __restrict__ bary, KParams p, int64_t p0,
+                                                       int64_t P, IndirectWs ws, exm_sec_rec* __restrict__ rec) {
+  const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if ((local & ~(int64_t)63) >= P) return;
+  const int64_t HW = (int64_t)V.H * V.W;
+  const int64_t gid = p0 + local;
+  const bool in_range = gid < HW * V.n;
+  const int32_t f = in_range ? tri_id[gid] : -1;
+  const int64_t region = local >> 6;
+  const int64_t rbase1 = region * 64 * (int64_t)p.N_b;
+  const int64_t rbase2 = rbase1 * (int64_t)p.N_s;
+  const uint64_t bal1 = __ballot(f >= 0);
+  const uint32_t below1 = lanes_below(bal1), n_cov = (uint32_t)__popcll(bal1);
+  const bool diff = !(p.flags & EXM_SPECULAR_ONLY);
+  const float invNbNs = (p.N_b > 0 && p.N_s > 0) ? 1.0f / ((float)p.N_b * (float)p.N_s) : 0.0f;
+  Surf S;
+  float2 b = make_float2(0.f, 0.f);
+  uint32_t pix = 0, vid = 0;
+  float kdx = 0.0f;
+  if (f >= 0) {
+    const int32_t view = (int32_t)(gid / HW);
+    pix = (uint32_t)(gid - view * HW);
+    vid = (uint32_t)V.view_id[view];
+    b = reinterpret_cast<const float2*>(bary)[gid];
+    S = query(M, T, f, b.x, b.y, p.flags);
+    kdx = diff ? (1.0f - S.m) * kInvPi : 0.0f;
+  }
+  uint64_t mask = 0;
+  uint32_t running = 0;
+  for (int j = 0; j < p.N_b; ++j) {
+    bool valid = false;
+    Surf Y;
+    int32_t hid = -1;
+    float fac[3] = {0.f, 0.f, 0.f};
+    exm_sec_rec r{-1, 0.f, 0.f};
+    if (f >= 0) {
+      HitRec h = ws.sec_hits[rbase1 + (int64_t)j * n_cov + below1];
+      const Draw d = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)j, 1u);
+      const SecRay sr = secondary_ray(M, f, b.x, b.y, d.u2, d.u3);
+      if (h.id >= 0 && front_facing(M, h.id, sr.df)) {
         refine_hit(M, h.id, sr, &h.b1, &h.b2);
         r = exm_sec_rec{h.id, h.b1, h.b2};
-        const Surf Y = query(M, T, h.id, h.b1, h.b2, p.flags);
+        hid = h.id;
+        Y = query(M, T, h.id, h.b1, h.b2, p.flags);
         const float kdy = diff ? (1.0f - Y.m) * kInvPi : 0.0f;
-        float Ls[3] = {0.f, 0.f, 0.f};
-        for (int s = 0; s < p.N_s; ++s) {
-          const Draw ds = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s, 2u + (uint32_t)j);
-          const EnvSample es = env_sample(E, ds);
-          const float c = dot(Y.ns, es.dir);
-          if (!(c > 0.0f)) continue;
-          if (!(p.flags & EXM_NO_VIS)) {
-            if (COUNT) ++n_sh;
-            const HitRec hs =
-                trace<true, COUNT>(B, make_ray(Y.x, es.dir), p.tmin, h.id, stack + threadIdx.x, kThreads, &tc_sh);
-            if (hs.id >= 0) continue;
-          }
-          bits |= 1ull << (j * p.N_s + s);
-          const float* e = E.env + 3 * (int64_t)es.texel;
-          const float wgt = c * es.inv_pdf;
-          Ls[0] += e[0] * wgt;
-          Ls[1] += e[1] * wgt;
-          Ls[2] += e[2] * wgt;
-        }
-        const float cx = fmaxf(dot(S.ns, w), 0.0f);
-        const float fac = cx / pb * invNs;
-        L[0] += kdx * S.a[0] * (kdy * Y.a[0] * Ls[0]) * fac;
-        L[1] += kdx * S.a[1] * (kdy * Y.a[1] * Ls[1]) * fac;
-        L[2] += kdx * S.a[2] * (kdy * Y.a[2] * Ls[2]) * fac;
+        const float cx = fmaxf(dot(S.ns, sr.df), 0.0f);
+        const float w = cx / sr.pb * invNbNs;
+        fac[0] = kdx * S.a[0] * (kdy * Y.a[0]) * w;
+        fac[1] = kdx * S.a[1] * (kdy * Y.a[1]) * w;
+        fac[2] = kdx * S.a[2] * (kdy * Y.a[2]) * w;
+        valid = true;
       }
-      myrec[j] = r;
     }
-    const float inv = p.N_b > 0 ? 1.0f / (float)p.N_b : 0.0f;
-    L[0] *= inv;
-    L[1] *= inv;
-    L[2] *= inv;
-  } else {
-    for (int j = 0; j < p.N_b; ++j) myrec[j] = exm_sec_rec{-1, 0.f, 0.f};
+    if (in_range) rec[gid * p.N_b + j] = r;
+    for (int s2 = 0; s2 < p.N_s; ++s2) {
+      bool need = false;
+      EnvSample es;
+      float c = 0.0f;
+      if (valid) {
+        es = env_sample(E, philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s2, 2u + (uint32_t)j));
+        c = dot(Y.ns, es.dir);
+        need = c > 0.0f;
+      }
+      const uint64_t bal = __ballot(need);
+      if (need) {
+        const int64_t slot = rbase2 + running + lanes_below(bal);
+        RayRec R;
+        R.o[0] = Y.x.x;
+        R.o[1] = Y.x.y;
+        R.o[2] = Y.x.z;
+        R.skip = hid;
+        R.d[0] = es.dir.x;
+        R.d[1] = es.dir.y;
+        R.d[2] = es.dir.z;
+        R.tmin = p.tmin;
+        ws.sh_rays[slot] = R;
+        const float* e = E.env + 3 * (int64_t)es.texel;
+        const float wgt = c * es.inv_pdf;
+        ws.sh_contrib[3 * slot] = fac[0] * e[0] * wgt;
+        ws.sh_contrib[3 * slot + 1] = fac[1] * e[1] * wgt;
+        ws.sh_contrib[3 * slot + 2] = fac[2] * e[2] * wgt;
+        mask |= 1ull << (j * p.N_s + s2);
+      }
+      running += (uint32_t)__popcll(bal);
+    }
   }
+  ws.sh_mask[local] = mask;
+  if (__lane_id() == 0) ws.sh_count[region] = running;
+}
+
+__global__ __launch_bounds__(kThreads) void k_ind_finalize(ShadeViews V, KParams p, int64_t p0, int64_t P,
+                                                           IndirectWs ws, float* __restrict__ L_ind,
+                                                           uint64_t* __restrict__ sec_vis) {
+  const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if ((local & ~(int64_t)63) >= P) return;
+  const int64_t gid = p0 + local;
+  const bool valid = gid < (int64_t)V.H * V.W * V.n;
+  const uint64_t mask = ws.sh_mask[local];
+  const bool novis = (p.flags & EXM_NO_VIS) != 0;
+  const int64_t rbase = (local >> 6) * 64 * (int64_t)p.N_b * p.N_s;
+  const int n_slots = p.N_b * p.N_s;
+  uint32_t running = 0;
+  float L[3] = {0.f, 0.f, 0.f};
+  uint64_t bits = 0;
+  for (int t = 0; t < n_slots; ++t) {
+    const bool have = (mask >> t) & 1ull;
+    const uint64_t bal = __ballot(have);
+    if (have) {
+      const int64_t slot = rbase + running + lanes_below(bal);
+      if (novis || ws.sh_hit[slot] == 0) {
+        bits |= 1ull << t;
+        L[0] += ws.sh_contrib[3 * slot];
+        L[1] += ws.sh_contrib[3 * slot + 1];
+        L[2] += ws.sh_contrib[3 * slot + 2];
+      }
+    }
+    running += (uint32_t)__popcll(bal);
+  }
+  if (!valid) return;
   L_ind[3 * gid] = L[0];
   L_ind[3 * gid + 1] = L[1];
   L_ind[3 * gid + 2] = L[2];
   sec_vis[gid] = bits;
-  if (COUNT && f >= 0) {
-    atomicAdd(counters + 0, (unsigned long long)p.N_b);
-    atomicAdd(counters + 1, (unsigned long long)tc_sec.nodes);
-    atomicAdd(counters + 2, (unsigned long long)tc_sec.tris);
-    atomicAdd(counters + 3, (unsigned long long)n_sh);
-    atomicAdd(counters + 4, (unsigned long long)tc_sh.nodes);
-    atomicAdd(counters + 5, (unsigned long long)tc_sh.tris);
-  }
 }
 
 __device__ __forceinline__ void scatter7(const Surf& S, const float ga[3], float gm, const float gq[3],
@@ -332,19 +417,40 @@ KParams kparams(const exm_params* p) {
 
 hipError_t launch_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                                  const ShadeViews& v, const int32_t* tri_id, const float* bary, const exm_params* p,
-                                 float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis, unsigned long long* counters,
-                                 hipStream_t s) {
+                                 float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis, void* ws_ptr, size_t ws_bytes,
+                                 unsigned long long* counters, hipStream_t s) {
   const int64_t n = (int64_t)v.n * v.H * v.W;
-  const unsigned nb = (unsigned)((n + kThreads - 1) / kThreads);
+  const int64_t P = indirect_chunk(ws_bytes, p->N_b, p->N_s, n);
+  if (P <= 0) return hipErrorInvalidValue;  // the ABI layer checks the size first
+  const KParams kp = kparams(p);
   const TexView tv{mat->Ht, mat->Wt, mat->tex};
-  if (counters)
-    k_trace_indirect<true><<<nb, kThreads, 0, s>>>(mesh_view(m), tv, env_view(env), bvh_view(bvh), v, tri_id, bary,
-                                                   kparams(p), L_ind, sec_rec, sec_vis, counters);
-  else
-    k_trace_indirect<false><<<nb, kThreads, 0, s>>>(mesh_view(m), tv, env_view(env), bvh_view(bvh), v, tri_id, bary,
-                                                    kparams(p), L_ind, sec_rec, sec_vis, nullptr);
+  const IndirectWs ws = indirect_ws(ws_ptr, P, p->N_b, p->N_s);
+  const bool vis_rays = !(p->flags & EXM_NO_VIS) && p->N_s > 0;
+  for (int64_t p0 = 0; p0 < n; p0 += P) {
+    const int64_t Pc = std::min<int64_t>(P, ((n - p0) + 63) / 64 * 64);
+    const unsigned nb = (unsigned)((Pc + kThreads - 1) / kThreads);
+    if (p->N_b > 0) {
+      k_ind_gen1<<<nb, kThreads, 0, s>>>(mesh_view(m), v, tri_id, bary, kp, p0, Pc, ws);
+      const RayBatch rb1{ws.sec_rays, ws.sec_count, (int32_t)(Pc / 64), 64 * (int64_t)p->N_b, ws.counter};
+      hipError_t e = launch_trace_closest(bvh, rb1, ws.sec_hits, counters, s);
+      if (e != hipSuccess) return e;
+    }
+    k_ind_gen2<<<nb, kThreads, 0, s>>>(mesh_view(m), tv, env_view(env), v, tri_id, bary, kp, p0, Pc, ws,
+                                       sec_rec);
+    if (vis_rays && p->N_b > 0) {
+      const RayBatch rb2{ws.sh_rays, ws.sh_count, (int32_t)(Pc / 64), 64 * (int64_t)p->N_b * p->N_s, ws.counter};
+      hipError_t e = launch_trace_any(bvh, rb2, ws.sh_hit, counters ? counters + 3 : nullptr, s);
+      if (e != hipSuccess) return e;
+    }
+    k_ind_finalize<<<nb, kThreads, 0, s>>>(v, kp, p0, Pc, ws, L_ind, sec_vis);
+  }
   return hipGetLastError();
 }
+
+size_t trace_indirect_ws_bytes(int64_t n_pix, int32_t N_b, int32_t N_s) {
+  return indirect_ws_bytes((n_pix + 63) / 64 * 64, N_b, N_s);
+}
+size_t trace_indirect_ws_min(int32_t N_b, int32_t N_s) { return indirect_ws_bytes(64, N_b, N_s); }
 
 hipError_t launch_trace_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const ShadeViews& v,
                             const int32_t* tri_id, const float* bary, const exm_params* p, float lambda_ind,

@@ -88,8 +88,10 @@ def render_forward(mesh: DeviceMesh, mat: DeviceMaterial, env: DeviceEnv, cams_c
     L.exm_shade_fwd(mesh.s, mesh.bvh, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, bufs.L_dir, bufs.vis, ws,
                     stream)
     if p.N_b > 0:
+        ws = bufs.workspace(max(L.exm_trace_indirect_workspace_size(len(cams_c), bufs.H, bufs.W, p.N_b, p.N_s),
+                                L.exm_trace_indirect_workspace_min(p.N_b, p.N_s)))
         L.exm_trace_indirect(mesh.s, mesh.bvh, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, bufs.L_ind,
-                             bufs.sec_rec, bufs.sec_vis, stream)
+                             bufs.sec_rec, bufs.sec_vis, ws, stream)
 
 
 def render_backward(mesh: DeviceMesh, mat: DeviceMaterial, env: DeviceEnv, cams_c, p: PassParams,

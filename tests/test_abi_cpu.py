@@ -114,8 +114,13 @@ def test_indirect_and_backward_validation(L):
     env = L.exm_env(4, 8, 0x1000, 0x1000, 0x1000, 0x1000)
     p = L.params(8, N_b=16, N_s=8)  # 128 light-sample bits do not fit one u64
     s = L.lib.exm_trace_indirect(C.byref(m), 0x2000, C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000,
-                                 C.byref(p), 0x1000, 0x1000, 0x1000, None)
+                                 C.byref(p), 0x1000, 0x1000, 0x1000, 0x100000, 1 << 30, None)
     assert s == L.EXM_E_INVAL
+    p = L.params(8, N_b=4, N_s=4)
+    small = L.exm_trace_indirect_workspace_min(4, 4) - 1
+    s = L.lib.exm_trace_indirect(C.byref(m), 0x2000, C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000,
+                                 C.byref(p), 0x1000, 0x1000, 0x1000, 0x100000, small, None)
+    assert s == L.EXM_E_INVAL and "workspace" in L.last_error()
     p = L.params(8, N_b=4, N_s=4)
     s = L.lib.exm_trace_bwd(C.byref(m), C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000, C.byref(p),
                             float("nan"), 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, None)
