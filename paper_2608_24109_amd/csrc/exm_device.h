@@ -102,40 +102,92 @@ __device__ __forceinline__ int32_t upper_bound_u64(const uint64_t* a, int32_t n,
   return lo;
 }
 
-__device__ __forceinline__ EnvSample env_sample(const EnvView& e, const Draw& d) {
-  const uint64_t Q = e.cdf_row[e.He - 1];
+// Per-row constants of the within-texel theta sampling: (1 - cos(theta_i) for rows of the upper
+// half or 1 + cos(theta_{i+1}) for the lower half, cos(theta_i) - cos(theta_{i+1})), from
+// half-angle sines so that sin(theta) keeps full precision at both poles.
+__device__ __forceinline__ float2 env_row_consts(int32_t row, int32_t He) {
+  const float inv2He = 0.5f / (float)He;
+  const float dlt = 2.0f * sinpif((float)(2 * row + 1) * inv2He) * sinpif(inv2He);
+  float base;
+  if (2 * row < He) {
+    const float sa = sinpif((float)row * inv2He);
+    base = 2.0f * sa * sa;
+  } else {
+    const float sb = sinpif((float)(He - row - 1) * inv2He);
+    base = 2.0f * sb * sb;
+  }
+  return make_float2(base, dlt);
+}
+
+// (sin, cos) of phi_j = 2 pi j / We
+__device__ __forceinline__ float2 env_col_consts(int32_t col, int32_t We) {
+  float sj, cj;
+  sincospif(2.0f * (float)col / (float)We, &sj, &cj);
+  return make_float2(sj, cj);
+}
+
+// Block-shared copies of the row CDF and of the row/column constants (LDS), or nulls when the
+// map is too large for them; either way env_sample computes bit-identical results.
+struct EnvTabs {
+  const uint64_t* cdf_row;
+  const float2* rowc;
+  const float2* colc;
+};
+
+__host__ __device__ inline size_t env_tabs_bytes(int32_t He, int32_t We) {
+  return (size_t)He * 8 + (size_t)He * 8 + (size_t)We * 8;
+}
+constexpr size_t kEnvTabsMaxBytes = 48 * 1024;
+
+// Every thread of the block must call this (it synchronises the block).
+__device__ __forceinline__ EnvTabs load_env_tabs(const EnvView& e, void* lds, bool use) {
+  EnvTabs t{e.cdf_row, nullptr, nullptr};
+  if (!use) return t;
+  uint64_t* cr = static_cast<uint64_t*>(lds);
+  float2* rc = reinterpret_cast<float2*>(cr + e.He);
+  float2* cc = rc + e.He;
+  for (int32_t i = threadIdx.x; i < e.He; i += blockDim.x) {
+    cr[i] = e.cdf_row[i];
+    rc[i] = env_row_consts(i, e.He);
+  }
+  for (int32_t j = threadIdx.x; j < e.We; j += blockDim.x) cc[j] = env_col_consts(j, e.We);
+  __syncthreads();
+  t.cdf_row = cr;
+  t.rowc = rc;
+  t.colc = cc;
+  return t;
+}
+
+__device__ __forceinline__ EnvSample env_sample(const EnvView& e, const EnvTabs& tb, const Draw& d) {
+  const uint64_t Q = tb.cdf_row[e.He - 1];
   const uint64_t target = __umul64hi(d.x, Q);
   // target < Q whenever the tables are well formed; the clamps only keep a malformed table
   // (e.g. built from a NaN map) inside the arrays
-  const int32_t row = min(upper_bound_u64(e.cdf_row, e.He, target), e.He - 1);
-  const uint64_t rem = target - (row > 0 ? e.cdf_row[row - 1] : 0ull);
+  const int32_t row = min(upper_bound_u64(tb.cdf_row, e.He, target), e.He - 1);
+  const uint64_t rem = target - (row > 0 ? tb.cdf_row[row - 1] : 0ull);
   const int32_t col = min(upper_bound_u64(e.cdf_col + (int64_t)row * e.We, e.We, rem), e.We - 1);
   EnvSample s;
   s.texel = row * e.We + col;
-  // theta in [row, row+1] * pi/He with cos(theta) uniform; the complement 1 -/+ cos(theta) is
-  // formed from half-angle sines so that sin(theta) keeps full precision at both poles
-  const float inv2He = 0.5f / (float)e.He;
-  const float dlt = 2.0f * sinpif((float)(2 * row + 1) * inv2He) * sinpif(inv2He);  // c_i - c_{i+1}
+  // theta in [row, row+1] * pi/He with cos(theta) uniform
+  const float2 rc = tb.rowc ? tb.rowc[row] : env_row_consts(row, e.He);
   float ct, st2;
   if (2 * row < e.He) {
-    const float sa = sinpif((float)row * inv2He);
-    const float omc = 2.0f * sa * sa + d.u3 * dlt;  // 1 - cos(theta)
+    const float omc = rc.x + d.u3 * rc.y;  // 1 - cos(theta)
     ct = 1.0f - omc;
     st2 = omc * (2.0f - omc);
   } else {
-    const float sb = sinpif((float)(e.He - row - 1) * inv2He);
-    const float opc = 2.0f * sb * sb + (1.0f - d.u3) * dlt;  // 1 + cos(theta)
+    const float opc = rc.x + (1.0f - d.u3) * rc.y;  // 1 + cos(theta)
     ct = opc - 1.0f;
     st2 = opc * (2.0f - opc);
   }
   const float st = sqrtf(fmaxf(st2, 0.0f));
   // phi = 2 pi (col + u2) / We by angle addition (keeps u2's resolution at large col)
-  float sj, cj, sd, cd;
-  sincospif(2.0f * (float)col / (float)e.We, &sj, &cj);
+  const float2 cj = tb.colc ? tb.colc[col] : env_col_consts(col, e.We);
+  float sd, cd;
   sincospif(2.0f * d.u2 / (float)e.We, &sd, &cd);
-  const float cphi = cj * cd - sj * sd, sphi = sj * cd + cj * sd;
+  const float cphi = cj.y * cd - cj.x * sd, sphi = cj.x * cd + cj.y * sd;
   s.dir = mk(st * cphi, ct, st * sphi);
-  s.inv_pdf = 1.0f / e.pdf[s.texel];
+  s.inv_pdf = __builtin_amdgcn_rcpf(e.pdf[s.texel]);
   return s;
 }
 
@@ -275,7 +327,7 @@ __device__ __forceinline__ Spec spec_terms(f3 n, f3 wi, f3 wo, float ci, float r
   s.ci = ci;
   if (!(hl >= 1e-12f) || !(s.co > 0.0f) || !(ci > 0.0f)) return s;
   s.on = true;
-  s.h = (1.0f / hl) * hs;
+  s.h = __builtin_amdgcn_rcpf(hl) * hs;
   const float alpha = r * r;
   s.alpha2 = alpha * alpha;
   s.alpha_clamped = s.alpha2 < 1e-12f;
@@ -283,11 +335,11 @@ __device__ __forceinline__ Spec spec_terms(f3 n, f3 wi, f3 wo, float ci, float r
   s.chh = dot(n, s.h);
   const f3 nx = cross(n, s.h);
   s.d = dot(nx, nx) + s.alpha2 * s.chh * s.chh;
-  s.D = s.alpha2 / (kPi * s.d * s.d);
+  s.D = s.alpha2 * __builtin_amdgcn_rcpf(kPi * s.d * s.d);
   s.si = sqrtf(s.alpha2 + (1.0f - s.alpha2) * ci * ci);
   s.so = sqrtf(s.alpha2 + (1.0f - s.alpha2) * s.co * s.co);
-  s.G1i = 2.0f * ci / (ci + s.si);
-  s.G1o = 2.0f * s.co / (s.co + s.so);
+  s.G1i = 2.0f * ci * __builtin_amdgcn_rcpf(ci + s.si);
+  s.G1o = 2.0f * s.co * __builtin_amdgcn_rcpf(s.co + s.so);
   const float x = 1.0f - fmaxf(dot(wi, s.h), 0.0f);
   const float x2 = x * x;
   s.x5 = x2 * x2 * x;
@@ -388,10 +440,11 @@ struct TraceCount {
   uint32_t nodes = 0, tris = 0;
 };
 
-// Resumable traversal state: the current node reference and the depth of the lane's stack of
-// deferred node references (kept in LDS at stack[slot * stride]).
+// Resumable traversal state: the node to visit next, one postponed leaf, the depth of the
+// lane's stack of deferred node references (kept in LDS at stack[slot * stride]).
 struct TravState {
   int32_t ref;
+  int32_t leaf;
   int32_t sp;
   uint32_t steps;
 };
@@ -400,8 +453,11 @@ constexpr int32_t kEmptyRef = (int32_t)0x80000000;
 constexpr uint32_t kMaxSteps = 1u << 22;  // the builder bounds the work far below this; the cap
                                           // only keeps a corrupted structure from trapping a wave
 
+__device__ __forceinline__ bool is_leaf(int32_t ref) { return ref < 0 && ref != kEmptyRef; }
+
 __device__ __forceinline__ void trav_begin(const BvhView& B, TravState& s, HitRec& h) {
   s.ref = B.root_is_leaf ? B.nodes[0].c0 : 0;
+  s.leaf = kEmptyRef;
   s.sp = 0;
   s.steps = 0;
   h.id = -1;
@@ -409,14 +465,20 @@ __device__ __forceinline__ void trav_begin(const BvhView& B, TravState& s, HitRe
   h.b1 = h.b2 = 0.0f;
 }
 
-// One traversal step: an internal node (both child boxes tested, near child next, far child
-// deferred) or a leaf (its triangles tested). Returns true when the query is finished: the
-// stack is empty, or ANY and a hit was found.
+__device__ __forceinline__ int32_t trav_pop(TravState& s, const int32_t* stack, int stride) {
+  return s.sp > 0 ? stack[(--s.sp) * stride] : kEmptyRef;
+}
+
+// One round of the speculative while-while traversal (Aila and Laine 2009): internal nodes are
+// visited until every lane of the wave that is still descending holds a postponed leaf, then
+// the postponed leaves are intersected together, so node and leaf work each run with most
+// lanes of the wave active. Returns true when the query is finished: nothing left to visit, or
+// ANY and a hit was found.
 template <bool ANY, bool COUNT>
-__device__ __forceinline__ bool trav_step(const BvhView& B, const Ray& r, float tmin, int32_t skip, int32_t* stack,
-                                          int stride, TravState& s, HitRec& h, TraceCount* counts) {
-  if (++s.steps > kMaxSteps) return true;
-  if (s.ref >= 0) {
+__device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float tmin, int32_t skip, int32_t* stack,
+                                           int stride, TravState& s, HitRec& h, TraceCount* counts) {
+  while (s.ref >= 0) {
+    if (++s.steps > kMaxSteps) return true;
     if (COUNT) counts->nodes++;
     const BvhNode& N = B.nodes[s.ref];
     const float4 a = reinterpret_cast<const float4*>(&N)[0];
@@ -432,14 +494,23 @@ __device__ __forceinline__ bool trav_step(const BvhView& B, const Ray& r, float 
       const bool first0 = t0 <= t1;
       s.ref = first0 ? e.x : e.y;
       if (s.sp < kStack) stack[(s.sp++) * stride] = first0 ? e.y : e.x;
-      return false;
-    }
-    if (h0 || h1) {
+    } else if (h0 || h1) {
       s.ref = h0 ? e.x : e.y;
-      return false;
+    } else {
+      s.ref = trav_pop(s, stack, stride);
     }
-  } else if (s.ref != kEmptyRef) {
-    const uint32_t v = ~(uint32_t)s.ref;
+    if (is_leaf(s.ref) && s.leaf == kEmptyRef) {  // postpone the leaf, keep descending
+      s.leaf = s.ref;
+      s.ref = trav_pop(s, stack, stride);
+    }
+    if (__ballot(s.leaf == kEmptyRef) == 0ull) break;
+  }
+  if (s.leaf == kEmptyRef && is_leaf(s.ref)) {  // a round that starts on a leaf (root leaf)
+    s.leaf = s.ref;
+    s.ref = trav_pop(s, stack, stride);
+  }
+  while (s.leaf != kEmptyRef) {
+    const uint32_t v = ~(uint32_t)s.leaf;
     const int32_t first = (int32_t)(v >> 4), cnt = (int32_t)(v & 15u);
     for (int32_t i = first; i < first + cnt; ++i) {
       const BvhTri T = B.tris[i];
@@ -459,10 +530,13 @@ __device__ __forceinline__ bool trav_step(const BvhView& B, const Ray& r, float 
         }
       }
     }
+    s.leaf = kEmptyRef;
+    if (is_leaf(s.ref)) {
+      s.leaf = s.ref;
+      s.ref = trav_pop(s, stack, stride);
+    }
   }
-  if (s.sp == 0) return true;
-  s.ref = stack[(--s.sp) * stride];
-  return false;
+  return s.ref == kEmptyRef;
 }
 
 // Whole query in one call (ANY: first hit; else closest hit).
@@ -472,7 +546,7 @@ __device__ __forceinline__ HitRec trace(const BvhView& B, const Ray& r, float tm
   TravState s;
   HitRec h;
   trav_begin(B, s, h);
-  while (!trav_step<ANY, COUNT>(B, r, tmin, skip, stack, stride, s, h, counts)) {
+  while (!trav_round<ANY, COUNT>(B, r, tmin, skip, stack, stride, s, h, counts)) {
   }
   return h;
 }

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kThreads) void k_trace(BvhView B, RayBatch rb, int3
     if (__ballot(have_ray) == 0ull) break;
     if (have_ray) {
       while (true) {
-        if (trav_step<ANY, COUNT>(B, ray, tmin, skip, stack, kThreads, ts, h, &tc)) {
+        if (trav_round<ANY, COUNT>(B, ray, tmin, skip, stack, kThreads, ts, h, &tc)) {
           if (ANY)
             out_any[slot] = h.id >= 0 ? 1 : 0;
           else

@@ -45,7 +45,7 @@ __device__ __forceinline__ void brdf_eval(const Surf& S, f3 wi, f3 wo, float ci,
   if (p.flags & EXM_DIFFUSE_ONLY) return;
   const Spec s = spec_terms(S.ns, wi, wo, ci, S.r, p.eps);
   if (!s.on) return;
-  const float k = s.D * s.G1i * s.G1o / s.den;
+  const float k = s.D * s.G1i * s.G1o * __builtin_amdgcn_rcpf(s.den);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const float F0 = (1.0f - S.m) * p.f_diel + S.m * S.a[c];
@@ -63,7 +63,10 @@ template <bool COUNT>
 __global__ __launch_bounds__(kThreads) void k_dir_gen(MeshView M, TexView T, EnvView E, ShadeViews V,
                                                       const int32_t* __restrict__ tri_id,
                                                       const float* __restrict__ bary, KParams p, int64_t p0,
-                                                      int64_t P, DirectWs ws, unsigned long long* __restrict__ counters) {
+                                                      int64_t P, DirectWs ws, unsigned long long* __restrict__ counters,
+                                                      bool use_lds) {
+  extern __shared__ __align__(16) char smem[];
+  const EnvTabs tb = load_env_tabs(E, smem, use_lds);
   const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if ((local & ~(int64_t)63) >= P) return;  // whole waves only
   const int64_t HW = (int64_t)V.H * V.W;
@@ -89,7 +92,7 @@ __global__ __launch_bounds__(kThreads) void k_dir_gen(MeshView M, TexView T, Env
     EnvSample es;
     float c = 0.0f;
     if (f >= 0) {
-      es = env_sample(E, philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)k, 0u));
+      es = env_sample(E, tb, philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)k, 0u));
       c = dot(S.ns, es.dir);
       need = c > 0.0f;
     }
@@ -187,7 +190,8 @@ __device__ __forceinline__ void brdf_adjoint(const Surf& S, f3 wi, f3 wo, float 
     const Spec s = spec_terms(S.ns, wi, wo, ci, S.r, p.eps);
     if (s.on) {
       const float DG = s.D * s.G1i * s.G1o;
-      const float k = DG / s.den;
+      const float rden = __builtin_amdgcn_rcpf(s.den);
+      const float k = DG * rden;
       float sumWF = 0.0f, sumWfs = 0.0f;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -203,25 +207,28 @@ __device__ __forceinline__ void brdf_adjoint(const Surf& S, f3 wi, f3 wo, float 
         g.m += W[c] * ci * k * dF0 * (S.a[c] - p.f_diel);
       }
       // derivatives of D and of G = G1(ci) G1(co)
-      const float dD_dd = -2.0f * s.D / s.d;
-      const float dG1i_dc = 2.0f * s.alpha2 / (s.si * (ci + s.si) * (ci + s.si));
-      const float dG1o_dc = 2.0f * s.alpha2 / (s.so * (s.co + s.so) * (s.co + s.so));
+      const float rd = __builtin_amdgcn_rcpf(s.d);
+      const float ri = __builtin_amdgcn_rcpf(s.si * (ci + s.si) * (ci + s.si));
+      const float ro = __builtin_amdgcn_rcpf(s.so * (s.co + s.so) * (s.co + s.so));
+      const float dD_dd = -2.0f * s.D * rd;
+      const float dG1i_dc = 2.0f * s.alpha2 * ri;
+      const float dG1o_dc = 2.0f * s.alpha2 * ro;
       const float G = s.G1i * s.G1o;
       // alpha^2 path
       if (!s.alpha_clamped) {
-        const float dD_da2 = s.D / s.alpha2 - 2.0f * s.D * s.chh * s.chh / s.d;
-        const float dG1i_da2 = -ci * (1.0f - ci * ci) / (s.si * (ci + s.si) * (ci + s.si));
-        const float dG1o_da2 = -s.co * (1.0f - s.co * s.co) / (s.so * (s.co + s.so) * (s.co + s.so));
+        const float dD_da2 = s.D * __builtin_amdgcn_rcpf(s.alpha2) - 2.0f * s.D * s.chh * s.chh * rd;
+        const float dG1i_da2 = -ci * (1.0f - ci * ci) * ri;
+        const float dG1o_da2 = -s.co * (1.0f - s.co * s.co) * ro;
         const float dDG_da2 = dD_da2 * G + s.D * (dG1i_da2 * s.G1o + s.G1i * dG1o_da2);
         const float r3 = S.r * S.r * S.r;
-        g.r += ci * sumWF / s.den * dDG_da2 * 4.0f * r3;
+        g.r += ci * sumWF * rden * dDG_da2 * 4.0f * r3;
       }
       // shading-normal path: D through n.h and |n x h|^2, G through n.wi and n.wo, 1/den
       const f3 gd = 2.0f * (S.ns - s.chh * s.h) + (2.0f * s.alpha2 * s.chh) * s.h;  // dd/dn
       const f3 gD = dD_dd * gd;
       const f3 gG = (dG1i_dc * s.G1o) * wi + (s.G1i * dG1o_dc) * wo;
       const f3 gden = 4.0f * (s.co * wi + ci * wo);
-      g.n = g.n + (ci * sumWF / s.den) * (G * gD + s.D * gG) - (ci * sumWfs / s.den) * gden;
+      g.n = g.n + (ci * sumWF * rden) * (G * gD + s.D * gG) - (ci * sumWfs * rden) * gden;
     }
   }
   // the cosine factor n.wi multiplies f_r
@@ -254,7 +261,10 @@ __global__ __launch_bounds__(kThreads) void k_shade_bwd(MeshView M, TexView T, E
                                                         const int32_t* __restrict__ tri_id,
                                                         const float* __restrict__ bary, KParams p,
                                                         const float* __restrict__ dI, const uint64_t* __restrict__ vis,
-                                                        float* __restrict__ dtex, double* __restrict__ denv) {
+                                                        float* __restrict__ dtex, double* __restrict__ denv,
+                                                        bool use_lds) {
+  extern __shared__ __align__(16) char smem[];
+  const EnvTabs tb = load_env_tabs(E, smem, use_lds);
   const int64_t HW = (int64_t)V.H * V.W;
   const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (gid >= HW * V.n) return;
@@ -277,7 +287,7 @@ __global__ __launch_bounds__(kThreads) void k_shade_bwd(MeshView M, TexView T, E
     const int k = __ffsll((long long)bits) - 1;
     bits &= bits - 1;
     const Draw d = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)k, 0u);
-    const EnvSample es = env_sample(E, d);
+    const EnvSample es = env_sample(E, tb, d);
     const float c = dot(S.ns, es.dir);
     const float* e = E.env + 3 * (int64_t)es.texel;
     const float s = invN * es.inv_pdf;
@@ -326,15 +336,17 @@ hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_mat
   const TexView tv{mat->Ht, mat->Wt, mat->tex};
   const DirectWs ws = direct_ws(ws_ptr, P, p->N_d);
   const bool trace = p->N_d > 0 && !(p->flags & EXM_NO_VIS);
+  const size_t lds = env_tabs_bytes(env->He, env->We);
+  const bool use_lds = lds <= kEnvTabsMaxBytes;
   for (int64_t p0 = 0; p0 < n; p0 += P) {
     const int64_t Pc = std::min<int64_t>(P, ((n - p0) + 63) / 64 * 64);
     const unsigned nb = (unsigned)((Pc + kThreads - 1) / kThreads);
     if (counters)
-      k_dir_gen<true><<<nb, kThreads, 0, s>>>(mesh_view(m), tv, env_view(env), v, tri_id, bary, kp, p0, Pc, ws,
-                                             counters);
+      k_dir_gen<true><<<nb, kThreads, use_lds ? lds : 0, s>>>(mesh_view(m), tv, env_view(env), v, tri_id, bary, kp,
+                                                             p0, Pc, ws, counters, use_lds);
     else
-      k_dir_gen<false><<<nb, kThreads, 0, s>>>(mesh_view(m), tv, env_view(env), v, tri_id, bary, kp, p0, Pc, ws,
-                                              nullptr);
+      k_dir_gen<false><<<nb, kThreads, use_lds ? lds : 0, s>>>(mesh_view(m), tv, env_view(env), v, tri_id, bary, kp,
+                                                              p0, Pc, ws, nullptr, use_lds);
     if (trace) {
       const RayBatch rb{ws.rays, ws.count, (int32_t)(Pc / 64), 64 * (int64_t)p->N_d, ws.counter};
       const hipError_t e = launch_trace_any(bvh, rb, ws.hit, counters, s);
@@ -352,9 +364,11 @@ hipError_t launch_shade_bwd(const exm_mesh* m, const exm_material* mat, const ex
                             const int32_t* tri_id, const float* bary, const exm_params* p, const float* dI,
                             const uint64_t* vis, float* dtex, double* denv, hipStream_t s) {
   const int64_t n = (int64_t)v.n * v.H * v.W;
-  k_shade_bwd<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+  const size_t lds = env_tabs_bytes(env->He, env->We);
+  const bool use_lds = lds <= kEnvTabsMaxBytes;
+  k_shade_bwd<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, use_lds ? lds : 0, s>>>(
       mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), v, tri_id, bary, kparams(p), dI, vis, dtex,
-      denv);
+      denv, use_lds);
   return hipGetLastError();
 }
 

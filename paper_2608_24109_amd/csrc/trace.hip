@@ -155,7 +155,10 @@ __global__ __launch_bounds__(kThreads) void k_ind_gen1(MeshView M, ShadeViews V,
 __global__ __launch_bounds__(kThreads) void k_ind_gen2(MeshView M, TexView T, EnvView E, ShadeViews V,
                                                        const int32_t* __restrict__ tri_id,
                                                        const float* __restrict__ bary, KParams p, int64_t p0,
-                                                       int64_t P, IndirectWs ws, exm_sec_rec* __restrict__ rec) {
+                                                       int64_t P, IndirectWs ws, exm_sec_rec* __restrict__ rec,
+                                                       bool use_lds) {
+  extern __shared__ __align__(16) char smem[];
+  const EnvTabs tb = load_env_tabs(E, smem, use_lds);
   const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if ((local & ~(int64_t)63) >= P) return;
   const int64_t HW = (int64_t)V.H * V.W;
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(kThreads) void k_ind_gen2(MeshView M, TexView T, En
       EnvSample es;
       float c = 0.0f;
       if (valid) {
-        es = env_sample(E, philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s2, 2u + (uint32_t)j));
+        es = env_sample(E, tb, philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s2, 2u + (uint32_t)j));
         c = dot(Y.ns, es.dir);
         need = c > 0.0f;
       }
@@ -308,7 +311,10 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
                                                         const float* __restrict__ dI,
                                                         const exm_sec_rec* __restrict__ rec,
                                                         const uint64_t* __restrict__ sec_vis,
-                                                        float* __restrict__ dtex, double* __restrict__ denv) {
+                                                        float* __restrict__ dtex, double* __restrict__ denv,
+                                                        bool use_lds) {
+  extern __shared__ __align__(16) char smem[];
+  const EnvTabs tb = load_env_tabs(E, smem, use_lds);
   const int64_t HW = (int64_t)V.H * V.W;
   const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (gid >= HW * V.n) return;
@@ -346,7 +352,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
     for (int s = 0; s < p.N_s; ++s) {
       if (!((bits >> (j * p.N_s + s)) & 1ull)) continue;
       const Draw ds = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s, 2u + (uint32_t)j);
-      const EnvSample es = env_sample(E, ds);
+      const EnvSample es = env_sample(E, tb, ds);
       const float c = dot(Y.ns, es.dir);
       const float* e = E.env + 3 * (int64_t)es.texel;
       const float wgt = c * es.inv_pdf * invNs;
@@ -373,7 +379,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
     for (int s = 0; s < p.N_s; ++s) {
       if (!((bits >> (j * p.N_s + s)) & 1ull)) continue;
       const Draw ds = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s, 2u + (uint32_t)j);
-      const EnvSample es = env_sample(E, ds);
+      const EnvSample es = env_sample(E, tb, ds);
       const float c = dot(Y.ns, es.dir);
       const float* e = E.env + 3 * (int64_t)es.texel;
       const float ip = es.inv_pdf * invNs;
@@ -426,6 +432,8 @@ hipError_t launch_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const ex
   const TexView tv{mat->Ht, mat->Wt, mat->tex};
   const IndirectWs ws = indirect_ws(ws_ptr, P, p->N_b, p->N_s);
   const bool vis_rays = !(p->flags & EXM_NO_VIS) && p->N_s > 0;
+  const size_t lds = env_tabs_bytes(env->He, env->We);
+  const bool use_lds = lds <= kEnvTabsMaxBytes;
   for (int64_t p0 = 0; p0 < n; p0 += P) {
     const int64_t Pc = std::min<int64_t>(P, ((n - p0) + 63) / 64 * 64);
     const unsigned nb = (unsigned)((Pc + kThreads - 1) / kThreads);
@@ -435,8 +443,8 @@ hipError_t launch_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const ex
       hipError_t e = launch_trace_closest(bvh, rb1, ws.sec_hits, counters, s);
       if (e != hipSuccess) return e;
     }
-    k_ind_gen2<<<nb, kThreads, 0, s>>>(mesh_view(m), tv, env_view(env), v, tri_id, bary, kp, p0, Pc, ws,
-                                       sec_rec);
+    k_ind_gen2<<<nb, kThreads, use_lds ? lds : 0, s>>>(mesh_view(m), tv, env_view(env), v, tri_id, bary, kp, p0,
+                                                       Pc, ws, sec_rec, use_lds);
     if (vis_rays && p->N_b > 0) {
       const RayBatch rb2{ws.sh_rays, ws.sh_count, (int32_t)(Pc / 64), 64 * (int64_t)p->N_b * p->N_s, ws.counter};
       hipError_t e = launch_trace_any(bvh, rb2, ws.sh_hit, counters ? counters + 3 : nullptr, s);
@@ -457,9 +465,11 @@ hipError_t launch_trace_bwd(const exm_mesh* m, const exm_material* mat, const ex
                             const float* dI, const exm_sec_rec* sec_rec, const uint64_t* sec_vis, float* dtex,
                             double* denv, hipStream_t s) {
   const int64_t n = (int64_t)v.n * v.H * v.W;
-  k_trace_bwd<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+  const size_t lds = env_tabs_bytes(env->He, env->We);
+  const bool use_lds = lds <= kEnvTabsMaxBytes;
+  k_trace_bwd<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, use_lds ? lds : 0, s>>>(
       mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), v, tri_id, bary, kparams(p), lambda_ind, dI,
-      sec_rec, sec_vis, dtex, denv);
+      sec_rec, sec_vis, dtex, denv, use_lds);
   return hipGetLastError();
 }
 
