@@ -91,7 +91,7 @@ def run_gpu(workload: str, steps: int, warmup: int):
     torch.cuda.synchronize()
 
     def step(tm):
-        tm("build_env_sampler", lambda: L.exm_build_env_sampler(env.env, env.cdf_row, env.cdf_col, env.pdf))
+        tm("build_env_sampler", lambda: env.update())
         tm("raster_gbuffer", lambda: raster(mesh, cc, bufs))
         tm("shade_fwd", lambda: L.exm_shade_fwd(mesh.s, mesh.bvh, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc,
                                                 bufs.L_dir, bufs.vis, ws_fwd))

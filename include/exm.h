@@ -90,6 +90,8 @@ typedef struct {
   const uint64_t* cdf_row; /* [He] */
   const uint64_t* cdf_col; /* [He,We] */
   const float* pdf;        /* [He,We] solid-angle density of the texel */
+  const uint32_t* guide;   /* [exm_env_guide_len(He,We)] cutpoint tables over the CDFs */
+  const float* rec;        /* [He,We,4] per texel (E.r, E.g, E.b, 1/pdf); 16-byte aligned */
 } exm_env;
 
 /* Estimator parameters. N_d direct env samples (Eq. 17), N_b secondary rays (Eq. 19), N_s
@@ -129,9 +131,17 @@ size_t exm_bvh_device_bytes(const exm_bvh* bvh);
 /* Importance-sampling distribution over env texels proportional to luminance times texel
  * solid angle (Direct Illumination). Integer tables: q_ij = max(1, floor(w_ij / max w *
  * 2^20)); cdf_row = inclusive prefix of row totals; cdf_col = inclusive prefix inside a row;
- * pdf_ij = q_ij / (Q Omega_i). Needs He >= 1, 2 <= We, He*We <= 2^24; uses no workspace. */
+ * pdf_ij = q_ij / (Q Omega_i). A texel is picked by inverting these CDFs (row, then column).
+ * Also written, as functions of the tables and the map: `guide`, cutpoint tables that narrow
+ * each inversion to a few entries without changing its result (Chen and Asau's guide-table
+ * method), and `rec`, the packed per-texel record (E, 1/pdf) read by the pick. All outputs
+ * are caller-owned device buffers; cdf_row, cdf_col 8-byte, rec 16-byte aligned. The tables
+ * describe the map at the time of the call: rebuild them after the map changes. Needs
+ * He >= 1, 2 <= We, He*We <= 2^24; uses no workspace. */
+size_t exm_env_guide_len(int32_t He, int32_t We); /* uint32 entries of `guide` */
 exm_status exm_build_env_sampler(const float* env, int32_t He, int32_t We, uint64_t* cdf_row,
-                                 uint64_t* cdf_col, float* pdf, hipStream_t stream);
+                                 uint64_t* cdf_col, float* pdf, uint32_t* guide, float* rec,
+                                 hipStream_t stream);
 
 /* G-buffer (Attribute Query: face f and barycentrics b of the visible point): per pixel the
  * closest triangle under a top-left fill rule at the pixel centre, id -1 for background, and

@@ -49,7 +49,7 @@ class exm_material(C.Structure):
 
 class exm_env(C.Structure):
     _fields_ = [("He", C.c_int32), ("We", C.c_int32), ("env", C.c_void_p), ("cdf_row", C.c_void_p),
-                ("cdf_col", C.c_void_p), ("pdf", C.c_void_p)]
+                ("cdf_col", C.c_void_p), ("pdf", C.c_void_p), ("guide", C.c_void_p), ("rec", C.c_void_p)]
 
 
 class exm_params(C.Structure):
@@ -72,7 +72,8 @@ def _load() -> C.CDLL:
         "exm_build_bvh": (st, [vp, i32, vp, i32, C.POINTER(vp), vp]),
         "exm_free_bvh": (st, [vp]),
         "exm_bvh_device_bytes": (C.c_size_t, [vp]),
-        "exm_build_env_sampler": (st, [vp, i32, i32, vp, vp, vp, vp]),
+        "exm_env_guide_len": (C.c_size_t, [i32, i32]),
+        "exm_build_env_sampler": (st, [vp, i32, i32, vp, vp, vp, vp, vp, vp]),
         "exm_raster_gbuffer": (st, [vp, vp, i32, vp, vp, vp]),
         "exm_shade_fwd_workspace_size": (C.c_size_t, [i32, i32, i32, i32]),
         "exm_shade_fwd_workspace_min": (C.c_size_t, [i32]),
@@ -184,15 +185,22 @@ def exm_build_bvh(pos: np.ndarray, tri: np.ndarray, stream=None) -> Bvh:
     return Bvh(out.value)
 
 
-def exm_build_env_sampler(env, cdf_row, cdf_col, pdf, stream=None) -> None:
+def exm_env_guide_len(He: int, We: int) -> int:
+    return int(lib.exm_env_guide_len(He, We))
+
+
+def exm_build_env_sampler(env, cdf_row, cdf_col, pdf, guide, rec, stream=None) -> None:
+    """`guide` is int32 storage for the uint32 cutpoint tables; `rec` is float32 [He,We,4]."""
     import torch
     He, We = env.shape[0], env.shape[1]
     _need(env, torch.float32, (He, We, 3), "env")
     _need(cdf_row, torch.uint64, (He,), "cdf_row")
     _need(cdf_col, torch.uint64, (He, We), "cdf_col")
     _need(pdf, torch.float32, (He, We), "pdf")
-    _check(lib.exm_build_env_sampler(_ptr(env), He, We, _ptr(cdf_row), _ptr(cdf_col), _ptr(pdf), _stream(stream)),
-           "exm_build_env_sampler")
+    _need(guide, torch.int32, (exm_env_guide_len(He, We),), "guide")
+    _need(rec, torch.float32, (He, We, 4), "rec")
+    _check(lib.exm_build_env_sampler(_ptr(env), He, We, _ptr(cdf_row), _ptr(cdf_col), _ptr(pdf), _ptr(guide),
+                                     _ptr(rec), _stream(stream)), "exm_build_env_sampler")
 
 
 def exm_raster_gbuffer(mesh: exm_mesh, cams, tri_id, bary, stream=None) -> None:

@@ -83,7 +83,10 @@ exm_status check_env_dims(int32_t He, int32_t We) {
 }
 
 exm_status check_env(const exm_env* e) {
-  if (!e || !e->env || !e->cdf_row || !e->cdf_col || !e->pdf) return fail(EXM_E_INVAL, "env or its tables are NULL");
+  if (!e || !e->env || !e->cdf_row || !e->cdf_col || !e->pdf || !e->guide || !e->rec)
+    return fail(EXM_E_INVAL, "env or its tables are NULL");
+  if (!aligned(e->rec, 16) || !aligned(e->cdf_row, 8) || !aligned(e->cdf_col, 8) || !aligned(e->guide, 4))
+    return fail(EXM_E_INVAL, "env tables are misaligned (rec 16 B, cdf 8 B, guide 4 B)");
   return check_env_dims(e->He, e->We);
 }
 
@@ -209,14 +212,20 @@ exm_status exm_free_bvh(exm_bvh* b) {
 
 size_t exm_bvh_device_bytes(const exm_bvh* b) { return b ? b->bytes : 0; }
 
+size_t exm_env_guide_len(int32_t He, int32_t We) {
+  if (He < 1 || We < 2) return 0;
+  return env_guide_len(He, We);
+}
+
 exm_status exm_build_env_sampler(const float* env, int32_t He, int32_t We, uint64_t* cdf_row, uint64_t* cdf_col,
-                                 float* pdf, hipStream_t stream) {
-  if (!env || !cdf_row || !cdf_col || !pdf) return fail(EXM_E_INVAL, "env sampler pointer is NULL");
+                                 float* pdf, uint32_t* guide, float* rec, hipStream_t stream) {
+  if (!env || !cdf_row || !cdf_col || !pdf || !guide || !rec)
+    return fail(EXM_E_INVAL, "env sampler pointer is NULL");
   EXM_TRY(check_env_dims(He, We));
-  if (!aligned(pdf, 8) || !aligned(cdf_row, 8) || !aligned(cdf_col, 8))
-    return fail(EXM_E_INVAL, "env tables must be 8-byte aligned");
+  if (!aligned(pdf, 8) || !aligned(cdf_row, 8) || !aligned(cdf_col, 8) || !aligned(rec, 16) || !aligned(guide, 4))
+    return fail(EXM_E_INVAL, "env tables are misaligned (cdf and pdf 8 B, rec 16 B, guide 4 B)");
   EXM_TRY(check_device());
-  hipError_t e = launch_env_sampler(env, He, We, cdf_row, cdf_col, pdf, stream);
+  hipError_t e = launch_env_sampler(env, He, We, cdf_row, cdf_col, pdf, guide, rec, stream);
   if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_build_env_sampler: ") + hipGetErrorString(e));
   return EXM_OK;
 }

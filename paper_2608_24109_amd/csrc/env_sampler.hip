@@ -5,12 +5,16 @@
 //   q_ij = max(1, floor(w_ij / max w * 2^20))                          (integer weights)
 //   cdf_col = inclusive prefix inside a row, cdf_row = inclusive prefix of row totals,
 //   pdf_ij = q_ij / (Q Omega_i).
+// Two derived tables speed up sampling without changing any pick: the cutpoint tables over
+// cdf_row and each row of cdf_col (their layout is described with env_guide_len), and a packed
+// record per texel (E_ij, 1/pdf_ij) so that a pick reads one 16-byte record.
 // Weights are computed in FP64 without FMA contraction so that the integer tables are the
 // exact function of the map. No workspace: intermediate values live in the output buffers
 // (cdf_col holds the FP64 weights, cdf_row the row maxima, pdf the row totals) until the
 // kernel that owns the final value overwrites them; the kernels run in stream order.
 #include <hip/hip_runtime.h>
 
+#include "exm_device.h"
 #include "exm_internal.h"
 
 namespace exm {
@@ -110,9 +114,11 @@ __global__ __launch_bounds__(kThreads) void k_row_scan(int32_t He, const uint64_
   }
 }
 
-// one block per row: pdf = q / (Q Omega)
-__global__ __launch_bounds__(kThreads) void k_pdf(int32_t He, int32_t We, const uint64_t* __restrict__ cdf_row,
-                                                  const uint64_t* __restrict__ cdf_col, float* __restrict__ pdf) {
+// one block per row: pdf = q / (Q Omega), and the texel's sampling record
+__global__ __launch_bounds__(kThreads) void k_pdf(const float* __restrict__ env, int32_t He, int32_t We,
+                                                  const uint64_t* __restrict__ cdf_row,
+                                                  const uint64_t* __restrict__ cdf_col, float* __restrict__ pdf,
+                                                  float4* __restrict__ rec) {
 #pragma clang fp contract(off)
   const int32_t i = blockIdx.x;
   const double Q = (double)cdf_row[He - 1];
@@ -120,20 +126,58 @@ __global__ __launch_bounds__(kThreads) void k_pdf(int32_t He, int32_t We, const 
   for (int32_t j = threadIdx.x; j < We; j += kThreads) {
     const int64_t t = (int64_t)i * We + j;
     const uint64_t q = cdf_col[t] - (j > 0 ? cdf_col[t - 1] : 0ull);
-    pdf[t] = (float)((double)q / (Q * om));
+    const float pd = (float)((double)q / (Q * om));
+    pdf[t] = pd;
+    rec[t] = make_float4(env[3 * t], env[3 * t + 1], env[3 * t + 2], __builtin_amdgcn_rcpf(pd));
   }
+}
+
+// smallest s with (T - 1) >> s < n: cuts [0, T) into at most n buckets of 2^s keys
+__device__ __forceinline__ uint32_t cut_shift(uint64_t T, int32_t n) {
+  uint32_t s = 0;
+  if (T == 0) return 0;
+  while (s < 63 && ((T - 1) >> s) > (uint64_t)(n - 1)) ++s;
+  return s;
+}
+
+// single block: row shift, row entries and the column shift of every row
+__global__ __launch_bounds__(kThreads) void k_guide_rows(int32_t He, int32_t We, const uint64_t* __restrict__ cdf_row,
+                                                         const uint64_t* __restrict__ cdf_col,
+                                                         uint32_t* __restrict__ guide) {
+  const uint32_t s = cut_shift(cdf_row[He - 1], He);
+  if (threadIdx.x == 0) guide[0] = s;
+  for (int32_t g = threadIdx.x; g <= He; g += kThreads) {
+    const uint64_t key = (uint64_t)g << s;
+    guide[1 + g] = (uint32_t)min(upper_bound_u64(cdf_row, He, key), He - 1);
+  }
+  for (int32_t i = threadIdx.x; i < He; i += kThreads)
+    guide[He + 2 + i] = cut_shift(cdf_col[(int64_t)i * We + We - 1], We);
+}
+
+// column entries: one thread per (row, g), g in [0, We]
+__global__ __launch_bounds__(kThreads) void k_guide_cols(int32_t He, int32_t We, const uint64_t* __restrict__ cdf_col,
+                                                         uint32_t* __restrict__ guide) {
+  const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (k >= (int64_t)He * (We + 1)) return;
+  const int32_t i = (int32_t)(k / (We + 1)), g = (int32_t)(k - (int64_t)i * (We + 1));
+  const uint64_t* row = cdf_col + (int64_t)i * We;
+  const uint32_t s = cut_shift(row[We - 1], We);
+  guide[2 * (int64_t)He + 2 + k] = (uint32_t)min(upper_bound_u64(row, We, (uint64_t)g << s), We - 1);
 }
 
 }  // namespace
 
 hipError_t launch_env_sampler(const float* env, int32_t He, int32_t We, uint64_t* cdf_row, uint64_t* cdf_col,
-                              float* pdf, hipStream_t s) {
+                              float* pdf, uint32_t* guide, float* rec, hipStream_t s) {
   // the pdf buffer (He*We floats) holds the He u64 row totals between k_quantise and k_row_scan
   uint64_t* row_tot = reinterpret_cast<uint64_t*>(pdf);
   k_weights<<<He, kThreads, 0, s>>>(env, He, We, cdf_row, cdf_col);
   k_quantise<<<He, kThreads, 0, s>>>(He, We, cdf_row, cdf_col, row_tot);
   k_row_scan<<<1, kThreads, 0, s>>>(He, row_tot, cdf_row);
-  k_pdf<<<He, kThreads, 0, s>>>(He, We, cdf_row, cdf_col, pdf);
+  k_pdf<<<He, kThreads, 0, s>>>(env, He, We, cdf_row, cdf_col, pdf, reinterpret_cast<float4*>(rec));
+  k_guide_rows<<<1, kThreads, 0, s>>>(He, We, cdf_row, cdf_col, guide);
+  const int64_t nc = (int64_t)He * (We + 1);
+  k_guide_cols<<<(unsigned)((nc + kThreads - 1) / kThreads), kThreads, 0, s>>>(He, We, cdf_col, guide);
   return hipGetLastError();
 }
 

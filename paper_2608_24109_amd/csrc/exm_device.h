@@ -79,12 +79,15 @@ struct EnvView {
   const uint64_t* cdf_row;
   const uint64_t* cdf_col;
   const float* pdf;
+  const uint32_t* guide;  // cutpoint tables over cdf_row and each row of cdf_col (layout below)
+  const float4* rec;      // per texel (E.r, E.g, E.b, 1/pdf)
 };
 
 struct EnvSample {
   int32_t texel;
   f3 dir;
   float inv_pdf;
+  float E[3];
 };
 
 // first index in [0, n) with a[i] > t (a is non-decreasing, a[n-1] > t)
@@ -92,6 +95,21 @@ __device__ __forceinline__ int32_t upper_bound_u64(const uint64_t* a, int32_t n,
   int32_t lo = 0, cnt = n;
   while (cnt > 0) {
     int32_t step = cnt >> 1;
+    if (a[lo + step] <= t) {
+      lo += step + 1;
+      cnt -= step + 1;
+    } else {
+      cnt = step;
+    }
+  }
+  return lo;
+}
+
+// first index in [lo, hi] with a[i] > t, given that one exists there (hi if none before it)
+__device__ __forceinline__ int32_t upper_bound_range(const uint64_t* a, int32_t lo, int32_t hi, uint64_t t) {
+  int32_t cnt = max(hi - lo, 0);
+  while (cnt > 0) {
+    const int32_t step = cnt >> 1;
     if (a[lo + step] <= t) {
       lo += step + 1;
       cnt -= step + 1;
@@ -126,35 +144,42 @@ __device__ __forceinline__ float2 env_col_consts(int32_t col, int32_t We) {
   return make_float2(sj, cj);
 }
 
-// Block-shared copies of the row CDF and of the row/column constants (LDS), or nulls when the
-// map is too large for them; either way env_sample computes bit-identical results.
+// Block-shared copies of the row CDF, the row/column constants and the row cutpoints (LDS), or
+// global pointers when the map is too large for them; either way env_sample computes
+// bit-identical results.
 struct EnvTabs {
   const uint64_t* cdf_row;
   const float2* rowc;
   const float2* colc;
+  const uint32_t* rguide;  // row shift + row entries (He + 2)
+  const uint32_t* cshift;  // column shift of each row (He)
 };
 
 __host__ __device__ inline size_t env_tabs_bytes(int32_t He, int32_t We) {
-  return (size_t)He * 8 + (size_t)He * 8 + (size_t)We * 8;
+  return (size_t)He * 8 + (size_t)He * 8 + (size_t)We * 8 + (size_t)(2 * He + 2) * 4;
 }
 constexpr size_t kEnvTabsMaxBytes = 48 * 1024;
 
 // Every thread of the block must call this (it synchronises the block).
 __device__ __forceinline__ EnvTabs load_env_tabs(const EnvView& e, void* lds, bool use) {
-  EnvTabs t{e.cdf_row, nullptr, nullptr};
+  EnvTabs t{e.cdf_row, nullptr, nullptr, e.guide, e.guide + e.He + 2};
   if (!use) return t;
   uint64_t* cr = static_cast<uint64_t*>(lds);
   float2* rc = reinterpret_cast<float2*>(cr + e.He);
   float2* cc = rc + e.He;
+  uint32_t* gd = reinterpret_cast<uint32_t*>(cc + e.We);
   for (int32_t i = threadIdx.x; i < e.He; i += blockDim.x) {
     cr[i] = e.cdf_row[i];
     rc[i] = env_row_consts(i, e.He);
   }
   for (int32_t j = threadIdx.x; j < e.We; j += blockDim.x) cc[j] = env_col_consts(j, e.We);
+  for (int32_t k = threadIdx.x; k < 2 * e.He + 2; k += blockDim.x) gd[k] = e.guide[k];
   __syncthreads();
   t.cdf_row = cr;
   t.rowc = rc;
   t.colc = cc;
+  t.rguide = gd;
+  t.cshift = gd + e.He + 2;
   return t;
 }
 
@@ -163,11 +188,17 @@ __device__ __forceinline__ EnvSample env_sample(const EnvView& e, const EnvTabs&
   const uint64_t target = __umul64hi(d.x, Q);
   // target < Q whenever the tables are well formed; the clamps only keep a malformed table
   // (e.g. built from a NaN map) inside the arrays
-  const int32_t row = min(upper_bound_u64(tb.cdf_row, e.He, target), e.He - 1);
+  const uint32_t gr = (uint32_t)min(target >> tb.rguide[0], (uint64_t)(e.He - 1));
+  const int32_t row = min(upper_bound_range(tb.cdf_row, (int32_t)tb.rguide[1 + gr], (int32_t)tb.rguide[2 + gr], target),
+                          e.He - 1);
   const uint64_t rem = target - (row > 0 ? tb.cdf_row[row - 1] : 0ull);
-  const int32_t col = min(upper_bound_u64(e.cdf_col + (int64_t)row * e.We, e.We, rem), e.We - 1);
+  const uint32_t gc = (uint32_t)min(rem >> tb.cshift[row], (uint64_t)(e.We - 1));
+  const uint32_t* cg = e.guide + 2 * (int64_t)e.He + 2 + (int64_t)row * (e.We + 1) + gc;
+  const int32_t col =
+      min(upper_bound_range(e.cdf_col + (int64_t)row * e.We, (int32_t)cg[0], (int32_t)cg[1], rem), e.We - 1);
   EnvSample s;
   s.texel = row * e.We + col;
+  const float4 rec = e.rec[s.texel];
   // theta in [row, row+1] * pi/He with cos(theta) uniform
   const float2 rc = tb.rowc ? tb.rowc[row] : env_row_consts(row, e.He);
   float ct, st2;
@@ -187,7 +218,10 @@ __device__ __forceinline__ EnvSample env_sample(const EnvView& e, const EnvTabs&
   sincospif(2.0f * d.u2 / (float)e.We, &sd, &cd);
   const float cphi = cj.y * cd - cj.x * sd, sphi = cj.x * cd + cj.y * sd;
   s.dir = mk(st * cphi, ct, st * sphi);
-  s.inv_pdf = __builtin_amdgcn_rcpf(e.pdf[s.texel]);
+  s.inv_pdf = rec.w;
+  s.E[0] = rec.x;
+  s.E[1] = rec.y;
+  s.E[2] = rec.z;
   return s;
 }
 

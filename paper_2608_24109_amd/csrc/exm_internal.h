@@ -58,6 +58,19 @@ struct exm_bvh {
 
 namespace exm {
 
+// Layout of the cutpoint ("guide") tables. A CDF a[0..n) with total T = a[n-1] is cut into at
+// most n buckets of 2^s keys, s the smallest shift with (T - 1) >> s < n; entry g holds the
+// first index whose CDF value exceeds g << s (clamped to n - 1), for g in [0, n]. A key t in
+// bucket g = t >> s then has its answer in [entry g, entry g + 1], so the search runs over
+// that range only and returns the same index as a search over the whole array.
+//   guide[0]                          row shift
+//   guide[1 .. He + 1]                row entries
+//   guide[He + 2 .. 2 He + 2)         shift of each row's column CDF
+//   guide[2 He + 2 + i (We + 1) + g]  column entries of row i
+inline size_t env_guide_len(int32_t He, int32_t We) {
+  return (size_t)He * (size_t)(We + 3) + 2;
+}
+
 // error reporting (thread-local last error)
 exm_status fail(exm_status s, const std::string& msg);
 exm_status check_launch(const char* what);
@@ -65,7 +78,7 @@ exm_status check_launch(const char* what);
 // host launchers (defined in the .hip files); arguments already validated
 hipError_t launch_mesh_prepare(const exm_mesh* m, hipStream_t s);
 hipError_t launch_env_sampler(const float* env, int32_t He, int32_t We, uint64_t* cdf_row, uint64_t* cdf_col,
-                              float* pdf, hipStream_t s);
+                              float* pdf, uint32_t* guide, float* rec, hipStream_t s);
 hipError_t launch_raster(const exm_mesh* m, const RasterViews& v, int32_t* tri_id, float* bary, hipStream_t s);
 hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                             const ShadeViews& v, const int32_t* tri_id, const float* bary, const exm_params* p,

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_dir_gen(MeshView M, TexView T, Env
       ws.rays[slot] = R;
       float fr[3];
       brdf_eval(S, es.dir, wo, c, p, fr);
-      const float* e = E.env + 3 * (int64_t)es.texel;
+      const float* e = es.E;
       const float wgt = c * es.inv_pdf;
       ws.contrib[3 * slot] = e[0] * fr[0] * wgt;
       ws.contrib[3 * slot + 1] = e[1] * fr[1] * wgt;
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(kThreads) void k_shade_bwd(MeshView M, TexView T, E
     const Draw d = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)k, 0u);
     const EnvSample es = env_sample(E, tb, d);
     const float c = dot(S.ns, es.dir);
-    const float* e = E.env + 3 * (int64_t)es.texel;
+    const float* e = es.E;
     const float s = invN * es.inv_pdf;
     const float W[3] = {g[0] * e[0] * s, g[1] * e[1] * s, g[2] * e[2] * s};
     float fr[3];
@@ -322,7 +322,9 @@ KParams kparams(const exm_params* p) {
 MeshView mesh_view(const exm_mesh* m) {
   return MeshView{m->nV, m->nF, m->pos, m->tri, m->uv, m->tri_uv, m->vnrm, m->ftan};
 }
-EnvView env_view(const exm_env* e) { return EnvView{e->He, e->We, e->env, e->cdf_row, e->cdf_col, e->pdf}; }
+EnvView env_view(const exm_env* e) {
+  return EnvView{e->He, e->We, e->env, e->cdf_row, e->cdf_col, e->pdf, e->guide, reinterpret_cast<const float4*>(e->rec)};
+}
 BvhView bvh_view(const exm_bvh* b) { return BvhView{b->nodes, b->tris, b->root_is_leaf}; }
 
 hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,

@@ -233,7 +233,7 @@ __global__ __launch_bounds__(kThreads) void k_ind_gen2(MeshView M, TexView T, En
         R.d[2] = es.dir.z;
         R.tmin = p.tmin;
         ws.sh_rays[slot] = R;
-        const float* e = E.env + 3 * (int64_t)es.texel;
+        const float* e = es.E;
         const float wgt = c * es.inv_pdf;
         ws.sh_contrib[3 * slot] = fac[0] * e[0] * wgt;
         ws.sh_contrib[3 * slot + 1] = fac[1] * e[1] * wgt;
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
       const Draw ds = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s, 2u + (uint32_t)j);
       const EnvSample es = env_sample(E, tb, ds);
       const float c = dot(Y.ns, es.dir);
-      const float* e = E.env + 3 * (int64_t)es.texel;
+      const float* e = es.E;
       const float wgt = c * es.inv_pdf * invNs;
       Es[0] += e[0] * wgt;
       Es[1] += e[1] * wgt;
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
       const Draw ds = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s, 2u + (uint32_t)j);
       const EnvSample es = env_sample(E, tb, ds);
       const float c = dot(Y.ns, es.dir);
-      const float* e = E.env + 3 * (int64_t)es.texel;
+      const float* e = es.E;
       const float ip = es.inv_pdf * invNs;
       double* de = denv + 3 * (int64_t)es.texel;
       unsafeAtomicAdd(de, (double)(H[0] * fdy[0] * c * ip));

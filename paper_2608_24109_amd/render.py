@@ -116,10 +116,11 @@ class RenderPBR(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, tex, env, mesh, mat, env_dev, cams, p: PassParams, lambda_ind: float = 1.0,
-                checkpoint: bool = False, chunk: int = 8):
+                checkpoint: bool = False, chunk: int = 8, rebuild_tables: bool = True):
         if tex.data_ptr() != mat.tex.data_ptr() or env.data_ptr() != env_dev.env.data_ptr():
             raise ValueError("tex/env must be the tensors bound to the device material/env")
-        env_dev.update()
+        if rebuild_tables:
+            env_dev.update()
         H, W = cams[0].H, cams[0].W
         out = torch.empty((len(cams), H, W, 3), dtype=torch.float32, device=tex.device)
         chunks = []
@@ -154,4 +155,5 @@ class RenderPBR(torch.autograd.Function):
             render_backward(mesh, mat, env_dev, cc, p, bufs, g, lambda_ind, dtex, denv)
             bufs.drop_gbuffer()
         ctx.state = None
-        return dtex, denv.to(torch.float32), None, None, None, None, None, None, None, None
+        ctx.denv64 = denv
+        return dtex, denv.to(torch.float32), None, None, None, None, None, None, None, None, None

@@ -60,15 +60,18 @@ class DeviceEnv:
         self.cdf_row = torch.empty(He, dtype=torch.uint64, device=device)
         self.cdf_col = torch.empty((He, We), dtype=torch.uint64, device=device)
         self.pdf = torch.empty((He, We), dtype=torch.float32, device=device)
+        self.guide = torch.empty(L.exm_env_guide_len(He, We), dtype=torch.int32, device=device)
+        self.rec = torch.empty((He, We, 4), dtype=torch.float32, device=device)
         self.s = L.exm_env(He, We, self.env.data_ptr(), self.cdf_row.data_ptr(), self.cdf_col.data_ptr(),
-                           self.pdf.data_ptr())
+                           self.pdf.data_ptr(), self.guide.data_ptr(), self.rec.data_ptr())
         self.update(stream=stream)
 
     def update(self, env: torch.Tensor | None = None, stream=None) -> None:
         """Copy in a new map (same shape) if given, then rebuild the tables."""
         if env is not None:
             self.env.copy_(env)
-        L.exm_build_env_sampler(self.env, self.cdf_row, self.cdf_col, self.pdf, stream)
+        L.exm_build_env_sampler(self.env, self.cdf_row, self.cdf_col, self.pdf, self.guide, self.rec, stream)
 
     def device_bytes(self) -> int:
-        return sum(x.numel() * x.element_size() for x in (self.env, self.cdf_row, self.cdf_col, self.pdf))
+        return sum(x.numel() * x.element_size()
+                   for x in (self.env, self.cdf_row, self.cdf_col, self.pdf, self.guide, self.rec))

@@ -69,7 +69,7 @@ def test_shade_validation(L):
     m = _mesh(L)
     cams = _cams(L)
     mat = L.exm_material(4, 4, 0x1000)
-    env = L.exm_env(4, 8, 0x1000, 0x1000, 0x1000, 0x1000)
+    env = L.exm_env(4, 8, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000)
     f = L.lib.exm_shade_fwd
     bvh = 0x2000
 
@@ -88,8 +88,13 @@ def test_shade_validation(L):
     assert call(L=None)[0] == L.EXM_E_INVAL
     mis = L.exm_material(4, 4, 0x1004)
     assert call(mat=C.byref(mis))[0] == L.EXM_E_INVAL
-    e1 = L.exm_env(4, 1, 0x1000, 0x1000, 0x1000, 0x1000)
+    e1 = L.exm_env(4, 1, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000)
     assert call(env=C.byref(e1))[0] == L.EXM_E_INVAL
+    no_guide = L.exm_env(4, 8, 0x1000, 0x1000, 0x1000, 0x1000, None, 0x1000)
+    assert call(env=C.byref(no_guide))[0] == L.EXM_E_INVAL
+    rec8 = L.exm_env(4, 8, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1008)
+    s, msg = call(env=C.byref(rec8))
+    assert s == L.EXM_E_INVAL and "misaligned" in msg
     unprep = L.exm_mesh(3, 1, 3, 0x1000, 0x1000, 0x1000, 0x1000, None, None)
     s, msg = call(m=C.byref(unprep))
     assert s == L.EXM_E_INVAL and "exm_mesh_prepare" in msg
@@ -111,7 +116,7 @@ def test_indirect_and_backward_validation(L):
     m = _mesh(L)
     cams = _cams(L)
     mat = L.exm_material(4, 4, 0x1000)
-    env = L.exm_env(4, 8, 0x1000, 0x1000, 0x1000, 0x1000)
+    env = L.exm_env(4, 8, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000)
     p = L.params(8, N_b=16, N_s=8)  # 128 light-sample bits do not fit one u64
     s = L.lib.exm_trace_indirect(C.byref(m), 0x2000, C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000,
                                  C.byref(p), 0x1000, 0x1000, 0x1000, 0x100000, 1 << 30, None)
@@ -132,10 +137,16 @@ def test_indirect_and_backward_validation(L):
 
 def test_env_sampler_and_bvh_validation(L):
     f = L.lib.exm_build_env_sampler
-    assert f(0x1000, 0, 8, 0x1000, 0x1000, 0x1000, None) == L.EXM_E_INVAL
-    assert f(0x1000, 4, 1, 0x1000, 0x1000, 0x1000, None) == L.EXM_E_INVAL
-    assert f(0x1000, 4096, 8192, 0x1000, 0x1000, 0x1000, None) == L.EXM_E_INVAL
-    assert f(0x1000, 4, 8, 0x1000, 0x1000, 0x1004, None) == L.EXM_E_INVAL
+    a = 0x1000
+    assert f(a, 0, 8, a, a, a, a, a, None) == L.EXM_E_INVAL
+    assert f(a, 4, 1, a, a, a, a, a, None) == L.EXM_E_INVAL
+    assert f(a, 4096, 8192, a, a, a, a, a, None) == L.EXM_E_INVAL
+    assert f(a, 4, 8, a, a, 0x1004, a, a, None) == L.EXM_E_INVAL
+    assert f(a, 4, 8, a, a, a, None, a, None) == L.EXM_E_INVAL
+    assert f(a, 4, 8, a, a, a, a, 0x1008, None) == L.EXM_E_INVAL
+    # cutpoint tables: row shift + (He + 1) row entries + He column shifts + He (We + 1) entries
+    assert L.exm_env_guide_len(512, 1024) == 1 + 513 + 512 + 512 * 1025
+    assert L.exm_env_guide_len(0, 8) == 0
     pos = np.zeros((3, 3), np.float32)
     tri = np.array([[0, 1, 3]], np.int32)
     out = C.c_void_p()

@@ -106,6 +106,60 @@ def test_env_tables_integer_equal(lib, He, We, sigma):
     assert np.allclose(pdf, t.pdf, rtol=2e-7, atol=0)
 
 
+def _guide_ref(a: np.ndarray, n: int):
+    """Cutpoint table of one CDF by its definition: shift s, then for g in [0, n] the first
+    index whose value exceeds g << s, clamped to n - 1."""
+    T = int(a[-1])
+    s = 0
+    while T > 0 and ((T - 1) >> s) > n - 1:
+        s += 1
+    keys = np.array([g << s for g in range(n + 1)], np.uint64)
+    return s, np.minimum(np.searchsorted(a, keys, side="right"), n - 1)
+
+
+@pytest.mark.parametrize("case", ["32x64", "512x1024", "7x13", "zeros", "one_bright", "1x2"])
+def test_env_guide_and_records(lib, case):
+    """The cutpoint tables and per-texel records that the pick reads are the stated functions
+    of the CDF tables and the map, and every key's answer lies inside its bucket's range."""
+    from paper_2608_24109_amd.scene import DeviceEnv
+    shapes = {"32x64": (32, 64), "512x1024": (512, 1024), "7x13": (7, 13), "zeros": (8, 16),
+              "one_bright": (16, 32), "1x2": (1, 2)}
+    He, We = shapes[case]
+    env = I.env_map(He, We, 1.5, seed=2)
+    if case == "zeros":
+        env[:] = 0.0
+    elif case == "one_bright":
+        env[:] = 1e-3
+        env[5, 7] = 1e4
+    log(f"[env guide] {case}")
+    d = DeviceEnv(env)
+    torch.cuda.synchronize()
+    cr = d.cdf_row.cpu().numpy()
+    cc = d.cdf_col.cpu().numpy()
+    gd = d.guide.cpu().numpy().view(np.uint32).astype(np.int64)
+    s, ref = _guide_ref(cr, He)
+    assert gd[0] == s and np.array_equal(gd[1:He + 2], ref)
+    cols = gd[2 * He + 2:].reshape(He, We + 1)
+    for i in range(He):
+        si, ri = _guide_ref(cc[i], We)
+        assert gd[He + 2 + i] == si and np.array_equal(cols[i], ri), f"row {i}"
+    # bucket invariant on random keys: the full-array answer lies in [entry g, entry g + 1]
+    rng = np.random.default_rng(7)
+    t = rng.integers(0, int(cr[-1]), 20000, dtype=np.uint64)
+    full = np.searchsorted(cr, t, side="right")
+    g = (t >> np.uint64(s)).astype(np.int64)
+    assert np.all((gd[1 + g] <= full) & (full <= gd[2 + g]))
+    for i in rng.integers(0, He, 8):
+        ti = rng.integers(0, int(cc[i, -1]), 5000, dtype=np.uint64)
+        fi = np.searchsorted(cc[i], ti, side="right")
+        gi = (ti >> np.uint64(gd[He + 2 + i])).astype(np.int64)
+        assert np.all((cols[i][gi] <= fi) & (fi <= cols[i][gi + 1]))
+    rec = d.rec.cpu().numpy()
+    assert np.array_equal(rec[..., :3], env)
+    pdf = d.pdf.cpu().numpy().astype(np.float64)
+    assert np.allclose(rec[..., 3], 1.0 / pdf, rtol=2.5e-7, atol=0)
+
+
 # ------------------------------------------------------------------------------------------
 # raster
 # ------------------------------------------------------------------------------------------
