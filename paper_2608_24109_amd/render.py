@@ -104,6 +104,41 @@ def render_backward(mesh: DeviceMesh, mat: DeviceMaterial, env: DeviceEnv, cams_
                         bufs.sec_vis, dtex, denv, stream)
 
 
+def _forward_chunks(tex_device, mesh, mat, env_dev, cams, p: PassParams, lambda_ind: float, chunk: int,
+                    keep: bool, checkpoint: bool):
+    """Renders `cams` in chunks of `chunk` views into one [V,H,W,3] image. With keep=True the
+    per-chunk records the adjoint needs are returned (G-buffer dropped if checkpoint)."""
+    H, W = cams[0].H, cams[0].W
+    out = torch.empty((len(cams), H, W, 3), dtype=torch.float32, device=tex_device)
+    chunks = []
+    for v0 in range(0, len(cams), chunk):
+        cs = cams[v0:v0 + chunk]
+        cc = L.cameras(cs, [getattr(c, "view_id", v0 + i) for i, c in enumerate(cs)])
+        bufs = PassBuffers(len(cs), H, W, p.N_b, device=tex_device)
+        render_forward(mesh, mat, env_dev, cc, p, bufs, rebuild_tables=False)
+        o = out[v0:v0 + len(cs)]
+        if p.N_b > 0:
+            torch.add(bufs.L_dir, bufs.L_ind, alpha=lambda_ind, out=o)
+        else:
+            o.copy_(bufs.L_dir)
+        if keep:
+            bufs.L_dir = bufs.L_ind = None
+            bufs.ws = None
+            if checkpoint:
+                bufs.drop_gbuffer()
+            chunks.append((cc, bufs))
+    return out, chunks
+
+
+def render_image(mesh: DeviceMesh, mat: DeviceMaterial, env_dev: DeviceEnv, cams, p: PassParams,
+                 lambda_ind: float = 1.0, chunk: int = 8, rebuild_tables: bool = True) -> torch.Tensor:
+    """I = L_dir + lambda_ind L_ind (Eq. 20) for `cams`, keeping nothing for a backward pass."""
+    if rebuild_tables:
+        env_dev.update()
+    out, _ = _forward_chunks(mat.tex.device, mesh, mat, env_dev, cams, p, lambda_ind, chunk, False, False)
+    return out
+
+
 class RenderPBR(torch.autograd.Function):
     """I = L_dir + lambda_ind L_ind for the views `cams`, differentiable w.r.t. the packed
     material map `tex` [Ht,Wt,8] and the env map `env` [He,We,3].
@@ -111,7 +146,8 @@ class RenderPBR(torch.autograd.Function):
     The maps passed in must be the tensors that `mat` and `env_dev` point to (the kernels read
     them through the device structs). Views are processed in chunks of `chunk` views; with
     checkpoint=True each chunk's G-buffer is freed after the forward and rasterised again in
-    backward.
+    backward. The env gradient is accumulated in FP64 and returned in FP32 (the FP64 sum stays
+    on ctx.denv64).
     """
 
     @staticmethod
@@ -121,24 +157,7 @@ class RenderPBR(torch.autograd.Function):
             raise ValueError("tex/env must be the tensors bound to the device material/env")
         if rebuild_tables:
             env_dev.update()
-        H, W = cams[0].H, cams[0].W
-        out = torch.empty((len(cams), H, W, 3), dtype=torch.float32, device=tex.device)
-        chunks = []
-        for v0 in range(0, len(cams), chunk):
-            cs = cams[v0:v0 + chunk]
-            cc = L.cameras(cs, [getattr(c, "view_id", v0 + i) for i, c in enumerate(cs)])
-            bufs = PassBuffers(len(cs), H, W, p.N_b, device=tex.device)
-            render_forward(mesh, mat, env_dev, cc, p, bufs, rebuild_tables=False)
-            o = out[v0:v0 + len(cs)]
-            if p.N_b > 0:
-                torch.add(bufs.L_dir, bufs.L_ind, alpha=lambda_ind, out=o)
-            else:
-                o.copy_(bufs.L_dir)
-            bufs.L_dir = bufs.L_ind = None
-            bufs.ws = None
-            if checkpoint:
-                bufs.drop_gbuffer()
-            chunks.append((cc, bufs))
+        out, chunks = _forward_chunks(tex.device, mesh, mat, env_dev, cams, p, lambda_ind, chunk, True, checkpoint)
         ctx.state = (mesh, mat, env_dev, chunks, p, lambda_ind, chunk)
         return out
 
