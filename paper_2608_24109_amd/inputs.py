@@ -26,6 +26,9 @@ SEED_MAPS = 1
 SEED_ENV = 2
 SEED_RNG_KEY = 3
 SEED_UPSTREAM = 4
+SEED_RELIGHT_ASSETS = 100   # asset i uses SEED_RELIGHT_ASSETS + i
+SEED_RELIGHT_ENVS = 200     # env k uses SEED_RELIGHT_ENVS + k
+SEED_RELIGHT_ARRIVALS = 300
 
 
 # --------------------------------------------------------------------------------------------
@@ -390,3 +393,98 @@ def config(name: str, views: int | None = None, res: int | None = None) -> Scene
         cams = ring_cameras(n, 4.5, H, W, elev_deg=elev)
         return make_scene(name, pos, tri, 4096, 4096, 512, 1024, 1.5, cams, N_d=64, N_b=4, N_s=4)
     raise KeyError(name)
+
+
+# --------------------------------------------------------------------------------------------
+# relighting service: assets, env maps and a request stream
+# --------------------------------------------------------------------------------------------
+
+@dataclass
+class RelightAssetSpec:
+    index: int
+    kind: str       # "sphere" (displaced cube-sphere) or "torus" (one displaced torus around Y)
+    n_tris: int     # target triangle count (log-uniform in [10k, 2M])
+    tex_res: int    # square material maps of tex_res^2 texels
+    seed: int
+
+
+def relight_asset_specs(n: int = 64, lo: int = 10_000, hi: int = 2_000_000,
+                        sizes=(512, 1024, 2048, 4096)) -> list[RelightAssetSpec]:
+    out = []
+    for i in range(n):
+        rng = np.random.default_rng(SEED_RELIGHT_ASSETS + i)
+        kind = "sphere" if rng.random() < 0.5 else "torus"
+        nt = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        res = int(sizes[int(rng.integers(len(sizes)))])
+        out.append(RelightAssetSpec(i, kind, nt, res, SEED_RELIGHT_ASSETS + i))
+    return out
+
+
+def relight_asset_mesh(spec: RelightAssetSpec):
+    """(pos, tri, uv, tri_uv) of an asset: about spec.n_tris triangles, cube-projected UVs."""
+    if spec.kind == "sphere":
+        n = max(2, int(round(math.sqrt(spec.n_tris / 12.0))))
+        pos, tri = displaced_cube_sphere(n, seed=spec.seed)
+    else:
+        nm = max(3, int(round(math.sqrt(spec.n_tris / 8.0))))
+        pos, tri = torus((0.0, 0.0, 0.0), "y", 4 * nm, nm, noise=ValueNoise(spec.seed))
+        pos, tri = pos.astype(np.float32), tri.astype(np.int32)
+    uv, tri_uv = cube_projected_uvs(pos, tri)
+    return pos, tri, uv, tri_uv
+
+
+def pbr_maps_device(Ht: int, Wt: int, seed: int, device="cuda"):
+    """Packed material map with the distributions of pbr_maps, drawn on the device from a
+    seeded torch generator (a different stream of numbers than pbr_maps' numpy generator)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    n = Ht * Wt
+    tex = torch.empty((n, 8), dtype=torch.float32, device=device)
+    tex[:, 0:3] = torch.rand((n, 3), generator=g, device=device)
+    tex[:, 3] = 0.1 + 0.9 * torch.rand(n, generator=g, device=device)
+    tex[:, 4] = torch.rand(n, generator=g, device=device)
+    nn = torch.randn((n, 3), generator=g, device=device, dtype=torch.float64) * 0.1
+    nn[:, 2] += 1.0
+    tex[:, 5:8] = (nn / nn.norm(dim=1, keepdim=True)).float()
+    return tex.view(Ht, Wt, 8)
+
+
+def relight_envs(n: int = 16, He: int = 256, We: int = 512, sigma: float = 1.0) -> list[np.ndarray]:
+    return [env_map(He, We, sigma, seed=SEED_RELIGHT_ENVS + k) for k in range(n)]
+
+
+@dataclass
+class RelightRequestSpec:
+    rid: int
+    arrival: float      # seconds after the start of the stream
+    asset: int
+    env: int
+    res: int            # square view of res^2 pixels
+    azimuth: float      # ring camera azimuth (radians), elevation 20 deg, looking at the origin
+    indirect: bool      # direct + one-bounce indirect, else direct only
+
+
+def relight_stream(rate: float = 200.0, seconds: float = 60.0, n_assets: int = 64, n_envs: int = 16,
+                   resolutions=(256, 512, 1024, 2048), seed: int = SEED_RELIGHT_ARRIVALS) -> list[RelightRequestSpec]:
+    """Poisson arrivals at `rate` per second over `seconds`; per request a uniform asset, env,
+    view resolution and azimuth, direct-only or direct + indirect with probability 1/2 each."""
+    rng = np.random.default_rng(seed)
+    out, t = [], 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= seconds:
+            break
+        out.append(RelightRequestSpec(len(out), t, int(rng.integers(n_assets)), int(rng.integers(n_envs)),
+                                      int(resolutions[int(rng.integers(len(resolutions)))]),
+                                      float(rng.uniform(0.0, 2.0 * math.pi)), bool(rng.random() < 0.5)))
+    return out
+
+
+def relight_camera(pos: np.ndarray, res: int, azimuth: float, elev_deg: float = 20.0) -> Camera:
+    """Ring camera at 2.9 x the asset's bounding radius (a unit sphere fills ~ 60% of the view)."""
+    R = 2.9 * float(np.sqrt((pos.astype(np.float64) ** 2).sum(1).max()))
+    e = math.radians(elev_deg)
+    eye = R * np.array([math.cos(e) * math.sin(azimuth), math.sin(e), math.cos(e) * math.cos(azimuth)])
+    mvp = perspective(45.0, 1.0, 0.1, 4.0 * R) @ look_at(eye, np.zeros(3), np.array([0.0, 1.0, 0.0]))
+    return Camera(mvp=mvp, eye=eye, H=res, W=res)

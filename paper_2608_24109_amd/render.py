@@ -41,10 +41,12 @@ WORKSPACE_CAP = 4 << 30
 class PassBuffers:
     """Per-view outputs of one forward pass (device tensors) and its ray workspace."""
 
-    def __init__(self, n: int, H: int, W: int, N_b: int, device="cuda", gbuffer: bool = True):
+    def __init__(self, n: int, H: int, W: int, N_b: int, device="cuda", gbuffer: bool = True,
+                 ws_cap: int = WORKSPACE_CAP):
         self.n, self.H, self.W, self.N_b = n, H, W, N_b
         self.device = device
         self.ws = None
+        self.ws_cap = ws_cap
         self.tri_id = torch.empty((n, H, W), dtype=torch.int32, device=device) if gbuffer else None
         self.bary = torch.empty((n, H, W, 2), dtype=torch.float32, device=device) if gbuffer else None
         self.L_dir = torch.empty((n, H, W, 3), dtype=torch.float32, device=device)
@@ -54,8 +56,8 @@ class PassBuffers:
         self.sec_vis = torch.empty((n, H, W), dtype=torch.uint64, device=device) if N_b > 0 else None
 
     def workspace(self, nbytes: int):
-        """The pass's ray workspace, grown to `nbytes` (capped at WORKSPACE_CAP) when needed."""
-        nbytes = min(int(nbytes), WORKSPACE_CAP)
+        """The pass's ray workspace, grown to `nbytes` (capped at ws_cap) when needed."""
+        nbytes = min(int(nbytes), self.ws_cap)
         if self.ws is None or self.ws.numel() < nbytes:
             self.ws = None
             self.ws = L.workspace(nbytes, self.device)
@@ -71,6 +73,16 @@ class PassBuffers:
         self.bary = None
 
 
+def shade_fwd_ws_bytes(n: int, H: int, W: int, p: PassParams) -> int:
+    """Workspace the direct pass asks for: whole views at once, or its minimum."""
+    return max(L.exm_shade_fwd_workspace_size(n, H, W, p.N_d), L.exm_shade_fwd_workspace_min(p.N_d))
+
+
+def trace_indirect_ws_bytes(n: int, H: int, W: int, p: PassParams) -> int:
+    return max(L.exm_trace_indirect_workspace_size(n, H, W, p.N_b, p.N_s),
+               L.exm_trace_indirect_workspace_min(p.N_b, p.N_s))
+
+
 def raster(mesh: DeviceMesh, cams_c, bufs: PassBuffers, stream=None) -> None:
     bufs.ensure_gbuffer()
     L.exm_raster_gbuffer(mesh.s, cams_c, bufs.tri_id, bufs.bary, stream)
@@ -83,13 +95,11 @@ def render_forward(mesh: DeviceMesh, mat: DeviceMaterial, env: DeviceEnv, cams_c
         env.update(stream=stream)
     if do_raster:
         raster(mesh, cams_c, bufs, stream)
-    ws = bufs.workspace(max(L.exm_shade_fwd_workspace_size(len(cams_c), bufs.H, bufs.W, p.N_d),
-                            L.exm_shade_fwd_workspace_min(p.N_d)))
+    ws = bufs.workspace(shade_fwd_ws_bytes(len(cams_c), bufs.H, bufs.W, p))
     L.exm_shade_fwd(mesh.s, mesh.bvh, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, bufs.L_dir, bufs.vis, ws,
                     stream)
     if p.N_b > 0:
-        ws = bufs.workspace(max(L.exm_trace_indirect_workspace_size(len(cams_c), bufs.H, bufs.W, p.N_b, p.N_s),
-                                L.exm_trace_indirect_workspace_min(p.N_b, p.N_s)))
+        ws = bufs.workspace(trace_indirect_ws_bytes(len(cams_c), bufs.H, bufs.W, p))
         L.exm_trace_indirect(mesh.s, mesh.bvh, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, bufs.L_ind,
                              bufs.sec_rec, bufs.sec_vis, ws, stream)
 

@@ -1,0 +1,53 @@
+"""Relighting service on the device: every request's image is bitwise the same when it is
+rendered in the mix (Poisson arrivals, several slots on their own streams, maps evicted and
+uploaded again under a tight HBM budget) and when it is rendered alone (one slot, one
+request on the device at a time). The tolerance is zero: each request's render is a
+deterministic function of its asset, env map, view and estimator parameters, whatever else
+runs beside it."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2608_24109_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_alone_equals_mix():
+    from paper_2608_24109_amd.server import (DeviceBackend, Scheduler, build_host_assets, latency_stats,
+                                             requests_from_specs, serve)
+    specs = I.relight_asset_specs(n=6, lo=10_000, hi=150_000, sizes=(512, 1024))
+    log("[server] building 6 assets")
+    assets = build_host_assets(specs)
+    envs = I.relight_envs(n=3)
+    be = DeviceBackend(assets, envs, slots=4)
+    stream = I.relight_stream(rate=400.0, seconds=0.1, n_assets=6, n_envs=3, resolutions=(64, 128, 256))
+    assert len(stream) >= 20
+    maps = sorted(be.map_bytes(a) for a in range(6))
+    budget = be.fixed_bytes() + maps[-1] + maps[-2] + 4 * 256 * 256 * 400
+    mix = requests_from_specs(stream)
+    sched = Scheduler(be, budget, slots=4)
+    log(f"[server] mix: {len(mix)} requests, budget {budget / 2**20:.1f} MiB")
+    serve(sched, mix)
+    st = latency_stats(mix)
+    log(f"[server] mix stats {st}; loads {sched.loads} evictions {sched.evictions}")
+    assert st["completed"] == len(mix)
+    assert sched.evictions > 0 and sched.peak <= budget
+    alone = requests_from_specs(stream)
+    solo = Scheduler(be, budget, slots=1)
+    for r in alone:
+        serve(solo, [r])
+    for a, b in zip(mix, alone):
+        assert a.rid == b.rid
+        ra, rb = a.result, b.result
+        assert ra.shape == (a.res, a.res, 3)
+        assert torch.isfinite(ra).all() and float(ra.max()) > 0
+        assert torch.equal(ra, rb), f"request {a.rid} differs alone and in the mix"
