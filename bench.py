@@ -31,6 +31,10 @@ FP32_LANE_PEAK_T = 39.32    # 256 CU x 64 lanes x 2.4 GHz, non-packed FP32 instr
 METRIC = "fwd+bwd Mpixels/s and indirect Mrays/s at 1024²; relight p50/p99 ms"
 
 
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -42,7 +46,11 @@ def parse():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, copy a buffer of this many MiB once (HBM counter calibration)")
     ap.add_argument("--no-extras", dest="extras", action="store_false",
-                    help="skip the tori workload (indirect Mrays/s)")
+                    help="skip the tori, tori32 and relight workloads")
+    ap.add_argument("--relight-seconds", type=float, default=60.0, help="length of the relight request stream")
+    ap.add_argument("--relight-rate", type=float, default=200.0, help="Poisson arrival rate (requests/s)")
+    ap.add_argument("--relight-budget-gib", type=float, default=8.0, help="HBM budget of the relight service")
+    ap.add_argument("--relight-slots", type=int, default=8, help="concurrent render slots (streams)")
     return ap.parse_args()
 
 
@@ -86,8 +94,11 @@ def run_gpu(workload: str, steps: int, warmup: int):
     dtex = torch.zeros_like(mat.tex)
     denv = torch.zeros(env.env.shape, dtype=torch.float64, device="cuda")
     lam = 1.0
+    He, We = sc.env.shape[:2]
     ws_fwd = bufs.workspace(max(L.exm_shade_fwd_workspace_size(V, H, W, p.N_d),
-                                L.exm_trace_indirect_workspace_size(V, H, W, p.N_b, p.N_s) if p.N_b else 0))
+                                L.exm_trace_indirect_workspace_size(V, H, W, p.N_b, p.N_s) if p.N_b else 0,
+                                L.exm_shade_bwd_workspace_size(V, H, W, p.N_d, He, We),
+                                L.exm_trace_bwd_workspace_size(V, H, W, p.N_b, p.N_s, He, We) if p.N_b else 0))
     torch.cuda.synchronize()
 
     def step(tm):
@@ -102,10 +113,10 @@ def run_gpu(workload: str, steps: int, warmup: int):
             tm("compose", lambda: torch.add(bufs.L_dir, bufs.L_ind, alpha=lam))
         tm("zero_grads", lambda: (dtex.zero_(), denv.zero_()))
         tm("shade_bwd", lambda: L.exm_shade_bwd(mesh.s, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc, dI, bufs.vis,
-                                                dtex, denv))
+                                                dtex, denv, ws_fwd))
         if p.N_b > 0:
             tm("trace_bwd", lambda: L.exm_trace_bwd(mesh.s, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc, lam, dI,
-                                                    bufs.sec_rec, bufs.sec_vis, dtex, denv))
+                                                    bufs.sec_rec, bufs.sec_vis, dtex, denv, ws_fwd))
 
     warm = Timer(torch)
     for _ in range(warmup):
@@ -145,6 +156,77 @@ def run_gpu(workload: str, steps: int, warmup: int):
     return sc, p, wall, kern, stats, (mesh, mat, env, bufs)
 
 
+def run_c3(steps: int, warmup: int):
+    """The differentiation form: RenderPBR over the 32 views of the tori mesh with 4096^2 maps,
+    G-buffer rasterised again in backward, env gradients on. One step = env tables, forward,
+    backward (gradient buffers allocated and cleared inside)."""
+    import torch
+
+    from paper_2608_24109_amd import inputs as I
+    from paper_2608_24109_amd.render import PassParams, RenderPBR
+    from paper_2608_24109_amd.scene import DeviceEnv, DeviceMaterial, DeviceMesh
+    sc = I.config("tori32")
+    mesh = DeviceMesh(sc.pos, sc.tri, sc.uv, sc.tri_uv)
+    mat = DeviceMaterial(sc.tex)
+    env = DeviceEnv(sc.env)
+    p = PassParams(N_d=sc.N_d, N_b=sc.N_b, N_s=sc.N_s, seed=sc.seed, tmin=sc.tmin)
+    V, H, W = len(sc.cams), sc.cams[0].H, sc.cams[0].W
+    g = torch.from_numpy(I.upstream_grad(V, H, W)).cuda()
+    tex = mat.tex.requires_grad_(True)
+    emap = env.env.requires_grad_(True)
+
+    def step():
+        out = RenderPBR.apply(tex, emap, mesh, mat, env, sc.cams, p, 1.0, True)
+        out.backward(g)
+        tex.grad = None
+        emap.grad = None
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    return {"workload": f"tori32: {sc.nF} tris, {V} views {H}x{W}, {sc.tex.shape[0]}^2 maps, "
+                        f"{sc.env.shape[0]}x{sc.env.shape[1]} env with gradients, N_d={p.N_d}, N_b={p.N_b}, "
+                        f"N_s={p.N_s}, G-buffer rasterised again in backward (autograd.Function)",
+            "steps": steps, "ms_per_step": round(wall * 1e3, 2), "fwd_bwd_Mpixels_s": round(V * H * W / wall / 1e6, 3)}
+
+
+def run_relight(seconds: float, rate: float, budget_gib: float, slots: int):
+    """The relighting service: 64 seeded assets (spheres and tori of 10k-2M triangles, maps of
+    512^2-4096^2), 16 env maps of 256x512, Poisson arrivals; p50/p99 latency (arrival to image
+    in host memory, host monotonic clock) and throughput; then the saturation throughput with
+    every request of a 5 s stream queued at once."""
+    from paper_2608_24109_amd import inputs as I
+    from paper_2608_24109_amd.server import (DeviceBackend, Scheduler, build_host_assets, latency_stats,
+                                             requests_from_specs, serve)
+    specs = I.relight_asset_specs()
+    assets = build_host_assets(specs, workers=min(16, len(os.sched_getaffinity(0))))
+    be = DeviceBackend(assets, I.relight_envs(), slots=slots)
+    budget = int(budget_gib * (1 << 30))
+    reqs = requests_from_specs(I.relight_stream(rate=rate, seconds=seconds))
+    sched = Scheduler(be, budget, slots=slots)
+    serve(sched, reqs, keep_results=False)
+    st = latency_stats(reqs)
+    sat_reqs = requests_from_specs(I.relight_stream(rate=rate, seconds=min(5.0, seconds)))
+    sat = Scheduler(be, budget, slots=slots)
+    serve(sat, sat_reqs, realtime=False, keep_results=False)
+    ss = latency_stats(sat_reqs)
+    r = lambda x: None if x is None else round(x, 3)  # noqa: E731
+    return {"workload": f"{len(specs)} assets ({sum(s.n_tris for s in specs) / 1e6:.1f}M tris, "
+                        f"{sum(be.map_bytes(a) for a in range(len(specs))) / 2**30:.1f} GiB of maps), 16 envs "
+                        f"256x512, views 256^2-2048^2, direct (N_d=8) or + indirect (N_b=4, N_s=4), "
+                        f"Poisson {rate:g} req/s for {seconds:g} s, HBM budget {budget_gib:g} GiB, {slots} slots",
+            "p50_ms": r(st["p50_ms"]), "p99_ms": r(st["p99_ms"]), "mean_ms": r(st["mean_ms"]),
+            "completed": st["completed"], "rejected": st["rejected"], "req_per_s": r(st["req_per_s"]),
+            "Mpixels_s": r(st["mpx_per_s"]), "map_loads": sched.loads, "map_evictions": sched.evictions,
+            "resident_fixed_GiB": round(sched.fixed / 2**30, 3), "peak_GiB": round(sched.peak / 2**30, 3),
+            "saturation_req_per_s": r(ss["req_per_s"]), "saturation_Mpixels_s": r(ss["mpx_per_s"])}
+
+
 def cpu_baseline(sc, p, n_pix: int, view: int = 0):
     """The FP64 oracle as it stands, on a seeded sample of `n_pix` pixels of one view (all pixels
     eligible, background included): forward value pass plus one forward-mode derivative pass
@@ -182,32 +264,33 @@ def cpu_baseline(sc, p, n_pix: int, view: int = 0):
 # Algorithmic bytes: what the method itself must read or write per unit, times the units of one
 # launch. Per covered pixel the attribute query reads 3 vertices (12 B position + 24 B FP64
 # normal), the triangle's vertex and UV indices (12 + 12 B), 3 UVs (24 B), the face tangent
-# (16 B) and 4 bilinear taps of 8 floats (128 B): 300 B. Each env sample reads its texel's pdf
-# (4 B) and the CDF entries a binary search visits (ceil(log2(He+1)) + ceil(log2(We+1)) u64),
-# and an unoccluded one the texel's radiance (12 B). Each traced ray reads the nodes it visits
-# (64 B) and the triangles it tests (48 B).
+# (16 B) and 4 bilinear taps of 8 floats (128 B): 300 B. Each env sample reads the two
+# cutpoint entries of its column bucket (8 B), the CDF entry that decides the pick (8 B) and the
+# texel's record (E and 1/pdf, 16 B): 32 B (the row tables are block-shared). Each traced ray
+# reads the nodes it visits (64 B) and the triangles it tests (48 B). An adjoint env sample
+# adds three FP64 read-modify-writes (48 B); a pixel's map adjoint 4 taps x 8 FP32 (256 B).
 SURF_BYTES = 3 * (12 + 24) + 12 + 12 + 24 + 16 + 4 * 32
+SAMPLE_BYTES = 8 + 8 + 16
 
 
 def algorithmic_bytes(kernel: str, st: dict, p) -> float:
     P, C = st["pixels"], st["covered"]
-    cdf = 8 * (math.ceil(math.log2(st["He"] + 1)) + math.ceil(math.log2(st["We"] + 1)))
     if kernel == "raster_gbuffer":  # G-buffer out, 8 B depth key in/out, mesh per view
         return (12.0 + 16.0) * P + st["views"] * 24.0 * st["tris"]
     if kernel == "build_env_sampler":
-        return st["He"] * st["We"] * (12 + 8 + 4) + 8.0 * st["He"]
+        return st["He"] * st["We"] * (12 + 8 + 4 + 16 + 4) + 8.0 * st["He"]
     if kernel == "shade_fwd":
-        return (32.0 * P + SURF_BYTES * C + (4 + cdf) * st["samples"] + 12.0 * st["unoccluded"]
+        return (32.0 * P + SURF_BYTES * C + SAMPLE_BYTES * st["samples"]
                 + 64.0 * st["shadow_nodes"] + 48.0 * st["shadow_tris"])
-    if kernel == "shade_bwd":  # + 4 taps x 8 channel atomics (8 B RMW) + 3 FP64 env atomics (16 B RMW)
-        return (32.0 * P + (SURF_BYTES + 256.0) * C + (4 + cdf + 12 + 48) * st["unoccluded"])
+    if kernel == "shade_bwd":
+        return 32.0 * P + (SURF_BYTES + 256.0) * C + (SAMPLE_BYTES + 48) * st["unoccluded"]
     if kernel == "trace_indirect":
         return (12.0 * P + 20.0 * C + st["sec_rays"] * 12.0 + st["sec_hits"] * SURF_BYTES
-                + (4 + cdf) * st["sec_shadow_rays"] + 12.0 * st["sec_unoccluded"]
+                + SAMPLE_BYTES * st["sec_shadow_rays"]
                 + 64.0 * (st["sec_nodes"] + st["sec_shadow_nodes"]) + 48.0 * (st["sec_tris"] + st["sec_shadow_tris"]))
     if kernel == "trace_bwd":
         return (44.0 * P + (SURF_BYTES + 224.0) * C + st["sec_hits"] * (SURF_BYTES + 224.0)
-                + (4 + cdf + 12 + 48) * st["sec_unoccluded"])
+                + (SAMPLE_BYTES + 48) * st["sec_unoccluded"])
     return float("nan")
 
 
@@ -242,6 +325,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    log(f"{a.workload}: {a.warmup} warmup + {a.steps} timed steps")
     sc, p, wall, kern, stats, _ = run_gpu(a.workload, a.steps, a.warmup)
     ms_step = wall / a.steps * 1e3
     value = stats["pixels"] / (ms_step * 1e-3) / 1e6
@@ -269,6 +353,7 @@ def main():
                              for k in kern if not math.isnan(algorithmic_bytes(k, stats, p))},
     }
     if a.extras:
+        log("tori (indirect)")
         sc2, p2, wall2, kern2, st2, _ = run_gpu("tori", max(2, a.steps // 3), 1)
         rays = st2["sec_rays"] + st2["sec_shadow_rays"]
         out["indirect"] = {
@@ -276,7 +361,12 @@ def main():
             "indirect_Mrays_s": round(rays / (kern2["trace_indirect"] * 1e-3) / 1e6, 1),
             "fwd_bwd_Mpixels_s": round(st2["pixels"] / (wall2 / max(2, a.steps // 3)) / 1e6, 3),
             "kernels_ms": {k: round(v, 3) for k, v in kern2.items()}}
+        log("tori32 (autograd.Function, checkpointed)")
+        out["checkpointed_32view"] = run_c3(max(2, a.steps // 5), 1)
+        log(f"relight service, {a.relight_seconds:g} s stream")
+        out["relight"] = run_relight(a.relight_seconds, a.relight_rate, a.relight_budget_gib, a.relight_slots)
     if not a.no_cpu:
+        log(f"oracle CPU baseline on {a.cpu_pixels} pixels")
         out["cpu_baseline"] = cpu_baseline(sc, p, a.cpu_pixels)
     print(json.dumps(out), flush=True)
 

@@ -201,7 +201,8 @@ exm_status exm_trace_indirect_counted(const exm_mesh* m, const exm_bvh* bvh, con
 exm_status exm_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env,
                          const exm_camera* cams_host, int32_t nViews, const int32_t* tri_id,
                          const float* bary, const exm_params* p, const float* dI,
-                         const uint64_t* vis, float* dtex, double* denv, hipStream_t stream);
+                         const uint64_t* vis, float* dtex, double* denv, void* ws, size_t ws_bytes,
+                         hipStream_t stream);
 
 /* Adjoint of the indirect pass for upstream lambda_ind * dI (Eq. 20): into the materials at
  * the primary and the secondary points and into E at the secondary light samples. */
@@ -209,7 +210,19 @@ exm_status exm_trace_bwd(const exm_mesh* m, const exm_material* mat, const exm_e
                          const exm_camera* cams_host, int32_t nViews, const int32_t* tri_id,
                          const float* bary, const exm_params* p, float lambda_ind,
                          const float* dI, const exm_sec_rec* sec_rec, const uint64_t* sec_vis,
-                         float* dtex, double* denv, hipStream_t stream);
+                         float* dtex, double* denv, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Workspace of the adjoints (device memory, 256-byte aligned, caller-owned): one 16-byte
+ * record per env sample of the pixels in flight (N_d per pixel for exm_shade_bwd, N_b * N_s
+ * for exm_trace_bwd) plus the bucket tables of the env map's binned reduction. _size is what
+ * the views of one launch (at most 8) take at once; any size from _min up works, the pixels
+ * then run in chunks. 0 for invalid arguments. */
+size_t exm_shade_bwd_workspace_size(int32_t nViews, int32_t H, int32_t W, int32_t N_d, int32_t He,
+                                    int32_t We);
+size_t exm_shade_bwd_workspace_min(int32_t N_d, int32_t He, int32_t We);
+size_t exm_trace_bwd_workspace_size(int32_t nViews, int32_t H, int32_t W, int32_t N_b, int32_t N_s,
+                                    int32_t He, int32_t We);
+size_t exm_trace_bwd_workspace_min(int32_t N_b, int32_t N_s, int32_t He, int32_t We);
 
 #ifdef __cplusplus
 }

@@ -84,8 +84,13 @@ def _load() -> C.CDLL:
         "exm_shade_fwd_counted": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp, vp]),
         "exm_trace_indirect_counted": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp,
                                             vp]),
-        "exm_shade_bwd": (st, [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
-        "exm_trace_bwd": (st, [vp, vp, vp, vp, i32, vp, vp, vp, C.c_float, vp, vp, vp, vp, vp, vp]),
+        "exm_shade_bwd": (st, [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
+        "exm_trace_bwd": (st, [vp, vp, vp, vp, i32, vp, vp, vp, C.c_float, vp, vp, vp, vp, vp, vp, C.c_size_t,
+                               vp]),
+        "exm_shade_bwd_workspace_size": (C.c_size_t, [i32, i32, i32, i32, i32, i32]),
+        "exm_shade_bwd_workspace_min": (C.c_size_t, [i32, i32, i32]),
+        "exm_trace_bwd_workspace_size": (C.c_size_t, [i32, i32, i32, i32, i32, i32, i32]),
+        "exm_trace_bwd_workspace_min": (C.c_size_t, [i32, i32, i32, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -276,19 +281,36 @@ def exm_trace_indirect_counted(mesh, bvh: Bvh, mat, env, cams, tri_id, bary, p: 
            "exm_trace_indirect_counted")
 
 
-def exm_shade_bwd(mesh, mat, env, cams, tri_id, bary, p: exm_params, dI, vis, dtex, denv, stream=None) -> None:
+def exm_shade_bwd_workspace_size(nViews: int, H: int, W: int, N_d: int, He: int, We: int) -> int:
+    return int(lib.exm_shade_bwd_workspace_size(nViews, H, W, N_d, He, We))
+
+
+def exm_shade_bwd_workspace_min(N_d: int, He: int, We: int) -> int:
+    return int(lib.exm_shade_bwd_workspace_min(N_d, He, We))
+
+
+def exm_trace_bwd_workspace_size(nViews: int, H: int, W: int, N_b: int, N_s: int, He: int, We: int) -> int:
+    return int(lib.exm_trace_bwd_workspace_size(nViews, H, W, N_b, N_s, He, We))
+
+
+def exm_trace_bwd_workspace_min(N_b: int, N_s: int, He: int, We: int) -> int:
+    return int(lib.exm_trace_bwd_workspace_min(N_b, N_s, He, We))
+
+
+def exm_shade_bwd(mesh, mat, env, cams, tri_id, bary, p: exm_params, dI, vis, dtex, denv, ws,
+                  stream=None) -> None:
     import torch
     n, H, W = len(cams), cams[0].H, cams[0].W
     _need(dI, torch.float32, (n, H, W, 3), "dI")
     _need(dtex, torch.float32, (mat.Ht, mat.Wt, 8), "dtex")
     _need(denv, torch.float64, (env.He, env.We, 3), "denv")
     _check(lib.exm_shade_bwd(C.byref(mesh), C.byref(mat), C.byref(env), cams, n, _ptr(tri_id), _ptr(bary),
-                             C.byref(p), _ptr(dI), _ptr(vis), _ptr(dtex), _ptr(denv), _stream(stream)),
-           "exm_shade_bwd")
+                             C.byref(p), _ptr(dI), _ptr(vis), _ptr(dtex), _ptr(denv), _ptr(ws), ws.numel(),
+                             _stream(stream)), "exm_shade_bwd")
 
 
 def exm_trace_bwd(mesh, mat, env, cams, tri_id, bary, p: exm_params, lambda_ind: float, dI, sec_rec, sec_vis,
-                  dtex, denv, stream=None) -> None:
+                  dtex, denv, ws, stream=None) -> None:
     import torch
     n, H, W = len(cams), cams[0].H, cams[0].W
     _need(dI, torch.float32, (n, H, W, 3), "dI")
@@ -296,4 +318,4 @@ def exm_trace_bwd(mesh, mat, env, cams, tri_id, bary, p: exm_params, lambda_ind:
     _need(denv, torch.float64, (env.He, env.We, 3), "denv")
     _check(lib.exm_trace_bwd(C.byref(mesh), C.byref(mat), C.byref(env), cams, n, _ptr(tri_id), _ptr(bary),
                              C.byref(p), float(lambda_ind), _ptr(dI), _ptr(sec_rec), _ptr(sec_vis), _ptr(dtex),
-                             _ptr(denv), _stream(stream)), "exm_trace_bwd")
+                             _ptr(denv), _ptr(ws), ws.numel(), _stream(stream)), "exm_trace_bwd")

@@ -354,9 +354,33 @@ exm_status exm_trace_indirect_counted(const exm_mesh* m, const exm_bvh* bvh, con
                              counters, stream);
 }
 
+size_t exm_shade_bwd_workspace_size(int32_t nViews, int32_t H, int32_t W, int32_t N_d, int32_t He, int32_t We) {
+  if (nViews <= 0 || H <= 0 || W <= 0 || N_d < 0 || N_d > 64 || He < 1 || We < 2) return 0;
+  const int32_t n = std::min(nViews, kViewsPerLaunch);
+  return shade_bwd_ws_bytes((int64_t)n * H * W, N_d, He, We);
+}
+
+size_t exm_shade_bwd_workspace_min(int32_t N_d, int32_t He, int32_t We) {
+  if (N_d < 0 || N_d > 64 || He < 1 || We < 2) return 0;
+  return shade_bwd_ws_min(N_d, He, We);
+}
+
+size_t exm_trace_bwd_workspace_size(int32_t nViews, int32_t H, int32_t W, int32_t N_b, int32_t N_s, int32_t He,
+                                    int32_t We) {
+  if (nViews <= 0 || H <= 0 || W <= 0 || N_b < 0 || N_s < 0 || (int64_t)N_b * N_s > 64 || He < 1 || We < 2) return 0;
+  const int32_t n = std::min(nViews, kViewsPerLaunch);
+  return trace_bwd_ws_bytes((int64_t)n * H * W, N_b, N_s, He, We);
+}
+
+size_t exm_trace_bwd_workspace_min(int32_t N_b, int32_t N_s, int32_t He, int32_t We) {
+  if (N_b < 0 || N_s < 0 || (int64_t)N_b * N_s > 64 || He < 1 || We < 2) return 0;
+  return trace_bwd_ws_min(N_b, N_s, He, We);
+}
+
 exm_status exm_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const exm_camera* cams,
                          int32_t nViews, const int32_t* tri_id, const float* bary, const exm_params* p, const float* dI,
-                         const uint64_t* vis, float* dtex, double* denv, hipStream_t stream) {
+                         const uint64_t* vis, float* dtex, double* denv, void* ws, size_t ws_bytes,
+                         hipStream_t stream) {
   EXM_TRY(check_mesh(m, true));
   EXM_TRY(check_material(mat));
   EXM_TRY(check_env(env));
@@ -364,12 +388,14 @@ exm_status exm_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_e
   EXM_TRY(check_gbuffer(tri_id, bary));
   EXM_TRY(check_params(p, false));
   if (!dI || !vis || !dtex || !denv) return fail(EXM_E_INVAL, "gradient pointer is NULL");
+  if (!ws || !aligned(ws, 256) || ws_bytes < shade_bwd_ws_min(p->N_d, env->He, env->We))
+    return fail(EXM_E_INVAL, "workspace must be 256-byte aligned and at least exm_shade_bwd_workspace_min bytes");
   EXM_TRY(check_device());
   const int64_t HW = (int64_t)cams[0].H * cams[0].W;
   for (int32_t v0 = 0; v0 < nViews; v0 += kViewsPerLaunch) {
     const int32_t n = std::min(kViewsPerLaunch, nViews - v0);
     hipError_t e = launch_shade_bwd(m, mat, env, shade_views(cams, v0, n), tri_id + v0 * HW, bary + 2 * v0 * HW, p,
-                                    dI + 3 * v0 * HW, vis + v0 * HW, dtex, denv, stream);
+                                    dI + 3 * v0 * HW, vis + v0 * HW, dtex, denv, ws, ws_bytes, stream);
     if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_shade_bwd: ") + hipGetErrorString(e));
   }
   return EXM_OK;
@@ -378,7 +404,7 @@ exm_status exm_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_e
 exm_status exm_trace_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const exm_camera* cams,
                          int32_t nViews, const int32_t* tri_id, const float* bary, const exm_params* p,
                          float lambda_ind, const float* dI, const exm_sec_rec* sec_rec, const uint64_t* sec_vis,
-                         float* dtex, double* denv, hipStream_t stream) {
+                         float* dtex, double* denv, void* ws, size_t ws_bytes, hipStream_t stream) {
   EXM_TRY(check_mesh(m, true));
   EXM_TRY(check_material(mat));
   EXM_TRY(check_env(env));
@@ -387,13 +413,15 @@ exm_status exm_trace_bwd(const exm_mesh* m, const exm_material* mat, const exm_e
   EXM_TRY(check_params(p, true));
   if (!std::isfinite(lambda_ind)) return fail(EXM_E_INVAL, "lambda_ind must be finite");
   if (!dI || !sec_vis || !dtex || !denv || (!sec_rec && p->N_b > 0)) return fail(EXM_E_INVAL, "pointer is NULL");
+  if (!ws || !aligned(ws, 256) || ws_bytes < trace_bwd_ws_min(p->N_b, p->N_s, env->He, env->We))
+    return fail(EXM_E_INVAL, "workspace must be 256-byte aligned and at least exm_trace_bwd_workspace_min bytes");
   EXM_TRY(check_device());
   const int64_t HW = (int64_t)cams[0].H * cams[0].W;
   for (int32_t v0 = 0; v0 < nViews; v0 += kViewsPerLaunch) {
     const int32_t n = std::min(kViewsPerLaunch, nViews - v0);
     hipError_t e = launch_trace_bwd(m, mat, env, shade_views(cams, v0, n), tri_id + v0 * HW, bary + 2 * v0 * HW, p,
                                     lambda_ind, dI + 3 * v0 * HW, sec_rec ? sec_rec + v0 * HW * p->N_b : nullptr,
-                                    sec_vis + v0 * HW, dtex, denv, stream);
+                                    sec_vis + v0 * HW, dtex, denv, ws, ws_bytes, stream);
     if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_trace_bwd: ") + hipGetErrorString(e));
   }
   return EXM_OK;

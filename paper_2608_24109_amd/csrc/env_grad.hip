@@ -1,0 +1,136 @@
+// Binned reduction of env-gradient records (counting sort by bucket, LDS sums per bucket).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "env_grad.h"
+
+namespace exm {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kSortBlocks = 1024;     // grid of the histogram and scatter passes
+constexpr int kMaxLdsBuckets = 8192;  // He * We <= 2^24 texels
+
+__global__ __launch_bounds__(kThreads) void k_clear(uint32_t* counter, uint32_t* bucket_count, int32_t B) {
+  const int32_t i = blockIdx.x * kThreads + threadIdx.x;
+  if (i == 0) *counter = 0u;
+  if (i <= B) bucket_count[i] = 0u;
+}
+
+// unused slots carry kNoTexel; any other texel outside the buckets is dropped as well
+__device__ __forceinline__ bool valid(const EnvGradWs& w, uint32_t t) {
+  return (t >> kBucketShift) < (uint32_t)w.n_buckets;
+}
+
+__device__ __forceinline__ uint32_t n_records(const EnvGradWs& w) {
+  return (uint32_t)min((int64_t)*w.counter, w.cap);
+}
+
+// global bucket sizes
+__global__ __launch_bounds__(kThreads) void k_hist(EnvGradWs w) {
+  __shared__ uint32_t h[kMaxLdsBuckets];
+  for (int32_t b = threadIdx.x; b < w.n_buckets; b += kThreads) h[b] = 0u;
+  __syncthreads();
+  const uint32_t n = n_records(w);
+  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+    const uint32_t t = w.rec[i].texel;
+    if (valid(w, t)) atomicAdd(&h[t >> kBucketShift], 1u);
+  }
+  __syncthreads();
+  for (int32_t b = threadIdx.x; b < w.n_buckets; b += kThreads)
+    if (h[b]) atomicAdd(&w.bucket_count[b], h[b]);
+}
+
+// exclusive scan of the bucket sizes (one block)
+__global__ __launch_bounds__(kThreads) void k_scan(EnvGradWs w) {
+  __shared__ uint32_t part[kThreads];
+  const int32_t B = w.n_buckets;
+  const int32_t per = (B + kThreads - 1) / kThreads;
+  const int32_t b0 = threadIdx.x * per, b1 = min(B, b0 + per);
+  uint32_t s = 0;
+  for (int32_t b = b0; b < b1; ++b) s += w.bucket_count[b];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int k = 0; k < kThreads; ++k) {
+      const uint32_t v = part[k];
+      part[k] = acc;
+      acc += v;
+    }
+    w.bucket_off[B] = acc;
+  }
+  __syncthreads();
+  uint32_t acc = part[threadIdx.x];
+  for (int32_t b = b0; b < b1; ++b) {
+    w.bucket_off[b] = acc;
+    w.bucket_cur[b] = acc;
+    acc += w.bucket_count[b];
+  }
+}
+
+// each block reserves its share of every bucket with one atomic, then places its records
+__global__ __launch_bounds__(kThreads) void k_scatter(EnvGradWs w) {
+  __shared__ uint32_t h[kMaxLdsBuckets];
+  for (int32_t b = threadIdx.x; b < w.n_buckets; b += kThreads) h[b] = 0u;
+  __syncthreads();
+  const uint32_t n = n_records(w);
+  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+    const uint32_t t = w.rec[i].texel;
+    if (valid(w, t)) atomicAdd(&h[t >> kBucketShift], 1u);
+  }
+  __syncthreads();
+  for (int32_t b = threadIdx.x; b < w.n_buckets; b += kThreads)
+    if (h[b]) h[b] = atomicAdd(&w.bucket_cur[b], h[b]);
+  __syncthreads();
+  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+    const EnvRec r = w.rec[i];
+    if (!valid(w, r.texel)) continue;
+    const uint32_t slot = atomicAdd(&h[r.texel >> kBucketShift], 1u);
+    w.sorted[slot] = r;
+  }
+}
+
+// one block per bucket: FP64 sums in LDS, then denv += sums
+__global__ __launch_bounds__(kThreads) void k_reduce(EnvGradWs w, int64_t n_texels, double* __restrict__ denv) {
+  __shared__ double acc[3 * kBucketTexels];
+  for (int32_t k = threadIdx.x; k < 3 * kBucketTexels; k += kThreads) acc[k] = 0.0;
+  __syncthreads();
+  const int32_t b = blockIdx.x;
+  const uint32_t r0 = w.bucket_off[b], r1 = w.bucket_off[b + 1];
+  for (uint32_t i = r0 + threadIdx.x; i < r1; i += kThreads) {
+    const EnvRec r = w.sorted[i];
+    const uint32_t t = r.texel & (kBucketTexels - 1);
+    atomicAdd(&acc[3 * t], (double)r.w[0]);
+    atomicAdd(&acc[3 * t + 1], (double)r.w[1]);
+    atomicAdd(&acc[3 * t + 2], (double)r.w[2]);
+  }
+  __syncthreads();
+  if (r1 == r0) return;
+  const int64_t base = (int64_t)b * kBucketTexels;
+  for (int32_t k = threadIdx.x; k < 3 * kBucketTexels; k += kThreads) {
+    const int64_t t = base + k / 3;
+    if (t < n_texels && acc[k] != 0.0) denv[3 * base + k] += acc[k];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_env_grad_clear(const EnvGradWs& w, hipStream_t s) {
+  const int32_t n = w.n_buckets + 1;
+  k_clear<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(w.counter, w.bucket_count, w.n_buckets);
+  return hipGetLastError();
+}
+
+hipError_t launch_env_grad_reduce(const EnvGradWs& w, int32_t He, int32_t We, double* denv, hipStream_t s) {
+  if (w.n_buckets > kMaxLdsBuckets) return hipErrorInvalidValue;  // the ABI bounds He * We
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kSortBlocks, (w.cap + kThreads - 1) / kThreads));
+  k_hist<<<grid, kThreads, 0, s>>>(w);
+  k_scan<<<1, kThreads, 0, s>>>(w);
+  k_scatter<<<grid, kThreads, 0, s>>>(w);
+  k_reduce<<<(unsigned)w.n_buckets, kThreads, 0, s>>>(w, (int64_t)He * We, denv);
+  return hipGetLastError();
+}
+
+}  // namespace exm

@@ -88,7 +88,9 @@ size_t shade_fwd_ws_bytes(int64_t n_pix, int32_t N_d);
 size_t shade_fwd_ws_min(int32_t N_d);
 hipError_t launch_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const ShadeViews& v,
                             const int32_t* tri_id, const float* bary, const exm_params* p, const float* dI,
-                            const uint64_t* vis, float* dtex, double* denv, hipStream_t s);
+                            const uint64_t* vis, float* dtex, double* denv, void* ws, size_t ws_bytes, hipStream_t s);
+size_t shade_bwd_ws_bytes(int64_t n_pix, int32_t N_d, int32_t He, int32_t We);
+size_t shade_bwd_ws_min(int32_t N_d, int32_t He, int32_t We);
 hipError_t launch_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                                  const ShadeViews& v, const int32_t* tri_id, const float* bary, const exm_params* p,
                                  float* L_ind, exm_sec_rec* sec_rec, uint64_t* sec_vis, void* ws, size_t ws_bytes,
@@ -98,7 +100,9 @@ size_t trace_indirect_ws_min(int32_t N_b, int32_t N_s);
 hipError_t launch_trace_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const ShadeViews& v,
                             const int32_t* tri_id, const float* bary, const exm_params* p, float lambda_ind,
                             const float* dI, const exm_sec_rec* sec_rec, const uint64_t* sec_vis, float* dtex,
-                            double* denv, hipStream_t s);
+                            double* denv, void* ws, size_t ws_bytes, hipStream_t s);
+size_t trace_bwd_ws_bytes(int64_t n_pix, int32_t N_b, int32_t N_s, int32_t He, int32_t We);
+size_t trace_bwd_ws_min(int32_t N_b, int32_t N_s, int32_t He, int32_t We);
 
 // host SAH builder (bvh_build.cpp): fills node/triangle arrays in host memory
 struct HostBvh {

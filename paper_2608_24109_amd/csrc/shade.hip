@@ -15,13 +15,15 @@
 // Adjoint, per covered pixel with upstream g = dLoss/dL_dir: the same samples again (same RNG
 // counters), skipping those whose bit is clear; accumulates d/d(a, r, m, n_s) over samples,
 // maps d/dn_s through the normalisation to d/dq of the normal map, and scatters the eight
-// channel gradients to the four bilinear taps; dLoss/dE of each sample goes to its env texel.
-// The pdf and every discrete choice are held fixed.
+// channel gradients to the four bilinear taps; dLoss/dE of each sample becomes a record that
+// the binned reduction of env_grad.hip adds to its env texel. The pdf and every discrete choice
+// are held fixed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdlib>
 
+#include "env_grad.h"
 #include "exm_device.h"
 #include "exm_rays.h"
 
@@ -259,20 +261,29 @@ __device__ __forceinline__ void scatter_tex(const Surf& S, const float g8[8], fl
 
 __global__ __launch_bounds__(kThreads) void k_shade_bwd(MeshView M, TexView T, EnvView E, ShadeViews V,
                                                         const int32_t* __restrict__ tri_id,
-                                                        const float* __restrict__ bary, KParams p,
-                                                        const float* __restrict__ dI, const uint64_t* __restrict__ vis,
-                                                        float* __restrict__ dtex, double* __restrict__ denv,
-                                                        bool use_lds) {
+                                                        const float* __restrict__ bary, KParams p, int64_t p0,
+                                                        int64_t P, const float* __restrict__ dI,
+                                                        const uint64_t* __restrict__ vis, float* __restrict__ dtex,
+                                                        EnvGradWs eg, bool use_lds) {
   extern __shared__ __align__(16) char smem[];
   const EnvTabs tb = load_env_tabs(E, smem, use_lds);
   const int64_t HW = (int64_t)V.H * V.W;
-  const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (gid >= HW * V.n) return;
-  const int32_t f = tri_id[gid];
-  uint64_t bits = vis[gid];
-  if (f < 0 || bits == 0) return;
-  const float g[3] = {dI[3 * gid], dI[3 * gid + 1], dI[3 * gid + 2]};
-  if (g[0] == 0.0f && g[1] == 0.0f && g[2] == 0.0f) return;
+  const int64_t gid = p0 + (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  // every lane stays until the wave has reserved its env-gradient records
+  bool act = gid < p0 + P && gid < HW * V.n;
+  int32_t f = -1;
+  uint64_t bits = 0;
+  float g[3] = {0.f, 0.f, 0.f};
+  if (act) {
+    f = tri_id[gid];
+    bits = vis[gid];
+    g[0] = dI[3 * gid];
+    g[1] = dI[3 * gid + 1];
+    g[2] = dI[3 * gid + 2];
+    act = f >= 0 && bits != 0 && (g[0] != 0.0f || g[1] != 0.0f || g[2] != 0.0f);
+  }
+  uint32_t slot = env_grad_reserve(eg.counter, act ? (uint32_t)__popcll(bits) : 0u);
+  if (!act) return;
   const int32_t view = (int32_t)(gid / HW);
   const uint32_t pix = (uint32_t)(gid - view * HW);
   const float2 b = reinterpret_cast<const float2*>(bary)[gid];
@@ -294,11 +305,8 @@ __global__ __launch_bounds__(kThreads) void k_shade_bwd(MeshView M, TexView T, E
     const float W[3] = {g[0] * e[0] * s, g[1] * e[1] * s, g[2] * e[2] * s};
     float fr[3];
     brdf_adjoint(S, es.dir, wo, c, p, W, fr, G);
-    double* de = denv + 3 * (int64_t)es.texel;
     const float cs = c * s;
-    unsafeAtomicAdd(de, (double)(g[0] * fr[0] * cs));
-    unsafeAtomicAdd(de + 1, (double)(g[1] * fr[1] * cs));
-    unsafeAtomicAdd(de + 2, (double)(g[2] * fr[2] * cs));
+    env_grad_put(eg, slot++, (uint32_t)es.texel, g[0] * fr[0] * cs, g[1] * fr[1] * cs, g[2] * fr[2] * cs);
   }
   float gq[3];
   normal_map_adjoint(S, G.n, gq);
@@ -364,14 +372,33 @@ size_t shade_fwd_ws_min(int32_t N_d) { return direct_ws_bytes(64, N_d); }
 
 hipError_t launch_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const ShadeViews& v,
                             const int32_t* tri_id, const float* bary, const exm_params* p, const float* dI,
-                            const uint64_t* vis, float* dtex, double* denv, hipStream_t s) {
+                            const uint64_t* vis, float* dtex, double* denv, void* ws, size_t ws_bytes, hipStream_t s) {
   const int64_t n = (int64_t)v.n * v.H * v.W;
+  const int64_t per_px = std::max(p->N_d, 0);
+  const int64_t P = env_grad_chunk(ws_bytes, per_px, env->He, env->We, n);
+  if (P <= 0) return hipErrorInvalidValue;  // the ABI layer checks the size first
   const size_t lds = env_tabs_bytes(env->He, env->We);
   const bool use_lds = lds <= kEnvTabsMaxBytes;
-  k_shade_bwd<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, use_lds ? lds : 0, s>>>(
-      mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), v, tri_id, bary, kparams(p), dI, vis, dtex,
-      denv, use_lds);
+  const KParams kp = kparams(p);
+  for (int64_t p0 = 0; p0 < n; p0 += P) {
+    const int64_t Pc = std::min<int64_t>(P, ((n - p0) + 63) / 64 * 64);
+    const EnvGradWs eg = env_grad_ws(ws, Pc * per_px, env->He, env->We);
+    hipError_t e = launch_env_grad_clear(eg, s);
+    if (e != hipSuccess) return e;
+    k_shade_bwd<<<(unsigned)((Pc + kThreads - 1) / kThreads), kThreads, use_lds ? lds : 0, s>>>(
+        mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), v, tri_id, bary, kp, p0, Pc, dI, vis, dtex,
+        eg, use_lds);
+    e = launch_env_grad_reduce(eg, env->He, env->We, denv, s);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
+}
+
+size_t shade_bwd_ws_bytes(int64_t n_pix, int32_t N_d, int32_t He, int32_t We) {
+  return env_grad_ws_bytes((n_pix + 63) / 64 * 64 * std::max(N_d, 0), He, We);
+}
+size_t shade_bwd_ws_min(int32_t N_d, int32_t He, int32_t We) {
+  return env_grad_ws_bytes(64 * (int64_t)std::max(N_d, 0), He, We);
 }
 
 }  // namespace exm

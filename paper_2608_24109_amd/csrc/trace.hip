@@ -20,6 +20,7 @@
 
 #include <algorithm>
 
+#include "env_grad.h"
 #include "exm_device.h"
 #include "exm_rays.h"
 
@@ -310,25 +311,35 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
                                                         const float* __restrict__ bary, KParams p, float lambda_ind,
                                                         const float* __restrict__ dI,
                                                         const exm_sec_rec* __restrict__ rec,
-                                                        const uint64_t* __restrict__ sec_vis,
-                                                        float* __restrict__ dtex, double* __restrict__ denv,
-                                                        bool use_lds) {
+                                                        const uint64_t* __restrict__ sec_vis, int64_t p0, int64_t P,
+                                                        float* __restrict__ dtex, EnvGradWs eg, bool use_lds) {
   extern __shared__ __align__(16) char smem[];
   const EnvTabs tb = load_env_tabs(E, smem, use_lds);
   const int64_t HW = (int64_t)V.H * V.W;
-  const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (gid >= HW * V.n) return;
-  const int32_t f = tri_id[gid];
-  if (f < 0 || p.N_b == 0) return;
-  if (p.flags & EXM_SPECULAR_ONLY) return;  // f_d = 0 at every point: no indirect light
-  const float G[3] = {lambda_ind * dI[3 * gid], lambda_ind * dI[3 * gid + 1], lambda_ind * dI[3 * gid + 2]};
-  if (G[0] == 0.0f && G[1] == 0.0f && G[2] == 0.0f) return;
+  const int64_t gid = p0 + (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  // every lane stays until the wave has reserved its env-gradient records; f_d = 0 at every
+  // point under EXM_SPECULAR_ONLY (no indirect light)
+  bool act = gid < p0 + P && gid < HW * V.n && p.N_b > 0 && !(p.flags & EXM_SPECULAR_ONLY);
+  int32_t f = -1;
+  uint64_t bits = 0;
+  float G[3] = {0.f, 0.f, 0.f};
+  if (act) {
+    f = tri_id[gid];
+    bits = sec_vis[gid];
+    G[0] = lambda_ind * dI[3 * gid];
+    G[1] = lambda_ind * dI[3 * gid + 1];
+    G[2] = lambda_ind * dI[3 * gid + 2];
+    act = f >= 0 && (G[0] != 0.0f || G[1] != 0.0f || G[2] != 0.0f);
+  }
+  const uint32_t n_rec = act ? (uint32_t)__popcll(bits) : 0u;
+  uint32_t slot = env_grad_reserve(eg.counter, n_rec);
+  if (!act) return;
+  const uint32_t slot_end = slot + n_rec;
   const int32_t view = (int32_t)(gid / HW);
   const uint32_t pix = (uint32_t)(gid - view * HW);
   const float2 b = reinterpret_cast<const float2*>(bary)[gid];
   const Surf S = query(M, T, f, b.x, b.y, p.flags);
   const uint32_t vid = (uint32_t)V.view_id[view];
-  const uint64_t bits = sec_vis[gid];
   const float invNb = 1.0f / (float)p.N_b;
   const float invNs = p.N_s > 0 ? 1.0f / (float)p.N_s : 0.0f;
   const float kdx = (1.0f - S.m) * kInvPi;
@@ -372,7 +383,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
                                      G[2] * fdx[2] * fdy[2] * Es[2]);
       gnx = gnx + sc * w;
     }
-    if (H[0] == 0.0f && H[1] == 0.0f && H[2] == 0.0f) continue;
+    if (H[0] == 0.0f && H[1] == 0.0f && H[2] == 0.0f) continue;  // its reserved records stay unused
     // secondary point: env texels, f_d(y) and n_s(y)
     float gfy[3] = {H[0] * Es[0], H[1] * Es[1], H[2] * Es[2]};
     f3 gny = mk(0, 0, 0);
@@ -383,10 +394,8 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
       const float c = dot(Y.ns, es.dir);
       const float* e = es.E;
       const float ip = es.inv_pdf * invNs;
-      double* de = denv + 3 * (int64_t)es.texel;
-      unsafeAtomicAdd(de, (double)(H[0] * fdy[0] * c * ip));
-      unsafeAtomicAdd(de + 1, (double)(H[1] * fdy[1] * c * ip));
-      unsafeAtomicAdd(de + 2, (double)(H[2] * fdy[2] * c * ip));
+      env_grad_put(eg, slot++, (uint32_t)es.texel, H[0] * fdy[0] * c * ip, H[1] * fdy[1] * c * ip,
+                   H[2] * fdy[2] * c * ip);
       const float sn = (H[0] * fdy[0] * e[0] + H[1] * fdy[1] * e[1] + H[2] * fdy[2] * e[2]) * ip;
       gny = gny + sn * es.dir;
     }
@@ -407,6 +416,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
   if (p.flags & EXM_METALLIC_OFF) gmx = 0.0f;
   nmap_adjoint(S, gnx, gqx);
   scatter7(S, gax, gmx, gqx, dtex);
+  while (slot < slot_end) env_grad_put(eg, slot++, kNoTexel, 0.f, 0.f, 0.f);
 }
 
 KParams kparams(const exm_params* p) {
@@ -463,14 +473,33 @@ size_t trace_indirect_ws_min(int32_t N_b, int32_t N_s) { return indirect_ws_byte
 hipError_t launch_trace_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const ShadeViews& v,
                             const int32_t* tri_id, const float* bary, const exm_params* p, float lambda_ind,
                             const float* dI, const exm_sec_rec* sec_rec, const uint64_t* sec_vis, float* dtex,
-                            double* denv, hipStream_t s) {
+                            double* denv, void* ws, size_t ws_bytes, hipStream_t s) {
   const int64_t n = (int64_t)v.n * v.H * v.W;
+  const int64_t per_px = (int64_t)std::max(p->N_b, 0) * std::max(p->N_s, 0);
+  const int64_t P = env_grad_chunk(ws_bytes, per_px, env->He, env->We, n);
+  if (P <= 0) return hipErrorInvalidValue;  // the ABI layer checks the size first
   const size_t lds = env_tabs_bytes(env->He, env->We);
   const bool use_lds = lds <= kEnvTabsMaxBytes;
-  k_trace_bwd<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, use_lds ? lds : 0, s>>>(
-      mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), v, tri_id, bary, kparams(p), lambda_ind, dI,
-      sec_rec, sec_vis, dtex, denv, use_lds);
+  const KParams kp = kparams(p);
+  for (int64_t p0 = 0; p0 < n; p0 += P) {
+    const int64_t Pc = std::min<int64_t>(P, ((n - p0) + 63) / 64 * 64);
+    const EnvGradWs eg = env_grad_ws(ws, Pc * per_px, env->He, env->We);
+    hipError_t e = launch_env_grad_clear(eg, s);
+    if (e != hipSuccess) return e;
+    k_trace_bwd<<<(unsigned)((Pc + kThreads - 1) / kThreads), kThreads, use_lds ? lds : 0, s>>>(
+        mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), v, tri_id, bary, kp, lambda_ind, dI,
+        sec_rec, sec_vis, p0, Pc, dtex, eg, use_lds);
+    e = launch_env_grad_reduce(eg, env->He, env->We, denv, s);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
+}
+
+size_t trace_bwd_ws_bytes(int64_t n_pix, int32_t N_b, int32_t N_s, int32_t He, int32_t We) {
+  return env_grad_ws_bytes((n_pix + 63) / 64 * 64 * std::max(N_b, 0) * std::max(N_s, 0), He, We);
+}
+size_t trace_bwd_ws_min(int32_t N_b, int32_t N_s, int32_t He, int32_t We) {
+  return env_grad_ws_bytes(64 * (int64_t)std::max(N_b, 0) * std::max(N_s, 0), He, We);
 }
 
 }  // namespace exm

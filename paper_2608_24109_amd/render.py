@@ -104,14 +104,26 @@ def render_forward(mesh: DeviceMesh, mat: DeviceMaterial, env: DeviceEnv, cams_c
                              bufs.sec_rec, bufs.sec_vis, ws, stream)
 
 
+def shade_bwd_ws_bytes(n: int, H: int, W: int, p: PassParams, He: int, We: int) -> int:
+    return max(L.exm_shade_bwd_workspace_size(n, H, W, p.N_d, He, We), L.exm_shade_bwd_workspace_min(p.N_d, He, We))
+
+
+def trace_bwd_ws_bytes(n: int, H: int, W: int, p: PassParams, He: int, We: int) -> int:
+    return max(L.exm_trace_bwd_workspace_size(n, H, W, p.N_b, p.N_s, He, We),
+               L.exm_trace_bwd_workspace_min(p.N_b, p.N_s, He, We))
+
+
 def render_backward(mesh: DeviceMesh, mat: DeviceMaterial, env: DeviceEnv, cams_c, p: PassParams,
                     bufs: PassBuffers, dI: torch.Tensor, lambda_ind: float, dtex: torch.Tensor,
                     denv: torch.Tensor, stream=None) -> None:
     pc = p.c()
-    L.exm_shade_bwd(mesh.s, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, dI, bufs.vis, dtex, denv, stream)
+    He, We = env.env.shape[:2]
+    ws = bufs.workspace(shade_bwd_ws_bytes(len(cams_c), bufs.H, bufs.W, p, He, We))
+    L.exm_shade_bwd(mesh.s, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, dI, bufs.vis, dtex, denv, ws, stream)
     if p.N_b > 0 and lambda_ind != 0.0:
+        ws = bufs.workspace(trace_bwd_ws_bytes(len(cams_c), bufs.H, bufs.W, p, He, We))
         L.exm_trace_bwd(mesh.s, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, lambda_ind, dI, bufs.sec_rec,
-                        bufs.sec_vis, dtex, denv, stream)
+                        bufs.sec_vis, dtex, denv, ws, stream)
 
 
 def _forward_chunks(tex_device, mesh, mat, env_dev, cams, p: PassParams, lambda_ind: float, chunk: int,
@@ -183,6 +195,7 @@ class RenderPBR(torch.autograd.Function):
             g = dI[k * chunk:k * chunk + bufs.n]
             render_backward(mesh, mat, env_dev, cc, p, bufs, g, lambda_ind, dtex, denv)
             bufs.drop_gbuffer()
+            bufs.ws = None
         ctx.state = None
         ctx.denv64 = denv
         return dtex, denv.to(torch.float32), None, None, None, None, None, None, None, None, None

@@ -112,6 +112,18 @@ def test_workspace_sizes(L):
     assert L.exm_shade_fwd_workspace_size(0, 8, 8, 8) == 0 and L.exm_shade_fwd_workspace_min(65) == 0
 
 
+def test_adjoint_workspace_sizes(L):
+    # one 16-byte record per env sample, twice (as appended and grouped), plus bucket tables
+    one = L.exm_shade_bwd_workspace_size(1, 1024, 1024, 64, 512, 1024)
+    assert one >= 2 * 16 * 64 * 1024 * 1024
+    assert L.exm_shade_bwd_workspace_size(16, 1024, 1024, 64, 512, 1024) == \
+        L.exm_shade_bwd_workspace_size(8, 1024, 1024, 64, 512, 1024)
+    assert L.exm_shade_bwd_workspace_min(64, 512, 1024) < one
+    assert L.exm_trace_bwd_workspace_size(1, 64, 64, 4, 4, 32, 64) >= 2 * 16 * 16 * 64 * 64
+    assert L.exm_trace_bwd_workspace_min(8, 16, 32, 64) == 0  # N_b * N_s > 64
+    assert L.exm_shade_bwd_workspace_size(1, 8, 8, 65, 32, 64) == 0
+
+
 def test_indirect_and_backward_validation(L):
     m = _mesh(L)
     cams = _cams(L)
@@ -127,12 +139,20 @@ def test_indirect_and_backward_validation(L):
                                  C.byref(p), 0x1000, 0x1000, 0x1000, 0x100000, small, None)
     assert s == L.EXM_E_INVAL and "workspace" in L.last_error()
     p = L.params(8, N_b=4, N_s=4)
+    big = 1 << 30
     s = L.lib.exm_trace_bwd(C.byref(m), C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000, C.byref(p),
-                            float("nan"), 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, None)
+                            float("nan"), 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x100000, big, None)
     assert s == L.EXM_E_INVAL
     s = L.lib.exm_shade_bwd(C.byref(m), C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000, C.byref(p),
-                            0x1000, 0x1000, None, 0x1000, None)
+                            0x1000, 0x1000, None, 0x1000, 0x100000, big, None)
     assert s == L.EXM_E_INVAL
+    small = L.exm_shade_bwd_workspace_min(8, 4, 8) - 1
+    s = L.lib.exm_shade_bwd(C.byref(m), C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000, C.byref(p),
+                            0x1000, 0x1000, 0x1000, 0x1000, 0x100000, small, None)
+    assert s == L.EXM_E_INVAL and "workspace" in L.last_error()
+    s = L.lib.exm_trace_bwd(C.byref(m), C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000, C.byref(p),
+                            1.0, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x100010, big, None)
+    assert s == L.EXM_E_INVAL and "workspace" in L.last_error()  # not 256-byte aligned
 
 
 def test_env_sampler_and_bvh_validation(L):
