@@ -123,12 +123,17 @@ def run_gpu(workload: str, steps: int, warmup: int):
         step(warm)
     torch.cuda.synchronize()
     tm = Timer(torch)
+    L.exm_timing_enable(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         step(tm)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern = tm.mean_ms()
+    gk = L.exm_timing_collect()
+    L.exm_timing_enable(False)
+    gpu_kern = {k: {"avg_ms": ms / n, "launches_per_step": n / steps, "ms_per_step": ms / steps}
+                for k, (ms, n) in gk.items()}
 
     # work counts of the workload, from the counting variants (outside the timed region)
     c_dir = torch.zeros(4, dtype=torch.uint64, device="cuda")
@@ -153,6 +158,7 @@ def run_gpu(workload: str, steps: int, warmup: int):
         stats.update(sec_rays=ci[0], sec_nodes=ci[1], sec_tris=ci[2], sec_shadow_rays=ci[3], sec_shadow_nodes=ci[4],
                      sec_shadow_tris=ci[5], sec_hits=int((bufs.sec_rec.cpu().numpy()[..., 0] >= 0).sum()),
                      sec_unoccluded=int(np.unpackbits(sv.view(np.uint8)).sum()))
+    stats["gpu_kernels"] = gpu_kern
     return sc, p, wall, kern, stats, (mesh, mat, env, bufs)
 
 
@@ -294,6 +300,27 @@ def algorithmic_bytes(kernel: str, st: dict, p) -> float:
     return float("nan")
 
 
+def kernel_bytes_per_step(kernel: str, st: dict, p) -> float:
+    """Algorithmic bytes of one GPU kernel over one step (same per-unit figures as above; the
+    ray workspace that links the wavefront kernels is this design's own traffic, not counted)."""
+    P, C = st["pixels"], st["covered"]
+    if kernel == "trace_any":  # direct shadow rays, and the secondary ones where the workload has them
+        return (33.0 * (st["shadow_rays"] + st.get("sec_shadow_rays", 0))
+                + 64.0 * (st["shadow_nodes"] + st.get("sec_shadow_nodes", 0))
+                + 48.0 * (st["shadow_tris"] + st.get("sec_shadow_tris", 0)))
+    if kernel == "trace_closest":  # ray record in, 16 B hit out
+        return 48.0 * st["sec_rays"] + 64.0 * st["sec_nodes"] + 48.0 * st["sec_tris"]
+    if kernel == "dir_gen":
+        return 12.0 * P + SURF_BYTES * C + SAMPLE_BYTES * st["samples"]
+    if kernel == "dir_finalize":
+        return 20.0 * P + 13.0 * st["shadow_rays"]
+    if kernel == "shade_bwd":
+        return 32.0 * P + (SURF_BYTES + 256.0) * C + (SAMPLE_BYTES + 16) * st["unoccluded"]
+    if kernel == "raster":
+        return st["views"] * 24.0 * st["tris"] + 8.0 * C
+    return float("nan")
+
+
 def pmc_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc summary, if it was taken
     on the current kernel sources (else None)."""
@@ -329,9 +356,10 @@ def main():
     sc, p, wall, kern, stats, _ = run_gpu(a.workload, a.steps, a.warmup)
     ms_step = wall / a.steps * 1e3
     value = stats["pixels"] / (ms_step * 1e-3) / 1e6
-    dom = max((k for k in kern if k not in ("compose", "zero_grads")), key=lambda k: kern[k])
-    alg = algorithmic_bytes(dom, stats, p)
-    achieved = alg / (kern[dom] * 1e-3) / 1e9
+    gk = stats.pop("gpu_kernels")
+    dom = max(gk, key=lambda k: gk[k]["ms_per_step"])
+    per_launch = kernel_bytes_per_step(dom, stats, p) / gk[dom]["launches_per_step"]
+    achieved = per_launch / (gk[dom]["avg_ms"] * 1e-3) / 1e9
     traffic = pmc_traffic(dom, a.workload)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mpixels/s", "n_gpus": 1, "steps": a.steps,
@@ -346,9 +374,14 @@ def main():
         "direct_shadow_Mrays_s": round(stats["shadow_rays"] / (kern["shade_fwd"] * 1e-3) / 1e6, 1),
         "nodes_per_shadow_ray": round(stats["shadow_nodes"] / max(stats["shadow_rays"], 1), 2),
         "tris_per_shadow_ray": round(stats["shadow_tris"] / max(stats["shadow_rays"], 1), 2),
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": None if traffic is None else round(traffic)},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": None if math.isnan(achieved) else round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": None if math.isnan(achieved) else round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": None if traffic is None else round(traffic),
+                     "algorithmic_bytes_per_launch": None if math.isnan(per_launch) else round(per_launch),
+                     "avg_launch_ms": round(gk[dom]["avg_ms"], 4)},
+        "gpu_kernels_ms": {k: round(v["avg_ms"], 4) for k, v in sorted(gk.items(), key=lambda kv: -kv[1]["ms_per_step"])},
+        "gpu_kernel_launches_per_step": {k: v["launches_per_step"] for k, v in gk.items()},
         "algorithmic_GBps": {k: round(algorithmic_bytes(k, stats, p) / (kern[k] * 1e-3) / 1e9, 1)
                              for k in kern if not math.isnan(algorithmic_bytes(k, stats, p))},
     }
@@ -360,7 +393,9 @@ def main():
             "workload": "tori: 1M tris, 8 views 1024x1024, 2048^2 maps, N_d=64, N_b=4, N_s=4, fwd+bwd",
             "indirect_Mrays_s": round(rays / (kern2["trace_indirect"] * 1e-3) / 1e6, 1),
             "fwd_bwd_Mpixels_s": round(st2["pixels"] / (wall2 / max(2, a.steps // 3)) / 1e6, 3),
-            "kernels_ms": {k: round(v, 3) for k, v in kern2.items()}}
+            "kernels_ms": {k: round(v, 3) for k, v in kern2.items()},
+            "gpu_kernels_ms": {k: round(v["avg_ms"], 4) for k, v in
+                               sorted(st2["gpu_kernels"].items(), key=lambda kv: -kv[1]["ms_per_step"])}}
         log("tori32 (autograd.Function, checkpointed)")
         out["checkpointed_32view"] = run_c3(max(2, a.steps // 5), 1)
         log(f"relight service, {a.relight_seconds:g} s stream")

@@ -224,6 +224,18 @@ size_t exm_trace_bwd_workspace_size(int32_t nViews, int32_t H, int32_t W, int32_
                                     int32_t He, int32_t We);
 size_t exm_trace_bwd_workspace_min(int32_t N_b, int32_t N_s, int32_t He, int32_t We);
 
+/* Measurement hooks. With timing enabled, every kernel the library launches is bracketed by
+ * two HIP events recorded on its launch stream (no events exist while it is off).
+ * exm_timing_enable clears the records; exm_timing_collect waits for the recorded events and
+ * adds their elapsed times to per-kernel totals, read back by index (0 <= i < count); names
+ * stay valid until the next enable. */
+exm_status exm_timing_enable(int32_t on);
+exm_status exm_timing_collect(void);
+int32_t exm_timing_count(void);
+const char* exm_timing_name(int32_t i);
+double exm_timing_total_ms(int32_t i);
+int64_t exm_timing_launches(int32_t i);
+
 #ifdef __cplusplus
 }
 #endif

@@ -91,6 +91,12 @@ def _load() -> C.CDLL:
         "exm_shade_bwd_workspace_min": (C.c_size_t, [i32, i32, i32]),
         "exm_trace_bwd_workspace_size": (C.c_size_t, [i32, i32, i32, i32, i32, i32, i32]),
         "exm_trace_bwd_workspace_min": (C.c_size_t, [i32, i32, i32, i32]),
+        "exm_timing_enable": (st, [i32]),
+        "exm_timing_collect": (st, []),
+        "exm_timing_count": (i32, []),
+        "exm_timing_name": (C.c_char_p, [i32]),
+        "exm_timing_total_ms": (C.c_double, [i32]),
+        "exm_timing_launches": (C.c_int64, [i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -319,3 +325,14 @@ def exm_trace_bwd(mesh, mat, env, cams, tri_id, bary, p: exm_params, lambda_ind:
     _check(lib.exm_trace_bwd(C.byref(mesh), C.byref(mat), C.byref(env), cams, n, _ptr(tri_id), _ptr(bary),
                              C.byref(p), float(lambda_ind), _ptr(dI), _ptr(sec_rec), _ptr(sec_vis), _ptr(dtex),
                              _ptr(denv), _ptr(ws), ws.numel(), _stream(stream)), "exm_trace_bwd")
+
+
+def exm_timing_enable(on: bool) -> None:
+    _check(lib.exm_timing_enable(1 if on else 0), "exm_timing_enable")
+
+
+def exm_timing_collect() -> dict:
+    """{kernel name: (total ms, launches)} of the launches recorded since timing was enabled."""
+    _check(lib.exm_timing_collect(), "exm_timing_collect")
+    return {lib.exm_timing_name(i).decode(): (float(lib.exm_timing_total_ms(i)), int(lib.exm_timing_launches(i)))
+            for i in range(lib.exm_timing_count())}

@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libexm.so")
 
 HIP_SOURCES = ["mesh.hip", "env_sampler.hip", "raster.hip", "shade.hip", "trace.hip", "rays.hip", "env_grad.hip"]
-CPP_SOURCES = ["abi.cpp", "bvh_build.cpp"]
+CPP_SOURCES = ["abi.cpp", "bvh_build.cpp", "timing.cpp"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include")]

@@ -4,6 +4,7 @@
 #include <algorithm>
 
 #include "env_grad.h"
+#include "exm_internal.h"
 
 namespace exm {
 namespace {
@@ -12,7 +13,7 @@ constexpr int kThreads = 256;
 constexpr int kSortBlocks = 1024;     // grid of the histogram and scatter passes
 constexpr int kMaxLdsBuckets = 8192;  // He * We <= 2^24 texels
 
-__global__ __launch_bounds__(kThreads) void k_clear(uint32_t* counter, uint32_t* bucket_count, int32_t B) {
+__global__ __launch_bounds__(kThreads) void k_eg_clear(uint32_t* counter, uint32_t* bucket_count, int32_t B) {
   const int32_t i = blockIdx.x * kThreads + threadIdx.x;
   if (i == 0) *counter = 0u;
   if (i <= B) bucket_count[i] = 0u;
@@ -28,7 +29,7 @@ __device__ __forceinline__ uint32_t n_records(const EnvGradWs& w) {
 }
 
 // global bucket sizes
-__global__ __launch_bounds__(kThreads) void k_hist(EnvGradWs w) {
+__global__ __launch_bounds__(kThreads) void k_eg_hist(EnvGradWs w) {
   __shared__ uint32_t h[kMaxLdsBuckets];
   for (int32_t b = threadIdx.x; b < w.n_buckets; b += kThreads) h[b] = 0u;
   __syncthreads();
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(kThreads) void k_hist(EnvGradWs w) {
 }
 
 // exclusive scan of the bucket sizes (one block)
-__global__ __launch_bounds__(kThreads) void k_scan(EnvGradWs w) {
+__global__ __launch_bounds__(kThreads) void k_eg_scan(EnvGradWs w) {
   __shared__ uint32_t part[kThreads];
   const int32_t B = w.n_buckets;
   const int32_t per = (B + kThreads - 1) / kThreads;
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(EnvGradWs w) {
 }
 
 // each block reserves its share of every bucket with one atomic, then places its records
-__global__ __launch_bounds__(kThreads) void k_scatter(EnvGradWs w) {
+__global__ __launch_bounds__(kThreads) void k_eg_scatter(EnvGradWs w) {
   __shared__ uint32_t h[kMaxLdsBuckets];
   for (int32_t b = threadIdx.x; b < w.n_buckets; b += kThreads) h[b] = 0u;
   __syncthreads();
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(EnvGradWs w) {
 }
 
 // one block per bucket: FP64 sums in LDS, then denv += sums
-__global__ __launch_bounds__(kThreads) void k_reduce(EnvGradWs w, int64_t n_texels, double* __restrict__ denv) {
+__global__ __launch_bounds__(kThreads) void k_eg_reduce(EnvGradWs w, int64_t n_texels, double* __restrict__ denv) {
   __shared__ double acc[3 * kBucketTexels];
   for (int32_t k = threadIdx.x; k < 3 * kBucketTexels; k += kThreads) acc[k] = 0.0;
   __syncthreads();
@@ -119,17 +120,32 @@ __global__ __launch_bounds__(kThreads) void k_reduce(EnvGradWs w, int64_t n_texe
 
 hipError_t launch_env_grad_clear(const EnvGradWs& w, hipStream_t s) {
   const int32_t n = w.n_buckets + 1;
-  k_clear<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(w.counter, w.bucket_count, w.n_buckets);
+  {
+    EXM_TIMED("env_grad_clear", s);
+    k_eg_clear<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(w.counter, w.bucket_count, w.n_buckets);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_env_grad_reduce(const EnvGradWs& w, int32_t He, int32_t We, double* denv, hipStream_t s) {
   if (w.n_buckets > kMaxLdsBuckets) return hipErrorInvalidValue;  // the ABI bounds He * We
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kSortBlocks, (w.cap + kThreads - 1) / kThreads));
-  k_hist<<<grid, kThreads, 0, s>>>(w);
-  k_scan<<<1, kThreads, 0, s>>>(w);
-  k_scatter<<<grid, kThreads, 0, s>>>(w);
-  k_reduce<<<(unsigned)w.n_buckets, kThreads, 0, s>>>(w, (int64_t)He * We, denv);
+  {
+    EXM_TIMED("env_grad_hist", s);
+    k_eg_hist<<<grid, kThreads, 0, s>>>(w);
+  }
+  {
+    EXM_TIMED("env_grad_scan", s);
+    k_eg_scan<<<1, kThreads, 0, s>>>(w);
+  }
+  {
+    EXM_TIMED("env_grad_scatter", s);
+    k_eg_scatter<<<grid, kThreads, 0, s>>>(w);
+  }
+  {
+    EXM_TIMED("env_grad_reduce", s);
+    k_eg_reduce<<<(unsigned)w.n_buckets, kThreads, 0, s>>>(w, (int64_t)He * We, denv);
+  }
   return hipGetLastError();
 }
 

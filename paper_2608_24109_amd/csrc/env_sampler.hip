@@ -171,13 +171,31 @@ hipError_t launch_env_sampler(const float* env, int32_t He, int32_t We, uint64_t
                               float* pdf, uint32_t* guide, float* rec, hipStream_t s) {
   // the pdf buffer (He*We floats) holds the He u64 row totals between k_quantise and k_row_scan
   uint64_t* row_tot = reinterpret_cast<uint64_t*>(pdf);
-  k_weights<<<He, kThreads, 0, s>>>(env, He, We, cdf_row, cdf_col);
-  k_quantise<<<He, kThreads, 0, s>>>(He, We, cdf_row, cdf_col, row_tot);
-  k_row_scan<<<1, kThreads, 0, s>>>(He, row_tot, cdf_row);
-  k_pdf<<<He, kThreads, 0, s>>>(env, He, We, cdf_row, cdf_col, pdf, reinterpret_cast<float4*>(rec));
-  k_guide_rows<<<1, kThreads, 0, s>>>(He, We, cdf_row, cdf_col, guide);
+  {
+    EXM_TIMED("env_weights", s);
+    k_weights<<<He, kThreads, 0, s>>>(env, He, We, cdf_row, cdf_col);
+  }
+  {
+    EXM_TIMED("env_quantise", s);
+    k_quantise<<<He, kThreads, 0, s>>>(He, We, cdf_row, cdf_col, row_tot);
+  }
+  {
+    EXM_TIMED("env_row_scan", s);
+    k_row_scan<<<1, kThreads, 0, s>>>(He, row_tot, cdf_row);
+  }
+  {
+    EXM_TIMED("env_pdf", s);
+    k_pdf<<<He, kThreads, 0, s>>>(env, He, We, cdf_row, cdf_col, pdf, reinterpret_cast<float4*>(rec));
+  }
+  {
+    EXM_TIMED("env_guide_rows", s);
+    k_guide_rows<<<1, kThreads, 0, s>>>(He, We, cdf_row, cdf_col, guide);
+  }
   const int64_t nc = (int64_t)He * (We + 1);
-  k_guide_cols<<<(unsigned)((nc + kThreads - 1) / kThreads), kThreads, 0, s>>>(He, We, cdf_col, guide);
+  {
+    EXM_TIMED("env_guide_cols", s);
+    k_guide_cols<<<(unsigned)((nc + kThreads - 1) / kThreads), kThreads, 0, s>>>(He, We, cdf_col, guide);
+  }
   return hipGetLastError();
 }
 

@@ -71,6 +71,22 @@ inline size_t env_guide_len(int32_t He, int32_t We) {
   return (size_t)He * (size_t)(We + 3) + 2;
 }
 
+// Brackets one kernel launch with HIP events on its stream when timing is enabled
+// (exm_timing_enable); names are string literals.
+class KernelTimer {
+ public:
+  KernelTimer(const char* name, hipStream_t s);
+  ~KernelTimer();
+  KernelTimer(const KernelTimer&) = delete;
+  KernelTimer& operator=(const KernelTimer&) = delete;
+
+ private:
+  const char* name_;
+  hipStream_t s_;
+  hipEvent_t a_ = nullptr;
+};
+#define EXM_TIMED(name, stream) ::exm::KernelTimer exm_kernel_timer_(name, stream)
+
 // error reporting (thread-local last error)
 exm_status fail(exm_status s, const std::string& msg);
 exm_status check_launch(const char* what);

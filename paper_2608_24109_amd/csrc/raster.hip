@@ -182,12 +182,21 @@ hipError_t launch_raster(const exm_mesh* m, const RasterViews& v, int32_t* tri_i
   const int64_t n = (int64_t)v.n * v.H * v.W;
   unsigned long long* keys = reinterpret_cast<unsigned long long*>(bary);
   const unsigned nb = (unsigned)((n + kThreads - 1) / kThreads);
-  k_clear<<<nb, kThreads, 0, s>>>(n, keys);
+  {
+    EXM_TIMED("raster_clear", s);
+    k_clear<<<nb, kThreads, 0, s>>>(n, keys);
+  }
   if (m->nF > 0) {
     dim3 grid((m->nF + kThreads - 1) / kThreads, v.n);
-    k_raster<<<grid, kThreads, 0, s>>>(m->nF, m->pos, m->tri, v, keys);
+    {
+      EXM_TIMED("raster", s);
+      k_raster<<<grid, kThreads, 0, s>>>(m->nF, m->pos, m->tri, v, keys);
+    }
   }
-  k_resolve<<<nb, kThreads, 0, s>>>(m->pos, m->tri, v, tri_id, bary);
+  {
+    EXM_TIMED("raster_resolve", s);
+    k_resolve<<<nb, kThreads, 0, s>>>(m->pos, m->tri, v, tri_id, bary);
+  }
   return hipGetLastError();
 }
 

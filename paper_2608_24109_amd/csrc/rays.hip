@@ -115,8 +115,11 @@ hipError_t launch_impl(const exm_bvh* bvh, const RayBatch& rb, HitRec* out_hit, 
   const int64_t waves_needed = rb.n_regions;
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((waves_needed + 3) / 4, (int64_t)cus * per_cu));
   k_reset_counter<<<1, 1, 0, s>>>(rb.region_counter);
-  k_trace<ANY, COUNT><<<(unsigned)blocks, kThreads, 0, s>>>(BvhView{bvh->nodes, bvh->tris, bvh->root_is_leaf}, rb,
-                                                             ray_refill_threshold(), out_hit, out_any, counters);
+  {
+    EXM_TIMED(ANY ? "trace_any" : "trace_closest", s);
+    k_trace<ANY, COUNT><<<(unsigned)blocks, kThreads, 0, s>>>(BvhView{bvh->nodes, bvh->tris, bvh->root_is_leaf}, rb,
+                                                               ray_refill_threshold(), out_hit, out_any, counters);
+  }
   return hipGetLastError();
 }
 

@@ -351,18 +351,24 @@ hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_mat
   for (int64_t p0 = 0; p0 < n; p0 += P) {
     const int64_t Pc = std::min<int64_t>(P, ((n - p0) + 63) / 64 * 64);
     const unsigned nb = (unsigned)((Pc + kThreads - 1) / kThreads);
-    if (counters)
-      k_dir_gen<true><<<nb, kThreads, use_lds ? lds : 0, s>>>(mesh_view(m), tv, env_view(env), v, tri_id, bary, kp,
-                                                             p0, Pc, ws, counters, use_lds);
-    else
-      k_dir_gen<false><<<nb, kThreads, use_lds ? lds : 0, s>>>(mesh_view(m), tv, env_view(env), v, tri_id, bary, kp,
-                                                              p0, Pc, ws, nullptr, use_lds);
+    {
+      EXM_TIMED("dir_gen", s);
+      if (counters)
+        k_dir_gen<true><<<nb, kThreads, use_lds ? lds : 0, s>>>(mesh_view(m), tv, env_view(env), v, tri_id, bary, kp,
+                                                               p0, Pc, ws, counters, use_lds);
+      else
+        k_dir_gen<false><<<nb, kThreads, use_lds ? lds : 0, s>>>(mesh_view(m), tv, env_view(env), v, tri_id, bary, kp,
+                                                                p0, Pc, ws, nullptr, use_lds);
+    }
     if (trace) {
       const RayBatch rb{ws.rays, ws.count, (int32_t)(Pc / 64), 64 * (int64_t)p->N_d, ws.counter};
       const hipError_t e = launch_trace_any(bvh, rb, ws.hit, counters, s);
       if (e != hipSuccess) return e;
     }
-    k_dir_finalize<<<nb, kThreads, 0, s>>>(v, kp, p0, Pc, ws, L_dir, vis);
+    {
+      EXM_TIMED("dir_finalize", s);
+      k_dir_finalize<<<nb, kThreads, 0, s>>>(v, kp, p0, Pc, ws, L_dir, vis);
+    }
   }
   return hipGetLastError();
 }
@@ -385,9 +391,12 @@ hipError_t launch_shade_bwd(const exm_mesh* m, const exm_material* mat, const ex
     const EnvGradWs eg = env_grad_ws(ws, Pc * per_px, env->He, env->We);
     hipError_t e = launch_env_grad_clear(eg, s);
     if (e != hipSuccess) return e;
-    k_shade_bwd<<<(unsigned)((Pc + kThreads - 1) / kThreads), kThreads, use_lds ? lds : 0, s>>>(
-        mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), v, tri_id, bary, kp, p0, Pc, dI, vis, dtex,
-        eg, use_lds);
+    {
+      EXM_TIMED("shade_bwd", s);
+      k_shade_bwd<<<(unsigned)((Pc + kThreads - 1) / kThreads), kThreads, use_lds ? lds : 0, s>>>(
+          mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), v, tri_id, bary, kp, p0, Pc, dI, vis, dtex,
+          eg, use_lds);
+    }
     e = launch_env_grad_reduce(eg, env->He, env->We, denv, s);
     if (e != hipSuccess) return e;
   }

@@ -448,19 +448,28 @@ hipError_t launch_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const ex
     const int64_t Pc = std::min<int64_t>(P, ((n - p0) + 63) / 64 * 64);
     const unsigned nb = (unsigned)((Pc + kThreads - 1) / kThreads);
     if (p->N_b > 0) {
-      k_ind_gen1<<<nb, kThreads, 0, s>>>(mesh_view(m), v, tri_id, bary, kp, p0, Pc, ws);
+      {
+        EXM_TIMED("ind_gen1", s);
+        k_ind_gen1<<<nb, kThreads, 0, s>>>(mesh_view(m), v, tri_id, bary, kp, p0, Pc, ws);
+      }
       const RayBatch rb1{ws.sec_rays, ws.sec_count, (int32_t)(Pc / 64), 64 * (int64_t)p->N_b, ws.counter};
       hipError_t e = launch_trace_closest(bvh, rb1, ws.sec_hits, counters, s);
       if (e != hipSuccess) return e;
     }
-    k_ind_gen2<<<nb, kThreads, use_lds ? lds : 0, s>>>(mesh_view(m), tv, env_view(env), v, tri_id, bary, kp, p0,
-                                                       Pc, ws, sec_rec, use_lds);
+    {
+      EXM_TIMED("ind_gen2", s);
+      k_ind_gen2<<<nb, kThreads, use_lds ? lds : 0, s>>>(mesh_view(m), tv, env_view(env), v, tri_id, bary, kp, p0,
+                                                         Pc, ws, sec_rec, use_lds);
+    }
     if (vis_rays && p->N_b > 0) {
       const RayBatch rb2{ws.sh_rays, ws.sh_count, (int32_t)(Pc / 64), 64 * (int64_t)p->N_b * p->N_s, ws.counter};
       hipError_t e = launch_trace_any(bvh, rb2, ws.sh_hit, counters ? counters + 3 : nullptr, s);
       if (e != hipSuccess) return e;
     }
-    k_ind_finalize<<<nb, kThreads, 0, s>>>(v, kp, p0, Pc, ws, L_ind, sec_vis);
+    {
+      EXM_TIMED("ind_finalize", s);
+      k_ind_finalize<<<nb, kThreads, 0, s>>>(v, kp, p0, Pc, ws, L_ind, sec_vis);
+    }
   }
   return hipGetLastError();
 }
@@ -486,9 +495,12 @@ hipError_t launch_trace_bwd(const exm_mesh* m, const exm_material* mat, const ex
     const EnvGradWs eg = env_grad_ws(ws, Pc * per_px, env->He, env->We);
     hipError_t e = launch_env_grad_clear(eg, s);
     if (e != hipSuccess) return e;
-    k_trace_bwd<<<(unsigned)((Pc + kThreads - 1) / kThreads), kThreads, use_lds ? lds : 0, s>>>(
-        mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), v, tri_id, bary, kp, lambda_ind, dI,
-        sec_rec, sec_vis, p0, Pc, dtex, eg, use_lds);
+    {
+      EXM_TIMED("trace_bwd", s);
+      k_trace_bwd<<<(unsigned)((Pc + kThreads - 1) / kThreads), kThreads, use_lds ? lds : 0, s>>>(
+          mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), v, tri_id, bary, kp, lambda_ind, dI,
+          sec_rec, sec_vis, p0, Pc, dtex, eg, use_lds);
+    }
     e = launch_env_grad_reduce(eg, env->He, env->We, denv, s);
     if (e != hipSuccess) return e;
   }

@@ -21,14 +21,22 @@ from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# ABI call -> kernel symbol fragment
+# timing name (the library's per-kernel timing hooks) -> kernel symbol fragment
 KERNELS = {
-    "shade_fwd": "k_shade_fwd<false>",
+    "trace_any": "k_trace<true,false>",
+    "trace_closest": "k_trace<false,false>",
+    "dir_gen": "k_dir_gen<false>",
+    "dir_finalize": "k_dir_finalize",
     "shade_bwd": "k_shade_bwd",
-    "trace_indirect": "k_trace_indirect<false>",
+    "ind_gen1": "k_ind_gen1",
+    "ind_gen2": "k_ind_gen2",
+    "ind_finalize": "k_ind_finalize",
     "trace_bwd": "k_trace_bwd",
+    "env_grad_hist": "k_eg_hist",
+    "env_grad_scatter": "k_eg_scatter",
+    "env_grad_reduce": "k_eg_reduce",
     "raster": "k_raster",
-    "resolve": "k_resolve",
+    "raster_resolve": "k_resolve",
 }
 COPY_KERNEL = "copyBuffer"
 

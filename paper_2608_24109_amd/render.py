@@ -34,8 +34,10 @@ class PassParams:
                         self.f_diel, self.eps, self.tmin, self.flags)
 
 
-# Upper bound of the ray workspace a pass allocates; larger passes run in pixel chunks.
-WORKSPACE_CAP = 4 << 30
+# Upper bound of the ray workspace a pass allocates; larger passes run in pixel chunks. 24 GiB
+# holds the direct pass of 8 views of 1024^2 at N_d = 64 in one chunk (one traversal launch per
+# pass, so one tail), a small share of the 288 GB of HBM.
+WORKSPACE_CAP = 24 << 30
 
 
 class PassBuffers:
