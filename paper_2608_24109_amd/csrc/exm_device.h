@@ -183,46 +183,110 @@ __device__ __forceinline__ EnvTabs load_env_tabs(const EnvView& e, void* lds, bo
   return t;
 }
 
-__device__ __forceinline__ EnvSample env_sample(const EnvView& e, const EnvTabs& tb, const Draw& d) {
+// K independent picks advanced stage by stage (rows in LDS, then the K cutpoint pairs, a
+// lockstep column search, the K records), so that each thread has K loads in flight at every
+// stage; every pick is the one a lone search returns. Picks with valid[j] false read nothing
+// and leave out[j] untouched.
+template <int K>
+__device__ __forceinline__ void env_sample_k(const EnvView& e, const EnvTabs& tb, const Draw (&d)[K],
+                                             const bool (&valid)[K], EnvSample (&out)[K]) {
   const uint64_t Q = tb.cdf_row[e.He - 1];
-  const uint64_t target = __umul64hi(d.x, Q);
-  // target < Q whenever the tables are well formed; the clamps only keep a malformed table
-  // (e.g. built from a NaN map) inside the arrays
-  const uint32_t gr = (uint32_t)min(target >> tb.rguide[0], (uint64_t)(e.He - 1));
-  const int32_t row = min(upper_bound_range(tb.cdf_row, (int32_t)tb.rguide[1 + gr], (int32_t)tb.rguide[2 + gr], target),
+  int32_t row[K], lo[K], cnt[K];
+  uint64_t rem[K];
+  const uint64_t* cdf[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    // target < Q whenever the tables are well formed; the clamps only keep a malformed table
+    // (e.g. built from a NaN map) inside the arrays
+    const uint64_t target = __umul64hi(d[j].x, Q);
+    const uint32_t gr = (uint32_t)min(target >> tb.rguide[0], (uint64_t)(e.He - 1));
+    const int32_t r = min(upper_bound_range(tb.cdf_row, (int32_t)tb.rguide[1 + gr], (int32_t)tb.rguide[2 + gr], target),
                           e.He - 1);
-  const uint64_t rem = target - (row > 0 ? tb.cdf_row[row - 1] : 0ull);
-  const uint32_t gc = (uint32_t)min(rem >> tb.cshift[row], (uint64_t)(e.We - 1));
-  const uint32_t* cg = e.guide + 2 * (int64_t)e.He + 2 + (int64_t)row * (e.We + 1) + gc;
-  const int32_t col =
-      min(upper_bound_range(e.cdf_col + (int64_t)row * e.We, (int32_t)cg[0], (int32_t)cg[1], rem), e.We - 1);
-  EnvSample s;
-  s.texel = row * e.We + col;
-  const float4 rec = e.rec[s.texel];
-  // theta in [row, row+1] * pi/He with cos(theta) uniform
-  const float2 rc = tb.rowc ? tb.rowc[row] : env_row_consts(row, e.He);
-  float ct, st2;
-  if (2 * row < e.He) {
-    const float omc = rc.x + d.u3 * rc.y;  // 1 - cos(theta)
-    ct = 1.0f - omc;
-    st2 = omc * (2.0f - omc);
-  } else {
-    const float opc = rc.x + (1.0f - d.u3) * rc.y;  // 1 + cos(theta)
-    ct = opc - 1.0f;
-    st2 = opc * (2.0f - opc);
+    row[j] = r;
+    rem[j] = target - (r > 0 ? tb.cdf_row[r - 1] : 0ull);
+    cdf[j] = e.cdf_col + (int64_t)r * e.We;
   }
-  const float st = sqrtf(fmaxf(st2, 0.0f));
-  // phi = 2 pi (col + u2) / We by angle addition (keeps u2's resolution at large col)
-  const float2 cj = tb.colc ? tb.colc[col] : env_col_consts(col, e.We);
-  float sd, cd;
-  sincospif(2.0f * d.u2 / (float)e.We, &sd, &cd);
-  const float cphi = cj.y * cd - cj.x * sd, sphi = cj.x * cd + cj.y * sd;
-  s.dir = mk(st * cphi, ct, st * sphi);
-  s.inv_pdf = rec.w;
-  s.E[0] = rec.x;
-  s.E[1] = rec.y;
-  s.E[2] = rec.z;
-  return s;
+  uint32_t g0[K], g1[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    g0[j] = g1[j] = 0u;
+    if (valid[j]) {
+      const uint32_t gc = (uint32_t)min(rem[j] >> tb.cshift[row[j]], (uint64_t)(e.We - 1));
+      const uint32_t* cg = e.guide + 2 * (int64_t)e.He + 2 + (int64_t)row[j] * (e.We + 1) + gc;
+      g0[j] = cg[0];
+      g1[j] = cg[1];
+    }
+  }
+  bool more = false;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    lo[j] = (int32_t)g0[j];
+    cnt[j] = valid[j] ? max((int32_t)g1[j] - (int32_t)g0[j], 0) : 0;
+    more |= cnt[j] > 0;
+  }
+  while (more) {  // binary search over [lo, lo + cnt], one probe of every pick per round
+    uint64_t v[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      if (cnt[j] > 0) v[j] = cdf[j][lo[j] + (cnt[j] >> 1)];
+    more = false;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      if (cnt[j] > 0) {
+        const int32_t step = cnt[j] >> 1;
+        if (v[j] <= rem[j]) {
+          lo[j] += step + 1;
+          cnt[j] -= step + 1;
+        } else {
+          cnt[j] = step;
+        }
+      }
+      more |= cnt[j] > 0;
+    }
+  }
+  float4 rec[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+    if (valid[j]) rec[j] = e.rec[row[j] * e.We + min(lo[j], e.We - 1)];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    if (!valid[j]) continue;
+    const int32_t r = row[j], col = min(lo[j], e.We - 1);
+    EnvSample s;
+    s.texel = r * e.We + col;
+    // theta in [row, row+1] * pi/He with cos(theta) uniform
+    const float2 rc = tb.rowc ? tb.rowc[r] : env_row_consts(r, e.He);
+    float ct, st2;
+    if (2 * r < e.He) {
+      const float omc = rc.x + d[j].u3 * rc.y;  // 1 - cos(theta)
+      ct = 1.0f - omc;
+      st2 = omc * (2.0f - omc);
+    } else {
+      const float opc = rc.x + (1.0f - d[j].u3) * rc.y;  // 1 + cos(theta)
+      ct = opc - 1.0f;
+      st2 = opc * (2.0f - opc);
+    }
+    const float st = sqrtf(fmaxf(st2, 0.0f));
+    // phi = 2 pi (col + u2) / We by angle addition (keeps u2's resolution at large col)
+    const float2 cj = tb.colc ? tb.colc[col] : env_col_consts(col, e.We);
+    float sd, cd;
+    sincospif(2.0f * d[j].u2 / (float)e.We, &sd, &cd);
+    const float cphi = cj.y * cd - cj.x * sd, sphi = cj.x * cd + cj.y * sd;
+    s.dir = mk(st * cphi, ct, st * sphi);
+    s.inv_pdf = rec[j].w;
+    s.E[0] = rec[j].x;
+    s.E[1] = rec[j].y;
+    s.E[2] = rec[j].z;
+    out[j] = s;
+  }
+}
+
+__device__ __forceinline__ EnvSample env_sample(const EnvView& e, const EnvTabs& tb, const Draw& d) {
+  const Draw dd[1] = {d};
+  const bool ok[1] = {true};
+  EnvSample s[1];
+  env_sample_k<1>(e, tb, dd, ok, s);
+  return s[0];
 }
 
 // ------------------------------------------------------------------------------------------

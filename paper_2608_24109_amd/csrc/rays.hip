@@ -129,7 +129,7 @@ int32_t ray_refill_threshold() {
   static const int32_t v = [] {
     const char* e = getenv("EXM_RAY_REFILL");
     const int x = e ? atoi(e) : 0;
-    return (x >= 1 && x <= 64) ? x : 16;
+    return (x >= 1 && x <= 64) ? x : 48;
   }();
   return v;
 }

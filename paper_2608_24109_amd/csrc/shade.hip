@@ -31,6 +31,7 @@ namespace exm {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kPicks = 2;  // env picks in flight per thread
 
 struct KParams {
   int32_t N_d;
@@ -89,38 +90,49 @@ __global__ __launch_bounds__(kThreads) void k_dir_gen(MeshView M, TexView T, Env
   uint64_t mask = 0;
   uint32_t running = 0;  // wave-uniform
   const int64_t rbase = region * 64 * (int64_t)p.N_d;
-  for (int k = 0; k < p.N_d; ++k) {
-    bool need = false;
-    EnvSample es;
-    float c = 0.0f;
-    if (f >= 0) {
-      es = env_sample(E, tb, philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)k, 0u));
-      c = dot(S.ns, es.dir);
-      need = c > 0.0f;
+  for (int k0 = 0; k0 < p.N_d; k0 += kPicks) {
+    Draw dr[kPicks];
+    bool ok[kPicks];
+    EnvSample es[kPicks];
+#pragma unroll
+    for (int j = 0; j < kPicks; ++j) {
+      ok[j] = f >= 0 && k0 + j < p.N_d;
+      if (ok[j]) dr[j] = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)(k0 + j), 0u);
     }
-    const uint64_t bal = __ballot(need);
-    if (need) {
-      const int64_t slot = rbase + running + lanes_below(bal);
-      RayRec R;
-      R.o[0] = S.x.x;
-      R.o[1] = S.x.y;
-      R.o[2] = S.x.z;
-      R.skip = f;
-      R.d[0] = es.dir.x;
-      R.d[1] = es.dir.y;
-      R.d[2] = es.dir.z;
-      R.tmin = p.tmin;
-      ws.rays[slot] = R;
-      float fr[3];
-      brdf_eval(S, es.dir, wo, c, p, fr);
-      const float* e = es.E;
-      const float wgt = c * es.inv_pdf;
-      ws.contrib[3 * slot] = e[0] * fr[0] * wgt;
-      ws.contrib[3 * slot + 1] = e[1] * fr[1] * wgt;
-      ws.contrib[3 * slot + 2] = e[2] * fr[2] * wgt;
-      mask |= 1ull << k;
+    env_sample_k<kPicks>(E, tb, dr, ok, es);
+#pragma unroll
+    for (int j = 0; j < kPicks; ++j) {
+      const int k = k0 + j;
+      if (k >= p.N_d) break;  // wave-uniform
+      bool need = false;
+      float c = 0.0f;
+      if (ok[j]) {
+        c = dot(S.ns, es[j].dir);
+        need = c > 0.0f;
+      }
+      const uint64_t bal = __ballot(need);
+      if (need) {
+        const int64_t slot = rbase + running + lanes_below(bal);
+        RayRec R;
+        R.o[0] = S.x.x;
+        R.o[1] = S.x.y;
+        R.o[2] = S.x.z;
+        R.skip = f;
+        R.d[0] = es[j].dir.x;
+        R.d[1] = es[j].dir.y;
+        R.d[2] = es[j].dir.z;
+        R.tmin = p.tmin;
+        ws.rays[slot] = R;
+        float fr[3];
+        brdf_eval(S, es[j].dir, wo, c, p, fr);
+        const float wgt = c * es[j].inv_pdf;
+        ws.contrib[3 * slot] = es[j].E[0] * fr[0] * wgt;
+        ws.contrib[3 * slot + 1] = es[j].E[1] * fr[1] * wgt;
+        ws.contrib[3 * slot + 2] = es[j].E[2] * fr[2] * wgt;
+        mask |= 1ull << k;
+      }
+      running += (uint32_t)__popcll(bal);
     }
-    running += (uint32_t)__popcll(bal);
   }
   ws.mask[local] = mask;
   const uint64_t covered = __ballot(f >= 0);
@@ -294,19 +306,31 @@ __global__ __launch_bounds__(kThreads) void k_shade_bwd(MeshView M, TexView T, E
   SurfGrad G;
   G.a[0] = G.a[1] = G.a[2] = G.r = G.m = 0.0f;
   G.n = mk(0, 0, 0);
-  while (bits) {
-    const int k = __ffsll((long long)bits) - 1;
-    bits &= bits - 1;
-    const Draw d = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)k, 0u);
-    const EnvSample es = env_sample(E, tb, d);
-    const float c = dot(S.ns, es.dir);
-    const float* e = es.E;
-    const float s = invN * es.inv_pdf;
-    const float W[3] = {g[0] * e[0] * s, g[1] * e[1] * s, g[2] * e[2] * s};
-    float fr[3];
-    brdf_adjoint(S, es.dir, wo, c, p, W, fr, G);
-    const float cs = c * s;
-    env_grad_put(eg, slot++, (uint32_t)es.texel, g[0] * fr[0] * cs, g[1] * fr[1] * cs, g[2] * fr[2] * cs);
+  while (bits) {  // set bits in increasing order, kPicks at a time
+    Draw dr[kPicks];
+    bool ok[kPicks];
+    EnvSample es[kPicks];
+#pragma unroll
+    for (int j = 0; j < kPicks; ++j) {
+      ok[j] = bits != 0ull;
+      if (ok[j]) {
+        const int k = __ffsll((long long)bits) - 1;
+        bits &= bits - 1;
+        dr[j] = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)k, 0u);
+      }
+    }
+    env_sample_k<kPicks>(E, tb, dr, ok, es);
+#pragma unroll
+    for (int j = 0; j < kPicks; ++j) {
+      if (!ok[j]) break;
+      const float c = dot(S.ns, es[j].dir);
+      const float s = invN * es[j].inv_pdf;
+      const float W[3] = {g[0] * es[j].E[0] * s, g[1] * es[j].E[1] * s, g[2] * es[j].E[2] * s};
+      float fr[3];
+      brdf_adjoint(S, es[j].dir, wo, c, p, W, fr, G);
+      const float cs = c * s;
+      env_grad_put(eg, slot++, (uint32_t)es[j].texel, g[0] * fr[0] * cs, g[1] * fr[1] * cs, g[2] * fr[2] * cs);
+    }
   }
   float gq[3];
   normal_map_adjoint(S, G.n, gq);
