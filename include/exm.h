@@ -46,12 +46,17 @@ const char* exm_last_error(void);
 
 /* Shading flags (exm_params.flags). METALLIC_OFF fixes m = 0 (dielectric model; UV-PBR Asset
  * Decomposition section, and the Implementation details of the Experiments). DIFFUSE_ONLY /
- * SPECULAR_ONLY drop f_s / f_d of Eq. 13 (tests). NO_VIS sets Vis = 1 (tests). */
+ * SPECULAR_ONLY drop f_s / f_d of Eq. 13 (tests). NO_VIS sets Vis = 1 (tests).
+ * NO_SECONDARY_MATERIAL is the "No Secondary Material" ablation of the Ablation Study
+ * (Indirect Lighting): the maps are not queried at secondary hits, which are shaded as a grey
+ * Lambertian (albedo 0.5, metallic 0) with the interpolated geometric normal; the adjoint then
+ * sends nothing to the maps at secondary hits. */
 enum {
   EXM_METALLIC_OFF = 1u << 0,
   EXM_DIFFUSE_ONLY = 1u << 1,
   EXM_SPECULAR_ONLY = 1u << 2,
   EXM_NO_VIS = 1u << 3,
+  EXM_NO_SECONDARY_MATERIAL = 1u << 4,
 };
 
 /* Fixed mesh-UV carrier M = (V, F), UV set U and face-corner UV index Phi (UV-PBR Asset

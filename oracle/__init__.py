@@ -18,6 +18,7 @@ METALLIC_OFF = 1 << 0
 DIFFUSE_ONLY = 1 << 1
 SPECULAR_ONLY = 1 << 2
 NO_VIS = 1 << 3
+NO_SECONDARY_MATERIAL = 1 << 4  # secondary hits shaded as a grey (0.5) Lambertian with n_g
 
 
 def build() -> str:

@@ -633,6 +633,11 @@ void shade_pixel(const Scene& S, const ora_camera* cam, uint32_t pixel, int32_t 
     sec_bary[2 * j + 1] = h.b2;
     double by[3] = {1.0 - h.b1 - h.b2, h.b1, h.b2};
     Attr<T> Y = query<T>(S, h.id, by);
+    if (p->flags & ORA_NO_SECONDARY_MATERIAL) {  // the material at y is not queried
+      for (int ch = 0; ch < 3; ++ch) Y.a[ch] = T(ORA_SECONDARY_ALBEDO);
+      Y.m = T(0.0);
+      Y.ns = lift<T>(Y.ng);
+    }
     T fdy[3];
     for (int ch = 0; ch < 3; ++ch)
       fdy[ch] = (p->flags & ORA_SPECULAR_ONLY) ? T(0.0) : (T(1.0) - Y.m) * Y.a[ch] / T(kPi);

@@ -24,7 +24,12 @@ enum {
   ORA_DIFFUSE_ONLY = 1u << 1,
   ORA_SPECULAR_ONLY = 1u << 2,
   ORA_NO_VIS = 1u << 3,
+  /* "No Secondary Material" ablation (Ablation Study, Indirect Lighting): no material query at
+     secondary hits; read here as a grey Lambertian (albedo ORA_SECONDARY_ALBEDO, metallic 0)
+     with the interpolated geometric normal */
+  ORA_NO_SECONDARY_MATERIAL = 1u << 4,
 };
+#define ORA_SECONDARY_ALBEDO 0.5
 
 typedef struct {
   int32_t nV, nF, nUV;

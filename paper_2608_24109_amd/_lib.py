@@ -24,6 +24,7 @@ EXM_METALLIC_OFF = 1 << 0
 EXM_DIFFUSE_ONLY = 1 << 1
 EXM_SPECULAR_ONLY = 1 << 2
 EXM_NO_VIS = 1 << 3
+EXM_NO_SECONDARY_MATERIAL = 1 << 4
 
 
 class ExmError(RuntimeError):

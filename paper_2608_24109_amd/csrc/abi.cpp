@@ -100,7 +100,7 @@ exm_status check_params(const exm_params* p, bool indirect) {
   if (!std::isfinite(p->tmin) || p->tmin < 0.f) return fail(EXM_E_INVAL, "tmin must be finite and >= 0");
   if (!std::isfinite(p->eps) || p->eps < 0.f) return fail(EXM_E_INVAL, "eps must be finite and >= 0");
   if (!std::isfinite(p->f_diel)) return fail(EXM_E_INVAL, "f_diel must be finite");
-  if (p->flags & ~0xFu) return fail(EXM_E_INVAL, "unknown flag bits");
+  if (p->flags & ~0x1Fu) return fail(EXM_E_INVAL, "unknown flag bits");
   return EXM_OK;
 }
 

@@ -340,8 +340,13 @@ __device__ __forceinline__ void bilinear_taps(const TexView& t, double u, double
   w[3] = fs * ft;
 }
 
+// Albedo of secondary hits under EXM_NO_SECONDARY_MATERIAL (a grey Lambertian, metallic 0,
+// shading normal = n_g; the "No Secondary Material" ablation of the Ablation Study).
+constexpr float kSecondaryAlbedo = 0.5f;
+
+// with_material = false: the maps are not read (the no-secondary-material reading above).
 __device__ __forceinline__ Surf query(const MeshView& M, const TexView& T, int32_t f, float b1, float b2,
-                                      uint32_t flags) {
+                                      uint32_t flags, bool with_material = true) {
   Surf S;
   const float b0 = 1.0f - b1 - b2;
   const int32_t v0 = M.tri[3 * f], v1 = M.tri[3 * f + 1], v2 = M.tri[3 * f + 2];
@@ -349,6 +354,23 @@ __device__ __forceinline__ Surf query(const MeshView& M, const TexView& T, int32
   S.x = (b0 * P0 + b1 * P1) + b2 * P2;
   const f3 N0 = ld3d(M.vnrm, v0), N1 = ld3d(M.vnrm, v1), N2 = ld3d(M.vnrm, v2);
   S.ng = normalize((b0 * N0 + b1 * N1) + b2 * N2);
+  if (!with_material) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      S.tap[k] = 0;
+      S.w[k] = 0.0f;
+    }
+    S.a[0] = S.a[1] = S.a[2] = kSecondaryAlbedo;
+    S.r = 1.0f;
+    S.m = 0.0f;
+    S.q[0] = S.q[1] = 0.0f;
+    S.q[2] = 1.0f;
+    S.map_ok = false;
+    S.ns = S.ng;
+    S.vlen = 1.0f;
+    S.T = S.B = mk(0, 0, 0);
+    return S;
+  }
   const int32_t t0 = M.tri_uv[3 * f], t1 = M.tri_uv[3 * f + 1], t2 = M.tri_uv[3 * f + 2];
   const double d1 = b1, d2 = b2, d0 = 1.0 - d1 - d2;
   const double u = (d0 * M.uv[2 * t0] + d1 * M.uv[2 * t1]) + d2 * M.uv[2 * t2];

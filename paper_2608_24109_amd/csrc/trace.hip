@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kThreads) void k_ind_gen2(MeshView M, TexView T, En
         refine_hit(M, h.id, sr, &h.b1, &h.b2);
         r = exm_sec_rec{h.id, h.b1, h.b2};
         hid = h.id;
-        Y = query(M, T, h.id, h.b1, h.b2, p.flags);
+        Y = query(M, T, h.id, h.b1, h.b2, p.flags, !(p.flags & EXM_NO_SECONDARY_MATERIAL));
         const float kdy = diff ? (1.0f - Y.m) * kInvPi : 0.0f;
         const float cx = fmaxf(dot(S.ns, sr.df), 0.0f);
         const float w = cx / sr.pb * invNbNs;
@@ -354,7 +354,8 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
     const float pb = sr.pb;
     const float cxr = dot(S.ns, w);
     const float cx = fmaxf(cxr, 0.0f);
-    const Surf Y = query(M, T, r.tri, r.b1, r.b2, p.flags);
+    const bool y_mat = !(p.flags & EXM_NO_SECONDARY_MATERIAL);
+    const Surf Y = query(M, T, r.tri, r.b1, r.b2, p.flags, y_mat);
     const float kdy = (1.0f - Y.m) * kInvPi;
     const float fdy[3] = {kdy * Y.a[0], kdy * Y.a[1], kdy * Y.a[2]};
     const float fdx[3] = {kdx * S.a[0], kdx * S.a[1], kdx * S.a[2]};
@@ -405,6 +406,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
       gmy -= gfy[c] * Y.a[c] * kInvPi;
     }
     if (p.flags & EXM_METALLIC_OFF) gmy = 0.0f;
+    if (!y_mat) continue;  // nothing at y depends on the maps
     nmap_adjoint(Y, gny, gqy);
     scatter7(Y, gay, gmy, gqy, dtex);
   }

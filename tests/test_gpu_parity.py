@@ -326,10 +326,11 @@ def test_direct_small_full_frame(small, flags, N_d):
     _compare_view(small, sc.cams[0], p, b, 0, 0)
 
 
-def test_indirect_small_tori_full_frame(small_tori):
+@pytest.mark.parametrize("no_sec_mat", [False, True])
+def test_indirect_small_tori_full_frame(small_tori, lib, no_sec_mat):
     sc = small_tori.sc
-    p = small_tori.params()
-    log("[indirect] small tori 2 x 96^2")
+    p = small_tori.params(flags=lib.EXM_NO_SECONDARY_MATERIAL if no_sec_mat else 0)
+    log(f"[indirect] small tori 2 x 96^2, no secondary material {no_sec_mat}")
     _, b = small_tori.forward(sc.cams, p)
     Li = b.L_ind.cpu().numpy()
     assert (Li > 0).mean() > 0.05  # interreflection actually happens
@@ -464,3 +465,11 @@ def test_gradients_direct_small(small, flags):
 def test_gradients_indirect_small_tori(small_tori):
     log("[grad] small tori direct + indirect, lambda 0.7")
     _check_grads(small_tori, small_tori.sc.cams[:1], small_tori.params(), lam=0.7, n_texels=32, n_dirs=3)
+
+
+def test_gradients_indirect_no_secondary_material(small_tori, lib):
+    """The ablation that does not query the maps at secondary hits: the adjoint sends nothing
+    to the maps at y, and what it sends to x and to E matches the oracle's derivative."""
+    log("[grad] small tori direct + indirect, no secondary material")
+    _check_grads(small_tori, small_tori.sc.cams[1:2], small_tori.params(flags=lib.EXM_NO_SECONDARY_MATERIAL),
+                 lam=1.0, n_texels=32, n_dirs=3, seed=1)

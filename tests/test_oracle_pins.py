@@ -457,17 +457,20 @@ def test_convex_mesh_has_no_indirect_light():
     assert np.all(r.sec_tri == -1)
 
 
-def test_floor_and_wall_interreflection_closed_form():
+@pytest.mark.parametrize("no_sec_mat", [False, True])
+def test_floor_and_wall_interreflection_closed_form(no_sec_mat):
     """Floor (albedo a_x) meeting a perpendicular wall (albedo a_w), both 1000x the viewed
     distances, under constant L: a floor point sees the wall over half of its hemisphere (also
     half of the cosine-weighted measure), so L_dir(floor) = a_x L / 2; a wall point likewise
-    sees half sky, L_sec(wall) = a_w L / 2; hence L_ind(floor) = a_x a_w L / 4 (Eq. 18-19)."""
+    sees half sky, L_sec(wall) = a_w L / 2; hence L_ind(floor) = a_x a_w L / 4 (Eq. 18-19).
+    With the no-secondary-material ablation the wall is shaded as the grey Lambertian
+    (albedo 0.5) whatever its maps hold: L_ind(floor) = a_x 0.5 L / 4."""
     S = 500.0
     floor_p, floor_t = I.quad_mesh(np.array([[-S, 0, S], [S, 0, S], [S, 0, -0.5], [-S, 0, -0.5]]), 1, 1)
     wall_p, wall_t = I.quad_mesh(np.array([[-S, 0, -0.5], [S, 0, -0.5], [S, 2 * S, -0.5], [-S, 2 * S, -0.5]]), 1, 1)
     pos = np.concatenate([floor_p, wall_p]).astype(np.float32)
     tri = np.concatenate([floor_t, wall_t + 4]).astype(np.int32)
-    ax, aw, L = 0.8, 0.6, 1.0
+    ax, aw, L = 0.8, 0.9, 1.0
     tuv = np.arange(12, dtype=np.int32).reshape(4, 3)
     # each face owns a non-degenerate UV triangle (so tangents exist): floor texels hold a_x,
     # wall texels hold a_w
@@ -484,12 +487,14 @@ def test_floor_and_wall_interreflection_closed_form():
     eye = np.array([0.0, 1.5, 0.3])  # looking straight down at the floor next to the wall
     cam = I.Camera(mvp=I.perspective(60, 1, 0.01, 50) @ I.look_at(eye, [0, 0, 0.3], [0, 0, -1]),
                    eye=eye, H=40, W=40)
-    r = O.render(m, cam, t, tex, env, N_d=64, N_b=32, N_s=2, tmin=1e-5, flags=O.DIFFUSE_ONLY)
+    flags = O.DIFFUSE_ONLY | (O.NO_SECONDARY_MATERIAL if no_sec_mat else 0)
+    r = O.render(m, cam, t, tex, env, N_d=64, N_b=32, N_s=2, tmin=1e-5, flags=flags)
     fl = (r.tri_id >= 0) & (r.tri_id < 2)
     assert fl.sum() > 600
     Ld, Li = r.L_dir[fl, 0], r.L_ind[fl, 0]
     assert abs(Ld.mean() - ax * L / 2) < 4 * Ld.std() / math.sqrt(Ld.size) + 2e-3
-    assert abs(Li.mean() - ax * aw * L / 4) < 4 * Li.std() / math.sqrt(Li.size) + 2e-3
+    ay = 0.5 if no_sec_mat else aw
+    assert abs(Li.mean() - ax * ay * L / 4) < 4 * Li.std() / math.sqrt(Li.size) + 2e-3
 
 
 # ------------------------------------------------------------------------------------------
