@@ -229,6 +229,24 @@ size_t exm_trace_bwd_workspace_size(int32_t nViews, int32_t H, int32_t W, int32_
                                     int32_t He, int32_t We);
 size_t exm_trace_bwd_workspace_min(int32_t N_b, int32_t N_s, int32_t He, int32_t We);
 
+/* Half-resolution indirect light (Implementation Details: secondary rays are evaluated at half
+ * resolution in both image dimensions and the indirect component is upsampled to full
+ * resolution). The caller renders the indirect pass on a half-resolution G-buffer of the same
+ * cameras (tri_id_half [nViews,Hh,Wh]) and exm_upsample_indirect writes the full-resolution
+ * L_ind [nViews,H,W,3] from L_half [nViews,Hh,Wh,3]: per axis the pixel x sits at
+ * u = ((x + 1/2) Hh / H) - 1/2 half-resolution pixels, bilinear over the two clamped taps;
+ * only covered half-resolution taps count and the weights are renormalised over them; 0 for
+ * background pixels and pixels without a covered tap. exm_upsample_indirect_bwd writes (does
+ * not accumulate) dL_half = U^T (lambda_ind * dI), the transpose of that map, ready to be the
+ * upstream gradient of exm_trace_bwd on the half-resolution buffers with lambda_ind = 1.
+ * Needs 1 <= Hh <= H, 1 <= Wh <= W. */
+exm_status exm_upsample_indirect(const int32_t* tri_id_half, int32_t Hh, int32_t Wh, const float* L_half,
+                                 const int32_t* tri_id, int32_t H, int32_t W, int32_t nViews, float* L_ind,
+                                 hipStream_t stream);
+exm_status exm_upsample_indirect_bwd(const int32_t* tri_id_half, int32_t Hh, int32_t Wh, const int32_t* tri_id,
+                                     int32_t H, int32_t W, int32_t nViews, float lambda_ind, const float* dI,
+                                     float* dL_half, hipStream_t stream);
+
 /* Measurement hooks. With timing enabled, every kernel the library launches is bracketed by
  * two HIP events recorded on its launch stream (no events exist while it is off).
  * exm_timing_enable clears the records; exm_timing_collect waits for the recorded events and

@@ -92,6 +92,8 @@ def _load() -> C.CDLL:
         "exm_shade_bwd_workspace_min": (C.c_size_t, [i32, i32, i32]),
         "exm_trace_bwd_workspace_size": (C.c_size_t, [i32, i32, i32, i32, i32, i32, i32]),
         "exm_trace_bwd_workspace_min": (C.c_size_t, [i32, i32, i32, i32]),
+        "exm_upsample_indirect": (st, [vp, i32, i32, vp, vp, i32, i32, i32, vp, vp]),
+        "exm_upsample_indirect_bwd": (st, [vp, i32, i32, vp, i32, i32, i32, C.c_float, vp, vp, vp]),
         "exm_timing_enable": (st, [i32]),
         "exm_timing_collect": (st, []),
         "exm_timing_count": (i32, []),
@@ -337,3 +339,27 @@ def exm_timing_collect() -> dict:
     _check(lib.exm_timing_collect(), "exm_timing_collect")
     return {lib.exm_timing_name(i).decode(): (float(lib.exm_timing_total_ms(i)), int(lib.exm_timing_launches(i)))
             for i in range(lib.exm_timing_count())}
+
+
+def exm_upsample_indirect(tri_id_half, L_half, tri_id, L_ind, stream=None) -> None:
+    import torch
+    n, Hh, Wh = tri_id_half.shape
+    _, H, W = tri_id.shape
+    _need(tri_id_half, torch.int32, (n, Hh, Wh), "tri_id_half")
+    _need(L_half, torch.float32, (n, Hh, Wh, 3), "L_half")
+    _need(tri_id, torch.int32, (n, H, W), "tri_id")
+    _need(L_ind, torch.float32, (n, H, W, 3), "L_ind")
+    _check(lib.exm_upsample_indirect(_ptr(tri_id_half), Hh, Wh, _ptr(L_half), _ptr(tri_id), H, W, n, _ptr(L_ind),
+                                     _stream(stream)), "exm_upsample_indirect")
+
+
+def exm_upsample_indirect_bwd(tri_id_half, tri_id, lambda_ind: float, dI, dL_half, stream=None) -> None:
+    import torch
+    n, Hh, Wh = tri_id_half.shape
+    _, H, W = tri_id.shape
+    _need(tri_id_half, torch.int32, (n, Hh, Wh), "tri_id_half")
+    _need(tri_id, torch.int32, (n, H, W), "tri_id")
+    _need(dI, torch.float32, (n, H, W, 3), "dI")
+    _need(dL_half, torch.float32, (n, Hh, Wh, 3), "dL_half")
+    _check(lib.exm_upsample_indirect_bwd(_ptr(tri_id_half), Hh, Wh, _ptr(tri_id), H, W, n, float(lambda_ind), _ptr(dI),
+                                         _ptr(dL_half), _stream(stream)), "exm_upsample_indirect_bwd")

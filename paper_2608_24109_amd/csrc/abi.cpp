@@ -427,4 +427,34 @@ exm_status exm_trace_bwd(const exm_mesh* m, const exm_material* mat, const exm_e
   return EXM_OK;
 }
 
+static exm_status check_upsample(const int32_t* tri_h, int32_t Hh, int32_t Wh, const int32_t* tri, int32_t H,
+                                 int32_t W, int32_t n) {
+  if (!tri_h || !tri) return fail(EXM_E_INVAL, "G-buffer pointer is NULL");
+  if (n < 1 || H < 1 || W < 1 || Hh < 1 || Wh < 1 || Hh > H || Wh > W || (int64_t)H * W > (1 << 26))
+    return fail(EXM_E_INVAL, "need 1 <= Hh <= H, 1 <= Wh <= W, nViews >= 1 and H * W <= 2^26");
+  return EXM_OK;
+}
+
+exm_status exm_upsample_indirect(const int32_t* tri_h, int32_t Hh, int32_t Wh, const float* L_half, const int32_t* tri,
+                                 int32_t H, int32_t W, int32_t n, float* L_ind, hipStream_t stream) {
+  EXM_TRY(check_upsample(tri_h, Hh, Wh, tri, H, W, n));
+  if (!L_half || !L_ind) return fail(EXM_E_INVAL, "radiance pointer is NULL");
+  EXM_TRY(check_device());
+  hipError_t e = launch_upsample(tri_h, Hh, Wh, L_half, tri, H, W, n, L_ind, stream);
+  if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_upsample_indirect: ") + hipGetErrorString(e));
+  return EXM_OK;
+}
+
+exm_status exm_upsample_indirect_bwd(const int32_t* tri_h, int32_t Hh, int32_t Wh, const int32_t* tri, int32_t H,
+                                     int32_t W, int32_t n, float lambda_ind, const float* dI, float* dL_half,
+                                     hipStream_t stream) {
+  EXM_TRY(check_upsample(tri_h, Hh, Wh, tri, H, W, n));
+  if (!dI || !dL_half) return fail(EXM_E_INVAL, "gradient pointer is NULL");
+  if (!std::isfinite(lambda_ind)) return fail(EXM_E_INVAL, "lambda_ind must be finite");
+  EXM_TRY(check_device());
+  hipError_t e = launch_upsample_bwd(tri_h, Hh, Wh, tri, H, W, n, lambda_ind, dI, dL_half, stream);
+  if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_upsample_indirect_bwd: ") + hipGetErrorString(e));
+  return EXM_OK;
+}
+
 }  // extern "C"

@@ -95,6 +95,11 @@ exm_status check_launch(const char* what);
 hipError_t launch_mesh_prepare(const exm_mesh* m, hipStream_t s);
 hipError_t launch_env_sampler(const float* env, int32_t He, int32_t We, uint64_t* cdf_row, uint64_t* cdf_col,
                               float* pdf, uint32_t* guide, float* rec, hipStream_t s);
+hipError_t launch_upsample(const int32_t* tri_half, int32_t Hh, int32_t Wh, const float* L_half, const int32_t* tri_id,
+                           int32_t H, int32_t W, int32_t n_views, float* L, hipStream_t s);
+hipError_t launch_upsample_bwd(const int32_t* tri_half, int32_t Hh, int32_t Wh, const int32_t* tri_id, int32_t H,
+                               int32_t W, int32_t n_views, float lambda, const float* dI, float* dL_half,
+                               hipStream_t s);
 hipError_t launch_raster(const exm_mesh* m, const RasterViews& v, int32_t* tri_id, float* bary, hipStream_t s);
 hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                             const ShadeViews& v, const int32_t* tri_id, const float* bary, const exm_params* p,

@@ -28,6 +28,7 @@ class PassParams:
     flags: int = 0
     f_diel: float = 0.04  # F_dielectric of Eq. 16
     eps: float = 1e-6     # epsilon of Eq. 15
+    half_res_indirect: bool = False  # indirect pass at half resolution, upsampled (Implementation Details)
 
     def c(self) -> L.exm_params:
         return L.params(self.N_d, self.N_b, self.N_s if self.N_b > 0 else 0, self.seed, self.iteration,
@@ -44,7 +45,7 @@ class PassBuffers:
     """Per-view outputs of one forward pass (device tensors) and its ray workspace."""
 
     def __init__(self, n: int, H: int, W: int, N_b: int, device="cuda", gbuffer: bool = True,
-                 ws_cap: int = WORKSPACE_CAP):
+                 ws_cap: int = WORKSPACE_CAP, half: bool = False):
         self.n, self.H, self.W, self.N_b = n, H, W, N_b
         self.device = device
         self.ws = None
@@ -54,8 +55,14 @@ class PassBuffers:
         self.L_dir = torch.empty((n, H, W, 3), dtype=torch.float32, device=device)
         self.vis = torch.empty((n, H, W), dtype=torch.uint64, device=device)
         self.L_ind = torch.empty((n, H, W, 3), dtype=torch.float32, device=device) if N_b > 0 else None
-        self.sec_rec = torch.empty((n, H, W, max(N_b, 1), 3), dtype=torch.int32, device=device) if N_b > 0 else None
-        self.sec_vis = torch.empty((n, H, W), dtype=torch.uint64, device=device) if N_b > 0 else None
+        self.sec_rec = None
+        self.sec_vis = None
+        self.half = None  # buffers of a half-resolution indirect pass
+        if N_b > 0 and half:
+            self.half = PassBuffers(n, (H + 1) // 2, (W + 1) // 2, N_b, device=device, ws_cap=ws_cap)
+        elif N_b > 0:
+            self.sec_rec = torch.empty((n, H, W, max(N_b, 1), 3), dtype=torch.int32, device=device)
+            self.sec_vis = torch.empty((n, H, W), dtype=torch.uint64, device=device)
 
     def workspace(self, nbytes: int):
         """The pass's ray workspace, grown to `nbytes` (capped at ws_cap) when needed."""
@@ -73,6 +80,17 @@ class PassBuffers:
     def drop_gbuffer(self):
         self.tri_id = None
         self.bary = None
+        if self.half is not None:
+            self.half.drop_gbuffer()
+
+
+def half_cameras(cams_c):
+    """The same cameras at half resolution in both image dimensions (rounded up)."""
+    out = (L.exm_camera * len(cams_c))()
+    for i, c in enumerate(cams_c):
+        out[i] = c
+        out[i].H, out[i].W = (c.H + 1) // 2, (c.W + 1) // 2
+    return out
 
 
 def shade_fwd_ws_bytes(n: int, H: int, W: int, p: PassParams) -> int:
@@ -100,7 +118,15 @@ def render_forward(mesh: DeviceMesh, mat: DeviceMaterial, env: DeviceEnv, cams_c
     ws = bufs.workspace(shade_fwd_ws_bytes(len(cams_c), bufs.H, bufs.W, p))
     L.exm_shade_fwd(mesh.s, mesh.bvh, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, bufs.L_dir, bufs.vis, ws,
                     stream)
-    if p.N_b > 0:
+    if p.N_b > 0 and bufs.half is not None:  # half-resolution indirect, upsampled
+        hb = bufs.half
+        ch = half_cameras(cams_c)
+        raster(mesh, ch, hb, stream)
+        ws = bufs.workspace(trace_indirect_ws_bytes(len(cams_c), hb.H, hb.W, p))
+        L.exm_trace_indirect(mesh.s, mesh.bvh, mat.s, env.s, ch, hb.tri_id, hb.bary, pc, hb.L_ind, hb.sec_rec,
+                             hb.sec_vis, ws, stream)
+        L.exm_upsample_indirect(hb.tri_id, hb.L_ind, bufs.tri_id, bufs.L_ind, stream)
+    elif p.N_b > 0:
         ws = bufs.workspace(trace_indirect_ws_bytes(len(cams_c), bufs.H, bufs.W, p))
         L.exm_trace_indirect(mesh.s, mesh.bvh, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, bufs.L_ind,
                              bufs.sec_rec, bufs.sec_vis, ws, stream)
@@ -122,7 +148,17 @@ def render_backward(mesh: DeviceMesh, mat: DeviceMaterial, env: DeviceEnv, cams_
     He, We = env.env.shape[:2]
     ws = bufs.workspace(shade_bwd_ws_bytes(len(cams_c), bufs.H, bufs.W, p, He, We))
     L.exm_shade_bwd(mesh.s, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, dI, bufs.vis, dtex, denv, ws, stream)
-    if p.N_b > 0 and lambda_ind != 0.0:
+    if p.N_b > 0 and lambda_ind != 0.0 and bufs.half is not None:
+        hb = bufs.half
+        ch = half_cameras(cams_c)
+        if hb.tri_id is None:
+            raster(mesh, ch, hb, stream)
+        dLh = torch.empty((hb.n, hb.H, hb.W, 3), dtype=torch.float32, device=dI.device)
+        L.exm_upsample_indirect_bwd(hb.tri_id, bufs.tri_id, lambda_ind, dI, dLh, stream)
+        ws = bufs.workspace(trace_bwd_ws_bytes(len(cams_c), hb.H, hb.W, p, He, We))
+        L.exm_trace_bwd(mesh.s, mat.s, env.s, ch, hb.tri_id, hb.bary, pc, 1.0, dLh, hb.sec_rec, hb.sec_vis, dtex,
+                        denv, ws, stream)
+    elif p.N_b > 0 and lambda_ind != 0.0:
         ws = bufs.workspace(trace_bwd_ws_bytes(len(cams_c), bufs.H, bufs.W, p, He, We))
         L.exm_trace_bwd(mesh.s, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, lambda_ind, dI, bufs.sec_rec,
                         bufs.sec_vis, dtex, denv, ws, stream)
@@ -138,7 +174,7 @@ def _forward_chunks(tex_device, mesh, mat, env_dev, cams, p: PassParams, lambda_
     for v0 in range(0, len(cams), chunk):
         cs = cams[v0:v0 + chunk]
         cc = L.cameras(cs, [getattr(c, "view_id", v0 + i) for i, c in enumerate(cs)])
-        bufs = PassBuffers(len(cs), H, W, p.N_b, device=tex_device)
+        bufs = PassBuffers(len(cs), H, W, p.N_b, device=tex_device, half=p.half_res_indirect)
         render_forward(mesh, mat, env_dev, cc, p, bufs, rebuild_tables=False)
         o = out[v0:v0 + len(cs)]
         if p.N_b > 0:
@@ -148,6 +184,8 @@ def _forward_chunks(tex_device, mesh, mat, env_dev, cams, p: PassParams, lambda_
         if keep:
             bufs.L_dir = bufs.L_ind = None
             bufs.ws = None
+            if bufs.half is not None:
+                bufs.half.L_dir = bufs.half.L_ind = bufs.half.vis = None
             if checkpoint:
                 bufs.drop_gbuffer()
             chunks.append((cc, bufs))

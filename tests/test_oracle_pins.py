@@ -568,3 +568,64 @@ def test_render_is_linear_in_env_and_in_albedo_when_dielectric(small_scene):
     d = np.sum(g * (r1.L_dir - r0.L_dir))
     jv = np.sum(g * rj.dL_dir)
     assert abs(d - jv) < 1e-10 * abs(jv) + 1e-10
+
+
+# ------------------------------------------------------------------------------------------
+# half-resolution indirect upsampling (the stated reading; the paper does not give the filter)
+# ------------------------------------------------------------------------------------------
+
+def test_upsample_reproduces_affine_and_constants():
+    rng = np.random.default_rng(0)
+    for (H, W, Hh, Wh) in [(64, 96, 32, 48), (37, 53, 19, 27)]:
+        th = np.zeros((Hh, Wh), np.int32)
+        tf = np.zeros((H, W), np.int32)
+        # constant in, constant out everywhere (all covered)
+        out = O.upsample_indirect(np.full((Hh, Wh, 3), 2.5), th, tf)
+        assert np.allclose(out, 2.5, rtol=0, atol=1e-12)
+        # an affine function of the half-resolution pixel centre is reproduced away from the
+        # clamped border: value at full pixel x equals the function at u(x)
+        a, b, c = rng.normal(size=3)
+        jj, ii = np.meshgrid(np.arange(Wh), np.arange(Hh))
+        Lh = (a * ii + b * jj + c)[..., None] * np.ones(3)
+        out = O.upsample_indirect(Lh, th, tf)
+        y = np.arange(H)[:, None] * np.ones((1, W))
+        x = np.ones((H, 1)) * np.arange(W)[None, :]
+        uy = (y + 0.5) * Hh / H - 0.5
+        ux = (x + 0.5) * Wh / W - 0.5
+        inner = (uy >= 0) & (uy <= Hh - 1) & (ux >= 0) & (ux <= Wh - 1)
+        assert np.allclose(out[inner, 0], (a * uy + b * ux + c)[inner], atol=1e-9)
+
+
+def test_upsample_two_x_weights_and_coverage():
+    # 2x: full pixel 2k sits at u = k - 1/4 -> taps (k-1, k) with weights (1/4, 3/4)
+    Hh, Wh = 4, 4
+    th = np.zeros((Hh, Wh), np.int32)
+    tf = np.zeros((8, 8), np.int32)
+    Lh = np.zeros((Hh, Wh, 3))
+    Lh[1, 1] = 1.0
+    out = O.upsample_indirect(Lh, th, tf)
+    assert abs(out[2, 2, 0] - 0.75 * 0.75) < 1e-12 and abs(out[3, 3, 0] - 0.75 * 0.75) < 1e-12
+    assert abs(out[1, 2, 0] - 0.25 * 0.75) < 1e-12 and out[5, 5, 0] == 0.0
+    # uncovered taps drop out and the rest renormalise; background pixels get 0
+    th2 = th.copy()
+    th2[1, 2] = -1
+    Lh2 = np.ones((Hh, Wh, 3))
+    Lh2[1, 2] = 100.0
+    tf2 = tf.copy()
+    tf2[0, 0] = -1
+    out2 = O.upsample_indirect(Lh2, th2, tf2)
+    assert np.allclose(out2[tf2 >= 0], 1.0) and np.all(out2[0, 0] == 0.0)
+    none = -np.ones((Hh, Wh), np.int32)
+    assert np.all(O.upsample_indirect(Lh2, none, tf) == 0.0)
+
+
+def test_upsample_transpose_is_adjoint():
+    rng = np.random.default_rng(1)
+    H, W, Hh, Wh = 37, 53, 19, 27
+    th = np.where(rng.random((Hh, Wh)) < 0.8, 0, -1).astype(np.int32)
+    tf = np.where(rng.random((H, W)) < 0.9, 0, -1).astype(np.int32)
+    x = rng.normal(size=(Hh, Wh, 3))
+    g = rng.normal(size=(H, W, 3))
+    lhs = float(np.sum(O.upsample_indirect(x, th, tf) * g))
+    rhs = float(np.sum(x * O.upsample_indirect_T(g, th, tf)))
+    assert abs(lhs - rhs) < 1e-10 * max(1.0, abs(lhs))
