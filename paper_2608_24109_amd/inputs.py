@@ -369,6 +369,8 @@ def config(name: str, views: int | None = None, res: int | None = None) -> Scene
              samples.
     tori32:  the tori mesh, 32 ring views 1024^2 (elevations alternating +-20 deg),
              4096^2 maps, env gradients on, G-buffer recomputed in backward.
+    paper_shape: cube-sphere n = 91 (99,372 tris, 49,688 vertices), 2048^2 maps, 256x512 env
+             exp(N(0,1)), 1 view 1600^2 (R=3), N_d 8, N_b 16 (half resolution), N_s 4.
     """
     if name == "small":
         pos, tri = icosphere(3)
@@ -385,6 +387,13 @@ def config(name: str, views: int | None = None, res: int | None = None) -> Scene
         H = W = res or 1024
         cams = ring_cameras(views or 8, 4.5, H, W)
         return make_scene(name, pos, tri, 2048, 2048, 512, 1024, 1.5, cams, N_d=64, N_b=4, N_s=4)
+    if name == "paper_shape":
+        # the paper's relighting timing shape: an object of ~100k triangles (52K vertices), one
+        # 1600^2 view, 2048^2 maps, a 256x512 env map, N_d 8, N_b 16 at half resolution, N_s 4
+        pos, tri = displaced_cube_sphere(91)
+        H = W = res or 1600
+        cams = ring_cameras(views or 1, 3.0, H, W)
+        return make_scene(name, pos, tri, 2048, 2048, 256, 512, 1.0, cams, N_d=8, N_b=16, N_s=4)
     if name == "tori32":
         pos, tri = interlocking_tori(1000, 250)
         H = W = res or 1024
