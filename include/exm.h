@@ -247,6 +247,48 @@ exm_status exm_upsample_indirect_bwd(const int32_t* tri_id_half, int32_t Hh, int
                                      int32_t H, int32_t W, int32_t nViews, float lambda_ind, const float* dI,
                                      float* dL_half, hipStream_t stream);
 
+/* ---- Stage-II objective and optimiser step (Stage-II Optimization, Eq. 21-24) ----
+ * Readings of what the paper leaves open: L_img = 0.8 * mean |log(1 + I_hat) - log(1 + I)| +
+ * 0.2 * (1 - mean SSIM) (D-SSIM weight 0.2 from the hyperparameter table, the log-L1 weight its
+ * complement; means over pixels and channels of a view); SSIM per channel (Wang et al. 2004) of
+ * the sRGB curve of the radiance clamped to [0, 1], 11-tap Gaussian window of sigma 1.5, zero
+ * padding, C1 = 1e-4, C2 = 9e-4. TV(P_hat) (Eq. 23): for the groups A, R, N (and M when metallic
+ * is optimised) the sum over right/down pairs of visible pixels of the group's channel-mean
+ * |difference| of the screen projection, divided by H * W. TV(E): the same over env texels
+ * with phi wrapping, divided by He * We. Chroma (Eq. 24): squared distance of the per-channel
+ * texel mean of E from its grey mean. Losses ACCUMULATE into a device double; gradients as
+ * stated per call. */
+
+/* Screen projection of the packed map: P [nViews,H,W,8] = the bilinear query (Eq. 10) at every
+ * visible pixel, 0 elsewhere; _bwd: dtex += its adjoint for dP [nViews,H,W,8]. */
+exm_status exm_project_maps(const exm_mesh* m, const exm_material* mat, int32_t nViews, int32_t H, int32_t W,
+                            const int32_t* tri_id, const float* bary, float* P, hipStream_t stream);
+exm_status exm_project_maps_bwd(const exm_mesh* m, const exm_material* mat, int32_t nViews, int32_t H, int32_t W,
+                                const int32_t* tri_id, const float* bary, const float* dP, float* dtex,
+                                hipStream_t stream);
+/* scale * L_img of each view (I_hat, I [nViews,H,W,3]) into *loss; dI_hat = scale * dL_img/dI_hat
+ * (written). Workspace: exm_image_loss_workspace_size(H, W) bytes, 256-byte aligned. */
+size_t exm_image_loss_workspace_size(int32_t H, int32_t W);
+exm_status exm_image_loss(const float* I_hat, const float* I, int32_t nViews, int32_t H, int32_t W, float scale,
+                          double* loss, float* dI_hat, void* ws, size_t ws_bytes, hipStream_t stream);
+/* scale * L_mat of the projections P [nViews,H,W,8] (visibility from tri_id) into *loss;
+ * dP = its gradient (written). metallic != 0 adds the M group. */
+exm_status exm_tv_screen(const float* P, const int32_t* tri_id, int32_t nViews, int32_t H, int32_t W,
+                         int32_t metallic, float scale, double* loss, float* dP, hipStream_t stream);
+/* w_tv * TV(E) + w_chroma * L_chroma into *loss; dE [He,We,3] += gradient (double). acc3 is a
+ * device scratch of 3 doubles. */
+exm_status exm_env_regularizers(const float* E, int32_t He, int32_t We, float w_tv, float w_chroma, double* loss,
+                                double* dE, double* acc3, hipStream_t stream);
+/* One Adam step (Kingma and Ba 2015) on n values laid out with n_chan channels (<= 8): m, v
+ * updated, param -= lr * m_hat / (sqrt(v_hat) + eps) for step t >= 1, then clamped to
+ * [lo[c], hi[c]] (lo, hi host arrays of n_chan): the projection that keeps E non-negative and
+ * the material channels in range. grad is float, or double when grad_is_f64. The moments and
+ * the parameter are updated in float; the coefficients (beta, 1 - beta, the bias corrections)
+ * are formed in double on the host and rounded once. */
+exm_status exm_adam_step(float* param, const void* grad, int32_t grad_is_f64, float* m, float* v, int64_t n,
+                         int32_t n_chan, const float* lo_host, const float* hi_host, double lr, double beta1,
+                         double beta2, double eps, int32_t t, hipStream_t stream);
+
 /* Measurement hooks. With timing enabled, every kernel the library launches is bracketed by
  * two HIP events recorded on its launch stream (no events exist while it is off).
  * exm_timing_enable clears the records; exm_timing_collect waits for the recorded events and

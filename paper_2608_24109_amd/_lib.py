@@ -94,6 +94,14 @@ def _load() -> C.CDLL:
         "exm_trace_bwd_workspace_min": (C.c_size_t, [i32, i32, i32, i32]),
         "exm_upsample_indirect": (st, [vp, i32, i32, vp, vp, i32, i32, i32, vp, vp]),
         "exm_upsample_indirect_bwd": (st, [vp, i32, i32, vp, i32, i32, i32, C.c_float, vp, vp, vp]),
+        "exm_project_maps": (st, [vp, vp, i32, i32, i32, vp, vp, vp, vp]),
+        "exm_project_maps_bwd": (st, [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp]),
+        "exm_image_loss_workspace_size": (C.c_size_t, [i32, i32]),
+        "exm_image_loss": (st, [vp, vp, i32, i32, i32, C.c_float, vp, vp, vp, C.c_size_t, vp]),
+        "exm_tv_screen": (st, [vp, vp, i32, i32, i32, i32, C.c_float, vp, vp, vp]),
+        "exm_env_regularizers": (st, [vp, i32, i32, C.c_float, C.c_float, vp, vp, vp, vp]),
+        "exm_adam_step": (st, [vp, vp, i32, vp, vp, C.c_int64, i32, vp, vp, C.c_double, C.c_double, C.c_double,
+                               C.c_double, i32, vp]),
         "exm_timing_enable": (st, [i32]),
         "exm_timing_collect": (st, []),
         "exm_timing_count": (i32, []),
@@ -363,3 +371,72 @@ def exm_upsample_indirect_bwd(tri_id_half, tri_id, lambda_ind: float, dI, dL_hal
     _need(dL_half, torch.float32, (n, Hh, Wh, 3), "dL_half")
     _check(lib.exm_upsample_indirect_bwd(_ptr(tri_id_half), Hh, Wh, _ptr(tri_id), H, W, n, float(lambda_ind), _ptr(dI),
                                          _ptr(dL_half), _stream(stream)), "exm_upsample_indirect_bwd")
+
+
+def exm_project_maps(mesh, mat: exm_material, tri_id, bary, P, stream=None) -> None:
+    import torch
+    n, H, W = tri_id.shape
+    _need(P, torch.float32, (n, H, W, 8), "P")
+    _check(lib.exm_project_maps(C.byref(mesh), C.byref(mat), n, H, W, _ptr(tri_id), _ptr(bary), _ptr(P),
+                                _stream(stream)), "exm_project_maps")
+
+
+def exm_project_maps_bwd(mesh, mat: exm_material, tri_id, bary, dP, dtex, stream=None) -> None:
+    import torch
+    n, H, W = tri_id.shape
+    _need(dP, torch.float32, (n, H, W, 8), "dP")
+    _need(dtex, torch.float32, (mat.Ht, mat.Wt, 8), "dtex")
+    _check(lib.exm_project_maps_bwd(C.byref(mesh), C.byref(mat), n, H, W, _ptr(tri_id), _ptr(bary), _ptr(dP),
+                                    _ptr(dtex), _stream(stream)), "exm_project_maps_bwd")
+
+
+def exm_image_loss_workspace_size(H: int, W: int) -> int:
+    return int(lib.exm_image_loss_workspace_size(H, W))
+
+
+def exm_image_loss(I_hat, I, scale: float, loss, dI_hat, ws, stream=None) -> None:
+    """loss: device float64 [1] (accumulated); dI_hat written."""
+    import torch
+    n, H, W = I_hat.shape[:3]
+    for t, name in ((I_hat, "I_hat"), (I, "I"), (dI_hat, "dI_hat")):
+        _need(t, torch.float32, (n, H, W, 3), name)
+    _need(loss, torch.float64, (1,), "loss")
+    _check(lib.exm_image_loss(_ptr(I_hat), _ptr(I), n, H, W, float(scale), _ptr(loss), _ptr(dI_hat), _ptr(ws),
+                              ws.numel(), _stream(stream)), "exm_image_loss")
+
+
+def exm_tv_screen(P, tri_id, metallic: bool, scale: float, loss, dP, stream=None) -> None:
+    import torch
+    n, H, W = tri_id.shape
+    _need(P, torch.float32, (n, H, W, 8), "P")
+    _need(dP, torch.float32, (n, H, W, 8), "dP")
+    _need(loss, torch.float64, (1,), "loss")
+    _check(lib.exm_tv_screen(_ptr(P), _ptr(tri_id), n, H, W, 1 if metallic else 0, float(scale), _ptr(loss), _ptr(dP),
+                             _stream(stream)), "exm_tv_screen")
+
+
+def exm_env_regularizers(E, w_tv: float, w_chroma: float, loss, dE, acc3, stream=None) -> None:
+    import torch
+    He, We = E.shape[:2]
+    _need(E, torch.float32, (He, We, 3), "E")
+    _need(dE, torch.float64, (He, We, 3), "dE")
+    _need(loss, torch.float64, (1,), "loss")
+    _need(acc3, torch.float64, (3,), "acc3")
+    _check(lib.exm_env_regularizers(_ptr(E), He, We, float(w_tv), float(w_chroma), _ptr(loss), _ptr(dE), _ptr(acc3),
+                                    _stream(stream)), "exm_env_regularizers")
+
+
+def exm_adam_step(param, grad, m, v, lo, hi, lr: float, t: int, beta1: float = 0.9, beta2: float = 0.999,
+                  eps: float = 1e-8, stream=None) -> None:
+    """param/m/v float32 of the same shape; grad float32 or float64; lo/hi per trailing channel."""
+    import torch
+    n_chan = param.shape[-1]
+    for x, name in ((m, "m"), (v, "v")):
+        _need(x, torch.float32, tuple(param.shape), name)
+    if tuple(grad.shape) != tuple(param.shape) or grad.dtype not in (torch.float32, torch.float64):
+        raise ValueError("grad must match param in shape, float32 or float64")
+    lo_a = (C.c_float * n_chan)(*[float(x) for x in lo])
+    hi_a = (C.c_float * n_chan)(*[float(x) for x in hi])
+    _check(lib.exm_adam_step(_ptr(param), _ptr(grad), 1 if grad.dtype == torch.float64 else 0, _ptr(m), _ptr(v),
+                             param.numel(), n_chan, lo_a, hi_a, float(lr), float(beta1), float(beta2), float(eps),
+                             int(t), _stream(stream)), "exm_adam_step")

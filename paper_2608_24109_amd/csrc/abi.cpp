@@ -457,4 +457,93 @@ exm_status exm_upsample_indirect_bwd(const int32_t* tri_h, int32_t Hh, int32_t W
   return EXM_OK;
 }
 
+static exm_status check_view_dims(int32_t n, int32_t H, int32_t W) {
+  if (n < 1 || H < 1 || W < 1 || (int64_t)H * W > (1 << 26)) return fail(EXM_E_INVAL, "bad view dimensions");
+  return EXM_OK;
+}
+
+exm_status exm_project_maps(const exm_mesh* m, const exm_material* mat, int32_t n, int32_t H, int32_t W,
+                            const int32_t* tri_id, const float* bary, float* P, hipStream_t stream) {
+  EXM_TRY(check_mesh(m, true));
+  EXM_TRY(check_material(mat));
+  EXM_TRY(check_view_dims(n, H, W));
+  EXM_TRY(check_gbuffer(tri_id, bary));
+  if (!P || !aligned(P, 16)) return fail(EXM_E_INVAL, "P must be a 16-byte aligned device pointer");
+  EXM_TRY(check_device());
+  hipError_t e = launch_project(m, mat, (int64_t)n * H * W, tri_id, bary, P, stream);
+  if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_project_maps: ") + hipGetErrorString(e));
+  return EXM_OK;
+}
+
+exm_status exm_project_maps_bwd(const exm_mesh* m, const exm_material* mat, int32_t n, int32_t H, int32_t W,
+                                const int32_t* tri_id, const float* bary, const float* dP, float* dtex,
+                                hipStream_t stream) {
+  EXM_TRY(check_mesh(m, true));
+  EXM_TRY(check_material(mat));
+  EXM_TRY(check_view_dims(n, H, W));
+  EXM_TRY(check_gbuffer(tri_id, bary));
+  if (!dP || !dtex) return fail(EXM_E_INVAL, "gradient pointer is NULL");
+  EXM_TRY(check_device());
+  hipError_t e = launch_project_bwd(m, mat, (int64_t)n * H * W, tri_id, bary, dP, dtex, stream);
+  if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_project_maps_bwd: ") + hipGetErrorString(e));
+  return EXM_OK;
+}
+
+size_t exm_image_loss_workspace_size(int32_t H, int32_t W) {
+  if (H < 1 || W < 1 || (int64_t)H * W > (1 << 26)) return 0;
+  return image_loss_ws_bytes(H, W);
+}
+
+exm_status exm_image_loss(const float* a, const float* b, int32_t n, int32_t H, int32_t W, float scale, double* loss,
+                          float* dA, void* ws, size_t ws_bytes, hipStream_t stream) {
+  EXM_TRY(check_view_dims(n, H, W));
+  if (!a || !b || !loss || !dA) return fail(EXM_E_INVAL, "pointer is NULL");
+  if (!std::isfinite(scale)) return fail(EXM_E_INVAL, "scale must be finite");
+  if (!ws || !aligned(ws, 256) || ws_bytes < image_loss_ws_bytes(H, W))
+    return fail(EXM_E_INVAL, "workspace must be 256-byte aligned and at least exm_image_loss_workspace_size bytes");
+  EXM_TRY(check_device());
+  hipError_t e = launch_image_loss(a, b, n, H, W, scale, loss, dA, ws, stream);
+  if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_image_loss: ") + hipGetErrorString(e));
+  return EXM_OK;
+}
+
+exm_status exm_tv_screen(const float* P, const int32_t* tri_id, int32_t n, int32_t H, int32_t W, int32_t metallic,
+                         float scale, double* loss, float* dP, hipStream_t stream) {
+  EXM_TRY(check_view_dims(n, H, W));
+  if (!P || !tri_id || !loss || !dP) return fail(EXM_E_INVAL, "pointer is NULL");
+  if (!aligned(dP, 16)) return fail(EXM_E_INVAL, "dP must be 16-byte aligned");
+  if (!std::isfinite(scale)) return fail(EXM_E_INVAL, "scale must be finite");
+  EXM_TRY(check_device());
+  hipError_t e = launch_tv_screen(P, tri_id, n, H, W, metallic, scale, loss, dP, stream);
+  if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_tv_screen: ") + hipGetErrorString(e));
+  return EXM_OK;
+}
+
+exm_status exm_env_regularizers(const float* E, int32_t He, int32_t We, float w_tv, float w_chroma, double* loss,
+                                double* dE, double* acc3, hipStream_t stream) {
+  EXM_TRY(check_env_dims(He, We));
+  if (!E || !loss || !dE || !acc3) return fail(EXM_E_INVAL, "pointer is NULL");
+  if (!std::isfinite(w_tv) || !std::isfinite(w_chroma)) return fail(EXM_E_INVAL, "weights must be finite");
+  EXM_TRY(check_device());
+  hipError_t e = launch_env_regularizers(E, He, We, w_tv, w_chroma, loss, dE, acc3, stream);
+  if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_env_regularizers: ") + hipGetErrorString(e));
+  return EXM_OK;
+}
+
+exm_status exm_adam_step(float* prm, const void* grad, int32_t grad_is_f64, float* m, float* v, int64_t n,
+                         int32_t n_chan, const float* lo, const float* hi, double lr, double b1, double b2, double eps,
+                         int32_t t, hipStream_t stream) {
+  if (!prm || !grad || !m || !v || !lo || !hi) return fail(EXM_E_INVAL, "pointer is NULL");
+  if (n < 0 || n_chan < 1 || n_chan > 8 || n % n_chan != 0) return fail(EXM_E_INVAL, "n must be a multiple of n_chan <= 8");
+  if (t < 1 || !(b1 >= 0.0 && b1 < 1.0) || !(b2 >= 0.0 && b2 < 1.0) || !(eps > 0.0) || !std::isfinite(lr))
+    return fail(EXM_E_INVAL, "need t >= 1, 0 <= beta < 1, eps > 0, finite lr");
+  for (int32_t c = 0; c < n_chan; ++c)
+    if (!(lo[c] <= hi[c])) return fail(EXM_E_INVAL, "bounds need lo <= hi");
+  if (n == 0) return EXM_OK;
+  EXM_TRY(check_device());
+  hipError_t e = launch_adam(prm, grad, grad_is_f64 != 0, m, v, n, n_chan, lo, hi, lr, b1, b2, eps, t, stream);
+  if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_adam_step: ") + hipGetErrorString(e));
+  return EXM_OK;
+}
+
 }  // extern "C"

@@ -340,6 +340,16 @@ __device__ __forceinline__ void bilinear_taps(const TexView& t, double u, double
   w[3] = fs * ft;
 }
 
+// bilinear taps of the maps at the point (b1, b2) of face f (UVs interpolated in FP64)
+__device__ __forceinline__ void surface_taps(const MeshView& M, const TexView& T, int32_t f, float b1, float b2,
+                                             int32_t tap[4], float w[4]) {
+  const int32_t t0 = M.tri_uv[3 * f], t1 = M.tri_uv[3 * f + 1], t2 = M.tri_uv[3 * f + 2];
+  const double d1 = b1, d2 = b2, d0 = 1.0 - d1 - d2;
+  const double u = (d0 * M.uv[2 * t0] + d1 * M.uv[2 * t1]) + d2 * M.uv[2 * t2];
+  const double v = (d0 * M.uv[2 * t0 + 1] + d1 * M.uv[2 * t1 + 1]) + d2 * M.uv[2 * t2 + 1];
+  bilinear_taps(T, u, v, tap, w);
+}
+
 // Albedo of secondary hits under EXM_NO_SECONDARY_MATERIAL (a grey Lambertian, metallic 0,
 // shading normal = n_g; the "No Secondary Material" ablation of the Ablation Study).
 constexpr float kSecondaryAlbedo = 0.5f;
@@ -371,11 +381,7 @@ __device__ __forceinline__ Surf query(const MeshView& M, const TexView& T, int32
     S.T = S.B = mk(0, 0, 0);
     return S;
   }
-  const int32_t t0 = M.tri_uv[3 * f], t1 = M.tri_uv[3 * f + 1], t2 = M.tri_uv[3 * f + 2];
-  const double d1 = b1, d2 = b2, d0 = 1.0 - d1 - d2;
-  const double u = (d0 * M.uv[2 * t0] + d1 * M.uv[2 * t1]) + d2 * M.uv[2 * t2];
-  const double v = (d0 * M.uv[2 * t0 + 1] + d1 * M.uv[2 * t1 + 1]) + d2 * M.uv[2 * t2 + 1];
-  bilinear_taps(T, u, v, S.tap, S.w);
+  surface_taps(M, T, f, b1, b2, S.tap, S.w);
   float ch[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) ch[c] = 0.0f;

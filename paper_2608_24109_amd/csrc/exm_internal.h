@@ -100,6 +100,20 @@ hipError_t launch_upsample(const int32_t* tri_half, int32_t Hh, int32_t Wh, cons
 hipError_t launch_upsample_bwd(const int32_t* tri_half, int32_t Hh, int32_t Wh, const int32_t* tri_id, int32_t H,
                                int32_t W, int32_t n_views, float lambda, const float* dI, float* dL_half,
                                hipStream_t s);
+size_t image_loss_ws_bytes(int32_t H, int32_t W);
+hipError_t launch_project(const exm_mesh* m, const exm_material* mat, int64_t n_px, const int32_t* tri_id,
+                          const float* bary, float* P, hipStream_t s);
+hipError_t launch_project_bwd(const exm_mesh* m, const exm_material* mat, int64_t n_px, const int32_t* tri_id,
+                              const float* bary, const float* dP, float* dtex, hipStream_t s);
+hipError_t launch_image_loss(const float* a, const float* b, int32_t n_views, int32_t H, int32_t W, float scale,
+                             double* loss, float* dA, void* ws, hipStream_t s);
+hipError_t launch_tv_screen(const float* P, const int32_t* tri, int32_t n_views, int32_t H, int32_t W, int32_t metallic,
+                            float scale, double* loss, float* dP, hipStream_t s);
+hipError_t launch_env_regularizers(const float* E, int32_t He, int32_t We, float w_tv, float w_chroma, double* loss,
+                                   double* dE, double* acc3, hipStream_t s);
+hipError_t launch_adam(float* prm, const void* grad, bool grad_f64, float* m, float* v, int64_t n, int32_t n_chan,
+                       const float* lo, const float* hi, double lr, double b1, double b2, double eps, int32_t t,
+                       hipStream_t s);
 hipError_t launch_raster(const exm_mesh* m, const RasterViews& v, int32_t* tri_id, float* bary, hipStream_t s);
 hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                             const ShadeViews& v, const int32_t* tri_id, const float* bary, const exm_params* p,
