@@ -195,3 +195,63 @@ def test_stage2_self_consistency():
     assert end - floor < 0.35 * (start - floor)
     assert err1 < 0.7 * err0
     assert float(env.env.min()) >= 0.0
+
+
+def _small_problem(indirect="train", iters=40):
+    from paper_2608_24109_amd import _lib as L
+    from paper_2608_24109_amd.optimize import Stage2, Stage2Config, initial_maps
+    from paper_2608_24109_amd.render import PassBuffers, PassParams, render_forward
+    from paper_2608_24109_amd.scene import DeviceEnv, DeviceMaterial, DeviceMesh
+    # two interlocking tori: a non-convex scene, so that the one-bounce term is not zero
+    pos, tri = I.interlocking_tori(40, 12)
+    uv, tri_uv = I.cube_projected_uvs(pos, tri)
+    tex, envm = I.pbr_maps(64, 64, seed=11), I.env_map(16, 32, 1.0, seed=12)
+    mesh = DeviceMesh(pos, tri, uv, tri_uv)
+    cams = I.ring_cameras(3, 3.0, 64, 64)
+    tmin = 1e-4 * I.aabb_diagonal(pos)
+    cfg = Stage2Config(iters=iters, ramp_iters=10, N_d=4, N_b=4, N_s=2, half_res_indirect=True, tmin=tmin,
+                       indirect=indirect)
+    mat_gt, env_gt = DeviceMaterial(tex), DeviceEnv(envm)
+    p = PassParams(N_d=16, N_b=4, N_s=2, tmin=tmin, flags=L.EXM_METALLIC_OFF)
+    tg = torch.empty((3, 64, 64, 3), dtype=torch.float32, device="cuda")
+    for k, c in enumerate(cams):
+        b = PassBuffers(1, 64, 64, p.N_b)
+        render_forward(mesh, mat_gt, env_gt, L.cameras([c], [k]), p, b)
+        tg[k] = (b.L_dir + b.L_ind)[0]
+    tex0, env0 = initial_maps(np.clip(tex[..., :3], 0, 1), 64, 64, 16, 32)
+    return Stage2(mesh, DeviceMaterial(tex0), DeviceEnv(env0), cams, tg, cfg)
+
+
+def test_indirect_ablation_modes():
+    """Eval-only Indirect trains on direct light only and evaluates with the one-bounce term;
+    Direct Only never adds it. At equal parameters the evaluated images agree with the full
+    method's bit for bit."""
+    full, evo, off = (_small_problem(m) for m in ("train", "eval_only", "off"))
+    assert full.bufs.L_ind is not None and evo.bufs.L_ind is None and off.bufs.L_ind is None
+    a, b, c = full.evaluate(1), evo.evaluate(1), off.evaluate(1)
+    assert torch.equal(a, b)
+    assert torch.equal(c, off.eval_bufs.L_dir)
+    assert float((a - c).abs().max()) > 0.0
+    for s in (evo, off):
+        s.run(10)
+        assert s.bufs.L_ind is None
+
+
+def test_stage2_resume_matches_uninterrupted_run():
+    """state_dict after 20 iterations, 10 more iterations; a fresh loop loaded from the state
+    takes the same 10 iterations to the same maps (the map adjoint sums with float atomics, so
+    the comparison allows their rounding order)."""
+    a = _small_problem()
+    a.run(20)
+    st = a.state_dict()
+    a.run(10)
+    b = _small_problem()
+    b.load_state_dict(st)
+    assert b.t == 20
+    b.run(10)
+    ta, tb = a.mat.tex.cpu().numpy(), b.mat.tex.cpu().numpy()
+    close = np.abs(ta - tb) <= 1e-5
+    log(f"  resumed maps: {close.mean():.6f} of values within 1e-5, max diff {np.abs(ta - tb).max():.3g}")
+    assert close.mean() > 0.999
+    assert np.abs(ta - tb).max() <= 20 * a.cfg.lr_tex
+    assert np.allclose(a.env.env.cpu().numpy(), b.env.env.cpu().numpy(), rtol=1e-4, atol=1e-5)
