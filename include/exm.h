@@ -289,6 +289,61 @@ exm_status exm_adam_step(float* param, const void* grad, int32_t grad_is_f64, fl
                          int32_t n_chan, const float* lo_host, const float* hi_host, double lr, double beta1,
                          double beta2, double eps, int32_t t, hipStream_t stream);
 
+/* ---- Stage-I topology operations (Vertex Splitting, Vertex Merging, UV Maintenance; Eq. 1-6) --
+ * A mesh being refined lives in caller-owned device arrays of fixed capacity; a round rewrites
+ * them in place and updates the counts. */
+typedef struct {
+  int32_t nV, nF, nUV;          /* current counts (updated by exm_topology_round) */
+  int32_t capV, capF, capUV;    /* capacities of the arrays below */
+  float* pos;                   /* [capV,3] vertex positions */
+  float* G;                     /* [capV] per-vertex EMA of the position-gradient norm (Eq. 1) */
+  float* uv;                    /* [capUV,2] UV coordinates */
+  int32_t* tri;                 /* [capF,3] faces (vertex indices) */
+  int32_t* tri_uv;              /* [capF,3] face-corner UV indices (Phi) */
+} exm_topo_mesh;
+
+#define EXM_TOPO_NO_SPLIT (1u << 0) /* merging only */
+#define EXM_TOPO_NO_MERGE (1u << 1) /* splitting only */
+
+typedef struct {
+  double beta_g;                /* EMA coefficient of Eq. 1 (0.95) */
+  double w_g, w_k;              /* split-score weights of Eq. 3 (0.6, 0.4) */
+  double tau_degen;             /* degeneracy threshold of Eq. 4 (0.05) */
+  double tau_uv;                /* UV seam threshold of Eq. 6 (UV units) */
+  double split_fraction;        /* share of the faces selected per splitting round */
+  int32_t max_faces;            /* face budget (200K) */
+  uint32_t flags;               /* EXM_TOPO_NO_SPLIT, EXM_TOPO_NO_MERGE */
+} exm_topo_params;
+
+typedef struct {
+  int32_t split_selected, split_invalid, split_conflict, splits;
+  int32_t merge_candidates, merge_conflict, merges, faces_deleted;
+  int32_t mis_iterations;       /* parallel passes of the conflict resolution */
+} exm_topo_stats;
+
+/* Eq. 1: G[v] = beta G[v] + (1 - beta) |grad[v]| for nV vertices; grad [nV,3] float. Evaluated in
+ * FP64 and rounded to float. */
+exm_status exm_vertex_grad_ema(float* G, const float* grad, int32_t nV, double beta, hipStream_t stream);
+/* C_rend of the merging criterion: counts[f] += number of pixels of a G-buffer (n_px ids, -1 for
+ * background) whose visible face is f (f < nF). Accumulates over calls (views). */
+exm_status exm_face_render_counts(const int32_t* tri_id, int64_t n_px, int32_t nF, int32_t* counts,
+                                  hipStream_t stream);
+/* Workspace of a round (and of exm_topology_scores) on a mesh of these counts. */
+size_t exm_topology_workspace_size(int32_t nV, int32_t nF, int32_t nUV, const exm_topo_params* p);
+/* Per-face terms of the criteria (FP64, [nF] each): S_f of Eq. 3 (with K_f of Eq. 2 and the face
+ * mean of G), K_f, D_f of Eq. 4 and the face area. */
+exm_status exm_topology_scores(const exm_topo_mesh* m, const exm_topo_params* p, double* S, double* K, double* D,
+                               double* area, void* ws, size_t ws_bytes, hipStream_t stream);
+/* One round of vertex splitting then vertex merging with the UV updates of Eq. 5-6 and the index
+ * compaction after merging, on the criteria of the mesh at the start of the round. c_rend [nF]
+ * is the render count of every face (NULL: every face counts as rendered). The arrays of *m are
+ * rewritten in place and its counts updated; the capacities must hold nV + K vertices,
+ * nF + 2K faces and nUV + 2K UVs, K = min(floor(split_fraction nF), floor((max_faces - nF)/2)).
+ * Synchronous: it waits on `stream` (the conflict resolution reads a counter back per pass) and
+ * fills *stats (host). Deterministic: the result does not depend on thread scheduling. */
+exm_status exm_topology_round(exm_topo_mesh* m, const int32_t* c_rend, const exm_topo_params* p, void* ws,
+                              size_t ws_bytes, exm_topo_stats* stats, hipStream_t stream);
+
 /* Measurement hooks. With timing enabled, every kernel the library launches is bracketed by
  * two HIP events recorded on its launch stream (no events exist while it is off).
  * exm_timing_enable clears the records; exm_timing_collect waits for the recorded events and

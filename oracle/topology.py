@@ -209,6 +209,9 @@ def topology_round(pos, G, uv, tri, tri_uv, c_rend, prm: TopoParams):
                 flip = j is None
                 if flip:
                     j = _edge_start(tri[g2], a, b)
+                if j is None:  # a neighbour with a repeated vertex: discarded
+                    stats["split_invalid"] += 1
+                    continue
                 d = int(tri[g2, (j + 2) % 3])
                 lc = _dot(_sub(_p(pos, c), pa), e) / ee
                 ld = _dot(_sub(_p(pos, d), pa), e) / ee

@@ -26,6 +26,9 @@ EXM_SPECULAR_ONLY = 1 << 2
 EXM_NO_VIS = 1 << 3
 EXM_NO_SECONDARY_MATERIAL = 1 << 4
 
+EXM_TOPO_NO_SPLIT = 1 << 0
+EXM_TOPO_NO_MERGE = 1 << 1
+
 
 class ExmError(RuntimeError):
     def __init__(self, status: int, where: str, msg: str):
@@ -60,6 +63,27 @@ class exm_params(C.Structure):
 
 
 SEC_REC_BYTES = 12  # exm_sec_rec {int32 tri; float b1, b2}
+
+
+class exm_topo_mesh(C.Structure):
+    _fields_ = [("nV", C.c_int32), ("nF", C.c_int32), ("nUV", C.c_int32), ("capV", C.c_int32), ("capF", C.c_int32),
+                ("capUV", C.c_int32), ("pos", C.c_void_p), ("G", C.c_void_p), ("uv", C.c_void_p),
+                ("tri", C.c_void_p), ("tri_uv", C.c_void_p)]
+
+
+class exm_topo_params(C.Structure):
+    _fields_ = [("beta_g", C.c_double), ("w_g", C.c_double), ("w_k", C.c_double), ("tau_degen", C.c_double),
+                ("tau_uv", C.c_double), ("split_fraction", C.c_double), ("max_faces", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class exm_topo_stats(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("split_selected", "split_invalid", "split_conflict", "splits",
+                                         "merge_candidates", "merge_conflict", "merges", "faces_deleted",
+                                         "mis_iterations")]
+
+    def as_dict(self) -> dict:
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
 def _load() -> C.CDLL:
@@ -102,6 +126,11 @@ def _load() -> C.CDLL:
         "exm_env_regularizers": (st, [vp, i32, i32, C.c_float, C.c_float, vp, vp, vp, vp]),
         "exm_adam_step": (st, [vp, vp, i32, vp, vp, C.c_int64, i32, vp, vp, C.c_double, C.c_double, C.c_double,
                                C.c_double, i32, vp]),
+        "exm_vertex_grad_ema": (st, [vp, vp, i32, C.c_double, vp]),
+        "exm_face_render_counts": (st, [vp, C.c_int64, i32, vp, vp]),
+        "exm_topology_workspace_size": (C.c_size_t, [i32, i32, i32, vp]),
+        "exm_topology_scores": (st, [vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
+        "exm_topology_round": (st, [vp, vp, vp, vp, C.c_size_t, vp, vp]),
         "exm_timing_enable": (st, [i32]),
         "exm_timing_collect": (st, []),
         "exm_timing_count": (i32, []),
@@ -440,3 +469,35 @@ def exm_adam_step(param, grad, m, v, lo, hi, lr: float, t: int, beta1: float = 0
     _check(lib.exm_adam_step(_ptr(param), _ptr(grad), 1 if grad.dtype == torch.float64 else 0, _ptr(m), _ptr(v),
                              param.numel(), n_chan, lo_a, hi_a, float(lr), float(beta1), float(beta2), float(eps),
                              int(t), _stream(stream)), "exm_adam_step")
+
+
+def exm_vertex_grad_ema(G, grad, beta: float, stream=None) -> None:
+    """Eq. 1 in place on G [nV] float32 with grad [nV,3] float32."""
+    import torch
+    nV = G.shape[0]
+    _need(grad, torch.float32, (nV, 3), "grad")
+    _check(lib.exm_vertex_grad_ema(_ptr(G), _ptr(grad), nV, float(beta), _stream(stream)), "exm_vertex_grad_ema")
+
+
+def exm_face_render_counts(tri_id, nF: int, counts, stream=None) -> None:
+    """counts [>= nF] int32 += per-face pixel counts of the G-buffer ids tri_id (any shape)."""
+    _check(lib.exm_face_render_counts(_ptr(tri_id), tri_id.numel(), int(nF), _ptr(counts), _stream(stream)),
+           "exm_face_render_counts")
+
+
+def exm_topology_workspace_size(nV: int, nF: int, nUV: int, p: exm_topo_params) -> int:
+    return int(lib.exm_topology_workspace_size(nV, nF, nUV, C.byref(p)))
+
+
+def exm_topology_scores(m: exm_topo_mesh, p: exm_topo_params, S, K, D, area, ws, stream=None) -> None:
+    _check(lib.exm_topology_scores(C.byref(m), C.byref(p), _ptr(S), _ptr(K), _ptr(D), _ptr(area), _ptr(ws),
+                                   ws.numel() * ws.element_size(), _stream(stream)), "exm_topology_scores")
+
+
+def exm_topology_round(m: exm_topo_mesh, c_rend, p: exm_topo_params, ws, stream=None) -> dict:
+    """One round in place on the arrays of m (its counts are updated); returns the round's counts."""
+    st = exm_topo_stats()
+    _check(lib.exm_topology_round(C.byref(m), _ptr(c_rend) if c_rend is not None else None, C.byref(p), _ptr(ws),
+                                  ws.numel() * ws.element_size(), C.byref(st), _stream(stream)),
+           "exm_topology_round")
+    return st.as_dict()

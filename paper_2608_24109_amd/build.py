@@ -15,7 +15,9 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libexm.so")
 
-HIP_SOURCES = ["mesh.hip", "env_sampler.hip", "raster.hip", "shade.hip", "trace.hip", "rays.hip", "env_grad.hip", "upsample.hip", "stage2.hip"]
+HIP_SOURCES = ["mesh.hip", "env_sampler.hip", "raster.hip", "shade.hip", "trace.hip", "rays.hip", "env_grad.hip", "upsample.hip", "stage2.hip", "topology.hip"]
+# sources whose FP64 decisions must match a reference evaluated without fused multiply-adds
+NO_CONTRACT = {"topology.hip"}
 CPP_SOURCES = ["abi.cpp", "bvh_build.cpp", "timing.cpp"]
 
 ARCH = "gfx950"
@@ -50,7 +52,8 @@ def _compile(src: str, extra: list[str]) -> str:
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     host = ["-x", "c++", "-pthread", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include"]
-    jobs = [(s, HIP_FLAGS) for s in HIP_SOURCES] + [(s, host) for s in CPP_SOURCES]
+    nofma = [f for f in HIP_FLAGS if not f.startswith("-ffp-contract")] + ["-ffp-contract=off"]
+    jobs = [(s, nofma if s in NO_CONTRACT else HIP_FLAGS) for s in HIP_SOURCES] + [(s, host) for s in CPP_SOURCES]
     with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
         objs = list(ex.map(lambda a: _compile(*a), jobs))
     tmp = LIB + ".tmp"

@@ -546,4 +546,83 @@ exm_status exm_adam_step(float* prm, const void* grad, int32_t grad_is_f64, floa
   return EXM_OK;
 }
 
+static exm_status check_topo_params(const exm_topo_params* p) {
+  if (!p) return fail(EXM_E_INVAL, "params pointer is NULL");
+  if (!(p->beta_g >= 0.0 && p->beta_g <= 1.0) || !std::isfinite(p->w_g) || !std::isfinite(p->w_k) ||
+      !std::isfinite(p->tau_degen) || !(p->tau_uv >= 0.0 && std::isfinite(p->tau_uv)) ||
+      !(p->split_fraction >= 0.0 && p->split_fraction <= 1.0) || p->max_faces < 0 || (p->flags & ~3u))
+    return fail(EXM_E_INVAL, "topology params out of range");
+  return EXM_OK;
+}
+
+static exm_status check_topo_mesh(const exm_topo_mesh* m) {
+  if (!m || !m->pos || !m->G || !m->uv || !m->tri || !m->tri_uv) return fail(EXM_E_INVAL, "mesh pointer is NULL");
+  if (m->nV < 0 || m->nF < 0 || m->nUV < 0 || m->nF > (1 << 26) || m->nV > (1 << 26) || m->nUV > (1 << 27))
+    return fail(EXM_E_INVAL, "mesh counts out of range");
+  if (m->nV > m->capV || m->nF > m->capF || m->nUV > m->capUV) return fail(EXM_E_INVAL, "counts exceed capacities");
+  if (m->nF > 0 && (m->nV < 3 || m->nUV < 1)) return fail(EXM_E_INVAL, "faces need vertices and UVs");
+  return EXM_OK;
+}
+
+exm_status exm_vertex_grad_ema(float* G, const float* grad, int32_t nV, double beta, hipStream_t stream) {
+  if (!G || !grad) return fail(EXM_E_INVAL, "pointer is NULL");
+  if (nV < 0 || !(beta >= 0.0 && beta <= 1.0)) return fail(EXM_E_INVAL, "need nV >= 0 and 0 <= beta <= 1");
+  if (nV == 0) return EXM_OK;
+  EXM_TRY(check_device());
+  hipError_t e = launch_grad_ema(G, grad, nV, beta, stream);
+  if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_vertex_grad_ema: ") + hipGetErrorString(e));
+  return EXM_OK;
+}
+
+exm_status exm_face_render_counts(const int32_t* tri_id, int64_t n_px, int32_t nF, int32_t* counts,
+                                  hipStream_t stream) {
+  if (!tri_id || !counts) return fail(EXM_E_INVAL, "pointer is NULL");
+  if (n_px < 0 || nF < 0) return fail(EXM_E_INVAL, "negative size");
+  if (n_px == 0) return EXM_OK;
+  EXM_TRY(check_device());
+  hipError_t e = launch_face_counts(tri_id, n_px, nF, counts, stream);
+  if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_face_render_counts: ") + hipGetErrorString(e));
+  return EXM_OK;
+}
+
+size_t exm_topology_workspace_size(int32_t nV, int32_t nF, int32_t nUV, const exm_topo_params* p) {
+  if (!p || nV < 0 || nF < 0 || nUV < 0) return 0;
+  return topology_ws_bytes(nV, nF, nUV, p);
+}
+
+exm_status exm_topology_scores(const exm_topo_mesh* m, const exm_topo_params* p, double* S, double* K, double* D,
+                               double* area, void* ws, size_t ws_bytes, hipStream_t stream) {
+  EXM_TRY(check_topo_mesh(m));
+  EXM_TRY(check_topo_params(p));
+  if (!S || !K || !D || !area || !ws) return fail(EXM_E_INVAL, "output or workspace pointer is NULL");
+  if (ws_bytes < topology_ws_bytes(m->nV, m->nF, m->nUV, p)) return fail(EXM_E_NOMEM, "workspace too small");
+  if (!aligned(ws, 256)) return fail(EXM_E_INVAL, "workspace must be 256-byte aligned");
+  EXM_TRY(check_device());
+  bool ok = true;
+  hipError_t e = topology_check_indices(m, ws, &ok, stream);
+  if (e == hipSuccess && !ok) return fail(EXM_E_INVAL, "a face or UV index is out of range");
+  if (e == hipSuccess) e = launch_topology_scores(m, p, S, K, D, area, ws, stream);
+  if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_topology_scores: ") + hipGetErrorString(e));
+  return EXM_OK;
+}
+
+exm_status exm_topology_round(exm_topo_mesh* m, const int32_t* c_rend, const exm_topo_params* p, void* ws,
+                              size_t ws_bytes, exm_topo_stats* stats, hipStream_t stream) {
+  EXM_TRY(check_topo_mesh(m));
+  EXM_TRY(check_topo_params(p));
+  if (!ws || !stats) return fail(EXM_E_INVAL, "workspace or stats pointer is NULL");
+  const int64_t K = topology_split_count(m->nF, p);
+  if ((int64_t)m->nV + K > m->capV || (int64_t)m->nF + 2 * K > m->capF || (int64_t)m->nUV + 2 * K > m->capUV)
+    return fail(EXM_E_INVAL, "capacities must hold nV + K vertices, nF + 2K faces and nUV + 2K UVs");
+  if (ws_bytes < topology_ws_bytes(m->nV, m->nF, m->nUV, p)) return fail(EXM_E_NOMEM, "workspace too small");
+  if (!aligned(ws, 256)) return fail(EXM_E_INVAL, "workspace must be 256-byte aligned");
+  EXM_TRY(check_device());
+  bool ok = true;
+  hipError_t e = topology_check_indices(m, ws, &ok, stream);
+  if (e == hipSuccess && !ok) return fail(EXM_E_INVAL, "a face or UV index is out of range");
+  if (e == hipSuccess) e = launch_topology_round(m, c_rend, p, ws, stats, stream);
+  if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_topology_round: ") + hipGetErrorString(e));
+  return EXM_OK;
+}
+
 }  // extern "C"

@@ -115,6 +115,15 @@ hipError_t launch_adam(float* prm, const void* grad, bool grad_f64, float* m, fl
                        const float* lo, const float* hi, double lr, double b1, double b2, double eps, int32_t t,
                        hipStream_t s);
 hipError_t launch_raster(const exm_mesh* m, const RasterViews& v, int32_t* tri_id, float* bary, hipStream_t s);
+int32_t topology_split_count(int32_t nF, const exm_topo_params* p);
+hipError_t topology_check_indices(const exm_topo_mesh* m, void* ws, bool* ok, hipStream_t s);
+size_t topology_ws_bytes(int32_t nV, int32_t nF, int32_t nUV, const exm_topo_params* p);
+hipError_t launch_grad_ema(float* G, const float* grad, int32_t nV, double beta, hipStream_t s);
+hipError_t launch_face_counts(const int32_t* tri_id, int64_t n_px, int32_t nF, int32_t* counts, hipStream_t s);
+hipError_t launch_topology_scores(const exm_topo_mesh* m, const exm_topo_params* p, double* S, double* K, double* D,
+                                  double* area, void* ws, hipStream_t s);
+hipError_t launch_topology_round(exm_topo_mesh* m, const int32_t* c_rend, const exm_topo_params* p, void* ws,
+                                 exm_topo_stats* st, hipStream_t s);
 hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                             const ShadeViews& v, const int32_t* tri_id, const float* bary, const exm_params* p,
                             float* L_dir, uint64_t* vis, void* ws, size_t ws_bytes, unsigned long long* counters,

@@ -177,3 +177,38 @@ def test_env_sampler_and_bvh_validation(L):
     assert L.lib.exm_build_bvh(pos.ctypes.data, 3, tri.ctypes.data, 1, C.byref(out), None) == L.EXM_E_INVAL
     assert L.lib.exm_free_bvh(None) == L.EXM_OK
     assert L.lib.exm_bvh_device_bytes(None) == 0
+
+
+def _topo(L, nV=3, nF=1, nUV=3, cap=(4, 3, 5), ptr=0x1000):
+    return L.exm_topo_mesh(nV, nF, nUV, cap[0], cap[1], cap[2], ptr, ptr, ptr, ptr, ptr)
+
+
+def test_topology_validation_and_workspace(L):
+    from paper_2608_24109_amd.topology import TopoConfig
+    p = TopoConfig().c()
+    # workspace: grows with the mesh, needs no device
+    small = L.exm_topology_workspace_size(642, 1280, 3840, p)
+    big = L.exm_topology_workspace_size(49688, 99372, 298116, p)
+    assert 0 < small < big and big > 99372 * 8 * 8
+    assert L.lib.exm_topology_workspace_size(-1, 4, 4, C.byref(p)) == 0
+    st = L.exm_topo_stats()
+    f = L.lib.exm_topology_round
+    ws = 0x1000
+    m = _topo(L)
+    assert _status(L, f, None, None, C.byref(p), ws, 1 << 20, C.byref(st), None)[0] == L.EXM_E_INVAL
+    bad = L.exm_topo_params(p.beta_g, p.w_g, p.w_k, p.tau_degen, p.tau_uv, 1.5, p.max_faces, p.flags)
+    assert _status(L, f, C.byref(m), None, C.byref(bad), ws, 1 << 20, C.byref(st), None)[0] == L.EXM_E_INVAL
+    over = _topo(L, nV=5)
+    s, msg = _status(L, f, C.byref(over), None, C.byref(p), ws, 1 << 20, C.byref(st), None)
+    assert s == L.EXM_E_INVAL and "capacities" in msg
+    # one split needs a vertex, two faces and two UVs of room
+    q = TopoConfig(split_fraction=1.0).c()
+    tight = _topo(L, cap=(3, 1, 3))
+    s, msg = _status(L, f, C.byref(tight), None, C.byref(q), ws, 1 << 20, C.byref(st), None)
+    assert s == L.EXM_E_INVAL and "nV + K" in msg
+    s, _ = _status(L, f, C.byref(m), None, C.byref(p), ws, 16, C.byref(st), None)
+    assert s == L.EXM_E_NOMEM
+    g = L.lib.exm_vertex_grad_ema
+    assert _status(L, g, 0x1000, 0x1000, 4, 1.5, None)[0] == L.EXM_E_INVAL
+    assert _status(L, g, None, 0x1000, 4, 0.9, None)[0] == L.EXM_E_INVAL
+    assert _status(L, L.lib.exm_face_render_counts, 0x1000, -1, 4, 0x1000, None)[0] == L.EXM_E_INVAL

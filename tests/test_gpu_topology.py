@@ -1,0 +1,193 @@
+"""Stage-I topology operations on the device (Eq. 1-6) against the FP64 reference in
+oracle/topology.py: the EMA and the render counts bit for bit, the per-face criteria within
+FP64 rounding, and whole rounds (split only, merge only, both, on closed and open meshes, three
+rounds in a row, and a mesh of the paper's size) equal in every output array, including the new
+positions and UVs.
+
+The arccos of Eq. 2 may differ in the last bit between the device and the host library, and the
+mean face area is summed in another order; so each case first checks on the reference that no
+two ranked split scores, and no face area and the mean area, lie within 1e-11 of each other
+(relative) — then the decisions cannot differ and the outputs must be identical."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from oracle import topology as T
+from paper_2608_24109_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def _prm(cfg) -> T.TopoParams:
+    return T.TopoParams(beta_g=cfg.beta_g, w_g=cfg.w_g, w_k=cfg.w_k, tau_degen=cfg.tau_degen, tau_uv=cfg.tau_uv,
+                        max_faces=cfg.max_faces, split_fraction=cfg.split_fraction, do_split=cfg.split,
+                        do_merge=cfg.merge)
+
+
+def _margins(pos, tri, G, prm):
+    S, K, Gf, D, area, ell = T.face_scores(pos, tri, G, prm)
+    mean = float(np.sum(area)) / tri.shape[0]
+    cand = np.sort(S[area >= mean])[::-1]
+    gaps = np.abs(np.diff(cand)) / np.maximum(np.abs(cand[1:]), 1e-300)
+    ok_s = cand.size < 2 or gaps.min() > 1e-11
+    ok_a = np.abs(area - mean).min() > 1e-11 * mean
+    return ok_s and ok_a
+
+
+def _jitter_sphere(subdiv, seed, amp=0.01):
+    pos, tri = I.icosphere(subdiv)
+    rng = np.random.default_rng(seed)
+    pos = (pos + amp * rng.normal(size=pos.shape)).astype(np.float32)
+    uv, tuv = I.cube_projected_uvs(pos, tri)
+    return pos, tri, uv, tuv, rng
+
+
+def _plant_slivers(pos, tri, rng, n):
+    ef = T.edge_faces(tri)
+    keys = list(ef)
+    for i in rng.choice(len(keys), n, replace=False):
+        a, b = keys[i]
+        pos[a] = pos[a] + 0.9 * (pos[b] - pos[a])
+    return pos
+
+
+def _grid(n, seed):
+    pos, tri = I.quad_mesh(np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0]], np.float64), n, n)
+    rng = np.random.default_rng(seed)
+    pos = pos.copy()
+    pos[:, :2] += (0.2 / n) * rng.uniform(-1, 1, size=(pos.shape[0], 2)).astype(np.float32)
+    pos[:, 2] = 0.05 * rng.normal(size=pos.shape[0]).astype(np.float32)
+    uv = np.ascontiguousarray(pos[:, :2].astype(np.float32))
+    return pos.astype(np.float32), tri, uv, tri.copy(), rng
+
+
+def _compare(dev_out, ref_out, dev_st, ref_st):
+    names = ("pos", "G", "uv", "tri", "tri_uv")
+    for n, a, b in zip(names, dev_out, ref_out):
+        assert a.shape == b.shape, (n, a.shape, b.shape)
+        assert np.array_equal(a, b), (n, np.argwhere(a != b)[:5])
+    for k, v in ref_st.items():
+        assert dev_st[k] == v, (k, dev_st[k], v)
+
+
+def _run_case(pos, tri, uv, tuv, G, c_rend, cfg, rounds=1):
+    from paper_2608_24109_amd.topology import DeviceTopoMesh
+    prm = _prm(cfg)
+    dm = DeviceTopoMesh(pos, tri, uv, tuv, G, cfg)
+    ref = (pos, G, uv, tri, tuv)
+    for r in range(rounds):
+        assert _margins(ref[0], ref[3], ref[1], prm), "scores or areas too close to decide reproducibly"
+        cr = np.ones(ref[3].shape[0], np.int32) if c_rend is None or r > 0 else c_rend
+        st = dm.round(torch.from_numpy(cr).cuda())
+        ref, rst = T.topology_round(ref[0], ref[1], ref[2], ref[3], ref[4], cr, prm)
+        log(f"  round {r}: {rst} (device passes {st['mis_iterations']})")
+        _compare(dm.to_numpy(), ref, st, rst)
+    return st
+
+
+def test_grad_ema_and_render_counts_match_the_reference():
+    from paper_2608_24109_amd import _lib as L
+    rng = np.random.default_rng(0)
+    G = rng.random(1000).astype(np.float32)
+    g = rng.normal(size=(1000, 3)).astype(np.float32)
+    Gd = torch.from_numpy(G).cuda()
+    L.exm_vertex_grad_ema(Gd, torch.from_numpy(g).cuda(), 0.95)
+    assert np.array_equal(Gd.cpu().numpy(), T.grad_ema(G, g, 0.95))
+    from paper_2608_24109_amd.topology import DeviceTopoMesh
+    sc = I.config("small")
+    dm = DeviceTopoMesh(sc.pos, sc.tri, sc.uv, sc.tri_uv)
+    cams = I.ring_cameras(3, 3.0, 96, 80)
+    counts = dm.render_counts(cams).cpu().numpy()
+    om = O.OracleMesh(sc.pos, sc.tri, sc.uv, sc.tri_uv)
+    ref = np.zeros(sc.tri.shape[0], np.int64)
+    for c in cams:
+        ids, _ = O.raster(om, c)
+        ids = ids.reshape(-1)
+        ref += np.bincount(ids[ids >= 0], minlength=sc.tri.shape[0])
+    assert np.array_equal(counts, ref) and (ref == 0).any() and (ref > 0).any()
+
+
+def test_scores_match_the_reference():
+    from paper_2608_24109_amd.topology import DeviceTopoMesh, TopoConfig
+    pos, tri, uv, tuv, rng = _jitter_sphere(4, 1)
+    G = rng.random(pos.shape[0]).astype(np.float32)
+    dm = DeviceTopoMesh(pos, tri, uv, tuv, G, TopoConfig())
+    out = {k: v.cpu().numpy() for k, v in dm.scores().items()}
+    S, K, Gf, D, area, ell = T.face_scores(pos, tri, G, _prm(TopoConfig()))
+    assert np.array_equal(out["area"], area) and np.array_equal(out["D"], D)
+    assert np.allclose(out["K"], K, rtol=1e-14, atol=1e-15) and np.allclose(out["S"], S, rtol=1e-14, atol=1e-15)
+
+
+def test_split_round_closed_mesh():
+    from paper_2608_24109_amd.topology import TopoConfig
+    pos, tri, uv, tuv, rng = _jitter_sphere(4, 2)
+    G = rng.random(pos.shape[0]).astype(np.float32)
+    st = _run_case(pos, tri, uv, tuv, G, None, TopoConfig(split_fraction=0.1, merge=False))
+    assert st["splits"] > 200 and st["split_conflict"] > 0
+
+
+def test_merge_round_closed_mesh():
+    from paper_2608_24109_amd.topology import TopoConfig
+    pos, tri, uv, tuv, rng = _jitter_sphere(4, 3)
+    pos = _plant_slivers(pos, tri, rng, 120)
+    c = np.ones(tri.shape[0], np.int32)
+    c[rng.choice(tri.shape[0], 200, replace=False)] = 0
+    st = _run_case(pos, tri, uv, tuv, np.zeros(pos.shape[0], np.float32), c, TopoConfig(split=False))
+    assert st["merges"] > 30 and st["merge_conflict"] > 0
+
+
+def test_full_rounds_open_mesh():
+    """An open, jittered height-field grid: boundary splits and boundary-edge collapses; three
+    rounds in a row, each side continuing from its own output."""
+    from paper_2608_24109_amd.topology import TopoConfig
+    pos, tri, uv, tuv, rng = _grid(40, 4)
+    pos = _plant_slivers(pos, tri, rng, 60)
+    G = rng.random(pos.shape[0]).astype(np.float32)
+    c = np.ones(tri.shape[0], np.int32)
+    c[rng.choice(tri.shape[0], 50, replace=False)] = 0
+    st = _run_case(pos, tri, uv, tuv, G, c, TopoConfig(split_fraction=0.1), rounds=3)
+    assert st["splits"] > 0
+
+
+def test_full_round_with_seams_and_budget():
+    """Cube-projected UVs (seams on the cube edges) and a face budget that caps the splits."""
+    from paper_2608_24109_amd.topology import TopoConfig
+    pos, tri, uv, tuv, rng = _jitter_sphere(4, 5)
+    pos = _plant_slivers(pos, tri, rng, 40)
+    G = rng.random(pos.shape[0]).astype(np.float32)
+    st = _run_case(pos, tri, uv, tuv, G, None, TopoConfig(split_fraction=0.2, max_faces=tri.shape[0] + 301))
+    assert st["split_selected"] == 150
+
+
+def test_empty_mesh_and_bad_indices():
+    from paper_2608_24109_amd import _lib as L
+    from paper_2608_24109_amd.topology import DeviceTopoMesh, TopoConfig
+    dm = DeviceTopoMesh(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 2)), np.zeros((0, 3)), cfg=TopoConfig())
+    st = dm.round()
+    assert st["splits"] == 0 and dm.nF == 0
+    pos, tri, uv, tuv, _ = _jitter_sphere(1, 6)
+    bad = tri.copy()
+    bad[3, 1] = pos.shape[0]  # one index past the vertex count: rejected before any kernel uses it
+    dm = DeviceTopoMesh(pos, bad, uv, tuv, cfg=TopoConfig())
+    with pytest.raises(L.ExmError):
+        dm.round()
+
+
+def test_paper_size_round():
+    """A 99,372-face displaced cube-sphere (the paper-shape asset) with slivers and unrendered
+    faces: one full round at the 5% split fraction within the 200K-face budget."""
+    from paper_2608_24109_amd.topology import TopoConfig
+    sc = I.config("paper_shape")
+    rng = np.random.default_rng(7)
+    pos = _plant_slivers(sc.pos.copy(), sc.tri, rng, 500)
+    G = rng.random(pos.shape[0]).astype(np.float32)
+    c = np.ones(sc.tri.shape[0], np.int32)
+    c[rng.choice(sc.tri.shape[0], 2000, replace=False)] = 0
+    st = _run_case(pos, sc.tri, sc.uv, sc.tri_uv, G, c, TopoConfig())
+    assert st["splits"] > 1000 and st["merges"] > 100
