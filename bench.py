@@ -444,6 +444,33 @@ def kernel_bytes_per_step(kernel: str, st: dict, p) -> float:
     return float("nan")
 
 
+# Algorithmic VALU work per unit, one lane operation each (add, mul, fma, min, max, compare,
+# select): a BVH2 node visit tests two child boxes, per child and axis 2 subtractions, 2
+# multiplications by the inverse direction, a min and a max (18), entry and exit as the max /
+# min of three axes and the ray interval (6) and their comparison (1), plus the child order (1):
+# 51. A watertight ray/triangle test (Woop, Benthin and Wald 2013): vertices relative to the
+# origin (9), shear (6), edge functions U, V, W (9), sign tests (6), determinant (2), scaled
+# distance (8), its reciprocal and product (2), range test (2): 44. The env-map pick and the
+# shading of one sample (dir_gen) and its adjoint (shade_bwd) take about 150 and 350 lane
+# operations (estimates from the instruction mix of the BRDF and its derivatives).
+NODE_OPS, TRI_OPS, GEN_SAMPLE_OPS, BWD_SAMPLE_OPS = 51.0, 44.0, 150.0, 350.0
+# plain (non-packed) FP32 vector issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def kernel_lane_ops_per_step(kernel: str, st: dict) -> float:
+    if kernel == "trace_any":
+        return (NODE_OPS * (st["shadow_nodes"] + st.get("sec_shadow_nodes", 0))
+                + TRI_OPS * (st["shadow_tris"] + st.get("sec_shadow_tris", 0)))
+    if kernel == "trace_closest":
+        return NODE_OPS * st["sec_nodes"] + TRI_OPS * st["sec_tris"]
+    if kernel == "dir_gen":
+        return GEN_SAMPLE_OPS * st["samples"]
+    if kernel == "shade_bwd":
+        return BWD_SAMPLE_OPS * st["samples"]
+    return float("nan")
+
+
 def pmc_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc summary, if it was taken
     on the current kernel sources (else None)."""
@@ -484,6 +511,12 @@ def main():
     per_launch = kernel_bytes_per_step(dom, stats, p) / gk[dom]["launches_per_step"]
     achieved = per_launch / (gk[dom]["avg_ms"] * 1e-3) / 1e9
     traffic = pmc_traffic(dom, a.workload)
+    ops_launch = kernel_lane_ops_per_step(dom, stats) / gk[dom]["launches_per_step"]
+    ops_rate = ops_launch / (gk[dom]["avg_ms"] * 1e-3) / 1e12
+
+    def alu_view(k):
+        o = kernel_lane_ops_per_step(k, stats) / gk[k]["launches_per_step"] / (gk[k]["avg_ms"] * 1e-3) / 1e12
+        return {"achieved": round(o, 3), "frac": round(o / VALU_PEAK_T, 4)}
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mpixels/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
@@ -497,12 +530,22 @@ def main():
         "direct_shadow_Mrays_s": round(stats["shadow_rays"] / (kern["shade_fwd"] * 1e-3) / 1e6, 1),
         "nodes_per_shadow_ray": round(stats["shadow_nodes"] / max(stats["shadow_rays"], 1), 2),
         "tris_per_shadow_ray": round(stats["shadow_tris"] / max(stats["shadow_rays"], 1), 2),
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": None if math.isnan(achieved) else round(achieved, 2),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": None if math.isnan(achieved) else round(achieved / HBM_PEAK_GBS, 5),
+        # the traversal is bound by VALU issue (its node and triangle bytes come from L2 and the
+        # MALL): the roofline is the ALU one, with the HBM view of the same launches beside it
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": None if math.isnan(ops_rate) else round(ops_rate, 3),
+                     "peak": round(VALU_PEAK_T, 2), "unit": "TFLOP/s",
+                     "frac": None if math.isnan(ops_rate) else round(ops_rate / VALU_PEAK_T, 4),
                      "traffic": None if traffic is None else round(traffic),
-                     "algorithmic_bytes_per_launch": None if math.isnan(per_launch) else round(per_launch),
+                     "algorithmic_lane_ops_per_launch": None if math.isnan(ops_launch) else round(ops_launch),
                      "avg_launch_ms": round(gk[dom]["avg_ms"], 4)},
+        "roofline_hbm": {"bound": "hbm", "kernel": dom,
+                         "achieved": None if math.isnan(achieved) else round(achieved, 2),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": None if math.isnan(achieved) else round(achieved / HBM_PEAK_GBS, 5),
+                         "algorithmic_bytes_per_launch": None if math.isnan(per_launch) else round(per_launch),
+                         "traffic_frac": None if traffic is None else
+                         round(traffic / (gk[dom]["avg_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "alu_rooflines": {k: alu_view(k) for k in ("trace_any", "dir_gen", "shade_bwd") if k in gk},
         "gpu_kernels_ms": {k: round(v["avg_ms"], 4) for k, v in sorted(gk.items(), key=lambda kv: -kv[1]["ms_per_step"])},
         "gpu_kernel_launches_per_step": {k: v["launches_per_step"] for k, v in gk.items()},
         "algorithmic_GBps": {k: round(algorithmic_bytes(k, stats, p) / (kern[k] * 1e-3) / 1e9, 1)
