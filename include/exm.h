@@ -202,12 +202,15 @@ exm_status exm_trace_indirect_counted(const exm_mesh* m, const exm_bvh* bvh, con
 
 /* Adjoint of the direct pass for upstream dI [nViews,H,W,3]: dtex [Ht,Wt,8] += d/dtex,
  * denv [He,We,3] += d/dE (double). Discrete choices (ids, texel picks, vis bits) and the
- * sampling pdf are held fixed. */
+ * sampling pdf are held fixed. dquery [nViews,H,W,8] (or NULL) is a gradient with respect to
+ * the eight queried map values of Eq. 10 at each visible pixel (such as the adjoint of a loss on
+ * the screen projection of the maps); it is added to the pixel's map adjoint before the one
+ * scatter into dtex, which gives what exm_project_maps_bwd would add. */
 exm_status exm_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env,
                          const exm_camera* cams_host, int32_t nViews, const int32_t* tri_id,
                          const float* bary, const exm_params* p, const float* dI,
-                         const uint64_t* vis, float* dtex, double* denv, void* ws, size_t ws_bytes,
-                         hipStream_t stream);
+                         const uint64_t* vis, const float* dquery, float* dtex, double* denv, void* ws,
+                         size_t ws_bytes, hipStream_t stream);
 
 /* Adjoint of the indirect pass for upstream lambda_ind * dI (Eq. 20): into the materials at
  * the primary and the secondary points and into E at the secondary light samples. */
@@ -267,7 +270,7 @@ exm_status exm_project_maps_bwd(const exm_mesh* m, const exm_material* mat, int3
                                 const int32_t* tri_id, const float* bary, const float* dP, float* dtex,
                                 hipStream_t stream);
 /* scale * L_img of each view (I_hat, I [nViews,H,W,3]) into *loss; dI_hat = scale * dL_img/dI_hat
- * (written). Workspace: exm_image_loss_workspace_size(H, W) bytes, 256-byte aligned. */
+ * (written). Workspace: exm_image_loss_workspace_size(H, W) bytes, 256-byte aligned. H <= 65535. */
 size_t exm_image_loss_workspace_size(int32_t H, int32_t W);
 exm_status exm_image_loss(const float* I_hat, const float* I, int32_t nViews, int32_t H, int32_t W, float scale,
                           double* loss, float* dI_hat, void* ws, size_t ws_bytes, hipStream_t stream);

@@ -109,7 +109,7 @@ def _load() -> C.CDLL:
         "exm_shade_fwd_counted": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp, vp]),
         "exm_trace_indirect_counted": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp,
                                             vp]),
-        "exm_shade_bwd": (st, [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
+        "exm_shade_bwd": (st, [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
         "exm_trace_bwd": (st, [vp, vp, vp, vp, i32, vp, vp, vp, C.c_float, vp, vp, vp, vp, vp, vp, C.c_size_t,
                                vp]),
         "exm_shade_bwd_workspace_size": (C.c_size_t, [i32, i32, i32, i32, i32, i32]),
@@ -344,15 +344,18 @@ def exm_trace_bwd_workspace_min(N_b: int, N_s: int, He: int, We: int) -> int:
 
 
 def exm_shade_bwd(mesh, mat, env, cams, tri_id, bary, p: exm_params, dI, vis, dtex, denv, ws,
-                  stream=None) -> None:
+                  stream=None, dquery=None) -> None:
+    """dquery: optional [n,H,W,8] gradient with respect to the queried map values."""
     import torch
     n, H, W = len(cams), cams[0].H, cams[0].W
     _need(dI, torch.float32, (n, H, W, 3), "dI")
     _need(dtex, torch.float32, (mat.Ht, mat.Wt, 8), "dtex")
     _need(denv, torch.float64, (env.He, env.We, 3), "denv")
+    if dquery is not None:
+        _need(dquery, torch.float32, (n, H, W, 8), "dquery")
     _check(lib.exm_shade_bwd(C.byref(mesh), C.byref(mat), C.byref(env), cams, n, _ptr(tri_id), _ptr(bary),
-                             C.byref(p), _ptr(dI), _ptr(vis), _ptr(dtex), _ptr(denv), _ptr(ws), ws.numel(),
-                             _stream(stream)), "exm_shade_bwd")
+                             C.byref(p), _ptr(dI), _ptr(vis), _ptr(dquery), _ptr(dtex), _ptr(denv), _ptr(ws),
+                             ws.numel(), _stream(stream)), "exm_shade_bwd")
 
 
 def exm_trace_bwd(mesh, mat, env, cams, tri_id, bary, p: exm_params, lambda_ind: float, dI, sec_rec, sec_vis,

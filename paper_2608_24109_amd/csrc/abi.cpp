@@ -379,8 +379,8 @@ size_t exm_trace_bwd_workspace_min(int32_t N_b, int32_t N_s, int32_t He, int32_t
 
 exm_status exm_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const exm_camera* cams,
                          int32_t nViews, const int32_t* tri_id, const float* bary, const exm_params* p, const float* dI,
-                         const uint64_t* vis, float* dtex, double* denv, void* ws, size_t ws_bytes,
-                         hipStream_t stream) {
+                         const uint64_t* vis, const float* dquery, float* dtex, double* denv, void* ws,
+                         size_t ws_bytes, hipStream_t stream) {
   EXM_TRY(check_mesh(m, true));
   EXM_TRY(check_material(mat));
   EXM_TRY(check_env(env));
@@ -388,6 +388,7 @@ exm_status exm_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_e
   EXM_TRY(check_gbuffer(tri_id, bary));
   EXM_TRY(check_params(p, false));
   if (!dI || !vis || !dtex || !denv) return fail(EXM_E_INVAL, "gradient pointer is NULL");
+  if (dquery && !aligned(dquery, 16)) return fail(EXM_E_INVAL, "dquery must be 16-byte aligned");
   if (!ws || !aligned(ws, 256) || ws_bytes < shade_bwd_ws_min(p->N_d, env->He, env->We))
     return fail(EXM_E_INVAL, "workspace must be 256-byte aligned and at least exm_shade_bwd_workspace_min bytes");
   EXM_TRY(check_device());
@@ -395,7 +396,8 @@ exm_status exm_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_e
   for (int32_t v0 = 0; v0 < nViews; v0 += kViewsPerLaunch) {
     const int32_t n = std::min(kViewsPerLaunch, nViews - v0);
     hipError_t e = launch_shade_bwd(m, mat, env, shade_views(cams, v0, n), tri_id + v0 * HW, bary + 2 * v0 * HW, p,
-                                    dI + 3 * v0 * HW, vis + v0 * HW, dtex, denv, ws, ws_bytes, stream);
+                                    dI + 3 * v0 * HW, vis + v0 * HW, dquery ? dquery + 8 * v0 * HW : nullptr, dtex,
+                                    denv, ws, ws_bytes, stream);
     if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_shade_bwd: ") + hipGetErrorString(e));
   }
   return EXM_OK;
@@ -497,6 +499,7 @@ size_t exm_image_loss_workspace_size(int32_t H, int32_t W) {
 exm_status exm_image_loss(const float* a, const float* b, int32_t n, int32_t H, int32_t W, float scale, double* loss,
                           float* dA, void* ws, size_t ws_bytes, hipStream_t stream) {
   EXM_TRY(check_view_dims(n, H, W));
+  if (H > 65535) return fail(EXM_E_INVAL, "H must be at most 65535");
   if (!a || !b || !loss || !dA) return fail(EXM_E_INVAL, "pointer is NULL");
   if (!std::isfinite(scale)) return fail(EXM_E_INVAL, "scale must be finite");
   if (!ws || !aligned(ws, 256) || ws_bytes < image_loss_ws_bytes(H, W))

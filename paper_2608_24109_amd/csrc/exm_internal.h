@@ -132,7 +132,8 @@ size_t shade_fwd_ws_bytes(int64_t n_pix, int32_t N_d);
 size_t shade_fwd_ws_min(int32_t N_d);
 hipError_t launch_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const ShadeViews& v,
                             const int32_t* tri_id, const float* bary, const exm_params* p, const float* dI,
-                            const uint64_t* vis, float* dtex, double* denv, void* ws, size_t ws_bytes, hipStream_t s);
+                            const uint64_t* vis, const float* dquery, float* dtex, double* denv, void* ws,
+                            size_t ws_bytes, hipStream_t s);
 size_t shade_bwd_ws_bytes(int64_t n_pix, int32_t N_d, int32_t He, int32_t We);
 size_t shade_bwd_ws_min(int32_t N_d, int32_t He, int32_t We);
 hipError_t launch_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,

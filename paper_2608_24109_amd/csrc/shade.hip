@@ -275,7 +275,8 @@ __global__ __launch_bounds__(kThreads) void k_shade_bwd(MeshView M, TexView T, E
                                                         const int32_t* __restrict__ tri_id,
                                                         const float* __restrict__ bary, KParams p, int64_t p0,
                                                         int64_t P, const float* __restrict__ dI,
-                                                        const uint64_t* __restrict__ vis, float* __restrict__ dtex,
+                                                        const uint64_t* __restrict__ vis,
+                                                        const float* __restrict__ dquery, float* __restrict__ dtex,
                                                         EnvGradWs eg, bool use_lds) {
   extern __shared__ __align__(16) char smem[];
   const EnvTabs tb = load_env_tabs(E, smem, use_lds);
@@ -286,16 +287,26 @@ __global__ __launch_bounds__(kThreads) void k_shade_bwd(MeshView M, TexView T, E
   int32_t f = -1;
   uint64_t bits = 0;
   float g[3] = {0.f, 0.f, 0.f};
+  float gx[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // the given query-value gradient
+  bool extra = false;
   if (act) {
     f = tri_id[gid];
     bits = vis[gid];
     g[0] = dI[3 * gid];
     g[1] = dI[3 * gid + 1];
     g[2] = dI[3 * gid + 2];
+    if (dquery && f >= 0) {
+      const float4 q0 = reinterpret_cast<const float4*>(dquery)[2 * gid];
+      const float4 q1 = reinterpret_cast<const float4*>(dquery)[2 * gid + 1];
+      gx[0] = q0.x, gx[1] = q0.y, gx[2] = q0.z, gx[3] = q0.w, gx[4] = q1.x, gx[5] = q1.y, gx[6] = q1.z, gx[7] = q1.w;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) extra |= gx[c] != 0.0f;
+    }
     act = f >= 0 && bits != 0 && (g[0] != 0.0f || g[1] != 0.0f || g[2] != 0.0f);
   }
   uint32_t slot = env_grad_reserve(eg.counter, act ? (uint32_t)__popcll(bits) : 0u);
-  if (!act) return;
+  if (!act && !extra) return;
+  if (!act) bits = 0;
   const int32_t view = (int32_t)(gid / HW);
   const uint32_t pix = (uint32_t)(gid - view * HW);
   const float2 b = reinterpret_cast<const float2*>(bary)[gid];
@@ -334,7 +345,8 @@ __global__ __launch_bounds__(kThreads) void k_shade_bwd(MeshView M, TexView T, E
   }
   float gq[3];
   normal_map_adjoint(S, G.n, gq);
-  const float g8[8] = {G.a[0], G.a[1], G.a[2], G.r, (p.flags & EXM_METALLIC_OFF) ? 0.0f : G.m, gq[0], gq[1], gq[2]};
+  const float g8[8] = {G.a[0] + gx[0], G.a[1] + gx[1], G.a[2] + gx[2], G.r + gx[3],
+                       ((p.flags & EXM_METALLIC_OFF) ? 0.0f : G.m) + gx[4], gq[0] + gx[5], gq[1] + gx[6], gq[2] + gx[7]};
   scatter_tex(S, g8, dtex);
 }
 
@@ -402,7 +414,8 @@ size_t shade_fwd_ws_min(int32_t N_d) { return direct_ws_bytes(64, N_d); }
 
 hipError_t launch_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const ShadeViews& v,
                             const int32_t* tri_id, const float* bary, const exm_params* p, const float* dI,
-                            const uint64_t* vis, float* dtex, double* denv, void* ws, size_t ws_bytes, hipStream_t s) {
+                            const uint64_t* vis, const float* dquery, float* dtex, double* denv, void* ws,
+                            size_t ws_bytes, hipStream_t s) {
   const int64_t n = (int64_t)v.n * v.H * v.W;
   const int64_t per_px = std::max(p->N_d, 0);
   const int64_t P = env_grad_chunk(ws_bytes, per_px, env->He, env->We, n);
@@ -418,8 +431,8 @@ hipError_t launch_shade_bwd(const exm_mesh* m, const exm_material* mat, const ex
     {
       EXM_TIMED("shade_bwd", s);
       k_shade_bwd<<<(unsigned)((Pc + kThreads - 1) / kThreads), kThreads, use_lds ? lds : 0, s>>>(
-          mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), v, tri_id, bary, kp, p0, Pc, dI, vis, dtex,
-          eg, use_lds);
+          mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), v, tri_id, bary, kp, p0, Pc, dI, vis,
+          dquery, dtex, eg, use_lds);
     }
     e = launch_env_grad_reduce(eg, env->He, env->We, denv, s);
     if (e != hipSuccess) return e;

@@ -149,35 +149,36 @@ __global__ __launch_bounds__(kThreads) void k_img_prep(const float* __restrict__
   block_add(l1, loss);
 }
 
-// horizontal then vertical pass of the Gaussian over `planes` planes of H x W (zero padding)
-__global__ __launch_bounds__(kThreads) void k_blur_h(const float* __restrict__ in, float* __restrict__ out,
-                                                     int32_t planes, int32_t H, int32_t W, Gauss g) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int64_t HW = (int64_t)H * W;
-  if (i >= HW * planes) return;
-  const int32_t x = (int32_t)(i % W);
+// horizontal then vertical pass of the Gaussian over planes of H x W (zero padding); grid
+// (x blocks, rows, planes), so no index division
+__global__ __launch_bounds__(kThreads) void k_blur_h(const float* __restrict__ in, float* __restrict__ out, int32_t H,
+                                                     int32_t W, Gauss g) {
+  const int32_t x = blockIdx.x * kThreads + threadIdx.x;
+  if (x >= W) return;
+  const int64_t row = ((int64_t)blockIdx.z * H + blockIdx.y) * W;
+  const float* r = in + row;
   float s = 0.0f;
 #pragma unroll
   for (int k = 0; k < kTaps; ++k) {
     const int32_t xx = x + k - kTaps / 2;
-    if (xx >= 0 && xx < W) s += g.g[k] * in[i + (xx - x)];
+    if (xx >= 0 && xx < W) s += g.g[k] * r[xx];
   }
-  out[i] = s;
+  out[row + x] = s;
 }
 
-__global__ __launch_bounds__(kThreads) void k_blur_v(const float* __restrict__ in, float* __restrict__ out,
-                                                     int32_t planes, int32_t H, int32_t W, Gauss g) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int64_t HW = (int64_t)H * W;
-  if (i >= HW * planes) return;
-  const int32_t y = (int32_t)((i % HW) / W);
+__global__ __launch_bounds__(kThreads) void k_blur_v(const float* __restrict__ in, float* __restrict__ out, int32_t H,
+                                                     int32_t W, Gauss g) {
+  const int32_t x = blockIdx.x * kThreads + threadIdx.x;
+  if (x >= W) return;
+  const int32_t y = blockIdx.y;
+  const float* col = in + (int64_t)blockIdx.z * H * W + x;
   float s = 0.0f;
 #pragma unroll
   for (int k = 0; k < kTaps; ++k) {
     const int32_t yy = y + k - kTaps / 2;
-    if (yy >= 0 && yy < H) s += g.g[k] * in[i + (int64_t)(yy - y) * W];
+    if (yy >= 0 && yy < H) s += g.g[k] * col[(int64_t)yy * W];
   }
-  out[i] = s;
+  out[((int64_t)blockIdx.z * H + y) * W + x] = s;
 }
 
 __global__ __launch_bounds__(kThreads) void k_ssim_terms(ImgWs w, int64_t HW, float scale, double* __restrict__ loss) {
@@ -382,14 +383,29 @@ hipError_t launch_image_loss(const float* a, const float* b, int32_t n_views, in
     const float* av = a + 3 * v * HW;
     const float* bv = b + 3 * v * HW;
     float* dv = dA + 3 * v * HW;
-    EXM_TIMED("image_loss", s);
-    k_img_prep<<<nblk(HW), kThreads, 0, s>>>(av, bv, HW, scale, w, dv, loss);
-    k_blur_h<<<nblk(15 * HW), kThreads, 0, s>>>(w.mom, w.tmp, 15, H, W, g);
-    k_blur_v<<<nblk(15 * HW), kThreads, 0, s>>>(w.tmp, w.bmom, 15, H, W, g);
-    k_ssim_terms<<<nblk(HW), kThreads, 0, s>>>(w, HW, scale, loss);
-    k_blur_h<<<nblk(9 * HW), kThreads, 0, s>>>(w.dmo, tmp9, 9, H, W, g);
-    k_blur_v<<<nblk(9 * HW), kThreads, 0, s>>>(tmp9, w.bdmo, 9, H, W, g);
-    k_img_grad<<<nblk(HW), kThreads, 0, s>>>(av, HW, scale, w, dv);
+    const dim3 g15(nblk(W), (unsigned)H, 15), g9(nblk(W), (unsigned)H, 9);
+    {
+      EXM_TIMED("image_loss_prep", s);
+      k_img_prep<<<nblk(HW), kThreads, 0, s>>>(av, bv, HW, scale, w, dv, loss);
+    }
+    {
+      EXM_TIMED("image_loss_blur", s);
+      k_blur_h<<<g15, kThreads, 0, s>>>(w.mom, w.tmp, H, W, g);
+      k_blur_v<<<g15, kThreads, 0, s>>>(w.tmp, w.bmom, H, W, g);
+    }
+    {
+      EXM_TIMED("image_loss_ssim", s);
+      k_ssim_terms<<<nblk(HW), kThreads, 0, s>>>(w, HW, scale, loss);
+    }
+    {
+      EXM_TIMED("image_loss_blur", s);
+      k_blur_h<<<g9, kThreads, 0, s>>>(w.dmo, tmp9, H, W, g);
+      k_blur_v<<<g9, kThreads, 0, s>>>(tmp9, w.bdmo, H, W, g);
+    }
+    {
+      EXM_TIMED("image_loss_grad", s);
+      k_img_grad<<<nblk(HW), kThreads, 0, s>>>(av, HW, scale, w, dv);
+    }
   }
   return hipGetLastError();
 }

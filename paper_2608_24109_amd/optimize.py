@@ -180,12 +180,13 @@ class Stage2:
         self.dtex.zero_()
         self.denv.zero_()
         L.exm_image_loss(img.contiguous(), self.targets[view:view + 1], 1.0, self.loss, self.dI, self.ws_img)
-        # material TV on the screen projection of the maps
+        # material TV on the screen projection of the maps; its gradient joins the direct pass's
+        # map adjoint (one scatter into the maps)
         L.exm_project_maps(self.mesh.s, self.mat.s, self.bufs.tri_id, self.bufs.bary, self.P)
         L.exm_tv_screen(self.P, self.bufs.tri_id, cfg.metallic, cfg.lambda_mat, self.loss, self.dP)
-        L.exm_project_maps_bwd(self.mesh.s, self.mat.s, self.bufs.tri_id, self.bufs.bary, self.dP, self.dtex)
         # adjoint of the render pass
-        render_backward(self.mesh, self.mat, self.env, cc, self.p, self.bufs, self.dI, lam, self.dtex, self.denv)
+        render_backward(self.mesh, self.mat, self.env, cc, self.p, self.bufs, self.dI, lam, self.dtex, self.denv,
+                        dquery=self.dP)
         # env regularisers
         L.exm_env_regularizers(self.env.env, cfg.lambda_env, cfg.lambda_chroma(t), self.loss, self.denv, self.acc3)
         # optimiser

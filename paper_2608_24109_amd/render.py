@@ -143,11 +143,15 @@ def trace_bwd_ws_bytes(n: int, H: int, W: int, p: PassParams, He: int, We: int) 
 
 def render_backward(mesh: DeviceMesh, mat: DeviceMaterial, env: DeviceEnv, cams_c, p: PassParams,
                     bufs: PassBuffers, dI: torch.Tensor, lambda_ind: float, dtex: torch.Tensor,
-                    denv: torch.Tensor, stream=None) -> None:
+                    denv: torch.Tensor, stream=None, dquery: torch.Tensor | None = None) -> None:
+    """Adjoints of the direct and indirect passes into dtex and denv (+=). dquery [n,H,W,8], if
+    given, is a gradient with respect to the queried map values at the visible pixels, scattered
+    with the direct pass's map adjoint."""
     pc = p.c()
     He, We = env.env.shape[:2]
     ws = bufs.workspace(shade_bwd_ws_bytes(len(cams_c), bufs.H, bufs.W, p, He, We))
-    L.exm_shade_bwd(mesh.s, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, dI, bufs.vis, dtex, denv, ws, stream)
+    L.exm_shade_bwd(mesh.s, mat.s, env.s, cams_c, bufs.tri_id, bufs.bary, pc, dI, bufs.vis, dtex, denv, ws, stream,
+                    dquery=dquery)
     if p.N_b > 0 and lambda_ind != 0.0 and bufs.half is not None:
         hb = bufs.half
         ch = half_cameras(cams_c)

@@ -144,12 +144,15 @@ def test_indirect_and_backward_validation(L):
                             float("nan"), 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x100000, big, None)
     assert s == L.EXM_E_INVAL
     s = L.lib.exm_shade_bwd(C.byref(m), C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000, C.byref(p),
-                            0x1000, 0x1000, None, 0x1000, 0x100000, big, None)
+                            0x1000, 0x1000, None, None, 0x1000, 0x100000, big, None)
     assert s == L.EXM_E_INVAL
     small = L.exm_shade_bwd_workspace_min(8, 4, 8) - 1
     s = L.lib.exm_shade_bwd(C.byref(m), C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000, C.byref(p),
-                            0x1000, 0x1000, 0x1000, 0x1000, 0x100000, small, None)
+                            0x1000, 0x1000, None, 0x1000, 0x1000, 0x100000, small, None)
     assert s == L.EXM_E_INVAL and "workspace" in L.last_error()
+    s = L.lib.exm_shade_bwd(C.byref(m), C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000, C.byref(p),
+                            0x1000, 0x1000, 0x1004, 0x1000, 0x1000, 0x100000, big, None)
+    assert s == L.EXM_E_INVAL and "dquery" in L.last_error()
     s = L.lib.exm_trace_bwd(C.byref(m), C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000, C.byref(p),
                             1.0, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x100010, big, None)
     assert s == L.EXM_E_INVAL and "workspace" in L.last_error()  # not 256-byte aligned

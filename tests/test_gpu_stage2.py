@@ -255,3 +255,34 @@ def test_stage2_resume_matches_uninterrupted_run():
     assert close.mean() > 0.999
     assert np.abs(ta - tb).max() <= 20 * a.cfg.lr_tex
     assert np.allclose(a.env.env.cpu().numpy(), b.env.env.cpu().numpy(), rtol=1e-4, atol=1e-5)
+
+
+def test_shade_bwd_with_query_gradient_equals_separate_scatter(ico):
+    """The query-value gradient given to the direct adjoint lands in the maps as the projection
+    adjoint would put it (one scatter instead of two; equal up to float summation order)."""
+    from paper_2608_24109_amd import _lib as L
+    from paper_2608_24109_amd.render import PassBuffers, PassParams, render_backward, render_forward
+    from paper_2608_24109_amd.scene import DeviceEnv, DeviceMaterial
+    sc, mesh, om = ico
+    cam = sc.cams[0]
+    mat, env = DeviceMaterial(sc.tex), DeviceEnv(sc.env)
+    p = PassParams(N_d=16, tmin=1e-4 * I.aabb_diagonal(sc.pos))
+    b = PassBuffers(1, cam.H, cam.W, 0)
+    cc = L.cameras([cam])
+    render_forward(mesh, mat, env, cc, p, b)
+    rng = np.random.default_rng(3)
+    dI = torch.from_numpy(rng.normal(size=(1, cam.H, cam.W, 3)).astype(np.float32)).cuda()
+    dq = torch.from_numpy(rng.normal(size=(1, cam.H, cam.W, 8)).astype(np.float32)).cuda()
+    outs = []
+    for fused in (True, False):
+        dtex = torch.zeros_like(mat.tex)
+        denv = torch.zeros(env.env.shape, dtype=torch.float64, device="cuda")
+        render_backward(mesh, mat, env, cc, p, b, dI, 0.0, dtex, denv, dquery=dq if fused else None)
+        if not fused:
+            L.exm_project_maps_bwd(mesh.s, mat.s, b.tri_id, b.bary, dq, dtex)
+        torch.cuda.synchronize()
+        outs.append((dtex.cpu().numpy(), denv.cpu().numpy()))
+    (t1, e1), (t2, e2) = outs
+    scale = np.abs(t2).max()
+    assert np.abs(t1 - t2).max() <= 1e-5 * scale and np.abs(t2).sum() > 0
+    assert np.allclose(e1, e2, rtol=1e-12, atol=1e-15)
