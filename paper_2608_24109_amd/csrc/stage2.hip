@@ -151,34 +151,72 @@ __global__ __launch_bounds__(kThreads) void k_img_prep(const float* __restrict__
 
 // horizontal then vertical pass of the Gaussian over planes of H x W (zero padding); grid
 // (x blocks, rows, planes), so no index division
+// The horizontal pass stages kSegH pixels of a row and their halo in LDS; each thread then
+// writes kPerThreadH consecutive outputs.
+constexpr int kPerThreadH = 4;
+constexpr int kSegH = kThreads * kPerThreadH;
+
 __global__ __launch_bounds__(kThreads) void k_blur_h(const float* __restrict__ in, float* __restrict__ out, int32_t H,
                                                      int32_t W, Gauss g) {
-  const int32_t x = blockIdx.x * kThreads + threadIdx.x;
-  if (x >= W) return;
+  __shared__ float seg[kSegH + kTaps - 1];
+  const int32_t x0 = blockIdx.x * kSegH;
   const int64_t row = ((int64_t)blockIdx.z * H + blockIdx.y) * W;
   const float* r = in + row;
-  float s = 0.0f;
-#pragma unroll
-  for (int k = 0; k < kTaps; ++k) {
-    const int32_t xx = x + k - kTaps / 2;
-    if (xx >= 0 && xx < W) s += g.g[k] * r[xx];
+  for (int32_t i = threadIdx.x; i < kSegH + kTaps - 1; i += kThreads) {
+    const int32_t xx = x0 - kTaps / 2 + i;
+    seg[i] = (xx >= 0 && xx < W) ? r[xx] : 0.0f;
   }
-  out[row + x] = s;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPerThreadH; ++q) {
+    const int32_t j = threadIdx.x * kPerThreadH + q;  // output x0 + j, taps seg[j .. j + 10]
+    if (x0 + j >= W) break;
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kTaps; ++k) s += g.g[k] * seg[j + k];
+    out[row + x0 + j] = s;
+  }
 }
+
+// The vertical pass walks a strip of kRowsV rows per block with the 11-row window in registers,
+// so each input row is read once per strip (one block per row would spread a column's rows over
+// the XCDs and fetch every row eleven times). Taps outside the image add zero, which leaves the
+// sum of the in-image taps unchanged.
+constexpr int kRowsV = 64;
 
 __global__ __launch_bounds__(kThreads) void k_blur_v(const float* __restrict__ in, float* __restrict__ out, int32_t H,
                                                      int32_t W, Gauss g) {
   const int32_t x = blockIdx.x * kThreads + threadIdx.x;
   if (x >= W) return;
-  const int32_t y = blockIdx.y;
+  const int32_t y0 = blockIdx.y * kRowsV, y1 = min(H, y0 + kRowsV);
   const float* col = in + (int64_t)blockIdx.z * H * W + x;
-  float s = 0.0f;
+  float* ocol = out + (int64_t)blockIdx.z * H * W + x;
+  float win[kTaps];
+  win[0] = 0.0f;
 #pragma unroll
-  for (int k = 0; k < kTaps; ++k) {
-    const int32_t yy = y + k - kTaps / 2;
-    if (yy >= 0 && yy < H) s += g.g[k] * col[(int64_t)yy * W];
+  for (int k = 0; k < kTaps - 1; ++k) {
+    const int32_t yy = y0 - kTaps / 2 + k;
+    win[k + 1] = (yy >= 0 && yy < H) ? col[(int64_t)yy * W] : 0.0f;
   }
-  out[((int64_t)blockIdx.z * H + y) * W + x] = s;
+  for (int32_t y = y0; y < y1; y += 4) {
+    float nxt[4];  // the next four rows in flight together
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int32_t yy = y + q + kTaps / 2;
+      nxt[q] = yy < H ? col[(int64_t)yy * W] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (y + q >= y1) break;
+#pragma unroll
+      for (int k = 0; k < kTaps - 1; ++k) win[k] = win[k + 1];
+      win[kTaps - 1] = nxt[q];
+      float s = 0.0f;
+#pragma unroll
+      for (int k = 0; k < kTaps; ++k) s += g.g[k] * win[k];
+      ocol[(int64_t)(y + q) * W] = s;
+    }
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_ssim_terms(ImgWs w, int64_t HW, float scale, double* __restrict__ loss) {
@@ -383,24 +421,33 @@ hipError_t launch_image_loss(const float* a, const float* b, int32_t n_views, in
     const float* av = a + 3 * v * HW;
     const float* bv = b + 3 * v * HW;
     float* dv = dA + 3 * v * HW;
-    const dim3 g15(nblk(W), (unsigned)H, 15), g9(nblk(W), (unsigned)H, 9);
+    const unsigned segs = (unsigned)((W + kSegH - 1) / kSegH);
+    const dim3 g15(segs, (unsigned)H, 15), g9(segs, (unsigned)H, 9);
+    const unsigned strips = (unsigned)((H + kRowsV - 1) / kRowsV);
+    const dim3 v15(nblk(W), strips, 15), v9(nblk(W), strips, 9);
     {
       EXM_TIMED("image_loss_prep", s);
       k_img_prep<<<nblk(HW), kThreads, 0, s>>>(av, bv, HW, scale, w, dv, loss);
     }
     {
-      EXM_TIMED("image_loss_blur", s);
+      EXM_TIMED("image_loss_blur_h", s);
       k_blur_h<<<g15, kThreads, 0, s>>>(w.mom, w.tmp, H, W, g);
-      k_blur_v<<<g15, kThreads, 0, s>>>(w.tmp, w.bmom, H, W, g);
+    }
+    {
+      EXM_TIMED("image_loss_blur_v", s);
+      k_blur_v<<<v15, kThreads, 0, s>>>(w.tmp, w.bmom, H, W, g);
     }
     {
       EXM_TIMED("image_loss_ssim", s);
       k_ssim_terms<<<nblk(HW), kThreads, 0, s>>>(w, HW, scale, loss);
     }
     {
-      EXM_TIMED("image_loss_blur", s);
+      EXM_TIMED("image_loss_blur_h", s);
       k_blur_h<<<g9, kThreads, 0, s>>>(w.dmo, tmp9, H, W, g);
-      k_blur_v<<<g9, kThreads, 0, s>>>(tmp9, w.bdmo, H, W, g);
+    }
+    {
+      EXM_TIMED("image_loss_blur_v", s);
+      k_blur_v<<<v9, kThreads, 0, s>>>(tmp9, w.bdmo, H, W, g);
     }
     {
       EXM_TIMED("image_loss_grad", s);

@@ -12,7 +12,6 @@ later change of the kernels invalidates it.
 from __future__ import annotations
 
 import csv
-import glob
 import hashlib
 import json
 import os
@@ -41,12 +40,19 @@ KERNELS = {
 COPY_KERNEL = "copyBuffer"
 
 
+# the sources the render-pass kernels (and the BVH they traverse) are built from; a change to
+# any of them invalidates a counter summary
+RENDER_PASS_SOURCES = ("mesh.hip", "env_sampler.hip", "raster.hip", "shade.hip", "trace.hip", "rays.hip",
+                       "env_grad.hip", "env_grad.h", "exm_device.h", "exm_rays.h", "exm_internal.h",
+                       "bvh_build.cpp")
+
+
 def source_digest() -> str:
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
-        if p.endswith((".hip", ".h", ".cpp")):
-            h.update(os.path.basename(p).encode())
-            h.update(open(p, "rb").read())
+    for name in RENDER_PASS_SOURCES:
+        p = os.path.join(HERE, "csrc", name)
+        h.update(name.encode())
+        h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
 
 
