@@ -596,13 +596,14 @@ __device__ __forceinline__ int32_t trav_pop(TravState& s, const int32_t* stack, 
 }
 
 // One round of the speculative while-while traversal (Aila and Laine 2009): internal nodes are
-// visited until every lane of the wave that is still descending holds a postponed leaf, then
-// the postponed leaves are intersected together, so node and leaf work each run with most
-// lanes of the wave active. Returns true when the query is finished: nothing left to visit, or
+// visited until fewer than leaf_gate lanes of the wave lack a postponed leaf, then the postponed
+// leaves are intersected together, so node and leaf work each run with most lanes of the wave
+// active. Returns true when the query is finished: nothing left to visit, or
 // ANY and a hit was found.
 template <bool ANY, bool COUNT>
 __device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float tmin, int32_t skip, int32_t* stack,
-                                           int stride, TravState& s, HitRec& h, TraceCount* counts) {
+                                           int stride, TravState& s, HitRec& h, TraceCount* counts,
+                                           int32_t leaf_gate = 1) {
   while (s.ref >= 0) {
     if (++s.steps > kMaxSteps) return true;
     if (COUNT) counts->nodes++;
@@ -629,7 +630,7 @@ __device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float
       s.leaf = s.ref;
       s.ref = trav_pop(s, stack, stride);
     }
-    if (__ballot(s.leaf == kEmptyRef) == 0ull) break;
+    if (__popcll(__ballot(s.leaf == kEmptyRef)) < leaf_gate) break;
   }
   if (s.leaf == kEmptyRef && is_leaf(s.ref)) {  // a round that starts on a leaf (root leaf)
     s.leaf = s.ref;

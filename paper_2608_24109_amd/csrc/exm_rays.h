@@ -27,6 +27,7 @@ struct RayBatch {
 };
 
 int32_t ray_refill_threshold();
+int32_t trav_leaf_gate();
 // any-hit: out[slot] = 1 if something is hit at t >= tmin (the skipped triangle excepted)
 hipError_t launch_trace_any(const exm_bvh* bvh, const RayBatch& rb, uint8_t* out, unsigned long long* counters,
                             hipStream_t s);
