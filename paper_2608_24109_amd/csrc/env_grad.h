@@ -3,9 +3,12 @@
 // The adjoint of an env sample is three FP32 weights for one texel (dLoss/dE of the sample).
 // Adjoint kernels append one 16-byte record per sample into a workspace (one atomic per wave
 // reserves the wave's range); then a counting sort groups the records by buckets of
-// kBucketTexels texels, and one block per bucket sums its records in LDS (FP64) and adds the
-// sums to denv with plain read-modify-writes (no block shares a texel). The sums equal the
-// per-sample atomics' up to the order of FP64 additions.
+// kBucketTexels texels, and one block per chunk of at most kReduceChunk records of a bucket sums
+// them in LDS (FP64) and adds the sums to denv: with plain read-modify-writes when the chunk is
+// its bucket's only one (no other block touches those texels), with FP64 atomics otherwise
+// (importance sampling puts many records in the buckets of bright texels, which one block per
+// bucket would serialise). The sums equal the per-sample atomics' up to the order of FP64
+// additions.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -17,6 +20,7 @@ namespace exm {
 constexpr int32_t kBucketShift = 11;
 constexpr int32_t kBucketTexels = 1 << kBucketShift;  // 2048 texels x 3 x 8 B = 48 KB of LDS
 constexpr uint32_t kNoTexel = 0xFFFFFFFFu;            // record slot reserved but unused
+constexpr int64_t kReduceChunk = 32768;               // records summed by one block
 
 struct alignas(16) EnvRec {
   uint32_t texel;
@@ -29,6 +33,7 @@ struct EnvGradWs {
   uint32_t* bucket_count;  // [B]
   uint32_t* bucket_off;    // [B + 1]
   uint32_t* bucket_cur;    // [B]
+  uint32_t* chunk_off;     // [B + 1] first reduction chunk of each bucket
   EnvRec* rec;             // [cap] as appended
   EnvRec* sorted;          // [cap] grouped by bucket
   int64_t cap;
@@ -43,7 +48,7 @@ inline size_t eg_align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 inline size_t env_grad_ws_bytes(int64_t cap, int32_t He, int32_t We) {
   const size_t B = (size_t)env_grad_buckets(He, We);
-  return 256 + 3 * eg_align256((B + 1) * 4) + 2 * eg_align256((size_t)cap * sizeof(EnvRec));
+  return 256 + 4 * eg_align256((B + 1) * 4) + 2 * eg_align256((size_t)cap * sizeof(EnvRec));
 }
 
 inline EnvGradWs env_grad_ws(void* ws, int64_t cap, int32_t He, int32_t We) {
@@ -57,6 +62,8 @@ inline EnvGradWs env_grad_ws(void* ws, int64_t cap, int32_t He, int32_t We) {
   w.bucket_off = reinterpret_cast<uint32_t*>(q);
   q += eg_align256(((size_t)B + 1) * 4);
   w.bucket_cur = reinterpret_cast<uint32_t*>(q);
+  q += eg_align256(((size_t)B + 1) * 4);
+  w.chunk_off = reinterpret_cast<uint32_t*>(q);
   q += eg_align256(((size_t)B + 1) * 4);
   w.rec = reinterpret_cast<EnvRec*>(q);
   q += eg_align256((size_t)cap * sizeof(EnvRec));
