@@ -552,6 +552,12 @@ def main():
                              for k in kern if not math.isnan(algorithmic_bytes(k, stats, p))},
     }
     if a.extras:
+        log("small (latency)")
+        _, _, wall0, kern0, st0, _ = run_gpu("small", 20, 3)
+        out["small_latency"] = {
+            "workload": "small: icosphere 1280 tris, 1 view 128x128, 256^2 maps, 32x64 env, N_d=16, fwd+bwd",
+            "ms_per_step": round(wall0 / 20 * 1e3, 4),
+            "kernels_ms": {k: round(v, 4) for k, v in kern0.items()}}
         log("tori (indirect)")
         sc2, p2, wall2, kern2, st2, _ = run_gpu("tori", max(2, a.steps // 3), 1)
         rays = st2["sec_rays"] + st2["sec_shadow_rays"]
