@@ -513,8 +513,9 @@ exm_status exm_image_loss(const float* a, const float* b, int32_t n, int32_t H, 
 exm_status exm_tv_screen(const float* P, const int32_t* tri_id, int32_t n, int32_t H, int32_t W, int32_t metallic,
                          float scale, double* loss, float* dP, hipStream_t stream) {
   EXM_TRY(check_view_dims(n, H, W));
+  if (n > 65535) return fail(EXM_E_INVAL, "at most 65535 views per call");
   if (!P || !tri_id || !loss || !dP) return fail(EXM_E_INVAL, "pointer is NULL");
-  if (!aligned(dP, 16)) return fail(EXM_E_INVAL, "dP must be 16-byte aligned");
+  if (!aligned(dP, 16) || !aligned(P, 16)) return fail(EXM_E_INVAL, "P and dP must be 16-byte aligned");
   if (!std::isfinite(scale)) return fail(EXM_E_INVAL, "scale must be finite");
   EXM_TRY(check_device());
   hipError_t e = launch_tv_screen(P, tri_id, n, H, W, metallic, scale, loss, dP, stream);

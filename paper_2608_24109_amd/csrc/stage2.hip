@@ -31,6 +31,13 @@ struct Gauss {
   float g[kTaps];
 };
 
+constexpr int32_t kTvRows = 4;
+
+// Kernels that also sum into an FP64 scalar run as grid-stride loops over at most this many
+// blocks, so that the scalar takes one atomic per block and not one per 256 pixels (ten
+// thousand same-address atomics per 1600^2 view serialise).
+constexpr unsigned kReduceBlocks = 1024;
+
 __device__ __forceinline__ void block_add(double v, double* out) {
   __shared__ double red[kThreads];
   red[threadIdx.x] = v;
@@ -127,9 +134,8 @@ struct ImgWs {
 __global__ __launch_bounds__(kThreads) void k_img_prep(const float* __restrict__ a, const float* __restrict__ b,
                                                        int64_t HW, float scale, ImgWs w, float* __restrict__ dA,
                                                        double* __restrict__ loss) {
-  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   double l1 = 0.0;
-  if (p < HW) {
+  for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < HW; p += (int64_t)gridDim.x * kThreads) {
     const float inv_n = 1.0f / (3.0f * (float)HW);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -144,8 +150,8 @@ __global__ __launch_bounds__(kThreads) void k_img_prep(const float* __restrict__
       w.mom[(3 * 3 + c) * HW + p] = y * y;
       w.mom[(4 * 3 + c) * HW + p] = x * y;
     }
-    l1 *= (double)scale * kLambdaLog / (3.0 * (double)HW);
   }
+  l1 *= (double)scale * kLambdaLog / (3.0 * (double)HW);
   block_add(l1, loss);
 }
 
@@ -220,9 +226,8 @@ __global__ __launch_bounds__(kThreads) void k_blur_v(const float* __restrict__ i
 }
 
 __global__ __launch_bounds__(kThreads) void k_ssim_terms(ImgWs w, int64_t HW, float scale, double* __restrict__ loss) {
-  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   double ssum = 0.0;
-  if (p < HW) {
+  for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < HW; p += (int64_t)gridDim.x * kThreads) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const float mx = w.bmom[(0 * 3 + c) * HW + p], my = w.bmom[(1 * 3 + c) * HW + p];
@@ -261,36 +266,41 @@ __global__ __launch_bounds__(kThreads) void k_img_grad(const float* __restrict__
 
 // ---- total variation --------------------------------------------------------------------
 
-struct Groups {
-  int32_t n;
-  int32_t a[4], b[4];
+// per-channel weight of the material TV: scale / (group size * H * W) for the channels of the
+// active groups (A, R, N, and M when the metallic map is optimised), 0 elsewhere
+struct TvWeights {
+  float w[8];
 };
 
+// grid (column blocks, bands of kTvRows rows, views): one thread per pixel and row of the band,
+// no index division, one atomic per block for the loss
 __global__ __launch_bounds__(kThreads) void k_tv_screen(const float* __restrict__ P, const int32_t* __restrict__ tri,
-                                                        int32_t n_views, int32_t H, int32_t W, Groups G, float scale,
+                                                        int32_t H, int32_t W, TvWeights cw,
                                                         double* __restrict__ loss, float* __restrict__ dP) {
-  const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t HW = (int64_t)H * W;
   double l = 0.0;
-  if (gid < HW * n_views) {
-    const int32_t v = (int32_t)(gid / HW);
-    const int32_t y = (int32_t)((gid - v * HW) / W), x = (int32_t)(gid - v * HW - (int64_t)y * W);
+  const int32_t x = blockIdx.x * kThreads + threadIdx.x;
+  const int32_t y_end = min(H, (int32_t)(blockIdx.y + 1) * kTvRows);
+  for (int32_t y = blockIdx.y * kTvRows; y < y_end && x < W; ++y) {
+    const int64_t gid = (int64_t)blockIdx.z * HW + (int64_t)y * W + x;
     float g[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (tri[gid] >= 0) {
-      const float* pp = P + 8 * gid;
+      const float4 p0 = reinterpret_cast<const float4*>(P)[2 * gid];
+      const float4 p1 = reinterpret_cast<const float4*>(P)[2 * gid + 1];
+      const float pp[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
       const int64_t nb[4] = {x + 1 < W ? gid + 1 : -1, x > 0 ? gid - 1 : -1, y + 1 < H ? gid + W : -1,
                              y > 0 ? gid - W : -1};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (nb[q] < 0 || tri[nb[q]] < 0) continue;
-        const float* pq = P + 8 * nb[q];
-        for (int k = 0; k < G.n; ++k) {
-          const float wk = scale / ((float)(G.b[k] - G.a[k]) * (float)HW);
-          for (int c = G.a[k]; c < G.b[k]; ++c) {
-            const float d = pp[c] - pq[c];
-            g[c] += wk * sgn(d);
-            if (q == 0 || q == 2) l += (double)wk * fabsf(d);  // each pair once (right, down)
-          }
+        const float4 q0 = reinterpret_cast<const float4*>(P)[2 * nb[q]];
+        const float4 q1 = reinterpret_cast<const float4*>(P)[2 * nb[q] + 1];
+        const float pq[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const float d = pp[c] - pq[c];
+          g[c] += cw.w[c] * sgn(d);
+          if (q == 0 || q == 2) l += (double)cw.w[c] * fabsf(d);  // each pair once (right, down)
         }
       }
     }
@@ -427,7 +437,7 @@ hipError_t launch_image_loss(const float* a, const float* b, int32_t n_views, in
     const dim3 v15(nblk(W), strips, 15), v9(nblk(W), strips, 9);
     {
       EXM_TIMED("image_loss_prep", s);
-      k_img_prep<<<nblk(HW), kThreads, 0, s>>>(av, bv, HW, scale, w, dv, loss);
+      k_img_prep<<<std::min(nblk(HW), kReduceBlocks), kThreads, 0, s>>>(av, bv, HW, scale, w, dv, loss);
     }
     {
       EXM_TIMED("image_loss_blur_h", s);
@@ -439,7 +449,7 @@ hipError_t launch_image_loss(const float* a, const float* b, int32_t n_views, in
     }
     {
       EXM_TIMED("image_loss_ssim", s);
-      k_ssim_terms<<<nblk(HW), kThreads, 0, s>>>(w, HW, scale, loss);
+      k_ssim_terms<<<std::min(nblk(HW), kReduceBlocks), kThreads, 0, s>>>(w, HW, scale, loss);
     }
     {
       EXM_TIMED("image_loss_blur_h", s);
@@ -459,15 +469,14 @@ hipError_t launch_image_loss(const float* a, const float* b, int32_t n_views, in
 
 hipError_t launch_tv_screen(const float* P, const int32_t* tri, int32_t n_views, int32_t H, int32_t W, int32_t metallic,
                             float scale, double* loss, float* dP, hipStream_t s) {
-  Groups G;
-  G.n = metallic ? 4 : 3;
+  TvWeights cw;
   const int32_t a[4] = {0, 3, 5, 4}, b[4] = {3, 4, 8, 5};  // A, R, N, M
-  for (int k = 0; k < 4; ++k) {
-    G.a[k] = a[k];
-    G.b[k] = b[k];
-  }
+  for (int c = 0; c < 8; ++c) cw.w[c] = 0.0f;
+  for (int k = 0; k < (metallic ? 4 : 3); ++k)
+    for (int c = a[k]; c < b[k]; ++c) cw.w[c] = scale / ((float)(b[k] - a[k]) * (float)((int64_t)H * W));
   EXM_TIMED("tv_screen", s);
-  k_tv_screen<<<nblk((int64_t)n_views * H * W), kThreads, 0, s>>>(P, tri, n_views, H, W, G, scale, loss, dP);
+  const dim3 grid(nblk(W), (unsigned)((H + kTvRows - 1) / kTvRows), (unsigned)n_views);
+  k_tv_screen<<<grid, kThreads, 0, s>>>(P, tri, H, W, cw, loss, dP);
   return hipGetLastError();
 }
 
