@@ -1,4 +1,4 @@
-// Binned reduction of env-gradient records (counting sort by bucket, LDS sums per bucket).
+// Binned reduction of env-gradient records (counting sort by bucket, LDS sums per chunk of a bucket).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

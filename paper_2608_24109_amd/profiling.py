@@ -15,6 +15,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 from collections import defaultdict
 
@@ -47,12 +48,19 @@ RENDER_PASS_SOURCES = ("mesh.hip", "env_sampler.hip", "raster.hip", "shade.hip",
                        "bvh_build.cpp")
 
 
+def _code_only(text: str) -> str:
+    """The source without comments and blank lines (a comment edit does not change a kernel)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
+    return "\n".join(ln for ln in lines if ln)
+
+
 def source_digest() -> str:
     h = hashlib.sha256()
     for name in RENDER_PASS_SOURCES:
         p = os.path.join(HERE, "csrc", name)
         h.update(name.encode())
-        h.update(open(p, "rb").read())
+        h.update(_code_only(open(p).read()).encode())
     return h.hexdigest()[:16]
 
 
