@@ -286,3 +286,22 @@ def test_shade_bwd_with_query_gradient_equals_separate_scatter(ico):
     scale = np.abs(t2).max()
     assert np.abs(t1 - t2).max() <= 1e-5 * scale and np.abs(t2).sum() > 0
     assert np.allclose(e1, e2, rtol=1e-12, atol=1e-15)
+
+
+def test_stage2_with_metallic_map():
+    """With the metallic map optimised (no METALLIC_OFF, the M group in the material TV) the loop
+    moves the metallic channel, keeps every map in its range and the objective finite."""
+    from paper_2608_24109_amd.optimize import TEX_HI, TEX_LO, Stage2, Stage2Config
+    base = _small_problem()
+    cfg = Stage2Config(iters=30, ramp_iters=10, N_d=4, N_b=4, N_s=2, half_res_indirect=True, tmin=base.cfg.tmin,
+                       metallic=True)
+    from paper_2608_24109_amd.scene import DeviceEnv, DeviceMaterial
+    tex0 = base.mat.tex.cpu().numpy()
+    tex0[..., 4] = 0.3
+    opt = Stage2(base.mesh, DeviceMaterial(tex0), DeviceEnv(base.env.env.cpu().numpy()), base.cams, base.targets, cfg)
+    curve = opt.run(30)
+    tex = opt.mat.tex.cpu().numpy()
+    assert np.all(np.isfinite(curve))
+    assert np.abs(tex[..., 4] - 0.3).max() > 1e-3
+    for c in range(5):
+        assert tex[..., c].min() >= TEX_LO[c] and tex[..., c].max() <= TEX_HI[c]

@@ -191,3 +191,11 @@ def test_paper_size_round():
     c[rng.choice(sc.tri.shape[0], 2000, replace=False)] = 0
     st = _run_case(pos, sc.tri, sc.uv, sc.tri_uv, G, c, TopoConfig())
     assert st["splits"] > 1000 and st["merges"] > 100
+
+
+def test_round_with_both_operations_off_keeps_the_mesh():
+    from paper_2608_24109_amd.topology import TopoConfig
+    pos, tri, uv, tuv, rng = _jitter_sphere(3, 8)
+    st = _run_case(pos, tri, uv, tuv, rng.random(pos.shape[0]).astype(np.float32), None,
+                   TopoConfig(split=False, merge=False))
+    assert st["splits"] == 0 and st["merges"] == 0
