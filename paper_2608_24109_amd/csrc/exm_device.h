@@ -545,15 +545,20 @@ __device__ __forceinline__ bool tri_hit(const Ray& r, const BvhTri& T, float tmi
   return true;
 }
 
-// slab test of one child box; returns entry distance or +inf
-__device__ __forceinline__ float box_enter(const float* lo, const float* hi, const Ray& r, float tmax) {
+// Slab test of one child box: true if the ray's interval [0, tmax] meets it, with the entry
+// distance in *tn. Any-hit queries pass CLAMP = false: their tmax stays +inf for the whole query,
+// and min(x, +inf) = x for every x (a NaN operand included, under the IEEE minimum the clamp
+// would use), so dropping the clamp gives the same answer.
+template <bool CLAMP>
+__device__ __forceinline__ bool box_hit(const float* lo, const float* hi, const Ray& r, float tmax, float* tn) {
   const float tx0 = (lo[0] - r.o.x) * r.inv.x, tx1 = (hi[0] - r.o.x) * r.inv.x;
   const float ty0 = (lo[1] - r.o.y) * r.inv.y, ty1 = (hi[1] - r.o.y) * r.inv.y;
   const float tz0 = (lo[2] - r.o.z) * r.inv.z, tz1 = (hi[2] - r.o.z) * r.inv.z;
-  const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
-  const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax));
+  *tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+  const float fz = CLAMP ? fminf(fmaxf(tz0, tz1), tmax) : fmaxf(tz0, tz1);
+  const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fz);
   // conservative by a few ulps so rays grazing a box face are not lost
-  return tn <= tf * 1.00000024f ? tn : __builtin_huge_valf();
+  return *tn <= tf * 1.00000024f;
 }
 
 struct HitRec {
@@ -567,17 +572,21 @@ struct TraceCount {
 };
 
 // Resumable traversal state: the node to visit next, one postponed leaf, the depth of the
-// lane's stack of deferred node references (kept in LDS at stack[slot * stride]).
+// lane's stack of deferred node references (kept in LDS at stack[slot * stride]), and the
+// number of rounds the query has taken.
 struct TravState {
   int32_t ref;
   int32_t leaf;
   int32_t sp;
-  uint32_t steps;
+  uint32_t rounds;
 };
 
 constexpr int32_t kEmptyRef = (int32_t)0x80000000;
-constexpr uint32_t kMaxSteps = 1u << 22;  // the builder bounds the work far below this; the cap
-                                          // only keeps a corrupted structure from trapping a wave
+// Work caps: node visits of one round (counted per wave: the lanes still in a round's node loop
+// have all made the same number of passes) and rounds of one query. The builder bounds the work
+// far below both; they only keep a corrupted structure from trapping a wave.
+constexpr uint32_t kMaxSteps = 1u << 22;
+constexpr uint32_t kMaxRounds = 1u << 22;
 
 __device__ __forceinline__ bool is_leaf(int32_t ref) { return ref < 0 && ref != kEmptyRef; }
 
@@ -585,7 +594,7 @@ __device__ __forceinline__ void trav_begin(const BvhView& B, TravState& s, HitRe
   s.ref = B.root_is_leaf ? B.nodes[0].c0 : 0;
   s.leaf = kEmptyRef;
   s.sp = 0;
-  s.steps = 0;
+  s.rounds = 0;
   h.id = -1;
   h.t = __builtin_huge_valf();
   h.b1 = h.b2 = 0.0f;
@@ -604,8 +613,11 @@ template <bool ANY, bool COUNT>
 __device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float tmin, int32_t skip, int32_t* stack,
                                            int stride, TravState& s, HitRec& h, TraceCount* counts,
                                            int32_t leaf_gate = 1) {
+  if (++s.rounds > kMaxRounds) return true;
+  uint32_t steps = 0;
   while (s.ref >= 0) {
-    if (++s.steps > kMaxSteps) return true;
+    steps = __builtin_amdgcn_readfirstlane(steps) + 1u;  // wave-uniform: kept in a scalar register
+    if (steps > kMaxSteps) return true;
     if (COUNT) counts->nodes++;
     const BvhNode& N = B.nodes[s.ref];
     const float4 a = reinterpret_cast<const float4*>(&N)[0];
@@ -614,9 +626,9 @@ __device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float
     const int4 e = reinterpret_cast<const int4*>(&N)[3];
     const float lo0[3] = {a.x, a.y, a.z}, hi0[3] = {a.w, b.x, b.y};
     const float lo1[3] = {b.z, b.w, c.x}, hi1[3] = {c.y, c.z, c.w};
-    const float t0 = box_enter(lo0, hi0, r, h.t);
-    const float t1 = box_enter(lo1, hi1, r, h.t);
-    const bool h0 = t0 != __builtin_huge_valf(), h1 = t1 != __builtin_huge_valf();
+    float t0, t1;
+    const bool h0 = box_hit<!ANY>(lo0, hi0, r, h.t, &t0);
+    const bool h1 = box_hit<!ANY>(lo1, hi1, r, h.t, &t1);
     if (h0 && h1) {
       const bool first0 = t0 <= t1;
       s.ref = first0 ? e.x : e.y;
@@ -640,11 +652,19 @@ __device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float
     const uint32_t v = ~(uint32_t)s.leaf;
     const int32_t first = (int32_t)(v >> 4), cnt = (int32_t)(v & 15u);
     for (int32_t i = first; i < first + cnt; ++i) {
-      const BvhTri T = B.tris[i];
+      // the whole 48-byte record in three 16-byte loads; the triangle the ray leaves from is
+      // tested like the others and its hit ignored, so that no branch on the id has to wait
+      // for a load of its own before the vertices are fetched
+      const float4* q = reinterpret_cast<const float4*>(B.tris + i);
+      const float4 q0 = q[0], q1 = q[1], q2 = q[2];
+      BvhTri T;
+      T.v0[0] = q0.x; T.v0[1] = q0.y; T.v0[2] = q0.z;
+      T.v1[0] = q0.w; T.v1[1] = q1.x; T.v1[2] = q1.y;
+      T.v2[0] = q1.z; T.v2[1] = q1.w; T.v2[2] = q2.x;
+      T.id = __float_as_int(q2.y);
       if (COUNT) counts->tris++;
-      if (T.id == skip) continue;
       float t, b1, b2;
-      if (tri_hit(r, T, tmin, h.t, &t, &b1, &b2)) {
+      if (tri_hit(r, T, tmin, h.t, &t, &b1, &b2) && T.id != skip) {
         if (ANY) {
           h.id = T.id;
           return true;
