@@ -485,9 +485,23 @@ struct BvhView {
 // ray precomputation for the watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013)
 struct Ray {
   f3 o, d, inv;
+  f3 off_lo, off_hi;  // slab offsets: o * inv moved outwards per axis (see make_ray)
   int kx, ky, kz;
   float Sx, Sy, Sz;
 };
+
+// Slab offsets for the one-FMA slab distance fma(plane, inv, -off): off approximates o * inv,
+// moved by 2^-21 |o * inv| (at least three ulps after rounding) so that the entry distance of
+// each axis comes out no larger and the exit distance no smaller than (plane - o) * inv would
+// give: the box test stays conservative, and the padding is a few ulps of the coordinates
+// along that axis alone.
+__device__ __forceinline__ void slab_offsets(float o, float inv, float* off_lo, float* off_hi) {
+  const float oi = o * inv;
+  const float e = fabsf(oi) * 0x1p-21f;
+  // the lo plane is the entry when inv >= 0, the hi plane otherwise
+  *off_lo = inv >= 0.0f ? oi + e : oi - e;
+  *off_hi = inv >= 0.0f ? oi - e : oi + e;
+}
 
 __device__ __forceinline__ float comp(f3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
 
@@ -497,7 +511,14 @@ __device__ __forceinline__ Ray make_ray(f3 o, f3 d) {
   r.d = d;
   // hardware reciprocals (1 ulp): the slab test pads its interval by a few ulps, and the shear
   // below only needs to be the same for every triangle a ray meets
-  r.inv = mk(__builtin_amdgcn_rcpf(d.x), __builtin_amdgcn_rcpf(d.y), __builtin_amdgcn_rcpf(d.z));
+  // a zero component gives +-2^64 instead of an infinite reciprocal, so that the slab distances
+  // below stay finite (inf - inf would read as NaN and could drop a slab the ray lies in)
+  r.inv = mk(copysignf(fminf(fabsf(__builtin_amdgcn_rcpf(d.x)), 0x1p64f), d.x),
+             copysignf(fminf(fabsf(__builtin_amdgcn_rcpf(d.y)), 0x1p64f), d.y),
+             copysignf(fminf(fabsf(__builtin_amdgcn_rcpf(d.z)), 0x1p64f), d.z));
+  slab_offsets(o.x, r.inv.x, &r.off_lo.x, &r.off_hi.x);
+  slab_offsets(o.y, r.inv.y, &r.off_lo.y, &r.off_hi.y);
+  slab_offsets(o.z, r.inv.z, &r.off_lo.z, &r.off_hi.z);
   const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
   r.kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
   r.kx = r.kz == 2 ? 0 : r.kz + 1;
@@ -551,9 +572,9 @@ __device__ __forceinline__ bool tri_hit(const Ray& r, const BvhTri& T, float tmi
 // would use), so dropping the clamp gives the same answer.
 template <bool CLAMP>
 __device__ __forceinline__ bool box_hit(const float* lo, const float* hi, const Ray& r, float tmax, float* tn) {
-  const float tx0 = (lo[0] - r.o.x) * r.inv.x, tx1 = (hi[0] - r.o.x) * r.inv.x;
-  const float ty0 = (lo[1] - r.o.y) * r.inv.y, ty1 = (hi[1] - r.o.y) * r.inv.y;
-  const float tz0 = (lo[2] - r.o.z) * r.inv.z, tz1 = (hi[2] - r.o.z) * r.inv.z;
+  const float tx0 = fmaf(lo[0], r.inv.x, -r.off_lo.x), tx1 = fmaf(hi[0], r.inv.x, -r.off_hi.x);
+  const float ty0 = fmaf(lo[1], r.inv.y, -r.off_lo.y), ty1 = fmaf(hi[1], r.inv.y, -r.off_hi.y);
+  const float tz0 = fmaf(lo[2], r.inv.z, -r.off_lo.z), tz1 = fmaf(hi[2], r.inv.z, -r.off_hi.z);
   *tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
   const float fz = CLAMP ? fminf(fmaxf(tz0, tz1), tmax) : fmaxf(tz0, tz1);
   const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fz);
