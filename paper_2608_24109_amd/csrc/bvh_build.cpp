@@ -7,7 +7,8 @@
 // d + need(N) <= kMaxDepth. A node at the bound is split at the object median of its longest
 // centroid axis (each child gets at most ceil(N/2) triangles, so need drops by one); leaves
 // therefore sit at depth <= kMaxDepth and a traversal stack of kStack entries never overflows
-// (kStack = kMaxDepth = 24: 24 KB of LDS per 256-lane block, which keeps six blocks per CU).
+// (kMaxDepth = 24 deferred references plus the stack's bottom sentinel, kStack = 25: 25 KB of LDS
+// per 256-lane block, which keeps six blocks per CU).
 // Subtrees above a size threshold are built on separate threads; node slots come from an
 // atomic counter and each thread partitions its own index range, so the result is
 // deterministic up to node numbering, which does not change any ray query's answer.

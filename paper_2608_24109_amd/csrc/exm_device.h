@@ -611,10 +611,13 @@ constexpr uint32_t kMaxRounds = 1u << 22;
 
 __device__ __forceinline__ bool is_leaf(int32_t ref) { return ref < 0 && ref != kEmptyRef; }
 
-__device__ __forceinline__ void trav_begin(const BvhView& B, TravState& s, HitRec& h) {
+// The lane's stack starts with kEmptyRef as a sentinel in its bottom slot: popping it ends the
+// query, so a pop never needs to test for an empty stack (a query pops nothing after it).
+__device__ __forceinline__ void trav_begin(const BvhView& B, TravState& s, HitRec& h, int32_t* stack) {
   s.ref = B.root_is_leaf ? B.nodes[0].c0 : 0;
   s.leaf = kEmptyRef;
-  s.sp = 0;
+  stack[0] = kEmptyRef;
+  s.sp = 1;
   s.rounds = 0;
   h.id = -1;
   h.t = __builtin_huge_valf();
@@ -622,7 +625,7 @@ __device__ __forceinline__ void trav_begin(const BvhView& B, TravState& s, HitRe
 }
 
 __device__ __forceinline__ int32_t trav_pop(TravState& s, const int32_t* stack, int stride) {
-  return s.sp > 0 ? stack[(--s.sp) * stride] : kEmptyRef;
+  return stack[(--s.sp) * stride];
 }
 
 // One round of the speculative while-while traversal (Aila and Laine 2009): internal nodes are
@@ -640,7 +643,7 @@ __device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float
     steps = __builtin_amdgcn_readfirstlane(steps) + 1u;  // wave-uniform: kept in a scalar register
     if (steps > kMaxSteps) return true;
     if (COUNT) counts->nodes++;
-    const BvhNode& N = B.nodes[s.ref];
+    const BvhNode& N = B.nodes[(uint32_t)s.ref];
     const float4 a = reinterpret_cast<const float4*>(&N)[0];
     const float4 b = reinterpret_cast<const float4*>(&N)[1];
     const float4 c = reinterpret_cast<const float4*>(&N)[2];
@@ -713,7 +716,7 @@ __device__ __forceinline__ HitRec trace(const BvhView& B, const Ray& r, float tm
                                         int stride, TraceCount* counts = nullptr) {
   TravState s;
   HitRec h;
-  trav_begin(B, s, h);
+  trav_begin(B, s, h, stack);
   while (!trav_round<ANY, COUNT>(B, r, tmin, skip, stack, stride, s, h, counts)) {
   }
   return h;

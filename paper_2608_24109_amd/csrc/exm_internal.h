@@ -29,7 +29,7 @@ struct alignas(16) BvhTri {
 static_assert(sizeof(BvhTri) == 48, "triangle layout");
 
 constexpr int kMaxDepth = 24;  // builder guarantee; traversal stack holds <= kMaxDepth refs
-constexpr int kStack = 24;
+constexpr int kStack = 25;  // 24 deferred references (the depth bound) + the bottom sentinel
 
 // Views per launch: camera data travels in kernel arguments.
 constexpr int kViewsPerLaunch = 8;

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kThreads) void k_trace(BvhView B, RayBatch rb, int3
         ray = make_ray(mk(R.o[0], R.o[1], R.o[2]), mk(R.d[0], R.d[1], R.d[2]));
         tmin = R.tmin;
         skip = R.skip;
-        trav_begin(B, ts, h);
+        trav_begin(B, ts, h, stack);
         have_ray = true;
         if (COUNT) ++n_rays;
       }
