@@ -21,6 +21,8 @@ constexpr int32_t kBucketShift = 11;
 constexpr int32_t kBucketTexels = 1 << kBucketShift;  // 2048 texels x 3 x 8 B = 48 KB of LDS
 constexpr uint32_t kNoTexel = 0xFFFFFFFFu;            // record slot reserved but unused
 constexpr int64_t kReduceChunk = 32768;               // records summed by one block
+constexpr int32_t kTileMaxBuckets = 1024;             // buckets of the tiled scatter (LDS cursors)
+constexpr int32_t kMaxScatterBlocks = 1024;           // blocks of the tiled histogram and scatter
 
 struct alignas(16) EnvRec {
   uint32_t texel;
@@ -34,6 +36,7 @@ struct EnvGradWs {
   uint32_t* bucket_off;    // [B + 1]
   uint32_t* bucket_cur;    // [B]
   uint32_t* chunk_off;     // [B + 1] first reduction chunk of each bucket
+  uint32_t* blk_off;       // [kMaxScatterBlocks, B] per-block counts, then first slots (B <= kTileMaxBuckets)
   EnvRec* rec;             // [cap] as appended
   EnvRec* sorted;          // [cap] grouped by bucket
   int64_t cap;
@@ -46,9 +49,14 @@ inline int32_t env_grad_buckets(int32_t He, int32_t We) {
 
 inline size_t eg_align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+inline size_t env_grad_blk_bytes(int32_t B) {
+  return B <= kTileMaxBuckets ? eg_align256((size_t)kMaxScatterBlocks * (size_t)B * 4) : 0;
+}
+
 inline size_t env_grad_ws_bytes(int64_t cap, int32_t He, int32_t We) {
-  const size_t B = (size_t)env_grad_buckets(He, We);
-  return 256 + 4 * eg_align256((B + 1) * 4) + 2 * eg_align256((size_t)cap * sizeof(EnvRec));
+  const int32_t B = env_grad_buckets(He, We);
+  return 256 + 4 * eg_align256(((size_t)B + 1) * 4) + env_grad_blk_bytes(B) +
+         2 * eg_align256((size_t)cap * sizeof(EnvRec));
 }
 
 inline EnvGradWs env_grad_ws(void* ws, int64_t cap, int32_t He, int32_t We) {
@@ -65,6 +73,8 @@ inline EnvGradWs env_grad_ws(void* ws, int64_t cap, int32_t He, int32_t We) {
   q += eg_align256(((size_t)B + 1) * 4);
   w.chunk_off = reinterpret_cast<uint32_t*>(q);
   q += eg_align256(((size_t)B + 1) * 4);
+  w.blk_off = reinterpret_cast<uint32_t*>(q);
+  q += env_grad_blk_bytes(B);
   w.rec = reinterpret_cast<EnvRec*>(q);
   q += eg_align256((size_t)cap * sizeof(EnvRec));
   w.sorted = reinterpret_cast<EnvRec*>(q);

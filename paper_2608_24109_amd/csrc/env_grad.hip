@@ -43,6 +43,64 @@ __global__ __launch_bounds__(kThreads) void k_eg_hist(EnvGradWs w) {
     if (h[b]) atomicAdd(&w.bucket_count[b], h[b]);
 }
 
+// Contiguous record range of block g of a G-block tiled pass (the histogram and the scatter split
+// the records the same way).
+__device__ __forceinline__ void block_range(uint32_t n, uint32_t g, uint32_t G, uint32_t* r0, uint32_t* r1) {
+  const uint32_t per = (uint32_t)(((uint64_t)n + G - 1) / G);
+  *r0 = (uint32_t)min((uint64_t)g * per, (uint64_t)n);
+  *r1 = (uint32_t)min((uint64_t)*r0 + per, (uint64_t)n);
+}
+
+// bucket sizes of each block's range (all B entries of the block's row) and the global sizes
+__global__ __launch_bounds__(kThreads) void k_eg_hist_blocks(EnvGradWs w) {
+  __shared__ uint32_t h[kTileMaxBuckets];
+  const int32_t B = w.n_buckets;
+  for (int32_t b = threadIdx.x; b < B; b += kThreads) h[b] = 0u;
+  __syncthreads();
+  uint32_t r0, r1;
+  block_range(n_records(w), blockIdx.x, gridDim.x, &r0, &r1);
+  for (uint32_t i = r0 + threadIdx.x; i < r1; i += kThreads) {
+    const uint32_t t = w.rec[i].texel;
+    if (valid(w, t)) atomicAdd(&h[t >> kBucketShift], 1u);
+  }
+  __syncthreads();
+  for (int32_t b = threadIdx.x; b < B; b += kThreads) {
+    w.blk_off[(size_t)blockIdx.x * B + b] = h[b];
+    if (h[b]) atomicAdd(&w.bucket_count[b], h[b]);
+  }
+}
+
+// after k_eg_scan: each block's first slot in every bucket (one block per bucket, an exclusive
+// scan over the G per-block counts; G <= kMaxScatterBlocks = 4 * kThreads)
+__global__ __launch_bounds__(kThreads) void k_eg_block_offsets(EnvGradWs w, uint32_t G) {
+  __shared__ uint32_t wsum[kThreads / 64];
+  const int32_t b = blockIdx.x;
+  const uint32_t per = (G + kThreads - 1) / kThreads;
+  const uint32_t g0 = min(G, threadIdx.x * per), g1 = min(G, g0 + per);
+  uint32_t v[kMaxScatterBlocks / kThreads];
+  uint32_t sum = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kMaxScatterBlocks / kThreads; ++k) {
+    v[k] = g0 + k < g1 ? w.blk_off[(size_t)(g0 + k) * w.n_buckets + b] : 0u;
+    sum += v[k];
+  }
+  uint32_t x = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if ((int)__lane_id() >= o) x += y;
+  }
+  if (__lane_id() == 63) wsum[threadIdx.x >> 6] = x;
+  __syncthreads();
+  uint32_t acc = w.bucket_off[b] + x - sum;
+  for (uint32_t q = 0; q < (threadIdx.x >> 6); ++q) acc += wsum[q];
+#pragma unroll
+  for (uint32_t k = 0; k < kMaxScatterBlocks / kThreads; ++k) {
+    if (g0 + k < g1) w.blk_off[(size_t)(g0 + k) * w.n_buckets + b] = acc;
+    acc += v[k];
+  }
+}
+
 __device__ __forceinline__ uint32_t n_chunks(uint32_t count) {
   return (uint32_t)((count + kReduceChunk - 1) / kReduceChunk);
 }
@@ -106,6 +164,79 @@ __global__ __launch_bounds__(kThreads) void k_eg_scatter(EnvGradWs w) {
   }
 }
 
+constexpr int kTileRecs = 2048;                      // records per tile of the tiled scatter
+constexpr int kTilePer = kTileRecs / kThreads;       // records per thread and tile
+static_assert(kMaxScatterBlocks % kThreads == 0, "block-offset scan: whole per-thread groups");
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if ((int)__lane_id() >= o) x += y;
+  }
+  return x;
+}
+
+// Tiled scatter (n_buckets <= kTileMaxBuckets): each block owns the contiguous range of the
+// records that k_eg_hist_blocks counted for it, starts from the first slots k_eg_block_offsets
+// gave it in every bucket, and walks its range in tiles of kTileRecs records: a counting sort of the tile by bucket in LDS, and the sorted tile
+// written out run by run behind the block's per-bucket cursors. A bucket's runs of consecutive
+// tiles are adjacent in memory, so the lines they share are completed microseconds apart and
+// merge in L2 instead of being written back part-filled; the stores of a run are coalesced.
+__global__ __launch_bounds__(kThreads) void k_eg_scatter_tiled(EnvGradWs w) {
+  __shared__ uint32_t cur[kTileMaxBuckets], cnt[kTileMaxBuckets], off[kTileMaxBuckets];
+  __shared__ uint4 lrec[kTileRecs];  // records as raw 16-byte words (texel first)
+  __shared__ uint32_t wsum[kThreads / 64];
+  const int32_t B = w.n_buckets;
+  uint32_t r0, r1;
+  block_range(n_records(w), blockIdx.x, gridDim.x, &r0, &r1);
+  for (int32_t b = threadIdx.x; b < B; b += kThreads) cur[b] = w.blk_off[(size_t)blockIdx.x * B + b];
+  const int32_t per = (B + kThreads - 1) / kThreads;  // buckets per thread in the tile scan
+  const int32_t b0 = min(B, (int32_t)threadIdx.x * per), b1 = min(B, b0 + per);
+  for (uint32_t t0 = r0; t0 < r1; t0 += kTileRecs) {
+    for (int32_t b = threadIdx.x; b < B; b += kThreads) cnt[b] = 0u;
+    __syncthreads();
+    uint4 r[kTilePer];
+    int32_t bk[kTilePer];
+    uint32_t rank[kTilePer];
+#pragma unroll
+    for (int k = 0; k < kTilePer; ++k) {
+      const uint32_t i = t0 + (uint32_t)(k * kThreads) + threadIdx.x;
+      r[k] = i < r1 ? reinterpret_cast<const uint4*>(w.rec)[i] : make_uint4(kNoTexel, 0u, 0u, 0u);
+      const bool ok = valid(w, r[k].x);
+      bk[k] = ok ? (int32_t)(r[k].x >> kBucketShift) : -1;
+      rank[k] = ok ? atomicAdd(&cnt[bk[k]], 1u) : 0u;
+    }
+    __syncthreads();
+    // exclusive scan of the tile's bucket counts
+    uint32_t sum = 0;
+    for (int32_t b = b0; b < b1; ++b) sum += cnt[b];
+    const uint32_t incl = wave_incl_scan(sum);
+    if (__lane_id() == 63) wsum[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    uint32_t excl = incl - sum;
+    for (uint32_t q = 0; q < (threadIdx.x >> 6); ++q) excl += wsum[q];
+    for (int32_t b = b0; b < b1; ++b) {
+      off[b] = excl;
+      excl += cnt[b];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTilePer; ++k)
+      if (bk[k] >= 0) lrec[off[bk[k]] + rank[k]] = r[k];
+    __syncthreads();
+    const uint32_t total = off[B - 1] + cnt[B - 1];
+    for (uint32_t i = threadIdx.x; i < total; i += kThreads) {
+      const uint4 q = lrec[i];
+      const uint32_t b = q.x >> kBucketShift;
+      reinterpret_cast<uint4*>(w.sorted)[cur[b] + (i - off[b])] = q;
+    }
+    __syncthreads();
+    for (int32_t b = threadIdx.x; b < B; b += kThreads) cur[b] += cnt[b];
+    __syncthreads();
+  }
+}
+
 // one block per chunk of a bucket's records: FP64 sums in LDS, then denv += sums (a plain
 // read-modify-write when the chunk is the bucket's only one, else FP64 atomics). Blocks past the
 // last chunk exit at once (the grid is sized for the largest possible chunk count).
@@ -162,17 +293,38 @@ hipError_t launch_env_grad_clear(const EnvGradWs& w, hipStream_t s) {
 hipError_t launch_env_grad_reduce(const EnvGradWs& w, int32_t He, int32_t We, double* denv, hipStream_t s) {
   if (w.n_buckets > kMaxLdsBuckets) return hipErrorInvalidValue;  // the ABI bounds He * We
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kSortBlocks, (w.cap + kThreads - 1) / kThreads));
+  const bool tiled = w.n_buckets <= kTileMaxBuckets;
+  unsigned tg = 1;  // tiled path: one contiguous range per resident scatter block
+  if (tiled) {
+    int dev = 0, cus = 256, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hipGetLastError();
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return hipGetLastError();
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_eg_scatter_tiled, kThreads, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    tg = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>(std::min<int64_t>((int64_t)cus * per_cu, kMaxScatterBlocks),
+                             (w.cap + kTileRecs - 1) / kTileRecs));
+  }
   {
     EXM_TIMED("env_grad_hist", s);
-    k_eg_hist<<<grid, kThreads, 0, s>>>(w);
+    if (tiled)
+      k_eg_hist_blocks<<<tg, kThreads, 0, s>>>(w);
+    else
+      k_eg_hist<<<grid, kThreads, 0, s>>>(w);
   }
   {
     EXM_TIMED("env_grad_scan", s);
     k_eg_scan<<<1, kThreads, 0, s>>>(w);
+    if (tiled) k_eg_block_offsets<<<(unsigned)w.n_buckets, kThreads, 0, s>>>(w, tg);
   }
   {
     EXM_TIMED("env_grad_scatter", s);
-    k_eg_scatter<<<grid, kThreads, 0, s>>>(w);
+    if (tiled)
+      k_eg_scatter_tiled<<<tg, kThreads, 0, s>>>(w);
+    else
+      k_eg_scatter<<<grid, kThreads, 0, s>>>(w);
   }
   {
     EXM_TIMED("env_grad_reduce", s);

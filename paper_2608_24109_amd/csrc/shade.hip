@@ -271,7 +271,7 @@ __device__ __forceinline__ void scatter_tex(const Surf& S, const float g8[8], fl
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_shade_bwd(MeshView M, TexView T, EnvView E, ShadeViews V,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_shade_bwd(MeshView M, TexView T, EnvView E, ShadeViews V,
                                                         const int32_t* __restrict__ tri_id,
                                                         const float* __restrict__ bary, KParams p, int64_t p0,
                                                         int64_t P, const float* __restrict__ dI,
