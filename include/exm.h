@@ -205,7 +205,10 @@ exm_status exm_trace_indirect_counted(const exm_mesh* m, const exm_bvh* bvh, con
  * sampling pdf are held fixed. dquery [nViews,H,W,8] (or NULL) is a gradient with respect to
  * the eight queried map values of Eq. 10 at each visible pixel (such as the adjoint of a loss on
  * the screen projection of the maps); it is added to the pixel's map adjoint before the one
- * scatter into dtex, which gives what exm_project_maps_bwd would add. */
+ * scatter into dtex, which gives what exm_project_maps_bwd would add. Part of the additions into
+ * dtex are plain read-modify-writes (a texel tile summed by one block): calls that add into the
+ * same dtex must not run concurrently (issue them on one stream, or order them with events).
+ * dtex must be 16-byte aligned (EXM_E_INVAL otherwise). */
 exm_status exm_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env,
                          const exm_camera* cams_host, int32_t nViews, const int32_t* tri_id,
                          const float* bary, const exm_params* p, const float* dI,
@@ -222,7 +225,9 @@ exm_status exm_trace_bwd(const exm_mesh* m, const exm_material* mat, const exm_e
 
 /* Workspace of the adjoints (device memory, 256-byte aligned, caller-owned): one 16-byte
  * record per env sample of the pixels in flight (N_d per pixel for exm_shade_bwd, N_b * N_s
- * for exm_trace_bwd) plus the bucket tables of the env map's binned reduction. _size is what
+ * for exm_trace_bwd) plus the bucket tables of the env map's binned reduction; for
+ * exm_shade_bwd also two 64-byte map-gradient records per pixel in flight and the tables of
+ * their tile sort (about 0.3 MB). _size is what
  * the views of one launch (at most 8) take at once; any size from _min up works, the pixels
  * then run in chunks. 0 for invalid arguments. */
 size_t exm_shade_bwd_workspace_size(int32_t nViews, int32_t H, int32_t W, int32_t N_d, int32_t He,

@@ -389,6 +389,7 @@ exm_status exm_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_e
   EXM_TRY(check_params(p, false));
   if (!dI || !vis || !dtex || !denv) return fail(EXM_E_INVAL, "gradient pointer is NULL");
   if (dquery && !aligned(dquery, 16)) return fail(EXM_E_INVAL, "dquery must be 16-byte aligned");
+  if (!aligned(dtex, 16)) return fail(EXM_E_INVAL, "dtex must be 16-byte aligned");
   if (!ws || !aligned(ws, 256) || ws_bytes < shade_bwd_ws_min(p->N_d, env->He, env->We))
     return fail(EXM_E_INVAL, "workspace must be 256-byte aligned and at least exm_shade_bwd_workspace_min bytes");
   EXM_TRY(check_device());

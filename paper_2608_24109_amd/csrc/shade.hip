@@ -26,6 +26,7 @@
 #include "env_grad.h"
 #include "exm_device.h"
 #include "exm_rays.h"
+#include "tex_grad.h"
 
 namespace exm {
 namespace {
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
                                                         int64_t P, const float* __restrict__ dI,
                                                         const uint64_t* __restrict__ vis,
                                                         const float* __restrict__ dquery, float* __restrict__ dtex,
-                                                        EnvGradWs eg, bool use_lds) {
+                                                        EnvGradWs eg, TexGradWs tg, bool tiled, bool use_lds) {
   extern __shared__ __align__(16) char smem[];
   const EnvTabs tb = load_env_tabs(E, smem, use_lds);
   const int64_t HW = (int64_t)V.H * V.W;
@@ -305,6 +306,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     act = f >= 0 && bits != 0 && (g[0] != 0.0f || g[1] != 0.0f || g[2] != 0.0f);
   }
   uint32_t slot = env_grad_reserve(eg.counter, act ? (uint32_t)__popcll(bits) : 0u);
+  const uint32_t tslot = tiled ? tex_grad_reserve(tg.counter, act || extra) : 0u;
   if (!act && !extra) return;
   if (!act) bits = 0;
   const int32_t view = (int32_t)(gid / HW);
@@ -347,7 +349,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   normal_map_adjoint(S, G.n, gq);
   const float g8[8] = {G.a[0] + gx[0], G.a[1] + gx[1], G.a[2] + gx[2], G.r + gx[3],
                        ((p.flags & EXM_METALLIC_OFF) ? 0.0f : G.m) + gx[4], gq[0] + gx[5], gq[1] + gx[6], gq[2] + gx[7]};
-  scatter_tex(S, g8, dtex);
+  if (tiled)
+    tex_grad_put(tg, tslot, S.tap, S.w, g8, dtex);
+  else
+    scatter_tex(S, g8, dtex);
+}
+
+// Largest pixel chunk (multiple of 64, at most max_px) whose env-gradient records (per_px per
+// pixel) and map-gradient records (one per pixel) fit in ws_bytes; the env part comes first.
+int64_t bwd_chunk(size_t ws_bytes, int64_t per_px, int32_t He, int32_t We, int64_t max_px) {
+  int64_t lo = 0, hi = (max_px + 63) / 64;
+  if (per_px > 0) hi = std::min<int64_t>(hi, ((int64_t)1 << 31) / (64 * per_px));
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (env_grad_ws_bytes(mid * 64 * per_px, He, We) + tex_grad_ws_bytes(mid * 64) <= ws_bytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo * 64;
 }
 
 KParams kparams(const exm_params* p) {
@@ -418,33 +438,45 @@ hipError_t launch_shade_bwd(const exm_mesh* m, const exm_material* mat, const ex
                             size_t ws_bytes, hipStream_t s) {
   const int64_t n = (int64_t)v.n * v.H * v.W;
   const int64_t per_px = std::max(p->N_d, 0);
-  const int64_t P = env_grad_chunk(ws_bytes, per_px, env->He, env->We, n);
+  const int64_t P = bwd_chunk(ws_bytes, per_px, env->He, env->We, n);
   if (P <= 0) return hipErrorInvalidValue;  // the ABI layer checks the size first
   const size_t lds = env_tabs_bytes(env->He, env->We);
   const bool use_lds = lds <= kEnvTabsMaxBytes;
   const KParams kp = kparams(p);
+  const bool tiled = tex_grad_tiled(mat->Ht, mat->Wt);
   for (int64_t p0 = 0; p0 < n; p0 += P) {
     const int64_t Pc = std::min<int64_t>(P, ((n - p0) + 63) / 64 * 64);
     const EnvGradWs eg = env_grad_ws(ws, Pc * per_px, env->He, env->We);
+    const TexGradWs tg =
+        tex_grad_ws(static_cast<char*>(ws) + env_grad_ws_bytes(Pc * per_px, env->He, env->We), Pc, mat->Ht, mat->Wt);
     hipError_t e = launch_env_grad_clear(eg, s);
     if (e != hipSuccess) return e;
+    if (tiled) {
+      e = launch_tex_grad_clear(tg, s);
+      if (e != hipSuccess) return e;
+    }
     {
       EXM_TIMED("shade_bwd", s);
       k_shade_bwd<<<(unsigned)((Pc + kThreads - 1) / kThreads), kThreads, use_lds ? lds : 0, s>>>(
           mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), v, tri_id, bary, kp, p0, Pc, dI, vis,
-          dquery, dtex, eg, use_lds);
+          dquery, dtex, eg, tg, tiled, use_lds);
     }
     e = launch_env_grad_reduce(eg, env->He, env->We, denv, s);
     if (e != hipSuccess) return e;
+    if (tiled) {
+      e = launch_tex_grad_reduce(tg, dtex, s);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipGetLastError();
 }
 
 size_t shade_bwd_ws_bytes(int64_t n_pix, int32_t N_d, int32_t He, int32_t We) {
-  return env_grad_ws_bytes((n_pix + 63) / 64 * 64 * std::max(N_d, 0), He, We);
+  const int64_t np = (n_pix + 63) / 64 * 64;
+  return env_grad_ws_bytes(np * std::max(N_d, 0), He, We) + tex_grad_ws_bytes(np);
 }
 size_t shade_bwd_ws_min(int32_t N_d, int32_t He, int32_t We) {
-  return env_grad_ws_bytes(64 * (int64_t)std::max(N_d, 0), He, We);
+  return env_grad_ws_bytes(64 * (int64_t)std::max(N_d, 0), He, We) + tex_grad_ws_bytes(64);
 }
 
 }  // namespace exm

@@ -153,6 +153,9 @@ def test_indirect_and_backward_validation(L):
     s = L.lib.exm_shade_bwd(C.byref(m), C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000, C.byref(p),
                             0x1000, 0x1000, 0x1004, 0x1000, 0x1000, 0x100000, big, None)
     assert s == L.EXM_E_INVAL and "dquery" in L.last_error()
+    s = L.lib.exm_shade_bwd(C.byref(m), C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000, C.byref(p),
+                            0x1000, 0x1000, None, 0x1008, 0x1000, 0x100000, big, None)
+    assert s == L.EXM_E_INVAL and "dtex" in L.last_error()
     s = L.lib.exm_trace_bwd(C.byref(m), C.byref(mat), C.byref(env), cams, 1, 0x1000, 0x1000, C.byref(p),
                             1.0, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x100010, big, None)
     assert s == L.EXM_E_INVAL and "workspace" in L.last_error()  # not 256-byte aligned
