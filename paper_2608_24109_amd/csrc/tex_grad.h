@@ -6,12 +6,13 @@
 // per wave reserves the wave's range). Taps that fall outside the tile of kTexTileW x kTexTileH
 // texels holding the first tap (the second column or row of taps crossing the tile's last column
 // or row: about one pixel in twenty) are added to dtex by the adjoint kernel itself, with atomics.
-// A counting sort groups the records by the tile of their first tap, and one block per chunk of
-// at most kTexChunk records of a tile adds w_k * g_c of the taps inside the tile into an LDS copy
-// of it, then adds the LDS sums to dtex: a plain read-modify-write when the chunk is its tile's
-// only one (no other block writes those texels, and the adjoint's atomics have completed before
-// the reduction starts), atomics whose lanes cover consecutive floats otherwise. The per-texel
-// sums equal those of the per-tap atomics up to the order of FP32 additions.
+// A counting sort groups the records by the tile of their first tap. One block per tile takes the
+// tile's records kTexChunk at a time: it stages them in LDS, lists for every texel of the tile
+// the (record, tap) pairs that reach it (a counting sort of the taps by texel with integer LDS
+// atomics), and lets the thread that owns the texel add w_k * g_c over its list to sums it keeps
+// in registers. The block ends with one plain read-modify-write of the tile in dtex: no other
+// block writes those texels, and the adjoint's atomics have completed before the reduction
+// starts. The per-texel sums equal those of the per-tap atomics up to the order of FP32 additions.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -23,7 +24,7 @@ namespace exm {
 constexpr int32_t kTexTileW = 64;               // texels per tile along a row
 constexpr int32_t kTexTileH = 32;               // rows per tile
 constexpr int32_t kTexMaxBuckets = 16384;       // tiles of the largest map this path handles
-constexpr int64_t kTexChunk = 8192;             // records summed by one block
+constexpr int64_t kTexChunk = 1024;             // records staged at a time by a tile's block
 constexpr uint32_t kTexStepBit = 0x80000000u;   // in col / row: the second tap is one further
 
 struct alignas(16) TexRec {
@@ -40,8 +41,6 @@ struct TexGradWs {
   uint32_t* bucket_count;  // [kTexMaxBuckets + 1]
   uint32_t* bucket_off;    // [kTexMaxBuckets + 1]
   uint32_t* bucket_cur;    // [kTexMaxBuckets + 1]
-  uint32_t* chunk_off;     // [kTexMaxBuckets + 1] first reduction chunk of each bucket
-  uint32_t* chunk_bucket;  // [tex_grad_max_chunks(cap)] bucket of each reduction chunk
   TexRec* rec;             // [cap] as appended
   TexRec* sorted;          // [cap] grouped by bucket
   int64_t cap;
@@ -60,13 +59,9 @@ inline bool tex_grad_tiled(int32_t Ht, int32_t Wt) {
 
 inline size_t tg_align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// reduction chunks of cap records at most (every bucket's last chunk may be partial)
-inline int64_t tex_grad_max_chunks(int64_t cap) { return (cap + kTexChunk - 1) / kTexChunk + kTexMaxBuckets; }
-
 // bytes for cap records (independent of the map size: the tables are sized for kTexMaxBuckets)
 inline size_t tex_grad_ws_bytes(int64_t cap) {
-  return 256 + 4 * tg_align256(((size_t)kTexMaxBuckets + 1) * 4) + tg_align256((size_t)tex_grad_max_chunks(cap) * 4) +
-         2 * tg_align256((size_t)cap * sizeof(TexRec));
+  return 256 + 3 * tg_align256(((size_t)kTexMaxBuckets + 1) * 4) + 2 * tg_align256((size_t)cap * sizeof(TexRec));
 }
 
 inline TexGradWs tex_grad_ws(void* ws, int64_t cap, int32_t Ht, int32_t Wt) {
@@ -81,10 +76,6 @@ inline TexGradWs tex_grad_ws(void* ws, int64_t cap, int32_t Ht, int32_t Wt) {
   q += tb;
   w.bucket_cur = reinterpret_cast<uint32_t*>(q);
   q += tb;
-  w.chunk_off = reinterpret_cast<uint32_t*>(q);
-  q += tb;
-  w.chunk_bucket = reinterpret_cast<uint32_t*>(q);
-  q += tg_align256((size_t)tex_grad_max_chunks(cap) * 4);
   w.rec = reinterpret_cast<TexRec*>(q);
   q += tg_align256((size_t)cap * sizeof(TexRec));
   w.sorted = reinterpret_cast<TexRec*>(q);
