@@ -18,6 +18,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace exm {
 
@@ -55,6 +56,13 @@ inline int32_t tex_grad_buckets(int32_t Ht, int32_t Wt) {
 // whether the tiled reduction handles a map of this size (else the adjoints scatter with atomics)
 inline bool tex_grad_tiled(int32_t Ht, int32_t Wt) {
   return Ht > 0 && Wt > 0 && tex_grad_buckets(Ht, Wt) <= kTexMaxBuckets;
+}
+
+// EXM_TEX_GRAD_TILED=0 makes the adjoint scatter with atomics at any map size (read at every call;
+// the tests compare the two paths with it)
+inline bool tex_grad_enabled() {
+  const char* e = getenv("EXM_TEX_GRAD_TILED");
+  return !(e && e[0] == '0');
 }
 
 inline size_t tg_align256(size_t x) { return (x + 255) & ~(size_t)255; }

@@ -35,6 +35,9 @@ KERNELS = {
     "env_grad_hist": "k_eg_hist",
     "env_grad_scatter": "k_eg_scatter",
     "env_grad_reduce": "k_eg_reduce",
+    "tex_grad_hist": "k_tg_hist",
+    "tex_grad_scatter": "k_tg_scatter",
+    "tex_grad_reduce": "k_tg_reduce",
     "raster": "k_raster",
     "raster_resolve": "k_resolve",
 }
@@ -44,8 +47,8 @@ COPY_KERNEL = "copyBuffer"
 # the sources the render-pass kernels (and the BVH they traverse) are built from; a change to
 # any of them invalidates a counter summary
 RENDER_PASS_SOURCES = ("mesh.hip", "env_sampler.hip", "raster.hip", "shade.hip", "trace.hip", "rays.hip",
-                       "env_grad.hip", "env_grad.h", "exm_device.h", "exm_rays.h", "exm_internal.h",
-                       "bvh_build.cpp")
+                       "env_grad.hip", "env_grad.h", "tex_grad.hip", "tex_grad.h", "exm_device.h", "exm_rays.h",
+                       "exm_internal.h", "bvh_build.cpp")
 
 
 def _code_only(text: str) -> str:
