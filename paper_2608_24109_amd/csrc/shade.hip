@@ -156,19 +156,41 @@ __global__ __launch_bounds__(kThreads) void k_dir_finalize(ShadeViews V, KParams
   uint32_t running = 0;
   float L[3] = {0.f, 0.f, 0.f};
   uint64_t bits = 0;
-  for (int k = 0; k < p.N_d; ++k) {
-    const bool have = (mask >> k) & 1ull;
-    const uint64_t bal = __ballot(have);
-    if (have) {
-      const int64_t slot = rbase + running + lanes_below(bal);
-      if (novis || ws.hit[slot] == 0) {
-        bits |= 1ull << k;
-        L[0] += ws.contrib[3 * slot];
-        L[1] += ws.contrib[3 * slot + 1];
-        L[2] += ws.contrib[3 * slot + 2];
+  // kGroup samples at a time: their slots, then all their hit flags, then the contributions of
+  // the unoccluded ones are loaded together (two memory round trips per group instead of two
+  // per sample); the sums still run in sample order
+  constexpr int kGroup = 8;
+  for (int k0 = 0; k0 < p.N_d; k0 += kGroup) {
+    int64_t slot[kGroup];
+    bool have[kGroup], lit[kGroup];
+#pragma unroll
+    for (int j = 0; j < kGroup; ++j) {
+      const int k = k0 + j;
+      have[j] = k < p.N_d && ((mask >> k) & 1ull);
+      const uint64_t bal = __ballot(have[j]);
+      slot[j] = rbase + running + lanes_below(bal);
+      running += (uint32_t)__popcll(bal);
+    }
+#pragma unroll
+    for (int j = 0; j < kGroup; ++j) lit[j] = have[j] && (novis || ws.hit[slot[j]] == 0);
+    float c[kGroup][3];
+#pragma unroll
+    for (int j = 0; j < kGroup; ++j) {
+      c[j][0] = c[j][1] = c[j][2] = 0.0f;
+      if (lit[j]) {
+        c[j][0] = ws.contrib[3 * slot[j]];
+        c[j][1] = ws.contrib[3 * slot[j] + 1];
+        c[j][2] = ws.contrib[3 * slot[j] + 2];
       }
     }
-    running += (uint32_t)__popcll(bal);
+#pragma unroll
+    for (int j = 0; j < kGroup; ++j) {
+      if (!lit[j]) continue;
+      bits |= 1ull << (k0 + j);
+      L[0] += c[j][0];
+      L[1] += c[j][1];
+      L[2] += c[j][2];
+    }
   }
   if (!valid) return;
   const float inv = p.N_d > 0 ? 1.0f / (float)p.N_d : 0.0f;
