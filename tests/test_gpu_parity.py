@@ -496,6 +496,36 @@ def test_tiled_map_gradient_equals_atomic_scatter(small, monkeypatch):
         assert np.array_equal(e_tiled, e_atom) or np.abs(e_tiled - e_atom).max() <= 1e-12 * np.abs(e_atom).max()
 
 
+def test_chunked_workspace_equals_whole_frame(small_tori):
+    """Forward and backward with a 1 MB workspace, so that every pass runs in many pixel chunks
+    (direct about 1,400 pixels, adjoint about 1,100, of 96^2 = 9,216), against the same calls with
+    room for the whole frame: images, visibility bits and secondary-hit records bitwise equal,
+    gradients equal up to the order of their sums."""
+    from paper_2608_24109_amd import _lib as L
+    from paper_2608_24109_amd.render import PassBuffers, render_backward, render_forward
+    dev = small_tori
+    cams = dev.sc.cams[:1]
+    p = dev.params()
+    cc = L.cameras(cams, [0])
+    g = torch.from_numpy(I.upstream_grad(1, cams[0].H, cams[0].W, seed=13)).cuda()
+    res = []
+    for cap in (None, 1 << 20):
+        kw = {} if cap is None else {"ws_cap": cap}
+        b = PassBuffers(1, cams[0].H, cams[0].W, p.N_b, **kw)
+        render_forward(dev.mesh, dev.mat, dev.env, cc, p, b)
+        dtex = torch.zeros_like(dev.mat.tex)
+        denv = torch.zeros(dev.env.env.shape, dtype=torch.float64, device="cuda")
+        render_backward(dev.mesh, dev.mat, dev.env, cc, p, b, g, 0.7, dtex, denv)
+        torch.cuda.synchronize()
+        res.append((b, dtex.cpu().numpy(), denv.cpu().numpy()))
+    (b1, t1, e1), (b2, t2, e2) = res
+    assert b2.ws.numel() <= 1 << 20
+    for k in ("L_dir", "vis", "L_ind", "sec_rec", "sec_vis"):
+        assert torch.equal(getattr(b1, k), getattr(b2, k)), k
+    assert np.abs(t1).max() > 0 and np.abs(t1 - t2).max() <= 1e-5 * np.abs(t1).max()
+    assert np.abs(e1).max() > 0 and np.abs(e1 - e2).max() <= 1e-12 * np.abs(e1).max()
+
+
 def test_gradients_indirect_small_tori(small_tori):
     log("[grad] small tori direct + indirect, lambda 0.7")
     _check_grads(small_tori, small_tori.sc.cams[:1], small_tori.params(), lam=0.7, n_texels=32, n_dirs=3)
