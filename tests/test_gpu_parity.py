@@ -526,6 +526,40 @@ def test_chunked_workspace_equals_whole_frame(small_tori):
     assert np.abs(e1).max() > 0 and np.abs(e1 - e2).max() <= 1e-12 * np.abs(e1).max()
 
 
+def test_eleven_views_in_one_call(small_tori):
+    """One call with 11 views (the library launches at most 8 at a time) against each view rendered
+    by a call of its own: every output of the forward bitwise equal, and the adjoint of the batch
+    equal to the sum of the single-view adjoints up to the order of the sums."""
+    from paper_2608_24109_amd import _lib as L
+    from paper_2608_24109_amd.render import PassBuffers, render_backward, render_forward
+    dev = small_tori
+    cams = I.ring_cameras(11, 4.5, 40, 48)
+    p = dev.params()
+    g = torch.from_numpy(I.upstream_grad(11, 40, 48, seed=17)).cuda()
+
+    def run(idx):
+        cc = L.cameras([cams[i] for i in idx], list(idx))
+        b = PassBuffers(len(idx), 40, 48, p.N_b)
+        render_forward(dev.mesh, dev.mat, dev.env, cc, p, b)
+        dtex = torch.zeros_like(dev.mat.tex)
+        denv = torch.zeros(dev.env.env.shape, dtype=torch.float64, device="cuda")
+        render_backward(dev.mesh, dev.mat, dev.env, cc, p, b, g[list(idx)].contiguous(), 0.7, dtex, denv)
+        torch.cuda.synchronize()
+        return b, dtex.double(), denv
+
+    ball, tall, eall = run(range(11))
+    tsum = torch.zeros_like(tall)
+    esum = torch.zeros_like(eall)
+    for v in range(11):
+        b, t, e = run([v])
+        for k in ("tri_id", "bary", "L_dir", "vis", "L_ind", "sec_rec", "sec_vis"):
+            assert torch.equal(getattr(b, k)[0], getattr(ball, k)[v]), (v, k)
+        tsum += t
+        esum += e
+    assert tall.abs().max() > 0 and (tall - tsum).abs().max() <= 1e-5 * tall.abs().max()
+    assert eall.abs().max() > 0 and (eall - esum).abs().max() <= 1e-11 * eall.abs().max()
+
+
 def test_gradients_indirect_small_tori(small_tori):
     log("[grad] small tori direct + indirect, lambda 0.7")
     _check_grads(small_tori, small_tori.sc.cams[:1], small_tori.params(), lam=0.7, n_texels=32, n_dirs=3)
