@@ -306,6 +306,8 @@ __device__ __forceinline__ void nmap_adjoint(const Surf& S, f3 gn, float gq[3]) 
   gq[2] = dot(S.ng, gv);
 }
 
+constexpr int kCacheS = 4;  // secondary light samples per secondary point kept between the adjoint's two passes
+
 __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, EnvView E, ShadeViews V,
                                                         const int32_t* __restrict__ tri_id,
                                                         const float* __restrict__ bary, KParams p, float lambda_ind,
@@ -359,9 +361,23 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
     const float kdy = (1.0f - Y.m) * kInvPi;
     const float fdy[3] = {kdy * Y.a[0], kdy * Y.a[1], kdy * Y.a[2]};
     const float fdx[3] = {kdx * S.a[0], kdx * S.a[1], kdx * S.a[2]};
-    // L_sec(y) without the f_d(y) factor, per channel: (1/N_s) sum E c / pdf
+    // L_sec(y) without the f_d(y) factor, per channel: (1/N_s) sum E c / pdf. The first kCacheS
+    // samples are kept for the second pass below, which would otherwise draw them again.
     float Es[3] = {0.f, 0.f, 0.f};
-    for (int s = 0; s < p.N_s; ++s) {
+    EnvSample cache[kCacheS];
+#pragma unroll
+    for (int s = 0; s < kCacheS; ++s) {
+      if (s >= p.N_s || !((bits >> (j * p.N_s + s)) & 1ull)) continue;
+      const Draw ds = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s, 2u + (uint32_t)j);
+      cache[s] = env_sample(E, tb, ds);
+      const float c = dot(Y.ns, cache[s].dir);
+      const float* e = cache[s].E;
+      const float wgt = c * cache[s].inv_pdf * invNs;
+      Es[0] += e[0] * wgt;
+      Es[1] += e[1] * wgt;
+      Es[2] += e[2] * wgt;
+    }
+    for (int s = kCacheS; s < p.N_s; ++s) {
       if (!((bits >> (j * p.N_s + s)) & 1ull)) continue;
       const Draw ds = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s, 2u + (uint32_t)j);
       const EnvSample es = env_sample(E, tb, ds);
@@ -390,8 +406,15 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
     f3 gny = mk(0, 0, 0);
     for (int s = 0; s < p.N_s; ++s) {
       if (!((bits >> (j * p.N_s + s)) & 1ull)) continue;
-      const Draw ds = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s, 2u + (uint32_t)j);
-      const EnvSample es = env_sample(E, tb, ds);
+      EnvSample es;
+      if (s < kCacheS) {
+#pragma unroll
+        for (int q = 0; q < kCacheS; ++q)
+          if (q == s) es = cache[q];
+      } else {
+        const Draw ds = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s, 2u + (uint32_t)j);
+        es = env_sample(E, tb, ds);
+      }
       const float c = dot(Y.ns, es.dir);
       const float* e = es.E;
       const float ip = es.inv_pdf * invNs;
