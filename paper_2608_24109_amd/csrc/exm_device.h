@@ -81,6 +81,7 @@ struct EnvView {
   const float* pdf;
   const uint32_t* guide;  // cutpoint tables over cdf_row and each row of cdf_col (layout below)
   const float4* rec;      // per texel (E.r, E.g, E.b, 1/pdf)
+  const uint32_t* cdf32;  // 32-bit copy of cdf_col inside guide, or null for maps too wide for it
 };
 
 struct EnvSample {
@@ -186,14 +187,15 @@ __device__ __forceinline__ EnvTabs load_env_tabs(const EnvView& e, void* lds, bo
 // K independent picks advanced stage by stage (rows in LDS, then the K cutpoint pairs, a
 // lockstep column search, the K records), so that each thread has K loads in flight at every
 // stage; every pick is the one a lone search returns. Picks with valid[j] false read nothing
-// and leave out[j] untouched.
-template <int K>
+// and leave out[j] untouched. REC false skips the record loads: out[j].E and out[j].inv_pdf are
+// then left unset, for the caller to fetch with env_rec only for the picks it keeps.
+template <int K, bool REC = true>
 __device__ __forceinline__ void env_sample_k(const EnvView& e, const EnvTabs& tb, const Draw (&d)[K],
                                              const bool (&valid)[K], EnvSample (&out)[K]) {
   const uint64_t Q = tb.cdf_row[e.He - 1];
   int32_t row[K], lo[K], cnt[K];
   uint64_t rem[K];
-  const uint64_t* cdf[K];
+  int64_t cbase[K];  // offset of the picked row in cdf_col (or its 32-bit copy)
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     // target < Q whenever the tables are well formed; the clamps only keep a malformed table
@@ -204,7 +206,7 @@ __device__ __forceinline__ void env_sample_k(const EnvView& e, const EnvTabs& tb
                           e.He - 1);
     row[j] = r;
     rem[j] = target - (r > 0 ? tb.cdf_row[r - 1] : 0ull);
-    cdf[j] = e.cdf_col + (int64_t)r * e.We;
+    cbase[j] = (int64_t)r * e.We;
   }
   uint32_t g0[K], g1[K];
 #pragma unroll
@@ -224,11 +226,15 @@ __device__ __forceinline__ void env_sample_k(const EnvView& e, const EnvTabs& tb
     cnt[j] = valid[j] ? max((int32_t)g1[j] - (int32_t)g0[j], 0) : 0;
     more |= cnt[j] > 0;
   }
+  const bool narrow = e.cdf32 != nullptr;  // uniform; the copy holds the same values
   while (more) {  // binary search over [lo, lo + cnt], one probe of every pick per round
     uint64_t v[K];
 #pragma unroll
     for (int j = 0; j < K; ++j)
-      if (cnt[j] > 0) v[j] = cdf[j][lo[j] + (cnt[j] >> 1)];
+      if (cnt[j] > 0) {
+        const int64_t at = cbase[j] + lo[j] + (cnt[j] >> 1);
+        v[j] = narrow ? (uint64_t)e.cdf32[at] : e.cdf_col[at];
+      }
     more = false;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -247,7 +253,7 @@ __device__ __forceinline__ void env_sample_k(const EnvView& e, const EnvTabs& tb
   float4 rec[K];
 #pragma unroll
   for (int j = 0; j < K; ++j)
-    if (valid[j]) rec[j] = e.rec[row[j] * e.We + min(lo[j], e.We - 1)];
+    if (REC && valid[j]) rec[j] = e.rec[row[j] * e.We + min(lo[j], e.We - 1)];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     if (!valid[j]) continue;
@@ -273,12 +279,23 @@ __device__ __forceinline__ void env_sample_k(const EnvView& e, const EnvTabs& tb
     sincospif(2.0f * d[j].u2 / (float)e.We, &sd, &cd);
     const float cphi = cj.y * cd - cj.x * sd, sphi = cj.x * cd + cj.y * sd;
     s.dir = mk(st * cphi, ct, st * sphi);
-    s.inv_pdf = rec[j].w;
-    s.E[0] = rec[j].x;
-    s.E[1] = rec[j].y;
-    s.E[2] = rec[j].z;
+    if (REC) {
+      s.inv_pdf = rec[j].w;
+      s.E[0] = rec[j].x;
+      s.E[1] = rec[j].y;
+      s.E[2] = rec[j].z;
+    }
     out[j] = s;
   }
+}
+
+// the record (E, 1/pdf) of a pick taken with REC false
+__device__ __forceinline__ void env_rec(const EnvView& e, EnvSample& s) {
+  const float4 r = e.rec[s.texel];
+  s.inv_pdf = r.w;
+  s.E[0] = r.x;
+  s.E[1] = r.y;
+  s.E[2] = r.z;
 }
 
 __device__ __forceinline__ EnvSample env_sample(const EnvView& e, const EnvTabs& tb, const Draw& d) {

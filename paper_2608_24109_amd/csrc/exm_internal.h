@@ -67,9 +67,15 @@ namespace exm {
 //   guide[1 .. He + 1]                row entries
 //   guide[He + 2 .. 2 He + 2)         shift of each row's column CDF
 //   guide[2 He + 2 + i (We + 1) + g]  column entries of row i
+// and, when We < kCdf32MaxW (a row total is at most We * 2^20 < 2^32), a 32-bit copy of cdf_col
+// that the column search reads instead of the 64-bit table (half the bytes per probe):
+//   guide[He (We + 3) + 2 + i We + j]  cdf_col[i][j]
+constexpr int32_t kCdf32MaxW = 4096;
 inline size_t env_guide_len(int32_t He, int32_t We) {
-  return (size_t)He * (size_t)(We + 3) + 2;
+  const size_t base = (size_t)He * (size_t)(We + 3) + 2;
+  return base + (We < kCdf32MaxW ? (size_t)He * (size_t)We : 0);
 }
+__host__ __device__ inline size_t env_cdf32_offset(int32_t He, int32_t We) { return (size_t)He * (size_t)(We + 3) + 2; }
 
 // Brackets one kernel launch with HIP events on its stream when timing is enabled
 // (exm_timing_enable); names are string literals.

@@ -100,19 +100,30 @@ __global__ __launch_bounds__(kThreads) void k_dir_gen(MeshView M, TexView T, Env
       ok[j] = f >= 0 && k0 + j < p.N_d;
       if (ok[j]) dr[j] = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)(k0 + j), 0u);
     }
-    env_sample_k<kPicks>(E, tb, dr, ok, es);
+    // records are read only for the picks above the shading hemisphere: the others are dropped
+    // whatever their records hold (two thirds of all picks on the displaced sphere)
+    env_sample_k<kPicks, false>(E, tb, dr, ok, es);
+    bool need[kPicks];
+    float cs[kPicks];
+#pragma unroll
+    for (int j = 0; j < kPicks; ++j) {
+      need[j] = false;
+      cs[j] = 0.0f;
+      if (ok[j]) {
+        cs[j] = dot(S.ns, es[j].dir);
+        need[j] = cs[j] > 0.0f;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kPicks; ++j)
+      if (need[j]) env_rec(E, es[j]);
 #pragma unroll
     for (int j = 0; j < kPicks; ++j) {
       const int k = k0 + j;
       if (k >= p.N_d) break;  // wave-uniform
-      bool need = false;
-      float c = 0.0f;
-      if (ok[j]) {
-        c = dot(S.ns, es[j].dir);
-        need = c > 0.0f;
-      }
-      const uint64_t bal = __ballot(need);
-      if (need) {
+      const float c = cs[j];
+      const uint64_t bal = __ballot(need[j]);
+      if (need[j]) {
         const int64_t slot = rbase + running + lanes_below(bal);
         RayRec R;
         R.o[0] = S.x.x;
@@ -409,7 +420,9 @@ MeshView mesh_view(const exm_mesh* m) {
   return MeshView{m->nV, m->nF, m->pos, m->tri, m->uv, m->tri_uv, m->vnrm, m->ftan};
 }
 EnvView env_view(const exm_env* e) {
-  return EnvView{e->He, e->We, e->env, e->cdf_row, e->cdf_col, e->pdf, e->guide, reinterpret_cast<const float4*>(e->rec)};
+  const uint32_t* c32 = e->We < kCdf32MaxW ? e->guide + env_cdf32_offset(e->He, e->We) : nullptr;
+  return EnvView{e->He,    e->We,    e->env, e->cdf_row, e->cdf_col, e->pdf,
+                 e->guide, reinterpret_cast<const float4*>(e->rec), c32};
 }
 BvhView bvh_view(const exm_bvh* b) { return BvhView{b->nodes, b->tris, b->root_is_leaf}; }
 

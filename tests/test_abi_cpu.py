@@ -171,7 +171,9 @@ def test_env_sampler_and_bvh_validation(L):
     assert f(a, 4, 8, a, a, a, None, a, None) == L.EXM_E_INVAL
     assert f(a, 4, 8, a, a, a, a, 0x1008, None) == L.EXM_E_INVAL
     # cutpoint tables: row shift + (He + 1) row entries + He column shifts + He (We + 1) entries
-    assert L.exm_env_guide_len(512, 1024) == 1 + 513 + 512 + 512 * 1025
+    # cutpoint tables, then the 32-bit copy of the column CDF for maps narrower than 4096 texels
+    assert L.exm_env_guide_len(512, 1024) == 1 + 513 + 512 + 512 * 1025 + 512 * 1024
+    assert L.exm_env_guide_len(4, 4096) == 1 + 5 + 4 + 4 * 4097
     assert L.exm_env_guide_len(0, 8) == 0
     pos = np.zeros((3, 3), np.float32)
     tri = np.array([[0, 1, 3]], np.int32)

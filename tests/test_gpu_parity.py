@@ -139,7 +139,9 @@ def test_env_guide_and_records(lib, case):
     gd = d.guide.cpu().numpy().view(np.uint32).astype(np.int64)
     s, ref = _guide_ref(cr, He)
     assert gd[0] == s and np.array_equal(gd[1:He + 2], ref)
-    cols = gd[2 * He + 2:].reshape(He, We + 1)
+    cols = gd[2 * He + 2:He * (We + 3) + 2].reshape(He, We + 1)
+    # the 32-bit copy of the column CDF that the pick's column search reads
+    assert np.array_equal(gd[He * (We + 3) + 2:], cc.reshape(-1).astype(np.int64))
     for i in range(He):
         si, ri = _guide_ref(cc[i], We)
         assert gd[He + 2 + i] == si and np.array_equal(cols[i], ri), f"row {i}"
