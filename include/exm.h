@@ -139,9 +139,9 @@ size_t exm_bvh_device_bytes(const exm_bvh* bvh);
  * pdf_ij = q_ij / (Q Omega_i). A texel is picked by inverting these CDFs (row, then column).
  * Also written, as functions of the tables and the map: `guide`, cutpoint tables that narrow
  * each inversion to a few entries without changing its result (Chen and Asau's guide-table
- * method), followed for We < 4096 by a uint32 copy of cdf_col (a row total is below 2^32
- * there) that the column search reads, and `rec`, the packed per-texel record (E, 1/pdf) read
- * by the pick. All outputs
+ * method), followed for We < 4096 by compact copies that the pick reads (cdf_col in uint32,
+ * a row total being below 2^32 there, and the column cutpoints in uint16), and `rec`, the
+ * packed per-texel record (E, 1/pdf) read by the pick. All outputs
  * are caller-owned device buffers; cdf_row, cdf_col 8-byte, rec 16-byte aligned. The tables
  * describe the map at the time of the call: rebuild them after the map changes. Needs
  * He >= 1, 2 <= We, He*We <= 2^24; uses no workspace. */

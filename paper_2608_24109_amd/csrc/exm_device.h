@@ -82,6 +82,7 @@ struct EnvView {
   const uint32_t* guide;  // cutpoint tables over cdf_row and each row of cdf_col (layout below)
   const float4* rec;      // per texel (E.r, E.g, E.b, 1/pdf)
   const uint32_t* cdf32;  // 32-bit copy of cdf_col inside guide, or null for maps too wide for it
+  const uint16_t* col16;  // 16-bit copy of the column entries inside guide (null with cdf32)
 };
 
 struct EnvSample {
@@ -208,15 +209,22 @@ __device__ __forceinline__ void env_sample_k(const EnvView& e, const EnvTabs& tb
     rem[j] = target - (r > 0 ? tb.cdf_row[r - 1] : 0ull);
     cbase[j] = (int64_t)r * e.We;
   }
+  const bool narrow = e.cdf32 != nullptr;  // uniform; the compact copies hold the same values
   uint32_t g0[K], g1[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     g0[j] = g1[j] = 0u;
     if (valid[j]) {
       const uint32_t gc = (uint32_t)min(rem[j] >> tb.cshift[row[j]], (uint64_t)(e.We - 1));
-      const uint32_t* cg = e.guide + 2 * (int64_t)e.He + 2 + (int64_t)row[j] * (e.We + 1) + gc;
-      g0[j] = cg[0];
-      g1[j] = cg[1];
+      const int64_t at = (int64_t)row[j] * (e.We + 1) + gc;
+      if (narrow) {
+        g0[j] = e.col16[at];
+        g1[j] = e.col16[at + 1];
+      } else {
+        const uint32_t* cg = e.guide + 2 * (int64_t)e.He + 2 + at;
+        g0[j] = cg[0];
+        g1[j] = cg[1];
+      }
     }
   }
   bool more = false;
@@ -226,7 +234,6 @@ __device__ __forceinline__ void env_sample_k(const EnvView& e, const EnvTabs& tb
     cnt[j] = valid[j] ? max((int32_t)g1[j] - (int32_t)g0[j], 0) : 0;
     more |= cnt[j] > 0;
   }
-  const bool narrow = e.cdf32 != nullptr;  // uniform; the copy holds the same values
   while (more) {  // binary search over [lo, lo + cnt], one probe of every pick per round
     uint64_t v[K];
 #pragma unroll

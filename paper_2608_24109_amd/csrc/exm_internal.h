@@ -67,15 +67,19 @@ namespace exm {
 //   guide[1 .. He + 1]                row entries
 //   guide[He + 2 .. 2 He + 2)         shift of each row's column CDF
 //   guide[2 He + 2 + i (We + 1) + g]  column entries of row i
-// and, when We < kCdf32MaxW (a row total is at most We * 2^20 < 2^32), a 32-bit copy of cdf_col
-// that the column search reads instead of the 64-bit table (half the bytes per probe):
-//   guide[He (We + 3) + 2 + i We + j]  cdf_col[i][j]
+// and, when We < kCdf32MaxW (a row total is at most We * 2^20 < 2^32), compact copies that the
+// pick reads instead (fewer bytes per probe, tables that fit an L2 together):
+//   guide[He (We + 3) + 2 + i We + j]               cdf_col[i][j] as 32 bits
+//   16-bit entry i (We + 1) + g of the words after  column entry g of row i
 constexpr int32_t kCdf32MaxW = 4096;
-inline size_t env_guide_len(int32_t He, int32_t We) {
-  const size_t base = (size_t)He * (size_t)(We + 3) + 2;
-  return base + (We < kCdf32MaxW ? (size_t)He * (size_t)We : 0);
-}
 __host__ __device__ inline size_t env_cdf32_offset(int32_t He, int32_t We) { return (size_t)He * (size_t)(We + 3) + 2; }
+__host__ __device__ inline size_t env_col16_offset(int32_t He, int32_t We) {
+  return env_cdf32_offset(He, We) + (size_t)He * (size_t)We;
+}
+inline size_t env_guide_len(int32_t He, int32_t We) {
+  if (We >= kCdf32MaxW) return env_cdf32_offset(He, We);
+  return env_col16_offset(He, We) + ((size_t)He * (size_t)(We + 1) + 1) / 2;
+}
 
 // Brackets one kernel launch with HIP events on its stream when timing is enabled
 // (exm_timing_enable); names are string literals.

@@ -420,9 +420,11 @@ MeshView mesh_view(const exm_mesh* m) {
   return MeshView{m->nV, m->nF, m->pos, m->tri, m->uv, m->tri_uv, m->vnrm, m->ftan};
 }
 EnvView env_view(const exm_env* e) {
-  const uint32_t* c32 = e->We < kCdf32MaxW ? e->guide + env_cdf32_offset(e->He, e->We) : nullptr;
+  const bool narrow = e->We < kCdf32MaxW;
+  const uint32_t* c32 = narrow ? e->guide + env_cdf32_offset(e->He, e->We) : nullptr;
+  const uint16_t* g16 = narrow ? reinterpret_cast<const uint16_t*>(e->guide + env_col16_offset(e->He, e->We)) : nullptr;
   return EnvView{e->He,    e->We,    e->env, e->cdf_row, e->cdf_col, e->pdf,
-                 e->guide, reinterpret_cast<const float4*>(e->rec), c32};
+                 e->guide, reinterpret_cast<const float4*>(e->rec), c32, g16};
 }
 BvhView bvh_view(const exm_bvh* b) { return BvhView{b->nodes, b->tris, b->root_is_leaf}; }
 

@@ -140,8 +140,11 @@ def test_env_guide_and_records(lib, case):
     s, ref = _guide_ref(cr, He)
     assert gd[0] == s and np.array_equal(gd[1:He + 2], ref)
     cols = gd[2 * He + 2:He * (We + 3) + 2].reshape(He, We + 1)
-    # the 32-bit copy of the column CDF that the pick's column search reads
-    assert np.array_equal(gd[He * (We + 3) + 2:], cc.reshape(-1).astype(np.int64))
+    # the compact copies the pick reads: the column CDF in 32 bits, the column entries in 16
+    o32 = He * (We + 3) + 2
+    assert np.array_equal(gd[o32:o32 + He * We], cc.reshape(-1).astype(np.int64))
+    e16 = d.guide.cpu().numpy()[o32 + He * We:].view(np.uint16)[:He * (We + 1)]
+    assert np.array_equal(e16.astype(np.int64), cols.reshape(-1))
     for i in range(He):
         si, ri = _guide_ref(cc[i], We)
         assert gd[He + 2 + i] == si and np.array_equal(cols[i], ri), f"row {i}"
