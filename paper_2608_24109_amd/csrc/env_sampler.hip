@@ -6,8 +6,8 @@
 //   cdf_col = inclusive prefix inside a row, cdf_row = inclusive prefix of row totals,
 //   pdf_ij = q_ij / (Q Omega_i).
 // Two derived tables speed up sampling without changing any pick: the cutpoint tables over
-// cdf_row and each row of cdf_col, with compact copies (cdf_col in 32 bits, column entries in 16)
-// for maps narrower than 4096 texels (their layout is described with env_guide_len), and a packed
+// cdf_row and each row of cdf_col, with compact copies (cdf_col in 32 and 16 bits, column entries
+// in 16) for maps narrower than 4096 texels (their layout is described with env_guide_len), and a packed
 // record per texel (E_ij, 1/pdf_ij) so that a pick reads one 16-byte record.
 // Weights are computed in FP64 without FMA contraction so that the integer tables are the
 // exact function of the map. No workspace: intermediate values live in the output buffers
@@ -166,8 +166,12 @@ __global__ __launch_bounds__(kThreads) void k_guide_cols(int32_t He, int32_t We,
   const uint32_t entry = (uint32_t)min(upper_bound_u64(row, We, (uint64_t)g << s), We - 1);
   guide[2 * (int64_t)He + 2 + k] = entry;
   if (We < kCdf32MaxW) {  // compact copies: the column CDF in 32 bits (row totals < 2^32), entries in 16
-    if (g < We) guide[env_cdf32_offset(He, We) + (int64_t)i * We + g] = (uint32_t)row[g];
     reinterpret_cast<uint16_t*>(guide + env_col16_offset(He, We))[k] = (uint16_t)entry;
+    if (g < We) {
+      const int64_t t = (int64_t)i * We + g;
+      guide[env_cdf32_offset(He, We) + t] = (uint32_t)row[g];
+      reinterpret_cast<uint16_t*>(guide + env_cdf16_offset(He, We))[t] = (uint16_t)(row[g] - 1u);
+    }
   }
 }
 

@@ -83,6 +83,7 @@ struct EnvView {
   const float4* rec;      // per texel (E.r, E.g, E.b, 1/pdf)
   const uint32_t* cdf32;  // 32-bit copy of cdf_col inside guide, or null for maps too wide for it
   const uint16_t* col16;  // 16-bit copy of the column entries inside guide (null with cdf32)
+  const uint16_t* cdf16;  // (cdf_col - 1) mod 2^16 inside guide (null with cdf32)
 };
 
 struct EnvSample {
@@ -210,12 +211,15 @@ __device__ __forceinline__ void env_sample_k(const EnvView& e, const EnvTabs& tb
     cbase[j] = (int64_t)r * e.We;
   }
   const bool narrow = e.cdf32 != nullptr;  // uniform; the compact copies hold the same values
-  uint32_t g0[K], g1[K];
+  uint32_t g0[K], g1[K], mask16[K];  // mask16: 2^s - 1 for a row whose shift s is at most 16, else 0
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     g0[j] = g1[j] = 0u;
+    mask16[j] = 0u;
     if (valid[j]) {
-      const uint32_t gc = (uint32_t)min(rem[j] >> tb.cshift[row[j]], (uint64_t)(e.We - 1));
+      const uint32_t cs = tb.cshift[row[j]];
+      if (narrow && cs <= 16u) mask16[j] = (1u << cs) - 1u;
+      const uint32_t gc = (uint32_t)min(rem[j] >> cs, (uint64_t)(e.We - 1));
       const int64_t at = (int64_t)row[j] * (e.We + 1) + gc;
       if (narrow) {
         g0[j] = e.col16[at];
@@ -235,19 +239,23 @@ __device__ __forceinline__ void env_sample_k(const EnvView& e, const EnvTabs& tb
     more |= cnt[j] > 0;
   }
   while (more) {  // binary search over [lo, lo + cnt], one probe of every pick per round
-    uint64_t v[K];
+    bool le[K];  // cdf_col[probe] <= rem
 #pragma unroll
     for (int j = 0; j < K; ++j)
       if (cnt[j] > 0) {
         const int64_t at = cbase[j] + lo[j] + (cnt[j] >> 1);
-        v[j] = narrow ? (uint64_t)e.cdf32[at] : e.cdf_col[at];
+        // a row with shift 0 (mask16 0, every probe above rem) takes the 32-bit path
+        if (mask16[j] != 0u)
+          le[j] = ((uint32_t)e.cdf16[at] & mask16[j]) < ((uint32_t)rem[j] & mask16[j]);
+        else
+          le[j] = (narrow ? (uint64_t)e.cdf32[at] : e.cdf_col[at]) <= rem[j];
       }
     more = false;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
       if (cnt[j] > 0) {
         const int32_t step = cnt[j] >> 1;
-        if (v[j] <= rem[j]) {
+        if (le[j]) {
           lo[j] += step + 1;
           cnt[j] -= step + 1;
         } else {

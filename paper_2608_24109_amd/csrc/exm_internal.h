@@ -71,14 +71,21 @@ namespace exm {
 // pick reads instead (fewer bytes per probe, tables that fit an L2 together):
 //   guide[He (We + 3) + 2 + i We + j]               cdf_col[i][j] as 32 bits
 //   16-bit entry i (We + 1) + g of the words after  column entry g of row i
+//   16-bit entry i We + j of the words after        (cdf_col[i][j] - 1) mod 2^16
+// The last table decides a probe of a row whose column shift s is at most 16 on its own: a probe
+// inside key t's bucket g = t >> s reads a value c with g 2^s < c <= (g + 1) 2^s, so c <= t holds
+// exactly when (c - 1) mod 2^s < t mod 2^s.
 constexpr int32_t kCdf32MaxW = 4096;
 __host__ __device__ inline size_t env_cdf32_offset(int32_t He, int32_t We) { return (size_t)He * (size_t)(We + 3) + 2; }
 __host__ __device__ inline size_t env_col16_offset(int32_t He, int32_t We) {
   return env_cdf32_offset(He, We) + (size_t)He * (size_t)We;
 }
+__host__ __device__ inline size_t env_cdf16_offset(int32_t He, int32_t We) {
+  return env_col16_offset(He, We) + ((size_t)He * (size_t)(We + 1) + 1) / 2;
+}
 inline size_t env_guide_len(int32_t He, int32_t We) {
   if (We >= kCdf32MaxW) return env_cdf32_offset(He, We);
-  return env_col16_offset(He, We) + ((size_t)He * (size_t)(We + 1) + 1) / 2;
+  return env_cdf16_offset(He, We) + ((size_t)He * (size_t)We + 1) / 2;
 }
 
 // Brackets one kernel launch with HIP events on its stream when timing is enabled

@@ -423,8 +423,9 @@ EnvView env_view(const exm_env* e) {
   const bool narrow = e->We < kCdf32MaxW;
   const uint32_t* c32 = narrow ? e->guide + env_cdf32_offset(e->He, e->We) : nullptr;
   const uint16_t* g16 = narrow ? reinterpret_cast<const uint16_t*>(e->guide + env_col16_offset(e->He, e->We)) : nullptr;
+  const uint16_t* c16 = narrow ? reinterpret_cast<const uint16_t*>(e->guide + env_cdf16_offset(e->He, e->We)) : nullptr;
   return EnvView{e->He,    e->We,    e->env, e->cdf_row, e->cdf_col, e->pdf,
-                 e->guide, reinterpret_cast<const float4*>(e->rec), c32, g16};
+                 e->guide, reinterpret_cast<const float4*>(e->rec), c32, g16, c16};
 }
 BvhView bvh_view(const exm_bvh* b) { return BvhView{b->nodes, b->tris, b->root_is_leaf}; }
 

@@ -171,10 +171,10 @@ def test_env_sampler_and_bvh_validation(L):
     assert f(a, 4, 8, a, a, a, None, a, None) == L.EXM_E_INVAL
     assert f(a, 4, 8, a, a, a, a, 0x1008, None) == L.EXM_E_INVAL
     # cutpoint tables: row shift + (He + 1) row entries + He column shifts + He (We + 1) entries
-    # cutpoint tables, then for maps narrower than 4096 texels the column CDF in 32 bits and the
-    # column entries in 16
-    assert L.exm_env_guide_len(512, 1024) == 1 + 513 + 512 + 512 * 1025 + 512 * 1024 + 512 * 1025 // 2
-    assert L.exm_env_guide_len(7, 13) == 1 + 8 + 7 + 7 * 14 + 7 * 13 + (7 * 14 + 1) // 2
+    # cutpoint tables, then for maps narrower than 4096 texels the column CDF in 32 bits, the
+    # column entries in 16 and the column CDF's low 16 bits
+    assert L.exm_env_guide_len(512, 1024) == 1 + 513 + 512 + 512 * 1025 + 512 * 1024 + 512 * 1025 // 2 + 512 * 512
+    assert L.exm_env_guide_len(7, 13) == 1 + 8 + 7 + 7 * 14 + 7 * 13 + (7 * 14 + 1) // 2 + (7 * 13 + 1) // 2
     assert L.exm_env_guide_len(4, 4096) == 1 + 5 + 4 + 4 * 4097
     assert L.exm_env_guide_len(0, 8) == 0
     pos = np.zeros((3, 3), np.float32)

@@ -143,8 +143,11 @@ def test_env_guide_and_records(lib, case):
     # the compact copies the pick reads: the column CDF in 32 bits, the column entries in 16
     o32 = He * (We + 3) + 2
     assert np.array_equal(gd[o32:o32 + He * We], cc.reshape(-1).astype(np.int64))
-    e16 = d.guide.cpu().numpy()[o32 + He * We:].view(np.uint16)[:He * (We + 1)]
+    o16 = o32 + He * We
+    e16 = d.guide.cpu().numpy()[o16:].view(np.uint16)[:He * (We + 1)]
     assert np.array_equal(e16.astype(np.int64), cols.reshape(-1))
+    c16 = d.guide.cpu().numpy()[o16 + (He * (We + 1) + 1) // 2:].view(np.uint16)[:He * We]
+    assert np.array_equal(c16.astype(np.int64), (cc.reshape(-1).astype(np.int64) - 1) & 0xFFFF)
     for i in range(He):
         si, ri = _guide_ref(cc[i], We)
         assert gd[He + 2 + i] == si and np.array_equal(cols[i], ri), f"row {i}"
@@ -341,6 +344,25 @@ def test_indirect_small_tori_full_frame(small_tori, lib, no_sec_mat):
     assert (Li > 0).mean() > 0.05  # interreflection actually happens
     for v in range(2):
         _compare_view(small_tori, sc.cams[v], p, b, v, v)
+
+
+def test_direct_smooth_env_both_column_paths():
+    """A nearly constant env map: its equator rows have column shifts near 20 (their probes read
+    the 32-bit column CDF) and its polar rows small ones (probes decided by the 16-bit residues);
+    picks, visibility bits and radiance match the oracle on the whole frame."""
+    sc = I.config("small")
+    rng = np.random.default_rng(5)
+    sc.env = (1.0 + 0.05 * rng.random((sc.env.shape[0], sc.env.shape[1], 3))).astype(np.float32)
+    dev = Dev(sc)
+    cr = dev.env.cdf_row.cpu().numpy()
+    tot = np.diff(np.concatenate([[0], cr.astype(np.int64)]))
+    We = sc.env.shape[1]
+    shift = np.array([next(k for k in range(64) if ((int(t) - 1) >> k) <= We - 1) for t in tot])
+    assert shift.max() > 16 and shift.min() <= 16, shift
+    p = dev.params()
+    log(f"[direct] smooth env, column shifts {shift.min()}..{shift.max()}")
+    _, b = dev.forward(sc.cams, p)
+    _compare_view(dev, sc.cams[0], p, b, 0, 0)
 
 
 def test_ragged_views_direct(small):
