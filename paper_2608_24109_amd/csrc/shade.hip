@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kThreads) void k_dir_gen(MeshView M, TexView T, Env
       if (ok[j]) dr[j] = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)(k0 + j), 0u);
     }
     // records are read only for the picks above the shading hemisphere: the others are dropped
-    // whatever their records hold (two thirds of all picks on the displaced sphere)
+    // whatever their records hold (half of all picks on the displaced sphere)
     env_sample_k<kPicks, false>(E, tb, dr, ok, es);
     bool need[kPicks];
     float cs[kPicks];
