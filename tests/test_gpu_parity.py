@@ -117,13 +117,13 @@ def _guide_ref(a: np.ndarray, n: int):
     return s, np.minimum(np.searchsorted(a, keys, side="right"), n - 1)
 
 
-@pytest.mark.parametrize("case", ["32x64", "512x1024", "7x13", "zeros", "one_bright", "1x2"])
+@pytest.mark.parametrize("case", ["32x64", "512x1024", "7x13", "zeros", "one_bright", "1x2", "4x4096"])
 def test_env_guide_and_records(lib, case):
     """The cutpoint tables and per-texel records that the pick reads are the stated functions
     of the CDF tables and the map, and every key's answer lies inside its bucket's range."""
     from paper_2608_24109_amd.scene import DeviceEnv
     shapes = {"32x64": (32, 64), "512x1024": (512, 1024), "7x13": (7, 13), "zeros": (8, 16),
-              "one_bright": (16, 32), "1x2": (1, 2)}
+              "one_bright": (16, 32), "1x2": (1, 2), "4x4096": (4, 4096)}
     He, We = shapes[case]
     env = I.env_map(He, We, 1.5, seed=2)
     if case == "zeros":
@@ -140,14 +140,16 @@ def test_env_guide_and_records(lib, case):
     s, ref = _guide_ref(cr, He)
     assert gd[0] == s and np.array_equal(gd[1:He + 2], ref)
     cols = gd[2 * He + 2:He * (We + 3) + 2].reshape(He, We + 1)
-    # the compact copies the pick reads: the column CDF in 32 bits, the column entries in 16
     o32 = He * (We + 3) + 2
-    assert np.array_equal(gd[o32:o32 + He * We], cc.reshape(-1).astype(np.int64))
-    o16 = o32 + He * We
-    e16 = d.guide.cpu().numpy()[o16:].view(np.uint16)[:He * (We + 1)]
-    assert np.array_equal(e16.astype(np.int64), cols.reshape(-1))
-    c16 = d.guide.cpu().numpy()[o16 + (He * (We + 1) + 1) // 2:].view(np.uint16)[:He * We]
-    assert np.array_equal(c16.astype(np.int64), (cc.reshape(-1).astype(np.int64) - 1) & 0xFFFF)
+    if We >= 4096:  # no compact copies: the pick reads cdf_col and the 32-bit cutpoints
+        assert len(gd) == o32
+    else:  # the compact copies the pick reads: the column CDF in 32 bits, the column entries in 16
+        assert np.array_equal(gd[o32:o32 + He * We], cc.reshape(-1).astype(np.int64))
+        o16 = o32 + He * We
+        e16 = d.guide.cpu().numpy()[o16:].view(np.uint16)[:He * (We + 1)]
+        assert np.array_equal(e16.astype(np.int64), cols.reshape(-1))
+        c16 = d.guide.cpu().numpy()[o16 + (He * (We + 1) + 1) // 2:].view(np.uint16)[:He * We]
+        assert np.array_equal(c16.astype(np.int64), (cc.reshape(-1).astype(np.int64) - 1) & 0xFFFF)
     for i in range(He):
         si, ri = _guide_ref(cc[i], We)
         assert gd[He + 2 + i] == si and np.array_equal(cols[i], ri), f"row {i}"
@@ -361,6 +363,20 @@ def test_direct_smooth_env_both_column_paths():
     assert shift.max() > 16 and shift.min() <= 16, shift
     p = dev.params()
     log(f"[direct] smooth env, column shifts {shift.min()}..{shift.max()}")
+    _, b = dev.forward(sc.cams, p)
+    _compare_view(dev, sc.cams[0], p, b, 0, 0)
+
+
+def test_direct_wide_env_map():
+    """An env map 4096 texels wide: the column search reads the 64-bit CDF and 32-bit cutpoints
+    (the compact copies exist only for narrower maps); picks, bits and radiance match the oracle."""
+    sc = I.config("small")
+    sc.env = I.env_map(8, 4096, 1.0, seed=9)
+    dev = Dev(sc)
+    from paper_2608_24109_amd import _lib as L
+    assert L.exm_env_guide_len(8, 4096) == 8 * (4096 + 3) + 2  # no compact copies
+    p = dev.params()
+    log("[direct] wide env 8x4096")
     _, b = dev.forward(sc.cams, p)
     _compare_view(dev, sc.cams[0], p, b, 0, 0)
 
