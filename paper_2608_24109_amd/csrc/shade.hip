@@ -32,7 +32,10 @@ namespace exm {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kPicks = 2;  // env picks in flight per thread
+// env picks in flight per thread in dir_gen and in the adjoint (on the displaced sphere, 3 or 4 in
+// dir_gen took 7.0 -> 7.5 / 8.6 ms, 4 in the adjoint 5.6 -> 9.8 ms)
+constexpr int kGenPicks = 2;
+constexpr int kBwdPicks = 2;
 
 struct KParams {
   int32_t N_d;
@@ -91,22 +94,22 @@ __global__ __launch_bounds__(kThreads) void k_dir_gen(MeshView M, TexView T, Env
   uint64_t mask = 0;
   uint32_t running = 0;  // wave-uniform
   const int64_t rbase = region * 64 * (int64_t)p.N_d;
-  for (int k0 = 0; k0 < p.N_d; k0 += kPicks) {
-    Draw dr[kPicks];
-    bool ok[kPicks];
-    EnvSample es[kPicks];
+  for (int k0 = 0; k0 < p.N_d; k0 += kGenPicks) {
+    Draw dr[kGenPicks];
+    bool ok[kGenPicks];
+    EnvSample es[kGenPicks];
 #pragma unroll
-    for (int j = 0; j < kPicks; ++j) {
+    for (int j = 0; j < kGenPicks; ++j) {
       ok[j] = f >= 0 && k0 + j < p.N_d;
       if (ok[j]) dr[j] = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)(k0 + j), 0u);
     }
     // records are read only for the picks above the shading hemisphere: the others are dropped
     // whatever their records hold (half of all picks on the displaced sphere)
-    env_sample_k<kPicks, false>(E, tb, dr, ok, es);
-    bool need[kPicks];
-    float cs[kPicks];
+    env_sample_k<kGenPicks, false>(E, tb, dr, ok, es);
+    bool need[kGenPicks];
+    float cs[kGenPicks];
 #pragma unroll
-    for (int j = 0; j < kPicks; ++j) {
+    for (int j = 0; j < kGenPicks; ++j) {
       need[j] = false;
       cs[j] = 0.0f;
       if (ok[j]) {
@@ -115,10 +118,10 @@ __global__ __launch_bounds__(kThreads) void k_dir_gen(MeshView M, TexView T, Env
       }
     }
 #pragma unroll
-    for (int j = 0; j < kPicks; ++j)
+    for (int j = 0; j < kGenPicks; ++j)
       if (need[j]) env_rec(E, es[j]);
 #pragma unroll
-    for (int j = 0; j < kPicks; ++j) {
+    for (int j = 0; j < kGenPicks; ++j) {
       const int k = k0 + j;
       if (k >= p.N_d) break;  // wave-uniform
       const float c = cs[j];
@@ -352,12 +355,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   SurfGrad G;
   G.a[0] = G.a[1] = G.a[2] = G.r = G.m = 0.0f;
   G.n = mk(0, 0, 0);
-  while (bits) {  // set bits in increasing order, kPicks at a time
-    Draw dr[kPicks];
-    bool ok[kPicks];
-    EnvSample es[kPicks];
+  while (bits) {  // set bits in increasing order, kBwdPicks at a time
+    Draw dr[kBwdPicks];
+    bool ok[kBwdPicks];
+    EnvSample es[kBwdPicks];
 #pragma unroll
-    for (int j = 0; j < kPicks; ++j) {
+    for (int j = 0; j < kBwdPicks; ++j) {
       ok[j] = bits != 0ull;
       if (ok[j]) {
         const int k = __ffsll((long long)bits) - 1;
@@ -365,9 +368,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         dr[j] = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)k, 0u);
       }
     }
-    env_sample_k<kPicks>(E, tb, dr, ok, es);
+    env_sample_k<kBwdPicks>(E, tb, dr, ok, es);
 #pragma unroll
-    for (int j = 0; j < kPicks; ++j) {
+    for (int j = 0; j < kBwdPicks; ++j) {
       if (!ok[j]) break;
       const float c = dot(S.ns, es[j].dir);
       const float s = invN * es[j].inv_pdf;
