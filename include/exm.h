@@ -140,8 +140,9 @@ size_t exm_bvh_device_bytes(const exm_bvh* bvh);
  * Also written, as functions of the tables and the map: `guide`, cutpoint tables that narrow
  * each inversion to a few entries without changing its result (Chen and Asau's guide-table
  * method), followed for We < 4096 by compact copies that the pick reads (cdf_col in uint32,
- * a row total being below 2^32 there, and the column cutpoints in uint16), and `rec`, the
- * packed per-texel record (E, 1/pdf) read by the pick. All outputs
+ * a row total being below 2^32 there; the column cutpoints in uint16; (cdf_col - 1) mod 2^16
+ * in uint16, which decides a search step in rows whose cutpoint buckets hold at most 2^16
+ * keys), and `rec`, the packed per-texel record (E, 1/pdf) read by the pick. All outputs
  * are caller-owned device buffers; cdf_row, cdf_col 8-byte, rec 16-byte aligned. The tables
  * describe the map at the time of the call: rebuild them after the map changes. Needs
  * He >= 1, 2 <= We, He*We <= 2^24; uses no workspace. */

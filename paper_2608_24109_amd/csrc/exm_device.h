@@ -82,8 +82,8 @@ struct EnvView {
   const uint32_t* guide;  // cutpoint tables over cdf_row and each row of cdf_col (layout below)
   const float4* rec;      // per texel (E.r, E.g, E.b, 1/pdf)
   const uint32_t* cdf32;  // 32-bit copy of cdf_col inside guide, or null for maps too wide for it
-  const uint16_t* col16;  // 16-bit copy of the column entries inside guide (null with cdf32)
-  const uint16_t* cdf16;  // (cdf_col - 1) mod 2^16 inside guide (null with cdf32)
+  const uint16_t* col16;  // 16-bit copy of the column entries inside guide (null when cdf32 is)
+  const uint16_t* cdf16;  // (cdf_col - 1) mod 2^16 inside guide (null when cdf32 is)
 };
 
 struct EnvSample {
