@@ -269,6 +269,7 @@ __device__ __forceinline__ void env_sample_k(const EnvView& e, const EnvTabs& tb
 #pragma unroll
   for (int j = 0; j < K; ++j)
     if (REC && valid[j]) rec[j] = e.rec[row[j] * e.We + min(lo[j], e.We - 1)];
+  const float two_over_We = 2.0f / (float)e.We;  // one division per call instead of one per pick
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     if (!valid[j]) continue;
@@ -291,7 +292,7 @@ __device__ __forceinline__ void env_sample_k(const EnvView& e, const EnvTabs& tb
     // phi = 2 pi (col + u2) / We by angle addition (keeps u2's resolution at large col)
     const float2 cj = tb.colc ? tb.colc[col] : env_col_consts(col, e.We);
     float sd, cd;
-    sincospif(2.0f * d[j].u2 / (float)e.We, &sd, &cd);
+    sincospif(d[j].u2 * two_over_We, &sd, &cd);
     const float cphi = cj.y * cd - cj.x * sd, sphi = cj.x * cd + cj.y * sd;
     s.dir = mk(st * cphi, ct, st * sphi);
     if (REC) {
