@@ -50,13 +50,16 @@ const char* exm_last_error(void);
  * NO_SECONDARY_MATERIAL is the "No Secondary Material" ablation of the Ablation Study
  * (Indirect Lighting): the maps are not queried at secondary hits, which are shaded as a grey
  * Lambertian (albedo 0.5, metallic 0) with the interpolated geometric normal; the adjoint then
- * sends nothing to the maps at secondary hits. */
+ * sends nothing to the maps at secondary hits. MAP_GRAD_ATOMIC makes the adjoints add the map
+ * gradient with one atomic per tap and channel at any map size, instead of the tiled reduction
+ * used for maps of at most 16,384 tiles of 64x32 texels (tests compare the two paths). */
 enum {
   EXM_METALLIC_OFF = 1u << 0,
   EXM_DIFFUSE_ONLY = 1u << 1,
   EXM_SPECULAR_ONLY = 1u << 2,
   EXM_NO_VIS = 1u << 3,
   EXM_NO_SECONDARY_MATERIAL = 1u << 4,
+  EXM_MAP_GRAD_ATOMIC = 1u << 5,
 };
 
 /* Fixed mesh-UV carrier M = (V, F), UV set U and face-corner UV index Phi (UV-PBR Asset
@@ -125,8 +128,11 @@ exm_status exm_mesh_prepare(const exm_mesh* m, hipStream_t stream);
 
 /* Binned-SAH BVH over the fixed triangles, built on the host and uploaded on `stream`
  * (ray queries for visibility and secondary hits: Direct Illumination, One-Bounce Indirect
- * Illumination). Host inputs; *out receives a handle. Returns EXM_E_NOMEM if device memory
- * runs out. exm_free_bvh waits for the stream work that uses the BVH to be done by the caller. */
+ * Illumination). Host inputs; *out receives a handle. At most 2^25 triangles: the builder bounds
+ * the depth at 24 so that the traversal's stack cannot overflow, which holds up to that size;
+ * larger meshes return EXM_E_UNSUPPORTED before anything is read. Returns EXM_E_NOMEM if device
+ * memory runs out. exm_free_bvh waits for the stream work that uses the BVH to be done by the
+ * caller. */
 exm_status exm_build_bvh(const float* pos_host, int32_t nV, const int32_t* tri_host, int32_t nF,
                          exm_bvh** out, hipStream_t stream);
 exm_status exm_free_bvh(exm_bvh* bvh);

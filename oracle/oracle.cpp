@@ -858,42 +858,82 @@ void ora_trace_any(const ora_mesh* m, const ora_bvh* b, int32_t n, const double*
                  : 0;
 }
 
-// Decision margins of one ray, brute force over all triangles except `skip`:
+// Decision margins of one ray, brute force over all triangles except `skip`. A decision of the
+// watertight test can only differ between two precisions where the ray passes close to a
+// triangle's boundary (the edge functions are near zero there) or where a hit lies close to
+// the start of the ray's range. Distances are measured in space along the part of the ray that
+// can matter, s >= s0 = tmin |d| - tol (s = distance from the origin):
 //  n_hits          number of triangles hit at t >= tmin
-//  max_hit_margin  max over hit triangles of min(distance of the hit point to the triangle's
-//                  boundary, |t - tmin|)            (small: every hit is fragile)
-//  min_margin      min over triangles whose plane is crossed at t >= tmin - tol of
-//                  min(distance of the crossing point to the triangle, |t - tmin|)
-//                                                    (small: some near miss could become a hit)
+//  max_hit_margin  max over hit triangles of min(distance from the ray to the triangle's
+//                  three edges, |t - tmin| |d|)          (small: every hit is fragile)
+//  min_margin      min over all triangles of the distance from the ray to their edges, and
+//                  over triangles whose interior the ray's line crosses, of |t - tmin| |d|
+//                                                        (small: some near miss could become a hit)
+// A triangle the ray does not come near contributes nothing small, whatever its plane does.
+namespace {
+// distance from point p to the segment a-b
+double point_segment_dist(D3 p, D3 a, D3 b) {
+  D3 ab = b - a;
+  double l2 = dot(ab, ab);
+  double w = l2 > 0 ? std::min(1.0, std::max(0.0, dot(p - a, ab) / l2)) : 0.0;
+  return norm(p - (a + mul(w, ab)));
+}
+// distance from point p to the ray o + s u (u unit), s >= s0
+double point_ray_dist(D3 p, D3 o, D3 u, double s0) {
+  double s = std::max(s0, dot(p - o, u));
+  return norm(p - (o + mul(s, u)));
+}
+// Minimum over s >= s0 and w in [0,1] of |o + s u - (a + w (b - a))|, u unit. The squared
+// distance is a convex quadratic in (s, w), so the minimum over this half-strip is the
+// unconstrained stationary point when it lies inside, and otherwise lies on one of the three
+// boundary pieces (s = s0, w = 0, w = 1), each a point-to-segment or point-to-ray distance.
+double ray_segment_dist(D3 o, D3 u, double s0, D3 a, D3 b) {
+  D3 e = b - a, r = o - a;
+  double best = std::min({point_segment_dist(o + mul(s0, u), a, b), point_ray_dist(a, o, u, s0),
+                          point_ray_dist(b, o, u, s0)});
+  // stationary point of |r + s u - w e|^2: [1, -u.e; -u.e, e.e] (s, w) = (-r.u, r.e)
+  double ue = dot(u, e), ee = dot(e, e);
+  double det = ee - ue * ue;
+  if (det > 1e-300 * ee) {
+    double ru = dot(r, u), re = dot(r, e);
+    double s = (-ru * ee + ue * re) / det;
+    double w = (re - ue * ru) / det;
+    if (s >= s0 && w >= 0.0 && w <= 1.0) best = std::min(best, norm((o + mul(s, u)) - (a + mul(w, e))));
+  }
+  return best;
+}
+}  // namespace
+
 void ora_ray_margins(const ora_mesh* m, const double o_[3], const double d_[3], double tmin, int32_t skip, double tol,
                      int32_t* n_hits, double* max_hit_margin, double* min_margin) {
   D3 o{o_[0], o_[1], o_[2]}, d{d_[0], d_[1], d_[2]};
+  const double dl = norm(d);
+  const D3 u = mul(1.0 / dl, d);
+  const double s0 = tmin * dl - tol;
   int32_t nh = 0;
   double mx = 0.0, mn = INFINITY;
-  auto seg_dist = [](D3 p, D3 a, D3 b) {
-    D3 ab = b - a;
-    double t = std::min(1.0, std::max(0.0, dot(p - a, ab) / dot(ab, ab)));
-    return norm(p - (a + mul(t, ab)));
-  };
   for (int32_t f = 0; f < m->nF; ++f) {
     if (f == skip) continue;
     D3 p0 = vtx(m, m->tri[3 * f]), p1 = vtx(m, m->tri[3 * f + 1]), p2 = vtx(m, m->tri[3 * f + 2]);
+    double edge = std::min({ray_segment_dist(o, u, s0, p0, p1), ray_segment_dist(o, u, s0, p1, p2),
+                            ray_segment_dist(o, u, s0, p2, p0)});
+    mn = std::min(mn, edge);
     D3 nrm = cross(p1 - p0, p2 - p0);
     double den = dot(nrm, d);
     if (den == 0.0) continue;
     double t = dot(nrm, p0 - o) / den;
-    if (t < tmin - tol) continue;
     D3 x = o + mul(t, d);
     double a2 = dot(nrm, nrm);
     double b0 = dot(cross(p1 - x, p2 - x), nrm) / a2;
     double b1 = dot(cross(p2 - x, p0 - x), nrm) / a2;
     double b2 = dot(cross(p0 - x, p1 - x), nrm) / a2;
-    bool inside = b0 >= 0 && b1 >= 0 && b2 >= 0;
-    double dist = std::min({seg_dist(x, p1, p2), seg_dist(x, p2, p0), seg_dist(x, p0, p1)});
-    double marg = std::min(dist, std::fabs(t - tmin));
-    if (inside && t >= tmin) { ++nh; mx = std::max(mx, marg); }
-    if (inside) mn = std::min(mn, std::fabs(t - tmin));
-    mn = std::min(mn, marg);
+    if (!(b0 >= 0 && b1 >= 0 && b2 >= 0)) continue;  // the line misses the interior
+    double dt = std::fabs(t - tmin) * dl;
+    mn = std::min(mn, dt);
+    if (t >= tmin) {
+      ++nh;
+      mx = std::max(mx, std::min(edge, dt));
+    }
   }
   *n_hits = nh;
   *max_hit_margin = mx;

@@ -25,6 +25,7 @@ EXM_DIFFUSE_ONLY = 1 << 1
 EXM_SPECULAR_ONLY = 1 << 2
 EXM_NO_VIS = 1 << 3
 EXM_NO_SECONDARY_MATERIAL = 1 << 4
+EXM_MAP_GRAD_ATOMIC = 1 << 5
 
 EXM_TOPO_NO_SPLIT = 1 << 0
 EXM_TOPO_NO_MERGE = 1 << 1

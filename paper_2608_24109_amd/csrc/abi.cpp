@@ -100,7 +100,7 @@ exm_status check_params(const exm_params* p, bool indirect) {
   if (!std::isfinite(p->tmin) || p->tmin < 0.f) return fail(EXM_E_INVAL, "tmin must be finite and >= 0");
   if (!std::isfinite(p->eps) || p->eps < 0.f) return fail(EXM_E_INVAL, "eps must be finite and >= 0");
   if (!std::isfinite(p->f_diel)) return fail(EXM_E_INVAL, "f_diel must be finite");
-  if (p->flags & ~0x1Fu) return fail(EXM_E_INVAL, "unknown flag bits");
+  if (p->flags & ~0x3Fu) return fail(EXM_E_INVAL, "unknown flag bits");
   return EXM_OK;
 }
 
@@ -163,7 +163,9 @@ exm_status exm_build_bvh(const float* pos_host, int32_t nV, const int32_t* tri_h
   if (!out) return fail(EXM_E_INVAL, "out is NULL");
   *out = nullptr;
   if (!pos_host || (nF > 0 && !tri_host)) return fail(EXM_E_INVAL, "host mesh arrays are NULL");
-  if (nV <= 0 || nF < 0 || nF >= (1 << 27)) return fail(EXM_E_INVAL, "bad mesh sizes");
+  if (nV <= 0 || nF < 0) return fail(EXM_E_INVAL, "bad mesh sizes");
+  if (nF > kMaxBvhTris)
+    return fail(EXM_E_UNSUPPORTED, "exm_build_bvh: more than 2^25 triangles (the BVH depth bound of the traversal stack)");
   for (int64_t i = 0; i < 3 * (int64_t)nF; ++i)
     if (tri_host[i] < 0 || tri_host[i] >= nV) return fail(EXM_E_INVAL, "triangle vertex index out of range");
   for (int64_t i = 0; i < 3 * (int64_t)nV; ++i)
@@ -172,6 +174,10 @@ exm_status exm_build_bvh(const float* pos_host, int32_t nV, const int32_t* tri_h
   HostBvh hb{};
   std::string err;
   if (!build_bvh_host(pos_host, nV, tri_host, nF, &hb, &err)) return fail(EXM_E_NOMEM, err);
+  if (hb.depth > kMaxDepth) {
+    free_bvh_host(&hb);
+    return fail(EXM_E_UNSUPPORTED, "exm_build_bvh: BVH deeper than the traversal stack");
+  }
   exm_bvh* b = new exm_bvh;
   b->n_nodes = hb.n_nodes;
   b->n_tris = hb.n_tris;

@@ -30,6 +30,9 @@ static_assert(sizeof(BvhTri) == 48, "triangle layout");
 
 constexpr int kMaxDepth = 24;  // builder guarantee; traversal stack holds <= kMaxDepth refs
 constexpr int kStack = 25;  // 24 deferred references (the depth bound) + the bottom sentinel
+// The builder's depth bound holds while need(nF) <= kMaxDepth, i.e. for at most 2 * 2^kMaxDepth
+// triangles (2^25); larger meshes would put leaves below the bound and overflow the stack.
+constexpr int64_t kMaxBvhTris = (int64_t)2 << kMaxDepth;
 
 // Views per launch: camera data travels in kernel arguments.
 constexpr int kViewsPerLaunch = 8;

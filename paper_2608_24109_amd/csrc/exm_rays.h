@@ -26,8 +26,11 @@ struct RayBatch {
   uint32_t* region_counter;  // workspace word, reset by the launcher
 };
 
-int32_t ray_refill_threshold();
-int32_t trav_leaf_gate();
+// A persistent traversal wave refills once fewer than kRayRefill lanes still traverse, and a
+// round's node phase hands over to its leaf phase once fewer than kTravLeafGate lanes lack a
+// postponed leaf (both swept on the displaced sphere and the tori: 32 and 8).
+constexpr int32_t kRayRefill = 32;
+constexpr int32_t kTravLeafGate = 8;
 // any-hit: out[slot] = 1 if something is hit at t >= tmin (the skipped triangle excepted)
 hipError_t launch_trace_any(const exm_bvh* bvh, const RayBatch& rb, uint8_t* out, unsigned long long* counters,
                             hipStream_t s);

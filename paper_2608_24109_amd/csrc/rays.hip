@@ -121,33 +121,13 @@ hipError_t launch_impl(const exm_bvh* bvh, const RayBatch& rb, HitRec* out_hit, 
   {
     EXM_TIMED(ANY ? "trace_any" : "trace_closest", s);
     k_trace<ANY, COUNT><<<(unsigned)blocks, kThreads, 0, s>>>(BvhView{bvh->nodes, bvh->tris, bvh->root_is_leaf}, rb,
-                                                               ray_refill_threshold(), trav_leaf_gate(), out_hit,
+                                                               kRayRefill, kTravLeafGate, out_hit,
                                                                out_any, counters);
   }
   return hipGetLastError();
 }
 
 }  // namespace
-
-// The node phase of a traversal round hands over to the leaf phase once fewer than this many
-// lanes still lack a postponed leaf (EXM_TRAV_LEAF_GATE, 1..64).
-int32_t trav_leaf_gate() {
-  static const int32_t v = [] {
-    const char* e = getenv("EXM_TRAV_LEAF_GATE");
-    const int x = e ? atoi(e) : 0;
-    return (x >= 1 && x <= 64) ? x : 8;
-  }();
-  return v;
-}
-
-int32_t ray_refill_threshold() {
-  static const int32_t v = [] {
-    const char* e = getenv("EXM_RAY_REFILL");
-    const int x = e ? atoi(e) : 0;
-    return (x >= 1 && x <= 64) ? x : 32;
-  }();
-  return v;
-}
 
 hipError_t launch_trace_any(const exm_bvh* bvh, const RayBatch& rb, uint8_t* out, unsigned long long* counters,
                             hipStream_t s) {

@@ -484,7 +484,7 @@ hipError_t launch_shade_bwd(const exm_mesh* m, const exm_material* mat, const ex
   const size_t lds = env_tabs_bytes(env->He, env->We);
   const bool use_lds = lds <= kEnvTabsMaxBytes;
   const KParams kp = kparams(p);
-  const bool tiled = tex_grad_tiled(mat->Ht, mat->Wt) && tex_grad_enabled();
+  const bool tiled = tex_grad_tiled(mat->Ht, mat->Wt) && !(p->flags & EXM_MAP_GRAD_ATOMIC);
   for (int64_t p0 = 0; p0 < n; p0 += P) {
     const int64_t Pc = std::min<int64_t>(P, ((n - p0) + 63) / 64 * 64);
     const EnvGradWs eg = env_grad_ws(ws, Pc * per_px, env->He, env->We);

@@ -58,12 +58,6 @@ inline bool tex_grad_tiled(int32_t Ht, int32_t Wt) {
   return Ht > 0 && Wt > 0 && tex_grad_buckets(Ht, Wt) <= kTexMaxBuckets;
 }
 
-// EXM_TEX_GRAD_TILED=0 makes the adjoint scatter with atomics at any map size (read at every call;
-// the tests compare the two paths with it)
-inline bool tex_grad_enabled() {
-  const char* e = getenv("EXM_TEX_GRAD_TILED");
-  return !(e && e[0] == '0');
-}
 
 inline size_t tg_align256(size_t x) { return (x + 255) & ~(size_t)255; }
 

@@ -50,9 +50,9 @@ def explain_flips(om, cam, tab, tex, env, pix, idx, stream, gpu_bit, diag, **kw)
             ok[i] = True
             continue
         nh, mx, mn = O.ray_margins(om, o[i], d[i], kw.get("tmin", 0.0), int(sk[i]), tol)
-        if gpu_bit[i]:  # GPU saw no occluder: every oracle hit must be fragile, or a near miss
-            ok[i] = (nh > 0 and mx < tol) or mn < tol
-        else:           # GPU saw an occluder the oracle did not: some near miss
+        if gpu_bit[i]:  # GPU saw no occluder: every hit the oracle's ray has must be fragile
+            ok[i] = mx < tol if nh > 0 else mn < tol
+        else:           # GPU saw an occluder (or another closest hit) the oracle did not: a near miss
             ok[i] = mn < tol
     return ok
 

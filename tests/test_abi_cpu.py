@@ -187,6 +187,11 @@ def test_env_sampler_and_bvh_validation(L):
     assert L.lib.exm_build_bvh(pos.ctypes.data, 3, tri.ctypes.data, 1, C.byref(out), None) == L.EXM_E_INVAL
     assert L.lib.exm_free_bvh(None) == L.EXM_OK
     assert L.lib.exm_bvh_device_bytes(None) == 0
+    # the depth bound (24 deferred references) holds up to 2 * 2^24 triangles; beyond it the
+    # build is refused before the index arrays are read (these hold one triangle only)
+    big = (2 << 24) + 1
+    assert L.lib.exm_build_bvh(pos.ctypes.data, 3, tri.ctypes.data, big, C.byref(out), None) == L.EXM_E_UNSUPPORTED
+    assert "2^25" in L.last_error() and not out.value
 
 
 def _topo(L, nV=3, nF=1, nUV=3, cap=(4, 3, 5), ptr=0x1000):

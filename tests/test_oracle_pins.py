@@ -231,6 +231,27 @@ def test_neutral_normal_map_gives_geometry_normal_and_tangent_orientation():
     assert np.allclose(ns, [0, -s, s], atol=1e-14)
 
 
+def test_vertex_normals_are_area_weighted():
+    """Attribute Query interpolates the geometry normal from vertex normals; the reading taken is
+    the normalised sum of the incident faces' (P1-P0)x(P2-P0), i.e. weighted by face area. Two
+    faces of areas 2 and 1 meet at a right angle along the edge v0-v2: at v0 and v2 the
+    area-weighted normal is (1,0,2)/sqrt(5), where an unweighted sum gives (1,0,1)/sqrt(2) and an
+    angle-weighted one (at v2: angles 45 deg and atan(1/2)) another value."""
+    pos = np.array([[0, 0, 0], [2, 0, 0], [0, 2, 0], [0, 0, 1]], dtype=np.float32)
+    tri = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)   # normals (0,0,4) and (2,0,0)
+    m = O.OracleMesh(pos, tri, np.zeros((6, 2), np.float32), np.arange(6, dtype=np.int32).reshape(2, 3),
+                     with_bvh=False)
+    vn = O.vertex_normals(m)
+    w = np.array([1.0, 0.0, 2.0]) / math.sqrt(5.0)
+    expect = np.array([w, [0, 0, 1], w, [1, 0, 0]])
+    assert np.abs(vn - expect).max() <= 1e-15
+    unweighted = np.array([1.0, 0.0, 1.0]) / math.sqrt(2.0)
+    a45, a27 = math.pi / 4, math.atan(0.5)
+    angle_weighted = np.array([a27, 0.0, a45]) / math.hypot(a27, a45)
+    for other in (unweighted, angle_weighted):
+        assert np.abs(other - w).max() > 1e-3  # the pin tells the three readings apart
+
+
 # ------------------------------------------------------------------------------------------
 # BRDF (Direct Illumination, Eq. 13-16)
 # ------------------------------------------------------------------------------------------
@@ -366,6 +387,20 @@ def test_philox_uniform_and_decorrelated():
     assert 32 < flips < 96  # one counter bit changes about half the output bits
 
 
+def test_philox_known_answer_vectors():
+    """Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): the known-answer vectors published
+    with the authors' Random123 library (counter and key all zero, all ones, and the digits of pi).
+    A wrong round count, multiplier, Weyl constant or output word order fails them."""
+    kat = [
+        ([0, 0, 0, 0], [0, 0], [0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8]),
+        ([0xffffffff] * 4, [0xffffffff] * 2, [0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd]),
+        ([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344], [0xa4093822, 0x299f31d0],
+         [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1]),
+    ]
+    for ctr, key, expect in kat:
+        assert [int(x) for x in O.philox(ctr, key)] == expect
+
+
 # ------------------------------------------------------------------------------------------
 # BVH and ray queries (visibility in Eq. 12/17, secondary hits in Eq. 19)
 # ------------------------------------------------------------------------------------------
@@ -406,6 +441,60 @@ def _const_scene(pos, tri, albedo, L, He=16, We=32, Ht=8, Wt=8):
     tex[..., 7] = 1.0
     env = np.full((He, We, 3), L, dtype=np.float32)
     return O.OracleMesh(pos, tri, uv, tuv), tex, env
+
+
+def _margin_mesh(P, T):
+    P = np.asarray(P, np.float32)
+    T = np.asarray(T, np.int32)
+    return O.OracleMesh(P, T, np.zeros((3 * len(T), 2), np.float32), np.arange(3 * len(T), dtype=np.int32).reshape(-1, 3),
+                        with_bvh=False)
+
+
+def test_ray_margins_hand_computed():
+    """The flip-accounting margins (a visibility decision of Eq. 12/17 or a secondary hit of
+    Eq. 19 can only differ between FP32 and FP64 near a triangle boundary or near t_min) against
+    distances worked out by hand on one triangle (0,0,0), (1,0,0), (0,1,0) in z = 0."""
+    m = _margin_mesh([[0, 0, 0], [1, 0, 0], [0, 1, 0]], [[0, 1, 2]])
+    down = [0.0, 0.0, -1.0]
+    # interior hit at t = 1: edges at 0.3 (y = 0), 0.25 (x = 0), 0.45/sqrt(2) (x + y = 1)
+    nh, mx, mn = O.ray_margins(m, [0.25, 0.3, 1.0], down, 0.1, -1, 1e-5)
+    assert nh == 1 and mx == pytest.approx(0.25, abs=1e-12) and mn == pytest.approx(0.25, abs=1e-12)
+    # a miss passing 0.01 outside the edge x = 0
+    nh, mx, mn = O.ray_margins(m, [-0.01, 0.5, 1.0], down, 0.1, -1, 1e-5)
+    assert nh == 0 and mn == pytest.approx(0.01, abs=1e-12)
+    # a hit at t = t_min + 1e-6, far from every edge
+    nh, mx, mn = O.ray_margins(m, [0.25, 0.3, 1.0], down, 1.0 - 1e-6, -1, 1e-7)
+    assert nh == 1 and mx == pytest.approx(1e-6, rel=1e-6) and mn == pytest.approx(1e-6, rel=1e-6)
+    # just before t_min: no hit, but the crossing is 1e-6 away from becoming one
+    nh, mx, mn = O.ray_margins(m, [0.25, 0.3, 1.0], down, 1.0 + 1e-6, -1, 1e-5)
+    assert nh == 0 and mn == pytest.approx(1e-6, rel=1e-6)
+    # a ray parallel to the plane, 0.002 above it, crossing over the edges x = 0 and x + y = 1
+    nh, mx, mn = O.ray_margins(m, [-1.0, 0.5, 0.002], [1.0, 0.0, 0.0], 0.0, -1, 1e-5)
+    assert nh == 0 and mn == pytest.approx(0.002, abs=1e-12)
+    # the same edge lies on the ray's line only behind its origin: the half-line stays 0.01 away
+    nh, mx, mn = O.ray_margins(m, [-0.01, 0.5, 0.0], [-1.0, 0.0, 0.0], 0.0, -1, 1e-5)
+    assert nh == 0 and mn == pytest.approx(0.01 - 1e-5, abs=1e-12)
+    # a skipped triangle counts for nothing
+    nh, mx, mn = O.ray_margins(m, [-0.01, 0.5, 1.0], down, 0.1, 0, 1e-5)
+    assert nh == 0 and mn == math.inf
+
+
+def test_ray_margins_do_not_excuse_distant_occluders_or_planes():
+    """A solid, distant occluder is not fragile; and a triangle whose plane the ray crosses right
+    at t_min, far from the triangle itself, is not a near miss."""
+    # origin triangle (skipped) at z = 0, a large occluder at z = 5
+    m = _margin_mesh([[0, 0, 0], [1, 0, 0], [0, 1, 0], [-10, -10, 5], [10, -10, 5], [0, 10, 5]],
+                     [[0, 1, 2], [3, 4, 5]])
+    nh, mx, mn = O.ray_margins(m, [0.2, 0.2, 0.0], [0.0, 0.0, 1.0], 1e-4, 0, 1e-5)
+    assert nh == 1 and mx > 1.0 and mn > 1.0
+    # the plane z = 0 of a far triangle is crossed at t = t_min exactly, 10 units from it
+    tmin = 0.01
+    d = np.array([1.0, 0.0, -0.01])
+    d /= np.linalg.norm(d)
+    o = np.array([0.0, 0.0, -tmin * d[2]])   # above the plane, so that o + tmin d lies on it
+    far = _margin_mesh([[10, 0, 0], [11, 0, 0], [10, 1, 0]], [[0, 1, 2]])
+    nh, mx, mn = O.ray_margins(far, o, d, tmin, -1, 1e-5)
+    assert nh == 0 and mn > 0.05
 
 
 def test_white_furnace_diffuse_quad():
