@@ -1,0 +1,101 @@
+"""Checks run in a child process whose host code is built with AddressSanitizer and
+UndefinedBehaviorSanitizer (the child is started by tests/test_host_sanitizers.py with the
+sanitizer runtime preloaded). Usage:
+
+    python sanitized_checks.py oracle  <liboracle_san.so> <out.npz>
+    python sanitized_checks.py abi     <libexm_san.so>
+    python sanitized_checks.py bvh     <bvh_check_san.so>
+
+`oracle` renders the small scenes with the sanitized oracle and saves every output, so the
+parent can compare them bitwise with the regular build; `abi` runs the CPU validation tests of
+the C ABI against the sanitized host layer; `bvh` runs the host BVH builder's invariant checks.
+A sanitizer finding aborts the child with a non-zero status."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+sys.path.insert(0, HERE)
+
+
+def oracle_outputs(O, I) -> dict:
+    """Every oracle output the parity tests use, on two small scenes (direct with a JVP; direct +
+    indirect), plus tables, raster, ray queries and margins."""
+    res = {}
+    sc = I.config("small")
+    om = O.OracleMesh(sc.pos, sc.tri, sc.uv, sc.tri_uv)
+    tab = O.EnvTables(sc.env)
+    res["env_q"], res["env_pdf"] = tab.q, tab.pdf
+    ids, bary = O.raster(om, sc.cams[0])
+    res["ids"], res["bary"] = ids, bary
+    res["vnrm"], res["ftan"] = O.vertex_normals(om), O.face_tangents(om)
+    rng = np.random.default_rng(5)
+    r = O.render(om, sc.cams[0], tab, sc.tex, sc.env, N_d=16, seed=sc.seed, tmin=sc.tmin,
+                 tex_dot=rng.normal(size=sc.tex.shape), env_dot=rng.normal(size=sc.env.shape))
+    for k in ("tri_id", "L_dir", "dL_dir", "vis"):
+        res["small_" + k] = r[k]
+    pos, tri = I.interlocking_tori(24, 10)
+    cams = I.ring_cameras(1, 4.5, 40, 40)
+    st = I.make_scene("tori_tiny", pos, tri, 64, 64, 16, 32, 1.0, cams, N_d=8, N_b=2, N_s=2)
+    om2 = O.OracleMesh(st.pos, st.tri, st.uv, st.tri_uv)
+    tab2 = O.EnvTables(st.env)
+    r = O.render(om2, cams[0], tab2, st.tex, st.env, N_d=8, N_b=2, N_s=2, seed=st.seed, tmin=st.tmin,
+                 env_dot=rng.normal(size=st.env.shape))
+    for k in ("L_dir", "L_ind", "dL_dir", "dL_ind", "vis", "sec_tri", "sec_bary", "sec_vis"):
+        res["tori_" + k] = r[k]
+    o = rng.normal(size=(500, 3)) * 0.2
+    d = rng.normal(size=(500, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    h, t, b2 = O.trace_closest(om2, o, d, 1e-4)
+    hb, tb, _ = O.trace_closest(om2, o, d, 1e-4, brute=True)
+    res["closest_id"], res["closest_t"], res["closest_b"] = h, t, b2
+    res["closest_brute_id"], res["closest_brute_t"] = hb, tb
+    res["any"] = O.trace_any(om2, o, d, 1e-4)
+    res["margins"] = np.array([O.ray_margins(om2, o[i], d[i], 1e-4, -1, 1e-5) for i in range(40)])
+    return res
+
+
+def main() -> int:
+    mode, lib_path = sys.argv[1], sys.argv[2]
+    if mode == "oracle":
+        import oracle as O
+        O.LIB_PATH = lib_path  # loaded on first use
+        from paper_2608_24109_amd import inputs as I
+        np.savez(sys.argv[3], **oracle_outputs(O, I))
+    elif mode == "abi":
+        from paper_2608_24109_amd import _lib as L
+        L.LIB_PATH = lib_path
+        L.lib = L._load()
+        import test_abi_cpu as T
+        names = sorted(n for n in dir(T) if n.startswith("test_"))
+        for n in names:
+            getattr(T, n)(L)
+        print(f"abi: {len(names)} validation tests passed under the sanitizers")
+    elif mode == "bvh":
+        from paper_2608_24109_amd import inputs as I
+        lib = C.CDLL(lib_path)
+        lib.bvh_check.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p]
+        quad = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0]], np.float64)
+        meshes = [I.icosphere(3), I.interlocking_tori(60, 20), I.quad_mesh(quad, 3, 2)]
+        same = (np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32), np.tile(np.array([[0, 1, 2]], np.int32), (3000, 1)))
+        for pos, tri in meshes + [same]:
+            pos = np.ascontiguousarray(pos, np.float32)
+            tri = np.ascontiguousarray(tri, np.int32)
+            st = np.zeros(4, np.int32)
+            rc = lib.bvh_check(pos.ctypes.data, pos.shape[0], tri.ctypes.data, tri.shape[0], st.ctypes.data)
+            if rc != 0:
+                print(f"bvh invariant {rc} broken on a mesh of {tri.shape[0]} triangles")
+                return 1
+        print("bvh: builder invariants hold under the sanitizers")
+    else:
+        raise SystemExit(f"unknown mode {mode}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

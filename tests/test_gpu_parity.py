@@ -83,6 +83,34 @@ def small_tori():
 # env tables
 # ------------------------------------------------------------------------------------------
 
+@pytest.mark.parametrize("which", ["roof", "sphere"])
+def test_mesh_prepare_matches_oracle(which):
+    """exm_mesh_prepare's FP64 vertex normals and per-face tangent frames against the oracle's
+    (Attribute Query): two faces of areas 2 and 1 at a right angle, whose shared vertices have the
+    area-weighted normal (1,0,2)/sqrt(5); and the displaced cube-sphere of the benchmark."""
+    from paper_2608_24109_amd.scene import DeviceMesh
+    if which == "roof":
+        pos = np.array([[0, 0, 0], [2, 0, 0], [0, 2, 0], [0, 0, 1]], dtype=np.float32)
+        tri = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)
+        uv = np.array([[0, 0], [1, 0], [0, 1], [0, 0], [1, 0], [0, 1]], dtype=np.float32)
+        tuv = np.arange(6, dtype=np.int32).reshape(2, 3)
+    else:
+        pos, tri = I.displaced_cube_sphere(129)
+        uv, tuv = I.cube_projected_uvs(pos, tri)
+    log(f"[mesh prepare] {which}")
+    dm = DeviceMesh(pos, tri, uv, tuv, with_bvh=False)
+    torch.cuda.synchronize()
+    om = O.OracleMesh(pos, tri, uv, tuv, with_bvh=False)
+    vn, ft = dm.vnrm.cpu().numpy(), dm.ftan.cpu().numpy()
+    assert np.abs(vn - O.vertex_normals(om)).max() <= 1e-12
+    if which == "roof":
+        w = np.array([1.0, 0.0, 2.0]) / np.sqrt(5.0)
+        assert np.abs(vn - np.array([w, [0, 0, 1], w, [1, 0, 0]])).max() <= 1e-15
+    ref = O.face_tangents(om)
+    assert np.array_equal(ft[:, 3], ref[:, 3].astype(np.float32))
+    assert np.abs(ft[:, :3] - ref[:, :3]).max() <= 2e-7 * np.abs(ref[:, :3]).max()
+
+
 @pytest.mark.parametrize("He,We,sigma", [(32, 64, 1.0), (512, 1024, 1.5), (7, 13, 2.0)])
 def test_env_tables_integer_equal(lib, He, We, sigma):
     from paper_2608_24109_amd.scene import DeviceEnv
