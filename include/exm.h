@@ -178,6 +178,19 @@ exm_status exm_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_materi
                          const int32_t* tri_id, const float* bary, const exm_params* p,
                          float* L_dir, uint64_t* vis, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* exm_shade_fwd without a workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * outputs, bit for bit, computed in a device scratch array of 64 MiB that the library holds on
+ * each GPU it runs on until the process ends (looked up on the first call on a device). It
+ * allocates nothing: any image size works, the pixels run in chunks of what fits in the
+ * scratch (at N_d = 64 about 23,000 pixels per chunk, at N_d = 8 about 180,000). Every call on
+ * one GPU shares that GPU's scratch: calls that overlap on one GPU (on different streams or
+ * from several threads) race; order them on one stream. */
+exm_status exm_shade_fwd_noalloc(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat,
+                                 const exm_env* env, const exm_camera* cams_host, int32_t nViews,
+                                 const int32_t* tri_id, const float* bary, const exm_params* p,
+                                 float* L_dir, uint64_t* vis, hipStream_t stream);
+
 /* One-bounce diffuse indirect, Eq. 18-19: L_ind [nViews,H,W,3] (overwritten), sec_rec
  * [nViews,H,W,N_b], sec_vis [nViews,H,W] u64 (bit j*N_s+s). ws: ray workspace as for
  * exm_shade_fwd, sized by exm_trace_indirect_workspace_size / _min. */

@@ -107,6 +107,7 @@ def _load() -> C.CDLL:
         "exm_trace_indirect_workspace_size": (C.c_size_t, [i32, i32, i32, i32, i32]),
         "exm_trace_indirect_workspace_min": (C.c_size_t, [i32, i32]),
         "exm_trace_indirect": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
+        "exm_shade_fwd_noalloc": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]),
         "exm_shade_fwd_counted": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp, vp]),
         "exm_trace_indirect_counted": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp,
                                             vp]),
@@ -287,6 +288,17 @@ def exm_shade_fwd(mesh, bvh: Bvh, mat: exm_material, env: exm_env, cams, tri_id,
     _check(lib.exm_shade_fwd(C.byref(mesh), bvh.handle, C.byref(mat), C.byref(env), cams, n, _ptr(tri_id),
                              _ptr(bary), C.byref(p), _ptr(L_dir), _ptr(vis), _ptr(ws), ws.numel(), _stream(stream)),
            "exm_shade_fwd")
+
+
+def exm_shade_fwd_noalloc(mesh, bvh: Bvh, mat: exm_material, env: exm_env, cams, tri_id, bary, p: exm_params, L_dir,
+                          vis, stream=None) -> None:
+    import torch
+    n, H, W = len(cams), cams[0].H, cams[0].W
+    _need(L_dir, torch.float32, (n, H, W, 3), "L_dir")
+    _need(vis, torch.uint64, (n, H, W), "vis")
+    _check(lib.exm_shade_fwd_noalloc(C.byref(mesh), bvh.handle, C.byref(mat), C.byref(env), cams, n, _ptr(tri_id),
+                                     _ptr(bary), C.byref(p), _ptr(L_dir), _ptr(vis), _stream(stream)),
+           "exm_shade_fwd_noalloc")
 
 
 def exm_trace_indirect_workspace_size(nViews: int, H: int, W: int, N_b: int, N_s: int) -> int:

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libexm.so")
 
-HIP_SOURCES = ["mesh.hip", "env_sampler.hip", "raster.hip", "shade.hip", "trace.hip", "rays.hip", "env_grad.hip", "upsample.hip", "stage2.hip", "topology.hip", "tex_grad.hip"]
+HIP_SOURCES = ["mesh.hip", "env_sampler.hip", "raster.hip", "shade.hip", "trace.hip", "rays.hip", "env_grad.hip", "upsample.hip", "stage2.hip", "topology.hip", "tex_grad.hip", "noalloc.hip"]
 # sources whose FP64 decisions must match a reference evaluated without fused multiply-adds
 NO_CONTRACT = {"topology.hip"}
 CPP_SOURCES = ["abi.cpp", "bvh_build.cpp", "timing.cpp"]

@@ -256,10 +256,11 @@ exm_status exm_raster_gbuffer(const exm_mesh* m, const exm_camera* cams, int32_t
   return EXM_OK;
 }
 
+// ws == nullptr with static_scratch: the pass runs in the library's device scratch (no allocation)
 static exm_status shade_fwd_impl(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                                  const exm_camera* cams, int32_t nViews, const int32_t* tri_id, const float* bary,
                                  const exm_params* p, float* L_dir, uint64_t* vis, void* ws, size_t ws_bytes,
-                                 uint64_t* counters, hipStream_t stream) {
+                                 uint64_t* counters, hipStream_t stream, bool static_scratch = false) {
   EXM_TRY(check_mesh(m, true));
   if (!bvh) return fail(EXM_E_INVAL, "bvh is NULL");
   EXM_TRY(check_material(mat));
@@ -268,9 +269,19 @@ static exm_status shade_fwd_impl(const exm_mesh* m, const exm_bvh* bvh, const ex
   EXM_TRY(check_gbuffer(tri_id, bary));
   EXM_TRY(check_params(p, false));
   if (!L_dir || !vis) return fail(EXM_E_INVAL, "output pointer is NULL");
-  if (!ws || !aligned(ws, 256) || ws_bytes < shade_fwd_ws_min(p->N_d))
+  if (static_scratch) {
+    if (shade_fwd_ws_min(p->N_d) > kNoAllocScratchBytes)
+      return fail(EXM_E_INVAL, "exm_shade_fwd_noalloc: the smallest pixel chunk needs more than the 64 MiB scratch");
+  } else if (!ws || !aligned(ws, 256) || ws_bytes < shade_fwd_ws_min(p->N_d)) {
     return fail(EXM_E_INVAL, "workspace must be 256-byte aligned and at least exm_shade_fwd_workspace_min bytes");
+  }
   EXM_TRY(check_device());
+  if (static_scratch) {
+    const hipError_t e = noalloc_scratch(&ws);
+    if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_shade_fwd_noalloc: scratch lookup: ") + hipGetErrorString(e));
+    if (!aligned(ws, 256)) return fail(EXM_E_HIP, "exm_shade_fwd_noalloc: scratch is not 256-byte aligned");
+    ws_bytes = kNoAllocScratchBytes;
+  }
   const int64_t HW = (int64_t)cams[0].H * cams[0].W;
   for (int32_t v0 = 0; v0 < nViews; v0 += kViewsPerLaunch) {
     const int32_t n = std::min(kViewsPerLaunch, nViews - v0);
@@ -322,6 +333,12 @@ exm_status exm_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_materi
                          const exm_params* p, float* L_dir, uint64_t* vis, void* ws, size_t ws_bytes,
                          hipStream_t stream) {
   return shade_fwd_impl(m, bvh, mat, env, cams, nViews, tri_id, bary, p, L_dir, vis, ws, ws_bytes, nullptr, stream);
+}
+
+exm_status exm_shade_fwd_noalloc(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
+                                 const exm_camera* cams, int32_t nViews, const int32_t* tri_id, const float* bary,
+                                 const exm_params* p, float* L_dir, uint64_t* vis, hipStream_t stream) {
+  return shade_fwd_impl(m, bvh, mat, env, cams, nViews, tri_id, bary, p, L_dir, vis, nullptr, 0, nullptr, stream, true);
 }
 
 exm_status exm_shade_fwd_counted(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,

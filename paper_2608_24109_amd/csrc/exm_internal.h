@@ -150,6 +150,10 @@ hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_mat
                             hipStream_t s);
 size_t shade_fwd_ws_bytes(int64_t n_pix, int32_t N_d);
 size_t shade_fwd_ws_min(int32_t N_d);
+// Scratch of exm_shade_fwd_noalloc: a device array of this many bytes per GPU; noalloc_scratch
+// gives the current device's address (looked up once per device).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+hipError_t noalloc_scratch(void** ptr);
 hipError_t launch_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env, const ShadeViews& v,
                             const int32_t* tri_id, const float* bary, const exm_params* p, const float* dI,
                             const uint64_t* vis, const float* dquery, float* dtex, double* denv, void* ws,
