@@ -1,11 +1,16 @@
 """Benchmark of the Stage-II UV-PBR render pass on one MI355X.
 
 One step = one pass of the whole hot path over the workload's views: env sampling tables,
-G-buffer raster, direct shading (+ one-bounce indirect where the workload has it), gradient
-buffers cleared, then the direct (+ indirect) adjoint into the UV maps and the env map.
-Inputs are resident in HBM before timing starts.
+G-buffer raster, direct shading and one-bounce indirect light, then the adjoint of both into
+the UV maps and the env map. Inputs are resident in HBM before timing starts.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere|tori|small]
+The headline workload (the default) is the differentiation form at its full size: the tori
+mesh (1M triangles), 32 views of 1024^2, 4096^2 maps, a 512x1024 env map with gradients,
+N_d 64 + N_b 4 x N_s 4, through the autograd.Function with the G-buffer rasterised again in
+backward. The sphere (8 views, direct), tori (8 views, indirect), small, serving and paper-shape
+rows run beside it as extras.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tori32|sphere|tori|small]
 
 Prints one JSON line. The metric is forward+backward Mpixels/s at 1024^2 (all pixels of the
 step counted, background included); per-kernel times come from HIP events recorded on the
@@ -40,13 +45,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="sphere", choices=["sphere", "tori", "small"])
+    ap.add_argument("--workload", default="tori32", choices=["tori32", "sphere", "tori", "small"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-views", type=int, default=4, help="views of the workload the oracle baseline renders")
+    ap.add_argument("--cpu-views", type=int, default=8, help="views of the workload the oracle baseline samples")
+    ap.add_argument("--cpu-pixels", type=int, default=16384, help="pixels per view the oracle baseline renders")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, copy a buffer of this many MiB once (HBM counter calibration)")
     ap.add_argument("--no-extras", dest="extras", action="store_false",
-                    help="skip the tori, tori32 and relight workloads")
+                    help="skip the extra workloads (sphere, tori, small, serving, paper shape, Stage I/II)")
     ap.add_argument("--relight-seconds", type=float, default=60.0, help="length of the relight request stream")
     ap.add_argument("--relight-rate", type=float, default=200.0, help="Poisson arrival rate (requests/s)")
     ap.add_argument("--relight-budget-gib", type=float, default=8.0, help="HBM budget of the relight service")
@@ -135,39 +141,62 @@ def run_gpu(workload: str, steps: int, warmup: int):
     gpu_kern = {k: {"avg_ms": ms / n, "launches_per_step": n / steps, "ms_per_step": ms / steps}
                 for k, (ms, n) in gk.items()}
 
-    # work counts of the workload, from the counting variants (outside the timed region)
-    c_dir = torch.zeros(4, dtype=torch.uint64, device="cuda")
-    L.exm_shade_fwd_counted(mesh.s, mesh.bvh, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc, bufs.L_dir, bufs.vis,
-                            ws_fwd, c_dir)
-    c_ind = torch.zeros(6, dtype=torch.uint64, device="cuda")
-    if p.N_b > 0:
-        L.exm_trace_indirect_counted(mesh.s, mesh.bvh, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc, bufs.L_ind,
-                                     bufs.sec_rec, bufs.sec_vis, ws_fwd, c_ind)
-    torch.cuda.synchronize()
-    cd = [int(x) for x in c_dir.cpu().numpy()]
-    ci = [int(x) for x in c_ind.cpu().numpy()]
-    ids = bufs.tri_id.cpu().numpy()
-    covered = int((ids >= 0).sum())
-    vis = bufs.vis.cpu().numpy().reshape(-1)
-    set_bits = int(np.unpackbits(vis.view(np.uint8)).sum())
-    stats = dict(views=V, H=H, W=W, pixels=V * H * W, covered=covered, tris=int(sc.nF),
-                 texels=int(sc.tex.shape[0] * sc.tex.shape[1]), He=int(sc.env.shape[0]), We=int(sc.env.shape[1]),
-                 samples=cd[3], shadow_rays=cd[0], shadow_nodes=cd[1], shadow_tris=cd[2], unoccluded=set_bits)
-    if p.N_b > 0:
-        sv = bufs.sec_vis.cpu().numpy().reshape(-1)
-        stats.update(sec_rays=ci[0], sec_nodes=ci[1], sec_tris=ci[2], sec_shadow_rays=ci[3], sec_shadow_nodes=ci[4],
-                     sec_shadow_tris=ci[5], sec_hits=int((bufs.sec_rec.cpu().numpy()[..., 0] >= 0).sum()),
-                     sec_unoccluded=int(np.unpackbits(sv.view(np.uint8)).sum()))
+    stats = count_work(sc, mesh, mat, env, p)
     stats["gpu_kernels"] = gpu_kern
     return sc, p, wall, kern, stats, (mesh, mat, env, bufs)
 
 
-def run_c3(steps: int, warmup: int):
-    """The differentiation form: RenderPBR over the 32 views of the tori mesh with 4096^2 maps,
-    G-buffer rasterised again in backward, env gradients on. One step = env tables, forward,
-    backward (gradient buffers allocated and cleared inside)."""
+def count_work(sc, mesh, mat, env, p, chunk: int = 8) -> dict:
+    """Work counts of one step of the workload, from the library's counting variants of the
+    direct and indirect passes (run outside the timed region, `chunk` views at a time): rays
+    traced, BVH nodes visited, triangles tested, env samples drawn, covered pixels, unoccluded
+    samples and secondary hits."""
     import torch
 
+    from paper_2608_24109_amd import _lib as L
+    from paper_2608_24109_amd.render import PassBuffers, raster
+    V, H, W = len(sc.cams), sc.cams[0].H, sc.cams[0].W
+    pc = p.c()
+    n = min(chunk, V)
+    bufs = PassBuffers(n, H, W, p.N_b)
+    ws = bufs.workspace(max(L.exm_shade_fwd_workspace_size(n, H, W, p.N_d),
+                            L.exm_trace_indirect_workspace_size(n, H, W, p.N_b, p.N_s) if p.N_b else 0))
+    c_dir = torch.zeros(4, dtype=torch.uint64, device="cuda")
+    c_ind = torch.zeros(6, dtype=torch.uint64, device="cuda")
+    covered = set_bits = sec_hits = sec_set = 0
+    env.update()
+    for v0 in range(0, V, n):
+        cc = L.cameras(sc.cams[v0:v0 + n], list(range(v0, v0 + n)))
+        raster(mesh, cc, bufs)
+        L.exm_shade_fwd_counted(mesh.s, mesh.bvh, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc, bufs.L_dir,
+                                bufs.vis, ws, c_dir)
+        if p.N_b > 0:
+            L.exm_trace_indirect_counted(mesh.s, mesh.bvh, mat.s, env.s, cc, bufs.tri_id, bufs.bary, pc, bufs.L_ind,
+                                         bufs.sec_rec, bufs.sec_vis, ws, c_ind)
+            sec_hits += int((bufs.sec_rec[..., 0] >= 0).sum())
+            sec_set += int(np.unpackbits(bufs.sec_vis.cpu().numpy().reshape(-1).view(np.uint8)).sum())
+        covered += int((bufs.tri_id >= 0).sum())
+        set_bits += int(np.unpackbits(bufs.vis.cpu().numpy().reshape(-1).view(np.uint8)).sum())
+    torch.cuda.synchronize()
+    cd = [int(x) for x in c_dir.cpu().numpy()]
+    ci = [int(x) for x in c_ind.cpu().numpy()]
+    stats = dict(views=V, H=H, W=W, pixels=V * H * W, covered=covered, tris=int(sc.nF),
+                 texels=int(sc.tex.shape[0] * sc.tex.shape[1]), He=int(sc.env.shape[0]), We=int(sc.env.shape[1]),
+                 samples=cd[3], shadow_rays=cd[0], shadow_nodes=cd[1], shadow_tris=cd[2], unoccluded=set_bits)
+    if p.N_b > 0:
+        stats.update(sec_rays=ci[0], sec_nodes=ci[1], sec_tris=ci[2], sec_shadow_rays=ci[3], sec_shadow_nodes=ci[4],
+                     sec_shadow_tris=ci[5], sec_hits=sec_hits, sec_unoccluded=sec_set)
+    return stats
+
+
+def run_tori32(steps: int, warmup: int):
+    """The headline: the differentiation form at full size. RenderPBR (the autograd.Function)
+    over the 32 views of the tori mesh with 4096^2 maps and env gradients, 8 views per chunk,
+    each chunk's G-buffer freed after the forward and rasterised again in backward. One step =
+    env tables, forward, backward (gradient buffers allocated and cleared inside)."""
+    import torch
+
+    from paper_2608_24109_amd import _lib as L
     from paper_2608_24109_amd import inputs as I
     from paper_2608_24109_amd.render import PassParams, RenderPBR
     from paper_2608_24109_amd.scene import DeviceEnv, DeviceMaterial, DeviceMesh
@@ -190,15 +219,20 @@ def run_c3(steps: int, warmup: int):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    L.exm_timing_enable(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / steps
-    return {"workload": f"tori32: {sc.nF} tris, {V} views {H}x{W}, {sc.tex.shape[0]}^2 maps, "
-                        f"{sc.env.shape[0]}x{sc.env.shape[1]} env with gradients, N_d={p.N_d}, N_b={p.N_b}, "
-                        f"N_s={p.N_s}, G-buffer rasterised again in backward (autograd.Function)",
-            "steps": steps, "ms_per_step": round(wall * 1e3, 2), "fwd_bwd_Mpixels_s": round(V * H * W / wall / 1e6, 3)}
+    wall = time.perf_counter() - t0
+    gk = L.exm_timing_collect()
+    L.exm_timing_enable(False)
+    tex.requires_grad_(False)
+    emap.requires_grad_(False)
+    stats = count_work(sc, mesh, mat, env, p)
+    stats["gpu_kernels"] = {k: {"avg_ms": ms / n, "launches_per_step": n / steps, "ms_per_step": ms / steps}
+                            for k, (ms, n) in gk.items()}
+    return sc, p, wall, stats
 
 
 def run_relight(seconds: float, rate: float, budget_gib: float, slots: int):
@@ -364,30 +398,35 @@ def run_topology(rounds: int = 5):
             "splits": st["splits"], "merges": st["merges"], "conflict_passes": st["mis_iterations"]}
 
 
-def cpu_baseline(sc, p, n_views: int):
-    """The FP64 oracle as it stands on the first `n_views` whole views of the workload (every
-    pixel, background included): its forward pass and one forward-mode derivative pass (the
-    gradient along one direction), timed on the host cores."""
+def cpu_baseline(sc, p, n_views: int, n_pix: int):
+    """The FP64 oracle as it stands on a bounded sample of the workload: `n_pix` pixels drawn
+    uniformly (seeded, background included in proportion) from each of `n_views` views spread
+    over the workload's views; its forward pass and one forward-mode derivative pass (the
+    gradient along one direction) per view, timed on the host cores."""
     import oracle as O
     om = O.OracleMesh(sc.pos, sc.tri, sc.uv, sc.tri_uv)
     tab = O.EnvTables(sc.env)
     cores = len(os.sched_getaffinity(0))
     tex_dot = np.zeros_like(sc.tex, dtype=np.float64)
     tex_dot[..., 0] = 1.0
+    rng = np.random.default_rng(12)
+    views = np.linspace(0, len(sc.cams) - 1, n_views).round().astype(int)
     px = 0
     t0 = time.perf_counter()
-    for v in range(n_views):
+    for v in views:
         cam = sc.cams[v]
-        O.render(om, cam, tab, sc.tex, sc.env, N_d=p.N_d, N_b=p.N_b, N_s=p.N_s, seed=p.seed, tmin=p.tmin,
-                 view_id=v, n_threads=cores)
-        O.render(om, cam, tab, sc.tex, sc.env, N_d=p.N_d, N_b=p.N_b, N_s=p.N_s, seed=p.seed, tmin=p.tmin,
-                 view_id=v, tex_dot=tex_dot, n_threads=cores)
-        px += cam.H * cam.W
+        pix = np.sort(rng.choice(cam.H * cam.W, min(n_pix, cam.H * cam.W), replace=False))
+        kw = dict(N_d=p.N_d, N_b=p.N_b, N_s=p.N_s, seed=p.seed, tmin=p.tmin, view_id=int(v), pix=pix,
+                  n_threads=cores)
+        O.render(om, cam, tab, sc.tex, sc.env, **kw)
+        O.render(om, cam, tab, sc.tex, sc.env, tex_dot=tex_dot, **kw)
+        px += pix.size
     t = time.perf_counter() - t0
-    return {"value": round(px / t / 1e6, 4), "unit": "Mpixels/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n_views} of the {len(sc.cams)} views of the {sc.name} workload ({px} pixels), FP64 "
-                      f"forward + one forward-mode derivative pass (the fwd+bwd work of those views), "
-                      f"{t:.1f} s on {cores} host threads"}
+    return {"value": round(px / t / 1e6, 5), "unit": "Mpixels/s", "cores": cores, "kind": "oracle",
+            "sample": f"{px} pixels of the {sc.name} workload ({n_pix} drawn uniformly from each of {len(views)} of "
+                      f"its {len(sc.cams)} views, background included), FP64 forward + one forward-mode derivative "
+                      f"pass (the fwd+bwd work of those pixels; each pass also rasterises its view), {t:.1f} s on "
+                      f"{cores} host threads"}
 
 
 # Algorithmic bytes: what the method itself must read or write per unit, times the units of one
@@ -451,8 +490,10 @@ def kernel_bytes_per_step(kernel: str, st: dict, p) -> float:
 # 51. A watertight ray/triangle test (Woop, Benthin and Wald 2013): vertices relative to the
 # origin (9), shear (6), edge functions U, V, W (9), sign tests (6), determinant (2), scaled
 # distance (8), its reciprocal and product (2), range test (2): 44. The env-map pick and the
-# shading of one sample (dir_gen) and its adjoint (shade_bwd) take about 150 and 350 lane
-# operations (estimates from the instruction mix of the BRDF and its derivatives).
+# shading of one sample (dir_gen, every sample drawn) and the adjoint of one unoccluded sample
+# (shade_bwd; samples that are occluded or face away contribute nothing and are skipped) take
+# about 150 and 350 lane operations (estimates from the instruction mix of the BRDF and its
+# derivatives). Every count stays below the lane operations the SQ counters show executed.
 NODE_OPS, TRI_OPS, GEN_SAMPLE_OPS, BWD_SAMPLE_OPS = 51.0, 44.0, 150.0, 350.0
 # plain (non-packed) FP32 vector issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -467,7 +508,7 @@ def kernel_lane_ops_per_step(kernel: str, st: dict) -> float:
     if kernel == "dir_gen":
         return GEN_SAMPLE_OPS * st["samples"]
     if kernel == "shade_bwd":
-        return BWD_SAMPLE_OPS * st["samples"]
+        return BWD_SAMPLE_OPS * st["unoccluded"]
     return float("nan")
 
 
@@ -488,6 +529,76 @@ def pmc_traffic(kernel: str, workload: str):
         return None
 
 
+def sq_lane_ops(kernel: str, workload: str):
+    """VALU lane operations executed per launch of `kernel` (SQ_THREAD_CYCLES_VALU) from the
+    committed SQ counter summary of the workload, if it was taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", f"sq_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        from paper_2608_24109_amd.profiling import source_digest
+        d = json.load(open(path))
+        if d.get("source_sha") != source_digest():
+            return None
+        return d["kernels"][kernel]["SQ_THREAD_CYCLES_VALU"]
+    except Exception:
+        return None
+
+
+def roofline_objects(workload: str, stats: dict, p) -> dict:
+    """The roofline object of the dominant kernel and the per-kernel views beside it."""
+    gk = stats["gpu_kernels"]
+    dom = max(gk, key=lambda k: gk[k]["ms_per_step"])
+
+    def rate(x, k):
+        return x / gk[k]["launches_per_step"] / (gk[k]["avg_ms"] * 1e-3)
+
+    ops_launch = kernel_lane_ops_per_step(dom, stats) / gk[dom]["launches_per_step"]
+    ops_rate = rate(kernel_lane_ops_per_step(dom, stats), dom) / 1e12
+    traffic = pmc_traffic(dom, workload)
+    executed = sq_lane_ops(dom, workload)
+    bytes_launch = kernel_bytes_per_step(dom, stats, p) / gk[dom]["launches_per_step"]
+    ok = not math.isnan(ops_rate)
+    out = {
+        # the traversal is bound by VALU issue (its node and triangle bytes come from L2 and the
+        # MALL), so the roofline is the ALU one: algorithmic lane operations per launch over the
+        # launch time, against the non-packed FP32 vector issue rate of the chip
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": round(ops_rate, 3) if ok else None,
+                     "peak": round(VALU_PEAK_T, 2), "unit": "T lane-ops/s",
+                     "frac": round(ops_rate / VALU_PEAK_T, 4) if ok else None,
+                     "traffic": None if traffic is None else round(traffic),
+                     "algorithmic_lane_ops_per_launch": round(ops_launch) if ok else None,
+                     "executed_lane_ops_per_launch": None if executed is None else round(executed),
+                     "avg_launch_ms": round(gk[dom]["avg_ms"], 4)},
+        # the same launches counted in the method's bytes (64 B per node visit, 48 B per triangle
+        # test, the ray in and the answer out): served from L2 and the 256 MB MALL, so no HBM
+        # peak applies to this rate
+        "cache_bytes": {"kernel": dom, "bytes_per_launch": None if math.isnan(bytes_launch) else round(bytes_launch),
+                        "GBps": None if math.isnan(bytes_launch) else
+                        round(bytes_launch / (gk[dom]["avg_ms"] * 1e-3) / 1e9, 1)},
+    }
+    alu = {}
+    for k in ("trace_any", "trace_closest", "dir_gen", "shade_bwd"):
+        if k not in gk:
+            continue
+        o = rate(kernel_lane_ops_per_step(k, stats), k) / 1e12
+        e = sq_lane_ops(k, workload)
+        alu[k] = {"achieved": round(o, 3), "frac": round(o / VALU_PEAK_T, 4),
+                  "algorithmic_lane_ops_per_launch": round(kernel_lane_ops_per_step(k, stats) / gk[k]["launches_per_step"]),
+                  "executed_lane_ops_per_launch": None if e is None else round(e)}
+    out["alu_rooflines"] = alu
+    hbm = {}
+    for k in gk:
+        t = pmc_traffic(k, workload)
+        if t is not None:
+            g = t / (gk[k]["avg_ms"] * 1e-3) / 1e9
+            hbm[k] = {"bytes_per_launch": round(t), "GBps": round(g, 1), "frac": round(g / HBM_PEAK_GBS, 4)}
+    # HBM bytes measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE, calibrated on a copy) over each
+    # kernel's launch time, against 8 TB/s; empty when the counters predate the kernel sources
+    out["hbm_measured"] = hbm
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -503,73 +614,76 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     log(f"{a.workload}: {a.warmup} warmup + {a.steps} timed steps")
-    sc, p, wall, kern, stats, _ = run_gpu(a.workload, a.steps, a.warmup)
+    kern = None
+    if a.workload == "tori32":
+        sc, p, wall, stats = run_tori32(a.steps, a.warmup)
+        desc = (f"tori32: {stats['tris']} tris, {stats['views']} views {stats['H']}x{stats['W']}, "
+                f"{sc.tex.shape[0]}^2 maps, {sc.env.shape[0]}x{sc.env.shape[1]} env with gradients, N_d={p.N_d}, "
+                f"N_b={p.N_b}, N_s={p.N_s}, G-buffer rasterised again in backward (autograd.Function), fwd+bwd")
+    else:
+        sc, p, wall, kern, stats, _ = run_gpu(a.workload, a.steps, a.warmup)
+        desc = (f"{sc.name}: {stats['tris']} tris, {stats['views']} views {stats['H']}x{stats['W']}, "
+                f"{sc.tex.shape[0]}^2 maps, {sc.env.shape[0]}x{sc.env.shape[1]} env, N_d={p.N_d}"
+                + (f", N_b={p.N_b}, N_s={p.N_s}" if p.N_b else "") + ", fwd+bwd")
     ms_step = wall / a.steps * 1e3
     value = stats["pixels"] / (ms_step * 1e-3) / 1e6
-    gk = stats.pop("gpu_kernels")
-    dom = max(gk, key=lambda k: gk[k]["ms_per_step"])
-    per_launch = kernel_bytes_per_step(dom, stats, p) / gk[dom]["launches_per_step"]
-    achieved = per_launch / (gk[dom]["avg_ms"] * 1e-3) / 1e9
-    traffic = pmc_traffic(dom, a.workload)
-    ops_launch = kernel_lane_ops_per_step(dom, stats) / gk[dom]["launches_per_step"]
-    ops_rate = ops_launch / (gk[dom]["avg_ms"] * 1e-3) / 1e12
-
-    def alu_view(k):
-        o = kernel_lane_ops_per_step(k, stats) / gk[k]["launches_per_step"] / (gk[k]["avg_ms"] * 1e-3) / 1e12
-        return {"achieved": round(o, 3), "frac": round(o / VALU_PEAK_T, 4)}
+    gk = stats["gpu_kernels"]
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mpixels/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{sc.name}: {stats['tris']} tris, {stats['views']} views {stats['H']}x{stats['W']}, "
-                               f"{sc.tex.shape[0]}^2 maps, {sc.env.shape[0]}x{sc.env.shape[1]} env, N_d={p.N_d}"
-                               + (f", N_b={p.N_b}, N_s={p.N_s}" if p.N_b else "") + ", fwd+bwd",
-                   "global_batch": stats["views"], "seq_len": stats["H"] * stats["W"], "parallelism": "none"},
-        "kernels_ms": {k: round(v, 4) for k, v in kern.items()},
+        "config": {"workload": desc, "global_batch": stats["views"], "seq_len": stats["H"] * stats["W"],
+                   "parallelism": "none"},
         "covered_fraction": round(stats["covered"] / stats["pixels"], 4),
-        "direct_shadow_Mrays_s": round(stats["shadow_rays"] / (kern["shade_fwd"] * 1e-3) / 1e6, 1),
-        "nodes_per_shadow_ray": round(stats["shadow_nodes"] / max(stats["shadow_rays"], 1), 2),
-        "tris_per_shadow_ray": round(stats["shadow_tris"] / max(stats["shadow_rays"], 1), 2),
-        # the traversal is bound by VALU issue (its node and triangle bytes come from L2 and the
-        # MALL): the roofline is the ALU one, with the HBM view of the same launches beside it
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": None if math.isnan(ops_rate) else round(ops_rate, 3),
-                     "peak": round(VALU_PEAK_T, 2), "unit": "TFLOP/s",
-                     "frac": None if math.isnan(ops_rate) else round(ops_rate / VALU_PEAK_T, 4),
-                     "traffic": None if traffic is None else round(traffic),
-                     "algorithmic_lane_ops_per_launch": None if math.isnan(ops_launch) else round(ops_launch),
-                     "avg_launch_ms": round(gk[dom]["avg_ms"], 4)},
-        "roofline_hbm": {"bound": "hbm", "kernel": dom,
-                         "achieved": None if math.isnan(achieved) else round(achieved, 2),
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": None if math.isnan(achieved) else round(achieved / HBM_PEAK_GBS, 5),
-                         "algorithmic_bytes_per_launch": None if math.isnan(per_launch) else round(per_launch),
-                         "traffic_frac": None if traffic is None else
-                         round(traffic / (gk[dom]["avg_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
-        "alu_rooflines": {k: alu_view(k) for k in ("trace_any", "dir_gen", "shade_bwd") if k in gk},
-        "gpu_kernels_ms": {k: round(v["avg_ms"], 4) for k, v in sorted(gk.items(), key=lambda kv: -kv[1]["ms_per_step"])},
-        "gpu_kernel_launches_per_step": {k: v["launches_per_step"] for k, v in gk.items()},
-        "algorithmic_GBps": {k: round(algorithmic_bytes(k, stats, p) / (kern[k] * 1e-3) / 1e9, 1)
-                             for k in kern if not math.isnan(algorithmic_bytes(k, stats, p))},
     }
+    traced = "trace_any" in gk
+    if traced:
+        # shadow rays (direct, and the secondary light samples where the workload has them) per
+        # second of the any-hit traversal kernel; indirect rays per second of the indirect pass's kernels
+        n_any = stats["shadow_rays"] + stats.get("sec_shadow_rays", 0)
+        out["shadow_Mrays_s_in_traversal"] = round(n_any / (gk["trace_any"]["ms_per_step"] * 1e-3) / 1e6, 1)
+        out["nodes_per_shadow_ray"] = round(stats["shadow_nodes"] / max(stats["shadow_rays"], 1), 2)
+        out["tris_per_shadow_ray"] = round(stats["shadow_tris"] / max(stats["shadow_rays"], 1), 2)
+    if p.N_b > 0:
+        ind = [k for k in gk if k in ("ind_gen1", "trace_closest", "ind_gen2", "ind_finalize")]
+        t_ind = sum(gk[k]["ms_per_step"] for k in ind)
+        # the secondary shadow rays' share of the any-hit traversal time, by their node visits
+        nodes_all = stats["shadow_nodes"] + stats["sec_shadow_nodes"]
+        t_ind += gk["trace_any"]["ms_per_step"] * stats["sec_shadow_nodes"] / max(nodes_all, 1)
+        rays = stats["sec_rays"] + stats["sec_shadow_rays"]
+        out["indirect_Mrays_s"] = round(rays / (t_ind * 1e-3) / 1e6, 1)
+    if kern is not None:
+        out["kernels_ms"] = {k: round(v, 4) for k, v in kern.items()}
+    out.update(roofline_objects(a.workload, stats, p))
+    out["gpu_kernels_ms"] = {k: round(v["avg_ms"], 4) for k, v in sorted(gk.items(), key=lambda kv: -kv[1]["ms_per_step"])}
+    out["gpu_kernel_launches_per_step"] = {k: v["launches_per_step"] for k, v in gk.items()}
+    out["gpu_kernels_ms_per_step"] = {k: round(v["ms_per_step"], 4) for k, v in gk.items()}
+    if kern is not None:
+        out["algorithmic_GBps"] = {k: round(algorithmic_bytes(k, stats, p) / (kern[k] * 1e-3) / 1e9, 1)
+                                   for k in kern if not math.isnan(algorithmic_bytes(k, stats, p))}
     if a.extras:
-        log("small (latency)")
-        _, _, wall0, kern0, st0, _ = run_gpu("small", 20, 3)
-        out["small_latency"] = {
-            "workload": "small: icosphere 1280 tris, 1 view 128x128, 256^2 maps, 32x64 env, N_d=16, fwd+bwd",
-            "ms_per_step": round(wall0 / 20 * 1e3, 4),
-            "kernels_ms": {k: round(v, 4) for k, v in kern0.items()}}
-        log("tori (indirect)")
-        sc2, p2, wall2, kern2, st2, _ = run_gpu("tori", max(2, a.steps // 3), 1)
-        rays = st2["sec_rays"] + st2["sec_shadow_rays"]
-        out["indirect"] = {
-            "workload": "tori: 1M tris, 8 views 1024x1024, 2048^2 maps, N_d=64, N_b=4, N_s=4, fwd+bwd",
-            "indirect_Mrays_s": round(rays / (kern2["trace_indirect"] * 1e-3) / 1e6, 1),
-            "fwd_bwd_Mpixels_s": round(st2["pixels"] / (wall2 / max(2, a.steps // 3)) / 1e6, 3),
-            "kernels_ms": {k: round(v, 3) for k, v in kern2.items()},
-            "gpu_kernels_ms": {k: round(v["avg_ms"], 4) for k, v in
-                               sorted(st2["gpu_kernels"].items(), key=lambda kv: -kv[1]["ms_per_step"])}}
-        log("tori32 (autograd.Function, checkpointed)")
-        out["checkpointed_32view"] = run_c3(max(2, a.steps // 5), 1)
+        for name, steps in (("sphere", max(3, a.steps // 2)), ("tori", max(2, a.steps // 3)), ("small", 20)):
+            if name == a.workload:
+                continue
+            log(f"{name}")
+            sc2, p2, wall2, kern2, st2, _ = run_gpu(name, steps, 1 if name != "small" else 3)
+            g2 = st2.pop("gpu_kernels")
+            row = {"workload": f"{sc2.name}: {st2['tris']} tris, {st2['views']} views {st2['H']}x{st2['W']}, "
+                               f"{sc2.tex.shape[0]}^2 maps, {sc2.env.shape[0]}x{sc2.env.shape[1]} env, N_d={p2.N_d}"
+                               + (f", N_b={p2.N_b}, N_s={p2.N_s}" if p2.N_b else "") + ", fwd+bwd",
+                   "fwd_bwd_Mpixels_s": round(st2["pixels"] / (wall2 / steps) / 1e6, 3),
+                   "ms_per_step": round(wall2 / steps * 1e3, 3),
+                   "kernels_ms": {k: round(v, 4) for k, v in kern2.items()},
+                   "gpu_kernels_ms": {k: round(v["avg_ms"], 4) for k, v in
+                                      sorted(g2.items(), key=lambda kv: -kv[1]["ms_per_step"])}}
+            if "trace_any" in g2:
+                row["direct_shadow_Mrays_s"] = round(st2["shadow_rays"] / (kern2["shade_fwd"] * 1e-3) / 1e6, 1)
+            if p2.N_b > 0:
+                row["indirect_Mrays_s"] = round((st2["sec_rays"] + st2["sec_shadow_rays"]) /
+                                                (kern2["trace_indirect"] * 1e-3) / 1e6, 1)
+            st2["gpu_kernels"] = g2
+            row.update(roofline_objects(name, st2, p2))
+            out[name] = row
         log("paper-shape relighting (1600^2, half-resolution indirect)")
         out["paper_shape_relight"] = run_paper_shape()
         log("Stage-II iterations (paper shape, 1600^2 training view)")
@@ -579,8 +693,8 @@ def main():
         log(f"relight service, {a.relight_seconds:g} s stream")
         out["relight"] = run_relight(a.relight_seconds, a.relight_rate, a.relight_budget_gib, a.relight_slots)
     if not a.no_cpu:
-        log(f"oracle CPU baseline on {a.cpu_views} views")
-        out["cpu_baseline"] = cpu_baseline(sc, p, a.cpu_views)
+        log(f"oracle CPU baseline on {a.cpu_pixels} pixels of each of {a.cpu_views} views")
+        out["cpu_baseline"] = cpu_baseline(sc, p, a.cpu_views, a.cpu_pixels)
     print(json.dumps(out), flush=True)
 
 

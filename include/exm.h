@@ -238,18 +238,21 @@ exm_status exm_shade_bwd(const exm_mesh* m, const exm_material* mat, const exm_e
                          size_t ws_bytes, hipStream_t stream);
 
 /* Adjoint of the indirect pass for upstream lambda_ind * dI (Eq. 20): into the materials at
- * the primary and the secondary points and into E at the secondary light samples. */
+ * the primary and the secondary points and into E at the secondary light samples. The map
+ * gradient is added as exm_shade_bwd adds its own (tiles summed by one block each, with plain
+ * read-modify-writes): calls that add into the same dtex must not run concurrently. */
 exm_status exm_trace_bwd(const exm_mesh* m, const exm_material* mat, const exm_env* env,
                          const exm_camera* cams_host, int32_t nViews, const int32_t* tri_id,
                          const float* bary, const exm_params* p, float lambda_ind,
                          const float* dI, const exm_sec_rec* sec_rec, const uint64_t* sec_vis,
                          float* dtex, double* denv, void* ws, size_t ws_bytes, hipStream_t stream);
 
-/* Workspace of the adjoints (device memory, 256-byte aligned, caller-owned): one 16-byte
- * record per env sample of the pixels in flight (N_d per pixel for exm_shade_bwd, N_b * N_s
- * for exm_trace_bwd) plus the bucket tables of the env map's binned reduction; for
- * exm_shade_bwd also two 64-byte map-gradient records per pixel in flight and the tables of
- * their tile sort (about 0.3 MB). _size is what
+/* Workspace of the adjoints (device memory, 256-byte aligned, caller-owned): two 16-byte
+ * records per env sample of the pixels in flight (N_d per pixel for exm_shade_bwd, N_b * N_s
+ * for exm_trace_bwd) plus the bucket tables of the env map's binned reduction; two 64-byte
+ * map-gradient records per surface point in flight (the pixel's for exm_shade_bwd, the pixel's
+ * and its N_b secondary points' for exm_trace_bwd) and the tables of their tile sort (about
+ * 0.3 MB). _size is what
  * the views of one launch (at most 8) take at once; any size from _min up works, the pixels
  * then run in chunks. 0 for invalid arguments. */
 size_t exm_shade_bwd_workspace_size(int32_t nViews, int32_t H, int32_t W, int32_t N_d, int32_t He,

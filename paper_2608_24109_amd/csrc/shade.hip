@@ -391,21 +391,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     scatter_tex(S, g8, dtex);
 }
 
-// Largest pixel chunk (multiple of 64, at most max_px) whose env-gradient records (per_px per
-// pixel) and map-gradient records (one per pixel) fit in ws_bytes; the env part comes first.
-int64_t bwd_chunk(size_t ws_bytes, int64_t per_px, int32_t He, int32_t We, int64_t max_px) {
-  int64_t lo = 0, hi = (max_px + 63) / 64;
-  if (per_px > 0) hi = std::min<int64_t>(hi, ((int64_t)1 << 31) / (64 * per_px));
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) / 2;
-    if (env_grad_ws_bytes(mid * 64 * per_px, He, We) + tex_grad_ws_bytes(mid * 64) <= ws_bytes)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo * 64;
-}
-
 KParams kparams(const exm_params* p) {
   KParams k;
   k.N_d = p->N_d;
@@ -479,7 +464,7 @@ hipError_t launch_shade_bwd(const exm_mesh* m, const exm_material* mat, const ex
                             size_t ws_bytes, hipStream_t s) {
   const int64_t n = (int64_t)v.n * v.H * v.W;
   const int64_t per_px = std::max(p->N_d, 0);
-  const int64_t P = bwd_chunk(ws_bytes, per_px, env->He, env->We, n);
+  const int64_t P = adjoint_chunk(ws_bytes, per_px, 1, env->He, env->We, n);
   if (P <= 0) return hipErrorInvalidValue;  // the ABI layer checks the size first
   const size_t lds = env_tabs_bytes(env->He, env->We);
   const bool use_lds = lds <= kEnvTabsMaxBytes;

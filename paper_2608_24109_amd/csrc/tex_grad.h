@@ -20,6 +20,8 @@
 #include <algorithm>
 #include <cstdlib>
 
+#include "env_grad.h"
+
 namespace exm {
 
 constexpr int32_t kTexTileW = 64;               // texels per tile along a row
@@ -100,6 +102,28 @@ __device__ __forceinline__ uint32_t tex_grad_reserve(uint32_t* counter, bool wan
   return base + (uint32_t)__popcll(m & ((1ull << __lane_id()) - 1ull));
 }
 
+// Reserves n consecutive record slots for each lane (n may differ between lanes); one atomic per
+// wave. Every lane of the wave must call it.
+__device__ __forceinline__ uint32_t tex_grad_reserve_n(uint32_t* counter, uint32_t n) {
+  uint32_t x = n;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if ((int)__lane_id() >= o) x += y;
+  }
+  const uint32_t total = __shfl(x, 63, 64);
+  uint32_t base = 0;
+  if (__lane_id() == 63 && total != 0u) base = atomicAdd(counter, total);
+  base = __shfl(base, 63, 64);
+  return base + x - n;
+}
+
+// A reserved record left unused: its first tap lies outside every map, so the sort drops it.
+__device__ __forceinline__ void tex_grad_skip(const TexGradWs& w, uint32_t slot) {
+  if ((int64_t)slot < w.cap)
+    *reinterpret_cast<uint2*>(w.rec + slot) = make_uint2(~kTexStepBit, ~kTexStepBit);
+}
+
 // Whether tap k (laid out as by bilinear_taps: tap 1 = tap 0 plus the column step dx, tap 2 = tap
 // 0 plus the row step dy, tap 3 = both) lies in the tile of tap 0 at (col, row).
 __host__ __device__ __forceinline__ bool tex_tap_in_tile(int k, uint32_t col, uint32_t row, bool dx, bool dy) {
@@ -128,6 +152,24 @@ __device__ __forceinline__ void tex_grad_put(const TexGradWs& w, uint32_t slot, 
   d[1] = make_uint4(__float_as_uint(wt[2]), __float_as_uint(wt[3]), __float_as_uint(g8[0]), __float_as_uint(g8[1]));
   d[2] = make_uint4(__float_as_uint(g8[2]), __float_as_uint(g8[3]), __float_as_uint(g8[4]), __float_as_uint(g8[5]));
   d[3] = make_uint4(__float_as_uint(g8[6]), __float_as_uint(g8[7]), 0u, 0u);
+}
+
+// Largest pixel chunk (multiple of 64, at most max_px) of an adjoint whose env-gradient records
+// (env_per_px per pixel) and map-gradient records (tex_per_px per pixel) fit in ws_bytes; the env
+// part comes first in the workspace.
+inline int64_t adjoint_chunk(size_t ws_bytes, int64_t env_per_px, int64_t tex_per_px, int32_t He, int32_t We,
+                             int64_t max_px) {
+  int64_t lo = 0, hi = (max_px + 63) / 64;
+  const int64_t per = std::max<int64_t>(std::max<int64_t>(env_per_px, tex_per_px), 1);
+  hi = std::min<int64_t>(hi, ((int64_t)1 << 31) / (64 * per));
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (env_grad_ws_bytes(mid * 64 * env_per_px, He, We) + tex_grad_ws_bytes(mid * 64 * tex_per_px) <= ws_bytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo * 64;
 }
 
 // zero the counters (a fill kernel, so that the sequence stays capturable)

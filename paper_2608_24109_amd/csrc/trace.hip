@@ -21,6 +21,7 @@
 #include <algorithm>
 
 #include "env_grad.h"
+#include "tex_grad.h"
 #include "exm_device.h"
 #include "exm_rays.h"
 
@@ -283,9 +284,15 @@ __global__ __launch_bounds__(kThreads) void k_ind_finalize(ShadeViews V, KParams
   sec_vis[gid] = bits;
 }
 
+// the map adjoint of one surface point (roughness has none here: f_d does not depend on it), as a
+// record of the tiled reduction in `slot`, or with one atomic per tap and channel
 __device__ __forceinline__ void scatter7(const Surf& S, const float ga[3], float gm, const float gq[3],
-                                         float* __restrict__ dtex) {
+                                         float* __restrict__ dtex, const TexGradWs& tg, bool tiled, uint32_t slot) {
   const float g8[8] = {ga[0], ga[1], ga[2], 0.0f, gm, gq[0], gq[1], gq[2]};
+  if (tiled) {
+    tex_grad_put(tg, slot, S.tap, S.w, g8, dtex);
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const float w = S.w[k];
@@ -314,7 +321,8 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
                                                         const float* __restrict__ dI,
                                                         const exm_sec_rec* __restrict__ rec,
                                                         const uint64_t* __restrict__ sec_vis, int64_t p0, int64_t P,
-                                                        float* __restrict__ dtex, EnvGradWs eg, bool use_lds) {
+                                                        float* __restrict__ dtex, EnvGradWs eg, TexGradWs tg,
+                                                        bool tiled, bool use_lds) {
   extern __shared__ __align__(16) char smem[];
   const EnvTabs tb = load_env_tabs(E, smem, use_lds);
   const int64_t HW = (int64_t)V.H * V.W;
@@ -333,10 +341,19 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
     G[2] = lambda_ind * dI[3 * gid + 2];
     act = f >= 0 && (G[0] != 0.0f || G[1] != 0.0f || G[2] != 0.0f);
   }
+  const bool y_mat = !(p.flags & EXM_NO_SECONDARY_MATERIAL);
+  // map-gradient records: one for x, one for each secondary hit whose maps are queried
+  uint32_t n_tex = 0;
+  if (act && tiled) {
+    n_tex = 1;
+    if (y_mat)
+      for (int j = 0; j < p.N_b; ++j) n_tex += rec[gid * p.N_b + j].tri >= 0 ? 1u : 0u;
+  }
   const uint32_t n_rec = act ? (uint32_t)__popcll(bits) : 0u;
   uint32_t slot = env_grad_reserve(eg.counter, n_rec);
+  uint32_t tslot = tiled ? tex_grad_reserve_n(tg.counter, n_tex) : 0u;
   if (!act) return;
-  const uint32_t slot_end = slot + n_rec;
+  const uint32_t slot_end = slot + n_rec, tslot_end = tslot + n_tex;
   const int32_t view = (int32_t)(gid / HW);
   const uint32_t pix = (uint32_t)(gid - view * HW);
   const float2 b = reinterpret_cast<const float2*>(bary)[gid];
@@ -356,7 +373,6 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
     const float pb = sr.pb;
     const float cxr = dot(S.ns, w);
     const float cx = fmaxf(cxr, 0.0f);
-    const bool y_mat = !(p.flags & EXM_NO_SECONDARY_MATERIAL);
     const Surf Y = query(M, T, r.tri, r.b1, r.b2, p.flags, y_mat);
     const float kdy = (1.0f - Y.m) * kInvPi;
     const float fdy[3] = {kdy * Y.a[0], kdy * Y.a[1], kdy * Y.a[2]};
@@ -431,7 +447,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
     if (p.flags & EXM_METALLIC_OFF) gmy = 0.0f;
     if (!y_mat) continue;  // nothing at y depends on the maps
     nmap_adjoint(Y, gny, gqy);
-    scatter7(Y, gay, gmy, gqy, dtex);
+    scatter7(Y, gay, gmy, gqy, dtex, tg, tiled, tslot++);
   }
   float gax[3], gmx = 0.0f, gqx[3];
   for (int c = 0; c < 3; ++c) {
@@ -440,8 +456,10 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
   }
   if (p.flags & EXM_METALLIC_OFF) gmx = 0.0f;
   nmap_adjoint(S, gnx, gqx);
-  scatter7(S, gax, gmx, gqx, dtex);
+  scatter7(S, gax, gmx, gqx, dtex, tg, tiled, tslot++);
   while (slot < slot_end) env_grad_put(eg, slot++, kNoTexel, 0.f, 0.f, 0.f);
+  if (tiled)
+    while (tslot < tslot_end) tex_grad_skip(tg, tslot++);
 }
 
 KParams kparams(const exm_params* p) {
@@ -510,33 +528,48 @@ hipError_t launch_trace_bwd(const exm_mesh* m, const exm_material* mat, const ex
                             double* denv, void* ws, size_t ws_bytes, hipStream_t s) {
   const int64_t n = (int64_t)v.n * v.H * v.W;
   const int64_t per_px = (int64_t)std::max(p->N_b, 0) * std::max(p->N_s, 0);
-  const int64_t P = env_grad_chunk(ws_bytes, per_px, env->He, env->We, n);
+  const int64_t tex_px = 1 + (int64_t)std::max(p->N_b, 0);
+  const int64_t P = adjoint_chunk(ws_bytes, per_px, tex_px, env->He, env->We, n);
   if (P <= 0) return hipErrorInvalidValue;  // the ABI layer checks the size first
   const size_t lds = env_tabs_bytes(env->He, env->We);
   const bool use_lds = lds <= kEnvTabsMaxBytes;
   const KParams kp = kparams(p);
+  const bool tiled = tex_grad_tiled(mat->Ht, mat->Wt) && !(p->flags & EXM_MAP_GRAD_ATOMIC);
   for (int64_t p0 = 0; p0 < n; p0 += P) {
     const int64_t Pc = std::min<int64_t>(P, ((n - p0) + 63) / 64 * 64);
     const EnvGradWs eg = env_grad_ws(ws, Pc * per_px, env->He, env->We);
+    const TexGradWs tg = tex_grad_ws(static_cast<char*>(ws) + env_grad_ws_bytes(Pc * per_px, env->He, env->We),
+                                     Pc * tex_px, mat->Ht, mat->Wt);
     hipError_t e = launch_env_grad_clear(eg, s);
     if (e != hipSuccess) return e;
+    if (tiled) {
+      e = launch_tex_grad_clear(tg, s);
+      if (e != hipSuccess) return e;
+    }
     {
       EXM_TIMED("trace_bwd", s);
       k_trace_bwd<<<(unsigned)((Pc + kThreads - 1) / kThreads), kThreads, use_lds ? lds : 0, s>>>(
           mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), v, tri_id, bary, kp, lambda_ind, dI,
-          sec_rec, sec_vis, p0, Pc, dtex, eg, use_lds);
+          sec_rec, sec_vis, p0, Pc, dtex, eg, tg, tiled, use_lds);
     }
     e = launch_env_grad_reduce(eg, env->He, env->We, denv, s);
     if (e != hipSuccess) return e;
+    if (tiled) {
+      e = launch_tex_grad_reduce(tg, dtex, s);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipGetLastError();
 }
 
 size_t trace_bwd_ws_bytes(int64_t n_pix, int32_t N_b, int32_t N_s, int32_t He, int32_t We) {
-  return env_grad_ws_bytes((n_pix + 63) / 64 * 64 * std::max(N_b, 0) * std::max(N_s, 0), He, We);
+  const int64_t np = (n_pix + 63) / 64 * 64;
+  return env_grad_ws_bytes(np * std::max(N_b, 0) * std::max(N_s, 0), He, We) +
+         tex_grad_ws_bytes(np * (1 + (int64_t)std::max(N_b, 0)));
 }
 size_t trace_bwd_ws_min(int32_t N_b, int32_t N_s, int32_t He, int32_t We) {
-  return env_grad_ws_bytes(64 * (int64_t)std::max(N_b, 0) * std::max(N_s, 0), He, We);
+  return env_grad_ws_bytes(64 * (int64_t)std::max(N_b, 0) * std::max(N_s, 0), He, We) +
+         tex_grad_ws_bytes(64 * (1 + (int64_t)std::max(N_b, 0)));
 }
 
 }  // namespace exm

@@ -3,7 +3,8 @@
   python -m paper_2608_24109_amd.profiling stats <kernel_stats.csv> <out.md> "<command>"
   python -m paper_2608_24109_amd.profiling pmc <fetch_counter_collection.csv> <write_counter_collection.csv>
          <workload> <copy_bytes> <out.json> "<fetch command>" "<write command>"
-  python -m paper_2608_24109_amd.profiling sq <out.md> <counter_collection.csv> "<command>" [<csv> "<command>" ...]
+  python -m paper_2608_24109_amd.profiling sq <out.md> <out.json> <counter_collection.csv> "<command>"
+         [<csv> "<command>" ...]
 
 The PMC summary converts FETCH_SIZE / WRITE_SIZE (KiB per dispatch) to bytes per launch of each
 render-pass kernel, scaled by what the same counters read for a plain device copy of known size
@@ -126,10 +127,10 @@ def pmc_json(fetch_csv: str, write_csv: str, workload: str, copy_bytes: float, o
 
 # MI355X: 256 CUs of 4 SIMDs in 32 shader engines; SQ_BUSY_CYCLES sums the engines' busy cycles
 N_SIMD, N_SE = 1024, 32
-SQ_KERNELS = ("trace_any", "dir_gen", "shade_bwd")
+SQ_KERNELS = ("trace_any", "trace_closest", "dir_gen", "shade_bwd", "ind_gen2", "trace_bwd")
 
 
-def sq_md(out: str, runs) -> dict:
+def sq_md(out: str, runs, out_json: str | None = None) -> dict:
     """Per-launch averages of SQ counters (one or more --pmc runs) for the main kernels, and three
     ratios: VALU lanes active per VALU instruction, the share of SIMD cycles issuing VALU (a wave64
     VALU instruction occupies a 16-lane SIMD for 4 cycles) and the share of wave cycles spent waiting."""
@@ -145,14 +146,15 @@ def sq_md(out: str, runs) -> dict:
                 if _name_matches(names[d], KERNELS[k]):
                     for c, v in cs.items():
                         vals[k][c].append(v)
-    res = {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in vals.items()}
+    res = {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in vals.items() if cs}
     lines = ["Commands:", ""] + [f"* `{cmd}`" for _, cmd in runs] + [
         "", "Per-launch averages; lanes = SQ_THREAD_CYCLES_VALU / SQ_INSTS_VALU; VALU busy = 4 SQ_INSTS_VALU / "
         f"(SQ_BUSY_CYCLES / {N_SE} x {N_SIMD} SIMDs); waiting = SQ_WAIT_ANY / SQ_WAVE_CYCLES.", ""]
     counters = sorted({c for cs in res.values() for c in cs})
-    lines += ["| counter | " + " | ".join(SQ_KERNELS) + " |", "|---|" + "---:|" * len(SQ_KERNELS)]
+    ks = [k for k in SQ_KERNELS if k in res]
+    lines += ["| counter | " + " | ".join(ks) + " |", "|---|" + "---:|" * len(ks)]
     for c in counters:
-        lines.append(f"| {c} | " + " | ".join(f"{res[k].get(c, float('nan')):.4g}" for k in SQ_KERNELS) + " |")
+        lines.append(f"| {c} | " + " | ".join(f"{res[k].get(c, float('nan')):.4g}" for k in ks) + " |")
 
     def ratio(k, f):
         try:
@@ -161,18 +163,21 @@ def sq_md(out: str, runs) -> dict:
             return "n/a"
 
     lines.append("| lanes active per VALU instruction | " + " | ".join(
-        ratio(k, lambda r: r["SQ_THREAD_CYCLES_VALU"] / r["SQ_INSTS_VALU"]) for k in SQ_KERNELS) + " |")
+        ratio(k, lambda r: r["SQ_THREAD_CYCLES_VALU"] / r["SQ_INSTS_VALU"]) for k in ks) + " |")
     lines.append("| VALU busy | " + " | ".join(
-        ratio(k, lambda r: 4 * r["SQ_INSTS_VALU"] / (r["SQ_BUSY_CYCLES"] / N_SE * N_SIMD)) for k in SQ_KERNELS) + " |")
+        ratio(k, lambda r: 4 * r["SQ_INSTS_VALU"] / (r["SQ_BUSY_CYCLES"] / N_SE * N_SIMD)) for k in ks) + " |")
     lines.append("| wave cycles waiting | " + " | ".join(
-        ratio(k, lambda r: r["SQ_WAIT_ANY"] / r["SQ_WAVE_CYCLES"]) for k in SQ_KERNELS) + " |")
+        ratio(k, lambda r: r["SQ_WAIT_ANY"] / r["SQ_WAVE_CYCLES"]) for k in ks) + " |")
     open(out, "w").write("\n".join(lines) + "\n")
+    if out_json:
+        json.dump({"source_sha": source_digest(), "commands": [cmd for _, cmd in runs], "kernels": res},
+                  open(out_json, "w"), indent=1)
     return res
 
 
 if __name__ == "__main__":
     if sys.argv[1] == "sq":
-        sq_md(sys.argv[2], list(zip(sys.argv[3::2], sys.argv[4::2])))
+        sq_md(sys.argv[2], list(zip(sys.argv[4::2], sys.argv[5::2])), sys.argv[3])
     elif sys.argv[1] == "stats":
         stats_md(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "pmc":

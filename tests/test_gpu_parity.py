@@ -544,19 +544,22 @@ def test_gradients_direct_map_tiling():
     _check_grads(dev, cams, dev.params(), n_texels=16, n_dirs=2, seed=2)
 
 
-def test_tiled_map_gradient_equals_atomic_scatter(small, lib):
-    """The tiled map-gradient reduction and the per-tap atomic scatter (what the adjoint uses past
+def test_tiled_map_gradient_equals_atomic_scatter(small, small_tori, lib):
+    """The tiled map-gradient reduction and the per-tap atomic scatter (what the adjoints use past
     16,384 tiles, selected here with the EXM_MAP_GRAD_ATOMIC flag) give the same dtex up to the
-    order of FP32 additions, on a 256^2 map and on a 40 x 70 one. (The atomic path is not pinned
-    to the oracle at the sizes where it runs by itself: at a width of 2^20 texels one rounding
-    step of the barycentrics moves a tap by a tenth of a texel, so device and oracle sample
-    different i.i.d. texels.)"""
+    order of FP32 additions: the direct adjoint on a 256^2 map and on a 40 x 70 one, and the direct
+    + indirect adjoints (the indirect one adds records for the primary and every secondary point)
+    on the small tori. (The atomic path is not pinned to the oracle at the sizes where it runs by
+    itself: at a width of 2^20 texels one rounding step of the barycentrics moves a tap by a tenth
+    of a texel, so device and oracle sample different i.i.d. texels.)"""
     pos, tri = I.icosphere(3)
     cams = I.ring_cameras(1, 3.0, 128, 128)
-    for dev in (small, Dev(I.make_scene("small_map", pos, tri, 40, 70, 32, 64, 1.0, cams, N_d=16))):
-        g = I.upstream_grad(1, 128, 128, seed=9)
-        _, d_tiled, e_tiled = _gpu_grad(dev, dev.sc.cams[:1], dev.params(), g)
-        _, d_atom, e_atom = _gpu_grad(dev, dev.sc.cams[:1], dev.params(flags=lib.EXM_MAP_GRAD_ATOMIC), g)
+    for dev in (small, Dev(I.make_scene("small_map", pos, tri, 40, 70, 32, 64, 1.0, cams, N_d=16)), small_tori):
+        H, W = dev.sc.cams[0].H, dev.sc.cams[0].W
+        g = I.upstream_grad(1, H, W, seed=9)
+        lam = 0.7 if dev.sc.N_b else 1.0
+        _, d_tiled, e_tiled = _gpu_grad(dev, dev.sc.cams[:1], dev.params(), g, lam)
+        _, d_atom, e_atom = _gpu_grad(dev, dev.sc.cams[:1], dev.params(flags=lib.EXM_MAP_GRAD_ATOMIC), g, lam)
         scale = np.abs(d_atom).max()
         assert scale > 0 and np.count_nonzero(d_atom) > 1000
         assert np.abs(d_tiled - d_atom).max() <= 1e-5 * scale, np.abs(d_tiled - d_atom).max() / scale
