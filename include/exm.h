@@ -178,6 +178,32 @@ exm_status exm_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_materi
                          const int32_t* tri_id, const float* bary, const exm_params* p,
                          float* L_dir, uint64_t* vis, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Batched direct pass for serving (relighting of exported assets, Computational Efficiency): one
+ * launch sequence (env sampling and shading, shadow-ray traversal, finalisation) over the pixels
+ * of several requests, each with its own asset (mesh, BVH, maps), env map and view. Per request:
+ * the same outputs, bit for bit, as exm_shade_fwd of that request alone with p and tmin: the
+ * random numbers are keyed by cam.view_id (the request id), so a result does not depend on the
+ * batch it runs in. At most 8 requests share one launch sequence; more are run 8 at a time. */
+typedef struct {
+  const exm_mesh* mesh;     /* prepared by exm_mesh_prepare */
+  const exm_bvh* bvh;
+  const exm_material* mat;
+  const exm_env* env;       /* with its tables from exm_build_env_sampler */
+  exm_camera cam;           /* the request's view (host); view_id keys its random numbers */
+  float tmin;               /* ray start distance of the asset (world units); replaces p->tmin */
+  const int32_t* tri_id;    /* [H,W] G-buffer of the view (exm_raster_gbuffer) */
+  const float* bary;        /* [H,W,2] */
+  float* L_dir;             /* [H,W,3] out */
+  uint64_t* vis;            /* [H,W] out */
+} exm_request;
+
+/* ws: device workspace (256-byte aligned) of at least exm_shade_fwd_batch_workspace_size bytes for
+ * these requests (the ray records of up to 8 requests at once; no chunking). reqs is host memory;
+ * p applies to every request except its tmin. */
+size_t exm_shade_fwd_batch_workspace_size(const exm_request* reqs_host, int32_t n_req, int32_t N_d);
+exm_status exm_shade_fwd_batch(const exm_request* reqs_host, int32_t n_req, const exm_params* p, void* ws,
+                               size_t ws_bytes, hipStream_t stream);
+
 /* exm_shade_fwd without a workspace argument, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * outputs, bit for bit, computed in a device scratch array of 64 MiB that the library holds on

@@ -63,6 +63,12 @@ class exm_params(C.Structure):
                 ("flags", C.c_uint32)]
 
 
+class exm_request(C.Structure):
+    _fields_ = [("mesh", C.c_void_p), ("bvh", C.c_void_p), ("mat", C.c_void_p), ("env", C.c_void_p),
+                ("cam", exm_camera), ("tmin", C.c_float), ("tri_id", C.c_void_p), ("bary", C.c_void_p),
+                ("L_dir", C.c_void_p), ("vis", C.c_void_p)]
+
+
 SEC_REC_BYTES = 12  # exm_sec_rec {int32 tri; float b1, b2}
 
 
@@ -107,6 +113,8 @@ def _load() -> C.CDLL:
         "exm_trace_indirect_workspace_size": (C.c_size_t, [i32, i32, i32, i32, i32]),
         "exm_trace_indirect_workspace_min": (C.c_size_t, [i32, i32]),
         "exm_trace_indirect": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
+        "exm_shade_fwd_batch_workspace_size": (C.c_size_t, [vp, i32, i32]),
+        "exm_shade_fwd_batch": (st, [vp, i32, vp, vp, C.c_size_t, vp]),
         "exm_shade_fwd_noalloc": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]),
         "exm_shade_fwd_counted": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp, vp]),
         "exm_trace_indirect_counted": (st, [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp,
@@ -288,6 +296,33 @@ def exm_shade_fwd(mesh, bvh: Bvh, mat: exm_material, env: exm_env, cams, tri_id,
     _check(lib.exm_shade_fwd(C.byref(mesh), bvh.handle, C.byref(mat), C.byref(env), cams, n, _ptr(tri_id),
                              _ptr(bary), C.byref(p), _ptr(L_dir), _ptr(vis), _ptr(ws), ws.numel(), _stream(stream)),
            "exm_shade_fwd")
+
+
+def request(mesh, mat, env, cam: exm_camera, tmin: float, tri_id, bary, L_dir, vis) -> exm_request:
+    """One request of a batched direct pass: device asset objects (DeviceMesh with its BVH,
+    DeviceMaterial, DeviceEnv), its camera, ray start distance and [1,H,W...] buffers. The
+    objects must outlive the call."""
+    import torch
+    H, W = cam.H, cam.W
+    _need(tri_id, torch.int32, (1, H, W), "tri_id")
+    _need(bary, torch.float32, (1, H, W, 2), "bary")
+    _need(L_dir, torch.float32, (1, H, W, 3), "L_dir")
+    _need(vis, torch.uint64, (1, H, W), "vis")
+    return exm_request(C.addressof(mesh.s), mesh.bvh.handle, C.addressof(mat.s), C.addressof(env.s), cam, float(tmin),
+                       _ptr(tri_id), _ptr(bary), _ptr(L_dir), _ptr(vis))
+
+
+def _requests(reqs) -> C.Array:
+    return (exm_request * len(reqs))(*reqs)
+
+
+def exm_shade_fwd_batch_workspace_size(reqs, N_d: int) -> int:
+    return int(lib.exm_shade_fwd_batch_workspace_size(_requests(reqs), len(reqs), N_d))
+
+
+def exm_shade_fwd_batch(reqs, p: exm_params, ws, stream=None) -> None:
+    _check(lib.exm_shade_fwd_batch(_requests(reqs), len(reqs), C.byref(p), _ptr(ws), ws.numel(), _stream(stream)),
+           "exm_shade_fwd_batch")
 
 
 def exm_shade_fwd_noalloc(mesh, bvh: Bvh, mat: exm_material, env: exm_env, cams, tri_id, bary, p: exm_params, L_dir,

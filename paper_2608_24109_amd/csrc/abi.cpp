@@ -110,6 +110,14 @@ exm_status check_gbuffer(const int32_t* tri_id, const float* bary) {
   return EXM_OK;
 }
 
+#define EXM_TRY(x)                        \
+  do {                                    \
+    exm_status _s = (x);                  \
+    if (_s != EXM_OK) return _s;          \
+  } while (0)
+
+}  // namespace
+
 ShadeViews shade_views(const exm_camera* c, int32_t first, int32_t n) {
   ShadeViews v;
   std::memset(&v, 0, sizeof(v));
@@ -122,14 +130,6 @@ ShadeViews shade_views(const exm_camera* c, int32_t first, int32_t n) {
   }
   return v;
 }
-
-#define EXM_TRY(x)                        \
-  do {                                    \
-    exm_status _s = (x);                  \
-    if (_s != EXM_OK) return _s;          \
-  } while (0)
-
-}  // namespace
 
 exm_status fail(exm_status s, const std::string& msg) {
   g_last_error = msg;
@@ -333,6 +333,40 @@ exm_status exm_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_materi
                          const exm_params* p, float* L_dir, uint64_t* vis, void* ws, size_t ws_bytes,
                          hipStream_t stream) {
   return shade_fwd_impl(m, bvh, mat, env, cams, nViews, tri_id, bary, p, L_dir, vis, ws, ws_bytes, nullptr, stream);
+}
+
+size_t exm_shade_fwd_batch_workspace_size(const exm_request* reqs, int32_t n_req, int32_t N_d) {
+  if (!reqs || n_req <= 0 || N_d < 0 || N_d > 64) return 0;
+  for (int32_t i = 0; i < n_req; ++i)
+    if (reqs[i].cam.H <= 0 || reqs[i].cam.W <= 0 || (int64_t)reqs[i].cam.H * reqs[i].cam.W > ((int64_t)1 << 26)) return 0;
+  return shade_fwd_batch_ws_bytes(reqs, n_req, N_d);
+}
+
+exm_status exm_shade_fwd_batch(const exm_request* reqs, int32_t n_req, const exm_params* p, void* ws, size_t ws_bytes,
+                               hipStream_t stream) {
+  if (!reqs || n_req <= 0) return fail(EXM_E_INVAL, "exm_shade_fwd_batch: no requests");
+  EXM_TRY(check_params(p, false));
+  for (int32_t i = 0; i < n_req; ++i) {
+    const exm_request& r = reqs[i];
+    EXM_TRY(check_mesh(r.mesh, true));
+    if (!r.bvh) return fail(EXM_E_INVAL, "exm_shade_fwd_batch: bvh is NULL");
+    EXM_TRY(check_material(r.mat));
+    EXM_TRY(check_env(r.env));
+    EXM_TRY(check_cams(&r.cam, 1));
+    if ((int64_t)r.cam.H * r.cam.W > ((int64_t)1 << 26)) return fail(EXM_E_INVAL, "exm_shade_fwd_batch: view too large");
+    EXM_TRY(check_gbuffer(r.tri_id, r.bary));
+    if (!r.L_dir || !r.vis) return fail(EXM_E_INVAL, "exm_shade_fwd_batch: output pointer is NULL");
+    if (!std::isfinite(r.tmin) || r.tmin < 0.f) return fail(EXM_E_INVAL, "exm_shade_fwd_batch: tmin must be finite and >= 0");
+  }
+  if (!ws || !aligned(ws, 256) || ws_bytes < shade_fwd_batch_ws_bytes(reqs, n_req, p->N_d))
+    return fail(EXM_E_INVAL, "workspace must be 256-byte aligned and at least exm_shade_fwd_batch_workspace_size bytes");
+  EXM_TRY(check_device());
+  for (int32_t i0 = 0; i0 < n_req; i0 += kMaxFrames) {
+    const int32_t n = std::min(kMaxFrames, n_req - i0);
+    const hipError_t e = launch_shade_fwd_batch(reqs + i0, n, p, ws, ws_bytes, nullptr, stream);
+    if (e != hipSuccess) return fail(EXM_E_HIP, std::string("exm_shade_fwd_batch: ") + hipGetErrorString(e));
+  }
+  return EXM_OK;
 }
 
 exm_status exm_shade_fwd_noalloc(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,

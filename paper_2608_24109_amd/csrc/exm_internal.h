@@ -36,6 +36,8 @@ constexpr int64_t kMaxBvhTris = (int64_t)2 << kMaxDepth;
 
 // Views per launch: camera data travels in kernel arguments.
 constexpr int kViewsPerLaunch = 8;
+// Requests per launch of a batched pass (their descriptors travel in kernel arguments too).
+constexpr int kMaxFrames = 8;
 
 struct RasterViews {
   int32_t n, H, W;
@@ -149,6 +151,11 @@ hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_mat
                             float* L_dir, uint64_t* vis, void* ws, size_t ws_bytes, unsigned long long* counters,
                             hipStream_t s);
 size_t shade_fwd_ws_bytes(int64_t n_pix, int32_t N_d);
+// a batch of at most 8 requests in one launch sequence (gen, trace, finalize)
+hipError_t launch_shade_fwd_batch(const exm_request* r, int32_t n, const exm_params* p, void* ws, size_t ws_bytes,
+                                  unsigned long long* counters, hipStream_t s);
+size_t shade_fwd_batch_ws_bytes(const exm_request* r, int32_t n, int32_t N_d);
+ShadeViews shade_views(const exm_camera* c, int32_t first, int32_t n);
 size_t shade_fwd_ws_min(int32_t N_d);
 // Scratch of exm_shade_fwd_noalloc: a device array of this many bytes per GPU; noalloc_scratch
 // gives the current device's address (looked up once per device).

@@ -31,9 +31,20 @@ struct RayBatch {
 // postponed leaf (both swept on the displaced sphere and the tori: 32 and 8).
 constexpr int32_t kRayRefill = 32;
 constexpr int32_t kTravLeafGate = 8;
+// The BVHs of a launch whose rays come from several assets (a batch of requests): region r's rays
+// belong to asset f, region_start[f] <= r < region_start[f + 1].
+struct BvhTable {
+  BvhView b[kMaxFrames];
+  int32_t region_start[kMaxFrames + 1];
+  int32_t n;
+};
+
 // any-hit: out[slot] = 1 if something is hit at t >= tmin (the skipped triangle excepted)
 hipError_t launch_trace_any(const exm_bvh* bvh, const RayBatch& rb, uint8_t* out, unsigned long long* counters,
                             hipStream_t s);
+// any-hit over the regions of a batch, each region traversing its own asset's BVH
+hipError_t launch_trace_any_batch(const BvhTable& t, const RayBatch& rb, uint8_t* out, unsigned long long* counters,
+                                  hipStream_t s);
 // closest hit: out[slot] = {id (-1 miss), t, b1, b2}
 hipError_t launch_trace_closest(const exm_bvh* bvh, const RayBatch& rb, HitRec* out, unsigned long long* counters,
                                 hipStream_t s);

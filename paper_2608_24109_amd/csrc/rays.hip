@@ -26,13 +26,17 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
 }
 
-template <bool ANY, bool COUNT>
-__global__ __launch_bounds__(kThreads) void k_trace(BvhView B, RayBatch rb, int32_t refill, int32_t leaf_gate,
-                                                    HitRec* __restrict__ out_hit,
+// BATCH: the regions come from several assets; a wave looks up the BVH of each region it claims
+// and every lane keeps the BVH of its own ray (lanes of one wave may hold rays of two regions).
+template <bool ANY, bool COUNT, bool BATCH>
+__global__ __launch_bounds__(kThreads) void k_trace(BvhView B0, BvhTable bt, RayBatch rb, int32_t refill,
+                                                    int32_t leaf_gate, HitRec* __restrict__ out_hit,
                                                     uint8_t* __restrict__ out_any,
                                                     unsigned long long* __restrict__ counters) {
   __shared__ int32_t stack_mem[kStack * kThreads];
   int32_t* stack = stack_mem + threadIdx.x;
+  BvhView B = B0;        // the BVH of the lane's ray
+  BvhView B_region = B0;  // the BVH of the region being handed out (wave-uniform)
   // wave-uniform region cursor
   int32_t region = -1;
   uint32_t next = 0, count = 0;
@@ -62,6 +66,11 @@ __global__ __launch_bounds__(kThreads) void k_trace(BvhView B, RayBatch rb, int3
         }
         count = rb.count[region];
         next = 0;
+        if (BATCH) {
+          int32_t f = 0;
+          while (f + 1 < bt.n && region >= bt.region_start[f + 1]) ++f;
+          B_region = bt.b[f];
+        }
         base = (int64_t)region * rb.region_stride;
         continue;
       }
@@ -69,6 +78,7 @@ __global__ __launch_bounds__(kThreads) void k_trace(BvhView B, RayBatch rb, int3
       const uint32_t rank = lanes_below(need);
       if (!have_ray && rank < avail) {
         slot = base + next + rank;
+        if (BATCH) B = B_region;
         const RayRec R = rb.rays[slot];
         ray = make_ray(mk(R.o[0], R.o[1], R.o[2]), mk(R.d[0], R.d[1], R.d[2]));
         tmin = R.tmin;
@@ -104,14 +114,14 @@ __global__ __launch_bounds__(kThreads) void k_trace(BvhView B, RayBatch rb, int3
 
 __global__ void k_reset_counter(uint32_t* c) { *c = 0u; }
 
-template <bool ANY, bool COUNT>
-hipError_t launch_impl(const exm_bvh* bvh, const RayBatch& rb, HitRec* out_hit, uint8_t* out_any,
+template <bool ANY, bool COUNT, bool BATCH>
+hipError_t launch_impl(const BvhView& B0, const BvhTable& bt, const RayBatch& rb, HitRec* out_hit, uint8_t* out_any,
                        unsigned long long* counters, hipStream_t s) {
   if (rb.n_regions <= 0) return hipSuccess;
   int dev = 0, cus = 256, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return hipGetLastError();
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return hipGetLastError();
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_trace<ANY, COUNT>, kThreads, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_trace<ANY, COUNT, BATCH>, kThreads, 0) !=
           hipSuccess ||
       per_cu < 1)
     per_cu = 1;
@@ -120,9 +130,8 @@ hipError_t launch_impl(const exm_bvh* bvh, const RayBatch& rb, HitRec* out_hit, 
   k_reset_counter<<<1, 1, 0, s>>>(rb.region_counter);
   {
     EXM_TIMED(ANY ? "trace_any" : "trace_closest", s);
-    k_trace<ANY, COUNT><<<(unsigned)blocks, kThreads, 0, s>>>(BvhView{bvh->nodes, bvh->tris, bvh->root_is_leaf}, rb,
-                                                               kRayRefill, kTravLeafGate, out_hit,
-                                                               out_any, counters);
+    k_trace<ANY, COUNT, BATCH><<<(unsigned)blocks, kThreads, 0, s>>>(B0, bt, rb, kRayRefill, kTravLeafGate, out_hit,
+                                                                      out_any, counters);
   }
   return hipGetLastError();
 }
@@ -131,14 +140,24 @@ hipError_t launch_impl(const exm_bvh* bvh, const RayBatch& rb, HitRec* out_hit, 
 
 hipError_t launch_trace_any(const exm_bvh* bvh, const RayBatch& rb, uint8_t* out, unsigned long long* counters,
                             hipStream_t s) {
-  return counters ? launch_impl<true, true>(bvh, rb, nullptr, out, counters, s)
-                  : launch_impl<true, false>(bvh, rb, nullptr, out, nullptr, s);
+  const BvhView B{bvh->nodes, bvh->tris, bvh->root_is_leaf};
+  const BvhTable none{};
+  return counters ? launch_impl<true, true, false>(B, none, rb, nullptr, out, counters, s)
+                  : launch_impl<true, false, false>(B, none, rb, nullptr, out, nullptr, s);
+}
+
+hipError_t launch_trace_any_batch(const BvhTable& t, const RayBatch& rb, uint8_t* out, unsigned long long* counters,
+                                  hipStream_t s) {
+  return counters ? launch_impl<true, true, true>(t.b[0], t, rb, nullptr, out, counters, s)
+                  : launch_impl<true, false, true>(t.b[0], t, rb, nullptr, out, nullptr, s);
 }
 
 hipError_t launch_trace_closest(const exm_bvh* bvh, const RayBatch& rb, HitRec* out, unsigned long long* counters,
                                 hipStream_t s) {
-  return counters ? launch_impl<false, true>(bvh, rb, out, nullptr, counters, s)
-                  : launch_impl<false, false>(bvh, rb, out, nullptr, nullptr, s);
+  const BvhView B{bvh->nodes, bvh->tris, bvh->root_is_leaf};
+  const BvhTable none{};
+  return counters ? launch_impl<false, true, false>(B, none, rb, out, nullptr, counters, s)
+                  : launch_impl<false, false, false>(B, none, rb, out, nullptr, nullptr, s);
 }
 
 }  // namespace exm

@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
 
 #include "env_grad.h"
 #include "exm_device.h"
@@ -64,20 +65,15 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return (uint32_t)__popcll(mask & ((1ull << __lane_id()) - 1ull));
 }
 
-// Chunk [p0, p0 + P) of the launch's pixels; P is a multiple of 64 and waves past it exit whole.
-// COUNT: also accumulates env samples drawn into counters[3].
+// One thread per pixel: pixel gid of the views V, workspace position `local` (its region is
+// local / 64). COUNT: also accumulates env samples drawn into counters[3].
 template <bool COUNT>
-__global__ __launch_bounds__(kThreads) void k_dir_gen(MeshView M, TexView T, EnvView E, ShadeViews V,
-                                                      const int32_t* __restrict__ tri_id,
-                                                      const float* __restrict__ bary, KParams p, int64_t p0,
-                                                      int64_t P, DirectWs ws, unsigned long long* __restrict__ counters,
-                                                      bool use_lds) {
-  extern __shared__ __align__(16) char smem[];
-  const EnvTabs tb = load_env_tabs(E, smem, use_lds);
-  const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if ((local & ~(int64_t)63) >= P) return;  // whole waves only
+__device__ __forceinline__ void dir_gen_pixel(const MeshView& M, const TexView& T, const EnvView& E, const EnvTabs& tb,
+                                              const ShadeViews& V, const int32_t* __restrict__ tri_id,
+                                              const float* __restrict__ bary, const KParams& p, int64_t gid,
+                                              int64_t local, const DirectWs& ws,
+                                              unsigned long long* __restrict__ counters) {
   const int64_t HW = (int64_t)V.H * V.W;
-  const int64_t gid = p0 + local;
   const int64_t region = local >> 6;
   const int32_t f = gid < HW * V.n ? tri_id[gid] : -1;
   Surf S;
@@ -157,12 +153,64 @@ __global__ __launch_bounds__(kThreads) void k_dir_gen(MeshView M, TexView T, Env
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_dir_finalize(ShadeViews V, KParams p, int64_t p0, int64_t P,
-                                                           DirectWs ws, float* __restrict__ L_dir,
-                                                           uint64_t* __restrict__ vis) {
+// Chunk [p0, p0 + P) of the launch's pixels; P is a multiple of 64 and waves past it exit whole.
+template <bool COUNT>
+__global__ __launch_bounds__(kThreads) void k_dir_gen(MeshView M, TexView T, EnvView E, ShadeViews V,
+                                                      const int32_t* __restrict__ tri_id,
+                                                      const float* __restrict__ bary, KParams p, int64_t p0,
+                                                      int64_t P, DirectWs ws, unsigned long long* __restrict__ counters,
+                                                      bool use_lds) {
+  extern __shared__ __align__(16) char smem[];
+  const EnvTabs tb = load_env_tabs(E, smem, use_lds);
   const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if ((local & ~(int64_t)63) >= P) return;
-  const int64_t gid = p0 + local;
+  if ((local & ~(int64_t)63) >= P) return;  // whole waves only
+  dir_gen_pixel<COUNT>(M, T, E, tb, V, tri_id, bary, p, p0 + local, local, ws, counters);
+}
+
+// The frames of a batched launch (requests with their own asset, env map and view): frame f
+// holds workspace pixels [block_start[f], block_start[f + 1]) * kThreads, so no block spans two.
+struct DirFrame {
+  MeshView M;
+  TexView T;
+  EnvView E;
+  ShadeViews V;
+  const int32_t* tri_id;
+  const float* bary;
+  float* L_dir;
+  uint64_t* vis;
+  float tmin;
+  int32_t use_lds;
+};
+struct DirBatch {
+  DirFrame f[kMaxFrames];
+  int32_t block_start[kMaxFrames + 1];
+  int32_t n;
+};
+static_assert(sizeof(DirBatch) <= 3584, "a batch travels in kernel arguments");
+
+__device__ __forceinline__ int32_t frame_of_block(const DirBatch& bt, int32_t block) {
+  int32_t f = 0;
+  while (f + 1 < bt.n && block >= bt.block_start[f + 1]) ++f;
+  return f;
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(kThreads) void k_dir_gen_batch(DirBatch bt, KParams p, DirectWs ws,
+                                                            unsigned long long* __restrict__ counters) {
+  extern __shared__ __align__(16) char smem[];
+  const int32_t fi = frame_of_block(bt, (int32_t)blockIdx.x);
+  const DirFrame& F = bt.f[fi];
+  const EnvTabs tb = load_env_tabs(F.E, smem, F.use_lds != 0);
+  const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  KParams pf = p;
+  pf.tmin = F.tmin;
+  dir_gen_pixel<COUNT>(F.M, F.T, F.E, tb, F.V, F.tri_id, F.bary, pf, local - (int64_t)bt.block_start[fi] * kThreads,
+                       local, ws, counters);
+}
+
+__device__ __forceinline__ void dir_finalize_pixel(const ShadeViews& V, const KParams& p, int64_t gid, int64_t local,
+                                                   const DirectWs& ws, float* __restrict__ L_dir,
+                                                   uint64_t* __restrict__ vis) {
   const bool valid = gid < (int64_t)V.H * V.W * V.n;
   const uint64_t mask = ws.mask[local];
   const bool novis = (p.flags & EXM_NO_VIS) != 0;
@@ -212,6 +260,21 @@ __global__ __launch_bounds__(kThreads) void k_dir_finalize(ShadeViews V, KParams
   L_dir[3 * gid + 1] = L[1] * inv;
   L_dir[3 * gid + 2] = L[2] * inv;
   vis[gid] = bits;
+}
+
+__global__ __launch_bounds__(kThreads) void k_dir_finalize(ShadeViews V, KParams p, int64_t p0, int64_t P,
+                                                           DirectWs ws, float* __restrict__ L_dir,
+                                                           uint64_t* __restrict__ vis) {
+  const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if ((local & ~(int64_t)63) >= P) return;
+  dir_finalize_pixel(V, p, p0 + local, local, ws, L_dir, vis);
+}
+
+__global__ __launch_bounds__(kThreads) void k_dir_finalize_batch(DirBatch bt, KParams p, DirectWs ws) {
+  const int32_t fi = frame_of_block(bt, (int32_t)blockIdx.x);
+  const DirFrame& F = bt.f[fi];
+  const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  dir_finalize_pixel(F.V, p, local - (int64_t)bt.block_start[fi] * kThreads, local, ws, F.L_dir, F.vis);
 }
 
 // Accumulated adjoint of one surface point w.r.t. its material values and shading normal.
@@ -453,6 +516,72 @@ hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_mat
     }
   }
   return hipGetLastError();
+}
+
+// Workspace pixels of a batch: each request's pixels rounded up to whole blocks.
+int64_t batch_pixels(const exm_request* r, int32_t n) {
+  int64_t P = 0;
+  for (int32_t i = 0; i < n; ++i) P += ((int64_t)r[i].cam.H * r[i].cam.W + kThreads - 1) / kThreads * kThreads;
+  return P;
+}
+
+hipError_t launch_shade_fwd_batch(const exm_request* r, int32_t n, const exm_params* p, void* ws_ptr, size_t ws_bytes,
+                                  unsigned long long* counters, hipStream_t s) {
+  if (n <= 0 || n > kMaxFrames) return hipErrorInvalidValue;
+  const int64_t P = batch_pixels(r, n);
+  if (direct_ws_bytes(P, p->N_d) > ws_bytes) return hipErrorInvalidValue;  // the ABI layer checks the size first
+  DirBatch bt;
+  BvhTable tt;
+  std::memset(&bt, 0, sizeof(bt));
+  std::memset(&tt, 0, sizeof(tt));
+  bt.n = tt.n = n;
+  size_t lds = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    DirFrame& F = bt.f[i];
+    F.M = mesh_view(r[i].mesh);
+    F.T = TexView{r[i].mat->Ht, r[i].mat->Wt, r[i].mat->tex};
+    F.E = env_view(r[i].env);
+    F.V = shade_views(&r[i].cam, 0, 1);
+    F.tri_id = r[i].tri_id;
+    F.bary = r[i].bary;
+    F.L_dir = r[i].L_dir;
+    F.vis = r[i].vis;
+    F.tmin = r[i].tmin;
+    const size_t b = env_tabs_bytes(r[i].env->He, r[i].env->We);
+    F.use_lds = b <= kEnvTabsMaxBytes;
+    if (F.use_lds) lds = std::max(lds, b);
+    tt.b[i] = bvh_view(r[i].bvh);
+    const int64_t nb = ((int64_t)r[i].cam.H * r[i].cam.W + kThreads - 1) / kThreads;
+    bt.block_start[i + 1] = bt.block_start[i] + (int32_t)nb;
+    tt.region_start[i + 1] = bt.block_start[i + 1] * (kThreads / 64);
+  }
+  const KParams kp = kparams(p);
+  const DirectWs ws = direct_ws(ws_ptr, P, p->N_d);
+  const unsigned nb = (unsigned)bt.block_start[n];
+  {
+    EXM_TIMED("dir_gen", s);
+    if (counters)
+      k_dir_gen_batch<true><<<nb, kThreads, lds, s>>>(bt, kp, ws, counters);
+    else
+      k_dir_gen_batch<false><<<nb, kThreads, lds, s>>>(bt, kp, ws, nullptr);
+  }
+  if (p->N_d > 0 && !(p->flags & EXM_NO_VIS)) {
+    const RayBatch rb{ws.rays, ws.count, (int32_t)(P / 64), 64 * (int64_t)p->N_d, ws.counter};
+    const hipError_t e = launch_trace_any_batch(tt, rb, ws.hit, counters, s);
+    if (e != hipSuccess) return e;
+  }
+  {
+    EXM_TIMED("dir_finalize", s);
+    k_dir_finalize_batch<<<nb, kThreads, 0, s>>>(bt, kp, ws);
+  }
+  return hipGetLastError();
+}
+
+size_t shade_fwd_batch_ws_bytes(const exm_request* r, int32_t n, int32_t N_d) {
+  size_t b = 0;
+  for (int32_t i = 0; i < n; i += kMaxFrames)
+    b = std::max(b, direct_ws_bytes(batch_pixels(r + i, std::min(kMaxFrames, n - i)), N_d));
+  return b;
 }
 
 size_t shade_fwd_ws_bytes(int64_t n_pix, int32_t N_d) { return direct_ws_bytes((n_pix + 63) / 64 * 64, N_d); }

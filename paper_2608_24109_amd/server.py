@@ -50,16 +50,21 @@ class Request:
 
 
 class Scheduler:
-    """FIFO admission into `slots` render slots under an HBM budget (bytes)."""
+    """FIFO admission into `slots` render slots under an HBM budget (bytes).
 
-    def __init__(self, backend, budget: int, slots: int):
+    With batch_max > 1 and a backend that has `launch_batch`, a slot takes a batch: the admitted
+    head of the queue plus the requests right behind it while they are direct-only and at most
+    batch_res^2 pixels (up to batch_max of them, each admitted by footprint as usual); the batch
+    renders in one launch sequence of the direct pass and its requests retire together."""
+
+    def __init__(self, backend, budget: int, slots: int, batch_max: int = 1, batch_res: int = 512):
         if slots < 1:
             raise ValueError("need at least one slot")
         self.b = backend
         self.budget = int(budget)
         self.free = list(range(slots - 1, -1, -1))
         self.queue: collections.deque[Request] = collections.deque()
-        self.inflight: dict[int, tuple[Request, object, int]] = {}
+        self.inflight: dict[int, tuple[list[Request], object, int]] = {}
         self.resident: collections.OrderedDict[int, int] = collections.OrderedDict()  # LRU first
         self.pins: collections.Counter = collections.Counter()
         self.fixed = int(backend.fixed_bytes())
@@ -67,6 +72,9 @@ class Scheduler:
         self.peak = self.used
         self.loads = 0
         self.evictions = 0
+        self.batch_max = max(1, int(batch_max)) if hasattr(backend, "launch_batch") else 1
+        self.batch_res = int(batch_res)
+        self.batches = 0
         if self.fixed > self.budget:
             raise ValueError(f"resident geometry and env tables ({self.fixed} B) exceed the budget")
 
@@ -77,60 +85,93 @@ class Scheduler:
     def idle(self) -> bool:
         return not self.queue and not self.inflight
 
+    def batchable(self, req: Request) -> bool:
+        return self.batch_max > 1 and not req.indirect and req.res <= self.batch_res
+
     def poll(self, clock) -> list[Request]:
         """Retire finished requests (completion time read from `clock`)."""
         out = []
         for slot in list(self.inflight):
-            req, tok, nb = self.inflight[slot]
+            reqs, tok, nb = self.inflight[slot]
             if self.b.done(tok):
-                req.t_done = clock()
-                req.result = self.b.result(tok)
-                req.status = "done"
+                res = self.b.result(tok)
+                res = res if isinstance(res, list) else [res]
+                t = clock()
+                for req, r in zip(reqs, res):
+                    req.t_done = t
+                    req.result = r
+                    req.status = "done"
+                    self.pins[req.asset] -= 1
+                    out.append(req)
                 del self.inflight[slot]
                 self.free.append(slot)
                 self.used -= nb
-                self.pins[req.asset] -= 1
-                out.append(req)
         return out
+
+    def _fits(self, req: Request, slot: int):
+        """Reserve the footprint of `req` (evicting idle maps as needed) and load its map into
+        `slot`'s stream; returns the request bytes, None if it must wait, -1 if it never fits."""
+        need = int(self.b.request_bytes(req))
+        mb = 0 if req.asset in self.resident else int(self.b.map_bytes(req.asset))
+        if self.fixed + need + mb > self.budget:
+            return -1
+        while self.used + need + mb > self.budget:
+            victim = next((a for a in self.resident if self.pins[a] == 0 and a != req.asset), None)
+            if victim is None:
+                break
+            self.used -= self.resident.pop(victim)
+            self.b.evict_map(victim)
+            self.evictions += 1
+        if self.used + need + mb > self.budget:
+            return None
+        if mb:
+            self.b.load_map(req.asset, slot)
+            self.resident[req.asset] = mb
+            self.used += mb
+            self.loads += 1
+        else:
+            self.resident.move_to_end(req.asset)
+        self.pins[req.asset] += 1
+        self.used += need
+        self.peak = max(self.peak, self.used)
+        return need
 
     def admit(self, clock) -> list[Request]:
         """Admit queued requests in order while a slot is free and their footprint fits."""
         started, rejected = [], []
         while self.queue and self.free:
             req = self.queue[0]
-            need = int(self.b.request_bytes(req))
-            mb = 0 if req.asset in self.resident else int(self.b.map_bytes(req.asset))
-            if self.fixed + need + mb > self.budget:
+            slot = self.free[-1]
+            need = self._fits(req, slot)
+            if need == -1:
                 self.queue.popleft()
                 req.status = "rejected"
                 req.t_done = clock()
                 rejected.append(req)
                 continue
-            while self.used + need + mb > self.budget:
-                victim = next((a for a in self.resident if self.pins[a] == 0 and a != req.asset), None)
-                if victim is None:
-                    break
-                self.used -= self.resident.pop(victim)
-                self.b.evict_map(victim)
-                self.evictions += 1
-            if self.used + need + mb > self.budget:
+            if need is None:
                 break  # wait for in-flight requests to release memory
             self.queue.popleft()
-            slot = self.free.pop()
-            if mb:
-                self.b.load_map(req.asset, slot)
-                self.resident[req.asset] = mb
-                self.used += mb
-                self.loads += 1
+            self.free.pop()
+            batch, total = [req], need
+            if self.batchable(req):
+                while self.queue and len(batch) < self.batch_max and self.batchable(self.queue[0]):
+                    nxt = self._fits(self.queue[0], slot)
+                    if nxt is None or nxt == -1:
+                        break
+                    batch.append(self.queue.popleft())
+                    total += nxt
+            t = clock()
+            for r in batch:
+                r.t_admit = t
+                r.status = "running"
+            if len(batch) > 1:
+                tok = self.b.launch_batch(batch, slot)
+                self.batches += 1
             else:
-                self.resident.move_to_end(req.asset)
-            self.pins[req.asset] += 1
-            self.used += need
-            self.peak = max(self.peak, self.used)
-            req.t_admit = clock()
-            req.status = "running"
-            self.inflight[slot] = (req, self.b.launch(req, slot), need)
-            started.append(req)
+                tok = self.b.launch(req, slot)
+            self.inflight[slot] = (batch, tok, total)
+            started.extend(batch)
         return started + rejected
 
 
@@ -273,7 +314,7 @@ class DeviceBackend:
             s.wait_event(ready)
             mat.tex.record_stream(s)
             bufs = PassBuffers(1, req.res, req.res, p.N_b, device=self.device, ws_cap=self.ws_cap)
-            render_forward(self.meshes[req.asset], mat, self.envs[req.env], L.cameras([cam], [0]), p, bufs,
+            render_forward(self.meshes[req.asset], mat, self.envs[req.env], L.cameras([cam], [req.rid]), p, bufs,
                            rebuild_tables=False)
             if p.N_b > 0:
                 bufs.L_dir.add_(bufs.L_ind)
@@ -282,6 +323,40 @@ class DeviceBackend:
             ev = torch.cuda.Event()
             ev.record(s)
         return _Token(ev, out, [bufs, mat])
+
+    def launch_batch(self, reqs: list[Request], slot: int) -> _Token:
+        """Direct-only requests rendered together: a G-buffer per request, then one batched
+        direct pass (exm_shade_fwd_batch) over all of them, on the slot's stream."""
+        from . import _lib as L
+        from . import inputs as I
+        from .render import PassBuffers, raster
+        torch = self.torch
+        s = self.streams[slot]
+        keep, bufs_all, creqs, outs = [], [], [], []
+        with torch.cuda.stream(s):
+            for req in reqs:
+                mat, ready = self.maps[req.asset]
+                s.wait_event(ready)
+                mat.tex.record_stream(s)
+                a = self.assets[req.asset]
+                cam = L.cameras([I.relight_camera(a.pos, req.res, req.azimuth)], [req.rid])
+                bufs = PassBuffers(1, req.res, req.res, 0, device=self.device)
+                raster(self.meshes[req.asset], cam, bufs)
+                creqs.append(L.request(self.meshes[req.asset], mat, self.envs[req.env], cam[0], a.tmin, bufs.tri_id,
+                                       bufs.bary, bufs.L_dir, bufs.vis))
+                bufs_all.append(bufs)
+                keep.append(mat)
+            p = self._params(reqs[0]).c()  # N_d and flags are shared; each request carries its tmin
+            ws = L.workspace(L.exm_shade_fwd_batch_workspace_size(creqs, p.N_d), self.device)
+            L.exm_shade_fwd_batch(creqs, p, ws)
+            keep += bufs_all + [ws]
+            for req, bufs in zip(reqs, bufs_all):
+                out = torch.empty((req.res, req.res, 3), dtype=torch.float32, pin_memory=True)
+                out.copy_(bufs.L_dir[0], non_blocking=True)
+                outs.append(out)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return _Token(ev, outs, keep)
 
     def done(self, tok: _Token) -> bool:
         return tok.event.query()

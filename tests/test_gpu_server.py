@@ -1,7 +1,8 @@
 """Relighting service on the device: every request's image is bitwise the same when it is
 rendered in the mix (Poisson arrivals, several slots on their own streams, maps evicted and
-uploaded again under a tight HBM budget) and when it is rendered alone (one slot, one
-request on the device at a time). The tolerance is zero: each request's render is a
+uploaded again under a tight HBM budget), in a batch (direct-only requests rendered together by
+the batched direct pass) and when it is rendered alone (one slot, one request on the device at a
+time). The tolerance is zero: each request's render is a
 deterministic function of its asset, env map, view and estimator parameters, whatever else
 runs beside it."""
 import sys
@@ -41,13 +42,21 @@ def test_alone_equals_mix():
     log(f"[server] mix stats {st}; loads {sched.loads} evictions {sched.evictions}")
     assert st["completed"] == len(mix)
     assert sched.evictions > 0 and sched.peak <= budget
+    # the same stream with batching: direct-only requests of at most 256^2 that stand together at
+    # the head of the queue render in one batched direct pass
+    bmix = requests_from_specs(stream)
+    bsched = Scheduler(be, budget, slots=4, batch_max=8, batch_res=256)
+    serve(bsched, bmix, realtime=False)
+    log(f"[server] batched mix: {bsched.batches} batches, stats {latency_stats(bmix)}")
+    assert bsched.batches > 0 and latency_stats(bmix)["completed"] == len(bmix)
     alone = requests_from_specs(stream)
     solo = Scheduler(be, budget, slots=1)
     for r in alone:
         serve(solo, [r])
-    for a, b in zip(mix, alone):
-        assert a.rid == b.rid
-        ra, rb = a.result, b.result
+    for a, c, b in zip(mix, bmix, alone):
+        assert a.rid == b.rid == c.rid
+        ra, rc, rb = a.result, c.result, b.result
         assert ra.shape == (a.res, a.res, 3)
         assert torch.isfinite(ra).all() and float(ra.max()) > 0
         assert torch.equal(ra, rb), f"request {a.rid} differs alone and in the mix"
+        assert torch.equal(rc, rb), f"request {a.rid} differs alone and in a batch"

@@ -157,3 +157,65 @@ def test_serve_realtime_poisson():
     assert st["completed"] == 150 and st["p99_ms"] >= st["p50_ms"] > 0
     assert s.evictions > 0 and s.peak <= s.budget
     assert not math.isnan(st["req_per_s"])
+
+
+class FakeBatchBackend(FakeBackend):
+    """Also renders batches: one launch for several requests, retired together."""
+
+    def launch_batch(self, rs, slot):
+        for r in rs:
+            assert r.asset in self.loaded, "launched without its map"
+        self.log.append(("batch", tuple(r.rid for r in rs), slot))
+        return ("batch", self.clock() + sum(r.res * r.res for r in rs) * 1e-6, len(rs))
+
+    def done(self, tok):
+        return self.clock() >= (tok[1] if isinstance(tok, tuple) else tok)
+
+    def result(self, tok):
+        return [tok[1]] * tok[2] if isinstance(tok, tuple) else tok
+
+
+def test_batches_take_the_queue_head_in_order():
+    """Direct-only requests of at most batch_res^2 pixels that stand together at the head of the
+    queue share one slot and one launch (at most batch_max of them); an indirect or larger request
+    ends the batch; every request is admitted by its own footprint and retired with its batch."""
+    clk = FakeClock()
+    b = FakeBatchBackend({a: 50 for a in range(4)}, clock=clk)
+    s = Scheduler(b, budget=100_000, slots=2, batch_max=3, batch_res=16)
+    reqs = [_req(0, 0), _req(1, 1), _req(2, 2), _req(3, 3), _req(4, 0, res=32), _req(5, 1), _req(6, 2)]
+    reqs[5].indirect = True
+    for r in reqs:
+        s.submit(r)
+    seen = []
+    while not s.idle():
+        seen += [r.rid for r in s.admit(clk)]
+        _check(s)
+        clk.t += 1.0
+        s.poll(clk)
+        _check(s)
+    assert seen == list(range(7))
+    batches = [e[1] for e in b.log if e[0] == "batch"]
+    singles = [e[1] for e in b.log if e[0] == "launch"]
+    # request 3 is batchable but the request behind it is too large, so it runs alone; 5 is
+    # indirect and 6 has no batchable follower
+    assert batches == [(0, 1, 2)] and singles == [3, 4, 5, 6]
+    assert s.batches == 1 and all(r.status == "done" for r in reqs)
+
+
+def test_batch_waits_for_memory_like_single_requests():
+    clk = FakeClock()
+    b = FakeBatchBackend({0: 100, 1: 100, 2: 100}, clock=clk)
+    # room for the fixed bytes, two maps and two requests of 10^2: the third request waits
+    s = Scheduler(b, budget=100 + 200 + 200, slots=4, batch_max=8, batch_res=16)
+    rs = [_req(0, 0), _req(1, 1), _req(2, 2)]
+    for r in rs:
+        s.submit(r)
+    s.admit(clk)
+    assert [r.status for r in rs] == ["running", "running", "queued"]
+    assert len(s.inflight) == 1 and s.batches == 1
+    _check(s)
+    clk.t = 1.0
+    s.poll(clk)
+    s.admit(clk)
+    assert rs[2].status == "running"
+    _check(s)
