@@ -661,20 +661,158 @@ __device__ __forceinline__ int32_t trav_pop(TravState& s, const int32_t* stack, 
   return stack[(--s.sp) * stride];
 }
 
+// inclusive prefix sum of x over the 64 lanes of the wave (every lane must be active)
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if ((int)__lane_id() >= o) x += y;
+  }
+  return x;
+}
+
+// Any-hit test of up to two leaves of one lane by that lane alone (their triangles in order).
+template <bool COUNT>
+__device__ __forceinline__ bool leaves_any_lane(const BvhView& B, const Ray& r, float tmin, int32_t skip,
+                                                int32_t leaf_a, int32_t leaf_b, TraceCount* counts) {
+  const int32_t leaves[2] = {leaf_a, leaf_b};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (leaves[k] == kEmptyRef) continue;
+    const uint32_t v = ~(uint32_t)leaves[k];
+    const uint32_t first = v >> 4, cnt = v & 15u;
+    for (uint32_t i = first; i < first + cnt; ++i) {
+      const float4* qp = reinterpret_cast<const float4*>(B.tris + i);
+      const float4 q0 = qp[0], q1 = qp[1], q2 = qp[2];
+      BvhTri T;
+      T.v0[0] = q0.x; T.v0[1] = q0.y; T.v0[2] = q0.z;
+      T.v1[0] = q0.w; T.v1[1] = q1.x; T.v1[2] = q1.y;
+      T.v2[0] = q1.z; T.v2[1] = q1.w; T.v2[2] = q2.x;
+      T.id = __float_as_int(q2.y);
+      if (COUNT) counts->tris++;
+      float t, b1, b2;
+      if (tri_hit(r, T, tmin, __builtin_huge_valf(), &t, &b1, &b2) && T.id != skip) return true;
+    }
+  }
+  return false;
+}
+
+// Any-hit test of every lane's pending leaves (up to two) against that lane's ray, with the
+// (lane, triangle) pairs of the whole wave spread over its 64 lanes: pair q (in lane order) goes
+// to lane q mod 64 in pass q / 64, which finds the pair's owner by a 4-ary search over the lanes'
+// prefix sums (three rounds of three independent cross-lane reads), takes the owner's ray,
+// triangle ranges and skipped triangle by cross-lane reads and runs the watertight test. A lane's
+// own pairs are a run of consecutive lanes in each pass, so one ballot tells every owner whether
+// any of its tests hit. The cross-lane reads need every lane of the wave to take part: if the
+// call is reached with some lanes inactive, each active lane tests its own leaves instead (same
+// answers). kEmptyRef stands for no leaf; returns true where the lane's ray hit something
+// (t >= tmin, its own triangle skipped).
+template <bool COUNT, bool PER_LANE_BVH>
+__device__ __forceinline__ bool leaves_any_wave(const BvhView& B, const Ray& r, float tmin, int32_t skip,
+                                                int32_t leaf_a, int32_t leaf_b, TraceCount* counts) {
+  if (__ballot(1) != ~0ull) return leaves_any_lane<COUNT>(B, r, tmin, skip, leaf_a, leaf_b, counts);
+  uint32_t ca = 0, fa = 0, cb = 0, fb = 0;
+  if (leaf_a != kEmptyRef) {
+    const uint32_t v = ~(uint32_t)leaf_a;
+    fa = v >> 4;
+    ca = v & 15u;
+  }
+  if (leaf_b != kEmptyRef) {
+    const uint32_t v = ~(uint32_t)leaf_b;
+    fb = v >> 4;
+    cb = v & 15u;
+  }
+  const uint32_t cnt = ca + cb;
+  const uint32_t incl = wave_incl_sum(cnt);
+  const uint32_t excl = incl - cnt;
+  // the wave's pair count, in a scalar register (every lane reads the same lane)
+  const uint32_t total = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)incl, 63, 64));
+  const uint32_t lane = __lane_id();
+  const int kpack = r.kx | (r.ky << 2) | (r.kz << 4);
+  const uint64_t tris_addr = reinterpret_cast<uint64_t>(B.tris);
+  bool hit = false;
+  for (uint32_t base = 0; base < total; base += 64) {  // scalar loop
+    const uint32_t q = base + lane;
+    // owner = the number of lanes whose pairs all come before q (incl[o - 1] <= q < incl[o]),
+    // found 16, 4 and 1 lanes at a time
+    uint32_t o = 0;
+#pragma unroll
+    for (uint32_t st = 16; st >= 1; st >>= 2) {
+      const uint32_t e1 = (uint32_t)__shfl((int)incl, (int)(o + st - 1), 64);
+      const uint32_t e2 = (uint32_t)__shfl((int)incl, (int)(o + 2 * st - 1), 64);
+      const uint32_t e3 = (uint32_t)__shfl((int)incl, (int)(o + 3 * st - 1), 64);
+      o += st * ((e1 <= q) + (e2 <= q) + (e3 <= q));
+    }
+    o = min(o, 63u);  // a q past the last pair has no owner; its reads below are unused
+    const uint32_t o_fa = (uint32_t)__shfl((int)fa, (int)o, 64);
+    const uint32_t o_ca = (uint32_t)__shfl((int)ca, (int)o, 64);
+    const uint32_t o_fb = (uint32_t)__shfl((int)fb, (int)o, 64);
+    const uint32_t o_excl = (uint32_t)__shfl((int)excl, (int)o, 64);
+    Ray ro;
+    ro.o = mk(__shfl(r.o.x, (int)o, 64), __shfl(r.o.y, (int)o, 64), __shfl(r.o.z, (int)o, 64));
+    ro.Sx = __shfl(r.Sx, (int)o, 64);
+    ro.Sy = __shfl(r.Sy, (int)o, 64);
+    ro.Sz = __shfl(r.Sz, (int)o, 64);
+    const int o_k = __shfl(kpack, (int)o, 64);
+    ro.kx = o_k & 3;
+    ro.ky = (o_k >> 2) & 3;
+    ro.kz = (o_k >> 4) & 3;
+    const float o_tmin = __shfl(tmin, (int)o, 64);
+    const int32_t o_skip = __shfl(skip, (int)o, 64);
+    const BvhTri* tris = B.tris;
+    if (PER_LANE_BVH) {
+      const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)tris_addr, (int)o, 64);
+      const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(tris_addr >> 32), (int)o, 64);
+      tris = reinterpret_cast<const BvhTri*>(((uint64_t)hi << 32) | lo);
+    }
+    bool my = false;
+    const uint32_t k = q - o_excl;  // the pair's place among its owner's (first leaf, then second)
+    if (q < total && k < 30u) {
+      const uint32_t idx = k < o_ca ? o_fa + k : o_fb + (k - o_ca);
+      const float4* qp = reinterpret_cast<const float4*>(tris + idx);
+      const float4 q0 = qp[0], q1 = qp[1], q2 = qp[2];
+      BvhTri T;
+      T.v0[0] = q0.x; T.v0[1] = q0.y; T.v0[2] = q0.z;
+      T.v1[0] = q0.w; T.v1[1] = q1.x; T.v1[2] = q1.y;
+      T.v2[0] = q1.z; T.v2[1] = q1.w; T.v2[2] = q2.x;
+      T.id = __float_as_int(q2.y);
+      float t, b1, b2;
+      my = tri_hit(ro, T, o_tmin, __builtin_huge_valf(), &t, &b1, &b2) && T.id != o_skip;
+    }
+    const uint64_t hits = __ballot(my);
+    // this lane's own pairs occupy lanes [lo, hi) of the pass
+    const uint32_t lo = min(max(excl, base), base + 64u) - base, hi = min(max(incl, base), base + 64u) - base;
+    const uint32_t n = hi - lo;
+    const uint64_t mine = n == 0 ? 0ull : ((n == 64 ? ~0ull : ((1ull << n) - 1ull)) << lo);
+    hit = hit || (hits & mine) != 0ull;
+    if (COUNT) counts->tris += n;
+  }
+  return hit;
+}
+
 // One round of the speculative while-while traversal (Aila and Laine 2009): internal nodes are
 // visited until fewer than leaf_gate lanes of the wave lack a postponed leaf, then the postponed
 // leaves are intersected together, so node and leaf work each run with most lanes of the wave
-// active. Returns true when the query is finished: nothing left to visit, or
-// ANY and a hit was found.
-template <bool ANY, bool COUNT>
+// active. Every lane of the wave calls it (lanes without a query hold s.ref = s.leaf = kEmptyRef):
+// any-hit queries test their leaves across the whole wave (leaf_any_wave). Returns true when
+// the lane's query is finished: nothing left to visit, or ANY and a hit was found.
+template <bool ANY, bool COUNT, bool PER_LANE_BVH = false>
 __device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float tmin, int32_t skip, int32_t* stack,
                                            int stride, TravState& s, HitRec& h, TraceCount* counts,
                                            int32_t leaf_gate = 1) {
-  if (++s.rounds > kMaxRounds) return true;
+  bool capped = false;
+  if (++s.rounds > kMaxRounds) {  // drop the query (no early return: the leaf phase needs every lane)
+    s.ref = s.leaf = kEmptyRef;
+    capped = true;
+  }
   uint32_t steps = 0;
   while (s.ref >= 0) {
     steps = __builtin_amdgcn_readfirstlane(steps) + 1u;  // wave-uniform: kept in a scalar register
-    if (steps > kMaxSteps) return true;
+    if (steps > kMaxSteps) {
+      s.ref = s.leaf = kEmptyRef;
+      capped = true;
+      break;
+    }
     if (COUNT) counts->nodes++;
     const BvhNode& N = B.nodes[(uint32_t)s.ref];
     const float4 a = reinterpret_cast<const float4*>(&N)[0];
@@ -701,9 +839,21 @@ __device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float
     }
     if (__popcll(__ballot(s.leaf == kEmptyRef)) < leaf_gate) break;
   }
-  if (s.leaf == kEmptyRef && is_leaf(s.ref)) {  // a round that starts on a leaf (root leaf)
+  if (s.leaf == kEmptyRef && is_leaf(s.ref)) {  // a round that starts on a leaf (a root leaf, or the
+                                                // second of two leaves met in the last round)
     s.leaf = s.ref;
     s.ref = trav_pop(s, stack, stride);
+  }
+  if (ANY) {
+    // the postponed leaf and, when the next reference is a leaf as well, that one too, tested
+    // across the wave (straight-line code: no lane may leave before the cross-lane reads)
+    const bool second = s.leaf != kEmptyRef && is_leaf(s.ref);
+    const int32_t leaf_b = second ? s.ref : kEmptyRef;
+    if (second) s.ref = trav_pop(s, stack, stride);
+    const bool hit = leaves_any_wave<COUNT, PER_LANE_BVH>(B, r, tmin, skip, s.leaf, leaf_b, counts);
+    s.leaf = kEmptyRef;
+    if (hit) h.id = 0;  // any-hit queries report only that something was hit
+    return hit || capped || s.ref == kEmptyRef;
   }
   while (s.leaf != kEmptyRef) {
     const uint32_t v = ~(uint32_t)s.leaf;
@@ -722,10 +872,6 @@ __device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float
       if (COUNT) counts->tris++;
       float t, b1, b2;
       if (tri_hit(r, T, tmin, h.t, &t, &b1, &b2) && T.id != skip) {
-        if (ANY) {
-          h.id = T.id;
-          return true;
-        }
         if (t < h.t || (t == h.t && T.id < h.id)) {
           h.id = T.id;
           h.t = t;
@@ -740,19 +886,7 @@ __device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float
       s.ref = trav_pop(s, stack, stride);
     }
   }
-  return s.ref == kEmptyRef;
-}
-
-// Whole query in one call (ANY: first hit; else closest hit).
-template <bool ANY, bool COUNT = false>
-__device__ __forceinline__ HitRec trace(const BvhView& B, const Ray& r, float tmin, int32_t skip, int32_t* stack,
-                                        int stride, TraceCount* counts = nullptr) {
-  TravState s;
-  HitRec h;
-  trav_begin(B, s, h, stack);
-  while (!trav_round<ANY, COUNT>(B, r, tmin, skip, stack, stride, s, h, counts)) {
-  }
-  return h;
+  return capped || s.ref == kEmptyRef;
 }
 
 }  // namespace exm

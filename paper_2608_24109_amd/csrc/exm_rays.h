@@ -28,9 +28,11 @@ struct RayBatch {
 
 // A persistent traversal wave refills once fewer than kRayRefill lanes still traverse, and a
 // round's node phase hands over to its leaf phase once fewer than kTravLeafGate lanes lack a
-// postponed leaf (both swept on the displaced sphere and the tori: 32 and 8).
-constexpr int32_t kRayRefill = 32;
-constexpr int32_t kTravLeafGate = 8;
+// postponed leaf. Swept with the wave-wide any-hit leaf phase (gate 2-32 x refill 24-48, any-hit
+// traversal of the displaced sphere and the tori): 24 and 16 (sphere 23.8 -> 22.0 ms against the
+// per-lane leaf loop at 32 and 8, tori 23.2 -> 22.9 ms).
+constexpr int32_t kRayRefill = 24;
+constexpr int32_t kTravLeafGate = 16;
 // The BVHs of a launch whose rays come from several assets (a batch of requests): region r's rays
 // belong to asset f, region_start[f] <= r < region_start[f + 1].
 struct BvhTable {

@@ -4,11 +4,13 @@
 // kernel is persistent: a wave claims a whole region with one atomic, then its lanes take the
 // region's rays one at a time as they finish (wave-local bookkeeping through ballots, no
 // atomics), so a wave is held neither by its longest ray nor by idle lanes. Traversal yields
-// back to refilling when fewer than `refill` lanes are still traversing (32), and a round's node
-// phase hands over to its leaf phase once fewer than `leaf_gate` lanes lack a postponed leaf (8:
-// waiting for every lane, as in the plain while-while loop, left most lanes idle; 13% less time
-// on the displaced sphere). Each lane keeps only a ray and its traversal state, so the kernel
-// stays small and many waves are resident to hide the latency of node fetches.
+// back to refilling when fewer than `refill` lanes are still traversing (24), and a round's node
+// phase hands over to its leaf phase once fewer than `leaf_gate` lanes lack a postponed leaf (16:
+// waiting for every lane, as in the plain while-while loop, left most lanes idle). Any-hit
+// queries test their leaves across the whole wave (every lane of the wave runs every round, with
+// or without a ray, so that the leaf phase's cross-lane reads see all lanes). Each lane keeps only
+// a ray and its traversal state, so the kernel stays small and many waves are resident to hide
+// the latency of node fetches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,11 +47,18 @@ __global__ __launch_bounds__(kThreads) void k_trace(BvhView B0, BvhTable bt, Ray
   // lane state
   bool have_ray = false;
   int64_t slot = 0;
-  Ray ray;
+  Ray ray;  // set below, before the first round
   float tmin = 0.0f;
   int32_t skip = -1;
   TravState ts;
+  ts.ref = ts.leaf = kEmptyRef;  // no query: every lane joins the wave's leaf phases anyway
+  ts.sp = 0;
+  ts.rounds = 0;
   HitRec h;
+  h.id = -1;
+  h.t = __builtin_huge_valf();
+  h.b1 = h.b2 = 0.0f;
+  ray = make_ray(mk(0.f, 0.f, 0.f), mk(0.f, 0.f, 1.f));
   TraceCount tc;
   uint32_t n_rays = 0;
 
@@ -91,18 +100,17 @@ __global__ __launch_bounds__(kThreads) void k_trace(BvhView B0, BvhTable bt, Ray
       need = __ballot(!have_ray);
     }
     if (__ballot(have_ray) == 0ull) break;
-    if (have_ray) {
-      while (true) {
-        if (trav_round<ANY, COUNT>(B, ray, tmin, skip, stack, kThreads, ts, h, &tc, leaf_gate)) {
-          if (ANY)
-            out_any[slot] = h.id >= 0 ? 1 : 0;
-          else
-            out_hit[slot] = h;
-          have_ray = false;
-          break;
-        }
-        if (__popcll(__ballot(1)) < refill) break;
+    while (true) {  // every lane of the wave calls trav_round (the any-hit leaf phase spans the wave)
+      const bool fin = trav_round<ANY, COUNT, BATCH>(B, ray, tmin, skip, stack, kThreads, ts, h, &tc, leaf_gate);
+      if (have_ray && fin) {
+        if (ANY)
+          out_any[slot] = h.id >= 0 ? 1 : 0;
+        else
+          out_hit[slot] = h;
+        have_ray = false;
+        ts.ref = ts.leaf = kEmptyRef;
       }
+      if (__popcll(__ballot(have_ray)) < refill) break;
     }
   }
   if (COUNT) {
