@@ -27,12 +27,16 @@ struct RayBatch {
 };
 
 // A persistent traversal wave refills once fewer than kRayRefill lanes still traverse, and a
-// round's node phase hands over to its leaf phase once fewer than kTravLeafGate lanes lack a
-// postponed leaf. Swept with the wave-wide any-hit leaf phase (gate 2-32 x refill 24-48, any-hit
-// traversal of the displaced sphere and the tori): 24 and 16 (sphere 23.8 -> 22.0 ms against the
-// per-lane leaf loop at 32 and 8, tori 23.2 -> 22.9 ms).
+// round's node phase hands over to its leaf phase once fewer than `gate` lanes lack a postponed
+// leaf: kTravLeafGateWide for batches whose regions hold at least kWideRegion ray slots (N_d >= 32
+// direct samples per pixel), kTravLeafGate otherwise. Swept with the wave-wide any-hit leaf phase
+// (gate 2-32 x refill 24-48): at N_d 64 gate 16 (any-hit traversal of the displaced sphere 23.8 ->
+// 22.0 ms against the per-lane leaf loop at refill 32 and gate 8, tori 23.2 -> 22.9 ms), at N_d 8
+// gate 8 (a 1600^2 relight 1.73 -> 1.68 ms; gate 16 took 1.86 ms).
 constexpr int32_t kRayRefill = 24;
-constexpr int32_t kTravLeafGate = 16;
+constexpr int32_t kTravLeafGate = 8;
+constexpr int32_t kTravLeafGateWide = 16;
+constexpr int64_t kWideRegion = 2048;
 // The BVHs of a launch whose rays come from several assets (a batch of requests): region r's rays
 // belong to asset f, region_start[f] <= r < region_start[f + 1].
 struct BvhTable {

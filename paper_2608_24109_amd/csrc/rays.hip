@@ -5,8 +5,9 @@
 // region's rays one at a time as they finish (wave-local bookkeeping through ballots, no
 // atomics), so a wave is held neither by its longest ray nor by idle lanes. Traversal yields
 // back to refilling when fewer than `refill` lanes are still traversing (24), and a round's node
-// phase hands over to its leaf phase once fewer than `leaf_gate` lanes lack a postponed leaf (16:
-// waiting for every lane, as in the plain while-while loop, left most lanes idle). Any-hit
+// phase hands over to its leaf phase once fewer than `leaf_gate` lanes lack a postponed leaf (8,
+// or 16 for regions of many rays: waiting for every lane, as in the plain while-while loop, left
+// most lanes idle). Any-hit
 // queries test their leaves across the whole wave (every lane of the wave runs every round, with
 // or without a ray, so that the leaf phase's cross-lane reads see all lanes). Each lane keeps only
 // a ray and its traversal state, so the kernel stays small and many waves are resident to hide
@@ -138,8 +139,9 @@ hipError_t launch_impl(const BvhView& B0, const BvhTable& bt, const RayBatch& rb
   k_reset_counter<<<1, 1, 0, s>>>(rb.region_counter);
   {
     EXM_TIMED(ANY ? "trace_any" : "trace_closest", s);
-    k_trace<ANY, COUNT, BATCH><<<(unsigned)blocks, kThreads, 0, s>>>(B0, bt, rb, kRayRefill, kTravLeafGate, out_hit,
-                                                                      out_any, counters);
+    const int32_t gate = rb.region_stride >= kWideRegion ? kTravLeafGateWide : kTravLeafGate;
+    k_trace<ANY, COUNT, BATCH><<<(unsigned)blocks, kThreads, 0, s>>>(B0, bt, rb, kRayRefill, gate, out_hit, out_any,
+                                                                      counters);
   }
   return hipGetLastError();
 }
