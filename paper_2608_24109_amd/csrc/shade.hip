@@ -4,12 +4,16 @@
 // env samples drawn from the importance-sampling tables; a sample with n_s . w > 0 traces an
 // any-hit shadow ray and, if unoccluded, adds E f_r (n_s . w) / pdf (Eq. 13-16 for f_r).
 // It runs as three kernels per chunk of pixels:
-//   gen      one thread per pixel: attribute query, all N_d samples, and for each sample with
-//            n_s . w > 0 its shadow ray and its contribution E f_r c / pdf, written compactly
-//            into its wave's region of the workspace (slots from ballots, no atomics);
+//   gen      one wave per 64 pixels: the attribute query one thread per pixel, then the N_d
+//            samples one thread per sample (64 / N_d pixels at a time); each sample with
+//            n_s . w > 0 writes its shadow ray and its contribution E f_r c / pdf compactly into
+//            the wave's region of the workspace (slots from ballots, no atomics), each pixel's
+//            rays together and in sample order;
 //   trace    the persistent any-hit kernel over the regions (rays.hip);
-//   finalize one thread per pixel: the same ballots locate each sample's slot; unoccluded
-//            contributions are summed in sample order; visibility bits are written.
+//   finalize one wave per 64 pixels: a pixel's rays start after those of the lanes below it
+//            (a prefix sum of the sample masks); one thread per sample loads its hit flag and
+//            contribution, the unoccluded contributions of a pixel are summed across its lanes
+//            and its visibility bits written.
 // The visibility bits of all samples are stored so the adjoint never traces a ray.
 //
 // Adjoint, per covered pixel with upstream g = dLoss/dL_dir: the same samples again (same RNG
@@ -45,7 +49,9 @@ struct KParams {
   RngKey key;
 };
 
-__device__ __forceinline__ void brdf_eval(const Surf& S, f3 wi, f3 wo, float ci, const KParams& p, float fr[3]) {
+// f_r of a surface point (S: n_s, albedo a, roughness r, metallic m)
+template <class SURF>
+__device__ __forceinline__ void brdf_eval(const SURF& S, f3 wi, f3 wo, float ci, const KParams& p, float fr[3]) {
   const float kd = (p.flags & EXM_SPECULAR_ONLY) ? 0.0f : (1.0f - S.m) * kInvPi;
   fr[0] = kd * S.a[0];
   fr[1] = kd * S.a[1];
@@ -65,91 +71,160 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return (uint32_t)__popcll(mask & ((1ull << __lane_id()) - 1ull));
 }
 
-// One thread per pixel: pixel gid of the views V, workspace position `local` (its region is
-// local / 64). COUNT: also accumulates env samples drawn into counters[3].
+// The shading point of a covered pixel, staged in LDS between the two phases of dir_gen: kRecWords
+// words per pixel, structure of arrays over the wave's 64 pixels (the lanes reading one pixel's
+// record read the same word: a broadcast).
+constexpr int kRecWords = 18;
+enum RecField { kRx = 0, kRns = 3, kRwo = 6, kRa = 9, kRr = 12, kRm = 13, kRf = 14, kRpix = 15, kRvid = 16, kRlane = 17 };
+
+struct ShadePt {
+  f3 x, ns, wo;
+  float a[3], r, m;
+  int32_t f;
+  uint32_t pix, vid, lane;
+};
+
+__device__ __forceinline__ ShadePt load_pt(const uint32_t* rec, uint32_t c) {
+  const float* rf = reinterpret_cast<const float*>(rec);
+  ShadePt q;
+  q.x = mk(rf[kRx * 64 + c], rf[(kRx + 1) * 64 + c], rf[(kRx + 2) * 64 + c]);
+  q.ns = mk(rf[kRns * 64 + c], rf[(kRns + 1) * 64 + c], rf[(kRns + 2) * 64 + c]);
+  q.wo = mk(rf[kRwo * 64 + c], rf[(kRwo + 1) * 64 + c], rf[(kRwo + 2) * 64 + c]);
+  q.a[0] = rf[kRa * 64 + c];
+  q.a[1] = rf[(kRa + 1) * 64 + c];
+  q.a[2] = rf[(kRa + 2) * 64 + c];
+  q.r = rf[kRr * 64 + c];
+  q.m = rf[kRm * 64 + c];
+  q.f = (int32_t)rec[kRf * 64 + c];
+  q.pix = rec[kRpix * 64 + c];
+  q.vid = rec[kRvid * 64 + c];
+  q.lane = rec[kRlane * 64 + c];
+  return q;
+}
+
+// One wave, 64 consecutive pixels (pixel gid of the views V at workspace position `local`; the
+// wave's region is local / 64). Phase A, one lane per pixel: the attribute query, staged in `rec`
+// (kRecWords x 64 words of LDS owned by the wave) at the pixel's rank among the covered ones.
+// Phase B, one lane per sample: each pass takes 64 / N_d covered pixels, lane k of a pixel's group
+// draws its sample k, and the samples with n_s . w > 0 get their shadow ray and contribution,
+// compacted by a ballot. The region therefore holds each pixel's rays together, in sample order,
+// the pixels in lane order: a traversal wave takes the rays of one or two pixels at a time
+// (one origin), and the sampling runs with every lane busy whatever the coverage. COUNT: also
+// accumulates env samples drawn into counters[3].
 template <bool COUNT>
-__device__ __forceinline__ void dir_gen_pixel(const MeshView& M, const TexView& T, const EnvView& E, const EnvTabs& tb,
-                                              const ShadeViews& V, const int32_t* __restrict__ tri_id,
-                                              const float* __restrict__ bary, const KParams& p, int64_t gid,
-                                              int64_t local, const DirectWs& ws,
-                                              unsigned long long* __restrict__ counters) {
+__device__ __forceinline__ void dir_gen_wave(const MeshView& M, const TexView& T, const EnvView& E, const EnvTabs& tb,
+                                             const ShadeViews& V, const int32_t* __restrict__ tri_id,
+                                             const float* __restrict__ bary, const KParams& p, int64_t gid,
+                                             int64_t local, const DirectWs& ws, unsigned long long* __restrict__ counters,
+                                             uint32_t* rec) {
   const int64_t HW = (int64_t)V.H * V.W;
   const int64_t region = local >> 6;
+  const uint32_t lane = __lane_id();
   const int32_t f = gid < HW * V.n ? tri_id[gid] : -1;
-  Surf S;
-  f3 wo = mk(0, 0, 0);
-  uint32_t pix = 0, vid = 0;
+  const uint64_t cov = __ballot(f >= 0);
+  const uint32_t n_cov = (uint32_t)__popcll(cov);
   if (f >= 0) {
     const int32_t view = (int32_t)(gid / HW);
-    pix = (uint32_t)(gid - view * HW);
-    vid = (uint32_t)V.view_id[view];
+    const uint32_t pix = (uint32_t)(gid - view * HW);
     const float2 b = reinterpret_cast<const float2*>(bary)[gid];
-    S = query(M, T, f, b.x, b.y, p.flags);
-    wo = normalize(mk(V.eye[view][0], V.eye[view][1], V.eye[view][2]) - S.x);
+    const Surf S = query(M, T, f, b.x, b.y, p.flags);
+    const f3 wo = normalize(mk(V.eye[view][0], V.eye[view][1], V.eye[view][2]) - S.x);
+    const uint32_t c = lanes_below(cov);
+    float* rf = reinterpret_cast<float*>(rec);
+    rf[kRx * 64 + c] = S.x.x;
+    rf[(kRx + 1) * 64 + c] = S.x.y;
+    rf[(kRx + 2) * 64 + c] = S.x.z;
+    rf[kRns * 64 + c] = S.ns.x;
+    rf[(kRns + 1) * 64 + c] = S.ns.y;
+    rf[(kRns + 2) * 64 + c] = S.ns.z;
+    rf[kRwo * 64 + c] = wo.x;
+    rf[(kRwo + 1) * 64 + c] = wo.y;
+    rf[(kRwo + 2) * 64 + c] = wo.z;
+    rf[kRa * 64 + c] = S.a[0];
+    rf[(kRa + 1) * 64 + c] = S.a[1];
+    rf[(kRa + 2) * 64 + c] = S.a[2];
+    rf[kRr * 64 + c] = S.r;
+    rf[kRm * 64 + c] = S.m;
+    rec[kRf * 64 + c] = (uint32_t)f;
+    rec[kRpix * 64 + c] = pix;
+    rec[kRvid * 64 + c] = (uint32_t)V.view_id[view];
+    rec[kRlane * 64 + c] = lane;
+  } else {
+    ws.mask[local] = 0ull;
   }
-  uint64_t mask = 0;
+  __builtin_amdgcn_wave_barrier();
   uint32_t running = 0;  // wave-uniform
   const int64_t rbase = region * 64 * (int64_t)p.N_d;
-  for (int k0 = 0; k0 < p.N_d; k0 += kGenPicks) {
-    Draw dr[kGenPicks];
-    bool ok[kGenPicks];
-    EnvSample es[kGenPicks];
+  if (p.N_d > 0) {
+    const uint32_t Nd = (uint32_t)p.N_d, G = 64u / Nd;  // pixels per pass
+    const uint32_t sub = lane / Nd, k = lane - sub * Nd;
+    const uint64_t group = Nd == 64u ? ~0ull : ((1ull << Nd) - 1ull);
+    const int64_t mbase = local & ~(int64_t)63;
+    for (uint32_t c0 = 0; c0 < n_cov; c0 += G * kGenPicks) {
+      Draw dr[kGenPicks];
+      bool ok[kGenPicks];
+      EnvSample es[kGenPicks];
+      ShadePt q[kGenPicks];
 #pragma unroll
-    for (int j = 0; j < kGenPicks; ++j) {
-      ok[j] = f >= 0 && k0 + j < p.N_d;
-      if (ok[j]) dr[j] = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)(k0 + j), 0u);
-    }
-    // records are read only for the picks above the shading hemisphere: the others are dropped
-    // whatever their records hold (half of all picks on the displaced sphere)
-    env_sample_k<kGenPicks, false>(E, tb, dr, ok, es);
-    bool need[kGenPicks];
-    float cs[kGenPicks];
+      for (int j = 0; j < kGenPicks; ++j) {
+        const uint32_t c = c0 + (uint32_t)j * G + sub;
+        ok[j] = sub < G && c < n_cov;
+        if (ok[j]) {
+          q[j] = load_pt(rec, c);
+          dr[j] = philox_draw(p.key.k0, p.key.k1, q[j].pix, q[j].vid, k, 0u);
+        }
+      }
+      // records are read only for the picks above the shading hemisphere: the others are dropped
+      // whatever their records hold (half of all picks on the displaced sphere)
+      env_sample_k<kGenPicks, false>(E, tb, dr, ok, es);
+      bool need[kGenPicks];
+      float cs[kGenPicks];
 #pragma unroll
-    for (int j = 0; j < kGenPicks; ++j) {
-      need[j] = false;
-      cs[j] = 0.0f;
-      if (ok[j]) {
-        cs[j] = dot(S.ns, es[j].dir);
-        need[j] = cs[j] > 0.0f;
+      for (int j = 0; j < kGenPicks; ++j) {
+        need[j] = false;
+        cs[j] = 0.0f;
+        if (ok[j]) {
+          cs[j] = dot(q[j].ns, es[j].dir);
+          need[j] = cs[j] > 0.0f;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kGenPicks; ++j)
+        if (need[j]) env_rec(E, es[j]);
+#pragma unroll
+      for (int j = 0; j < kGenPicks; ++j) {
+        if (c0 + (uint32_t)j * G >= n_cov) break;  // wave-uniform
+        const uint64_t bal = __ballot(need[j]);
+        if (need[j]) {
+          const int64_t slot = rbase + running + lanes_below(bal);
+          RayRec R;
+          R.o[0] = q[j].x.x;
+          R.o[1] = q[j].x.y;
+          R.o[2] = q[j].x.z;
+          R.skip = q[j].f;
+          R.d[0] = es[j].dir.x;
+          R.d[1] = es[j].dir.y;
+          R.d[2] = es[j].dir.z;
+          R.tmin = p.tmin;
+          ws.rays[slot] = R;
+          float fr[3];
+          brdf_eval(q[j], es[j].dir, q[j].wo, cs[j], p, fr);
+          const float wgt = cs[j] * es[j].inv_pdf;
+          ws.contrib[3 * slot] = es[j].E[0] * fr[0] * wgt;
+          ws.contrib[3 * slot + 1] = es[j].E[1] * fr[1] * wgt;
+          ws.contrib[3 * slot + 2] = es[j].E[2] * fr[2] * wgt;
+        }
+        // the pixel's sample mask: its group's bits of the ballot, written by the group's first lane
+        if (ok[j] && k == 0u) ws.mask[mbase + q[j].lane] = (bal >> (sub * Nd)) & group;
+        running += (uint32_t)__popcll(bal);
       }
     }
-#pragma unroll
-    for (int j = 0; j < kGenPicks; ++j)
-      if (need[j]) env_rec(E, es[j]);
-#pragma unroll
-    for (int j = 0; j < kGenPicks; ++j) {
-      const int k = k0 + j;
-      if (k >= p.N_d) break;  // wave-uniform
-      const float c = cs[j];
-      const uint64_t bal = __ballot(need[j]);
-      if (need[j]) {
-        const int64_t slot = rbase + running + lanes_below(bal);
-        RayRec R;
-        R.o[0] = S.x.x;
-        R.o[1] = S.x.y;
-        R.o[2] = S.x.z;
-        R.skip = f;
-        R.d[0] = es[j].dir.x;
-        R.d[1] = es[j].dir.y;
-        R.d[2] = es[j].dir.z;
-        R.tmin = p.tmin;
-        ws.rays[slot] = R;
-        float fr[3];
-        brdf_eval(S, es[j].dir, wo, c, p, fr);
-        const float wgt = c * es[j].inv_pdf;
-        ws.contrib[3 * slot] = es[j].E[0] * fr[0] * wgt;
-        ws.contrib[3 * slot + 1] = es[j].E[1] * fr[1] * wgt;
-        ws.contrib[3 * slot + 2] = es[j].E[2] * fr[2] * wgt;
-        mask |= 1ull << k;
-      }
-      running += (uint32_t)__popcll(bal);
-    }
+  } else if (f >= 0) {
+    ws.mask[local] = 0ull;
   }
-  ws.mask[local] = mask;
-  const uint64_t covered = __ballot(f >= 0);
-  if (__lane_id() == 0) {
+  if (lane == 0) {
     ws.count[region] = running;
-    if (COUNT) atomicAdd(counters + 3, (unsigned long long)__popcll(covered) * (unsigned long long)p.N_d);
+    if (COUNT) atomicAdd(counters + 3, (unsigned long long)n_cov * (unsigned long long)p.N_d);
   }
 }
 
@@ -161,10 +236,11 @@ __global__ __launch_bounds__(kThreads) void k_dir_gen(MeshView M, TexView T, Env
                                                       int64_t P, DirectWs ws, unsigned long long* __restrict__ counters,
                                                       bool use_lds) {
   extern __shared__ __align__(16) char smem[];
+  __shared__ uint32_t recs[kThreads / 64][kRecWords * 64];
   const EnvTabs tb = load_env_tabs(E, smem, use_lds);
   const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if ((local & ~(int64_t)63) >= P) return;  // whole waves only
-  dir_gen_pixel<COUNT>(M, T, E, tb, V, tri_id, bary, p, p0 + local, local, ws, counters);
+  dir_gen_wave<COUNT>(M, T, E, tb, V, tri_id, bary, p, p0 + local, local, ws, counters, recs[threadIdx.x >> 6]);
 }
 
 // The frames of a batched launch (requests with their own asset, env map and view): frame f
@@ -198,83 +274,142 @@ template <bool COUNT>
 __global__ __launch_bounds__(kThreads) void k_dir_gen_batch(DirBatch bt, KParams p, DirectWs ws,
                                                             unsigned long long* __restrict__ counters) {
   extern __shared__ __align__(16) char smem[];
+  __shared__ uint32_t recs[kThreads / 64][kRecWords * 64];
   const int32_t fi = frame_of_block(bt, (int32_t)blockIdx.x);
   const DirFrame& F = bt.f[fi];
   const EnvTabs tb = load_env_tabs(F.E, smem, F.use_lds != 0);
   const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   KParams pf = p;
   pf.tmin = F.tmin;
-  dir_gen_pixel<COUNT>(F.M, F.T, F.E, tb, F.V, F.tri_id, F.bary, pf, local - (int64_t)bt.block_start[fi] * kThreads,
-                       local, ws, counters);
+  dir_gen_wave<COUNT>(F.M, F.T, F.E, tb, F.V, F.tri_id, F.bary, pf, local - (int64_t)bt.block_start[fi] * kThreads,
+                      local, ws, counters, recs[threadIdx.x >> 6]);
 }
 
-__device__ __forceinline__ void dir_finalize_pixel(const ShadeViews& V, const KParams& p, int64_t gid, int64_t local,
-                                                   const DirectWs& ws, float* __restrict__ L_dir,
-                                                   uint64_t* __restrict__ vis) {
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// v summed over each aligned group of n lanes (n a power of two <= 64), the same sum on every lane
+// of a group: partner lanes swap within quads, then rows' halves and rows are mirrored (DPP, no
+// LDS traffic), then rows and half-waves are exchanged. Every lane of the wave must be active.
+__device__ __forceinline__ void group_sum(float& v, uint32_t n) {
+  if (n >= 2u) v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (n >= 4u) v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (n >= 8u) v += dpp_mov<0x141>(v);  // row_half_mirror
+  if (n >= 16u) v += dpp_mov<0x140>(v); // row_mirror
+  if (n >= 32u) v += __shfl_xor(v, 16, 64);
+  if (n >= 64u) v += __shfl_xor(v, 32, 64);
+}
+
+// One wave, 64 consecutive pixels (as in dir_gen_wave): a pixel's rays start after those of the
+// lanes below it (a prefix sum of the sample masks). The pixels with rays are then taken
+// 64 / N_d' at a time (N_d' = N_d rounded up to a power of two), one lane per sample, so that a
+// pixel's hit flags and contributions load together; the unoccluded contributions are summed
+// by a butterfly over the pixel's lanes (every lane ends with the same sum) and the pixel's
+// visibility bits come from one ballot. `stage` is 4 x 64 words of LDS owned by the wave.
+__device__ __forceinline__ void dir_finalize_wave(const ShadeViews& V, const KParams& p, int64_t gid, int64_t local,
+                                                  const DirectWs& ws, float* __restrict__ L_dir,
+                                                  uint64_t* __restrict__ vis, uint32_t* stage) {
+  const uint32_t lane = __lane_id();
   const bool valid = gid < (int64_t)V.H * V.W * V.n;
   const uint64_t mask = ws.mask[local];
+  const uint32_t n_mine = (uint32_t)__popcll(mask);
+  const uint32_t excl = wave_incl_sum(n_mine) - n_mine;
+  const uint64_t act = __ballot(n_mine > 0u);
+  if (n_mine > 0u) {
+    const uint32_t c = lanes_below(act);
+    stage[c] = (uint32_t)mask;
+    stage[64 + c] = (uint32_t)(mask >> 32);
+    stage[128 + c] = excl;
+    stage[192 + c] = lane;
+  } else if (valid) {
+    L_dir[3 * gid] = L_dir[3 * gid + 1] = L_dir[3 * gid + 2] = 0.0f;
+    vis[gid] = 0ull;
+  }
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t n_act = (uint32_t)__popcll(act);
+  if (n_act == 0u) return;  // wave-uniform
   const bool novis = (p.flags & EXM_NO_VIS) != 0;
   const int64_t rbase = (local >> 6) * 64 * (int64_t)p.N_d;
-  uint32_t running = 0;
-  float L[3] = {0.f, 0.f, 0.f};
-  uint64_t bits = 0;
-  // kGroup samples at a time: their slots, then all their hit flags, then the contributions of
-  // the unoccluded ones are loaded together (two memory round trips per group instead of two
-  // per sample); the sums still run in sample order
-  constexpr int kGroup = 8;
-  for (int k0 = 0; k0 < p.N_d; k0 += kGroup) {
-    int64_t slot[kGroup];
-    bool have[kGroup], lit[kGroup];
+  const int64_t gid0 = gid - (int64_t)lane;
+  const uint32_t Nd = (uint32_t)p.N_d;
+  uint32_t lg = 0;
+  while ((1u << lg) < Nd) ++lg;
+  const uint32_t Ndp = 1u << lg, G = 64u / Ndp, sub = lane >> lg, k = lane & (Ndp - 1u);
+  const uint64_t group = Nd == 64u ? ~0ull : ((1ull << Nd) - 1ull);
+  const float inv = 1.0f / (float)Nd;
+  // kFinPasses passes at a time, their hit flags and contributions loaded together (the
+  // contributions whatever the flags, so that no load waits for another)
+  constexpr int kFinPasses = 4;
+  for (uint32_t c0 = 0; c0 < n_act; c0 += G * kFinPasses) {
+    bool pix_ok[kFinPasses], have[kFinPasses];
+    uint32_t pl[kFinPasses];
+    int64_t slot[kFinPasses];
 #pragma unroll
-    for (int j = 0; j < kGroup; ++j) {
-      const int k = k0 + j;
-      have[j] = k < p.N_d && ((mask >> k) & 1ull);
-      const uint64_t bal = __ballot(have[j]);
-      slot[j] = rbase + running + lanes_below(bal);
-      running += (uint32_t)__popcll(bal);
+    for (int u = 0; u < kFinPasses; ++u) {
+      const uint32_t c = c0 + (uint32_t)u * G + sub;
+      pix_ok[u] = c < n_act;
+      uint64_t m = 0;
+      uint32_t first = 0;
+      pl[u] = 0;
+      if (pix_ok[u]) {
+        m = (uint64_t)stage[c] | ((uint64_t)stage[64 + c] << 32);
+        first = stage[128 + c];
+        pl[u] = stage[192 + c];
+      }
+      have[u] = pix_ok[u] && k < Nd && ((m >> k) & 1ull);
+      slot[u] = rbase + first + __popcll(m & ((1ull << k) - 1ull));
     }
+    uint8_t hb[kFinPasses];
+    float cv[kFinPasses][3];
 #pragma unroll
-    for (int j = 0; j < kGroup; ++j) lit[j] = have[j] && (novis || ws.hit[slot[j]] == 0);
-    float c[kGroup][3];
-#pragma unroll
-    for (int j = 0; j < kGroup; ++j) {
-      c[j][0] = c[j][1] = c[j][2] = 0.0f;
-      if (lit[j]) {
-        c[j][0] = ws.contrib[3 * slot[j]];
-        c[j][1] = ws.contrib[3 * slot[j] + 1];
-        c[j][2] = ws.contrib[3 * slot[j] + 2];
+    for (int u = 0; u < kFinPasses; ++u) {
+      hb[u] = 1;
+      cv[u][0] = cv[u][1] = cv[u][2] = 0.0f;
+      if (have[u]) {
+        if (!novis) hb[u] = ws.hit[slot[u]];
+        cv[u][0] = ws.contrib[3 * slot[u]];
+        cv[u][1] = ws.contrib[3 * slot[u] + 1];
+        cv[u][2] = ws.contrib[3 * slot[u] + 2];
       }
     }
 #pragma unroll
-    for (int j = 0; j < kGroup; ++j) {
-      if (!lit[j]) continue;
-      bits |= 1ull << (k0 + j);
-      L[0] += c[j][0];
-      L[1] += c[j][1];
-      L[2] += c[j][2];
+    for (int u = 0; u < kFinPasses; ++u) {
+      if (c0 + (uint32_t)u * G >= n_act) break;  // wave-uniform
+      const bool lit = have[u] && (novis || hb[u] == 0);
+      float L0 = lit ? cv[u][0] : 0.0f, L1 = lit ? cv[u][1] : 0.0f, L2 = lit ? cv[u][2] : 0.0f;
+      group_sum(L0, Ndp);
+      group_sum(L1, Ndp);
+      group_sum(L2, Ndp);
+      const uint64_t lb = __ballot(lit);
+      if (pix_ok[u] && k == 0u) {
+        const int64_t g = gid0 + pl[u];
+        L_dir[3 * g] = L0 * inv;
+        L_dir[3 * g + 1] = L1 * inv;
+        L_dir[3 * g + 2] = L2 * inv;
+        vis[g] = (lb >> (sub * Ndp)) & group;
+      }
     }
   }
-  if (!valid) return;
-  const float inv = p.N_d > 0 ? 1.0f / (float)p.N_d : 0.0f;
-  L_dir[3 * gid] = L[0] * inv;
-  L_dir[3 * gid + 1] = L[1] * inv;
-  L_dir[3 * gid + 2] = L[2] * inv;
-  vis[gid] = bits;
 }
 
 __global__ __launch_bounds__(kThreads) void k_dir_finalize(ShadeViews V, KParams p, int64_t p0, int64_t P,
                                                            DirectWs ws, float* __restrict__ L_dir,
                                                            uint64_t* __restrict__ vis) {
+  __shared__ uint32_t stage[kThreads / 64][4 * 64];
   const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if ((local & ~(int64_t)63) >= P) return;
-  dir_finalize_pixel(V, p, p0 + local, local, ws, L_dir, vis);
+  dir_finalize_wave(V, p, p0 + local, local, ws, L_dir, vis, stage[threadIdx.x >> 6]);
 }
 
 __global__ __launch_bounds__(kThreads) void k_dir_finalize_batch(DirBatch bt, KParams p, DirectWs ws) {
+  __shared__ uint32_t stage[kThreads / 64][4 * 64];
   const int32_t fi = frame_of_block(bt, (int32_t)blockIdx.x);
   const DirFrame& F = bt.f[fi];
   const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  dir_finalize_pixel(F.V, p, local - (int64_t)bt.block_start[fi] * kThreads, local, ws, F.L_dir, F.vis);
+  dir_finalize_wave(F.V, p, local - (int64_t)bt.block_start[fi] * kThreads, local, ws, F.L_dir, F.vis,
+                    stage[threadIdx.x >> 6]);
 }
 
 // Accumulated adjoint of one surface point w.r.t. its material values and shading normal.

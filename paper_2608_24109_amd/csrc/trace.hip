@@ -10,8 +10,9 @@
 // It runs per chunk of pixels as gen1 (secondary rays) -> closest-hit trace -> gen2 (hit
 // validity, FP64 refinement, query at y, light samples with their shadow rays and their whole
 // contribution f_d(x) f_d(y) E c / pdf * (n_s(x).w / p_b) / (N_b N_s)) -> any-hit trace ->
-// finalize (sum of the unoccluded contributions in (j, s) order). Ray slots come from wave
-// ballots as in the direct pass.
+// finalize (sum of the unoccluded contributions in (j, s) order). A covered pixel's N_b secondary
+// rays sit together (the covered pixels of a wave ranked by a ballot), so a traversal wave takes
+// rays of few origins at a time; the light samples' slots come from wave ballots.
 // The hit records and the light-sample visibility bits are stored for the adjoint.
 //
 // Adjoint, for upstream G = lambda_ind dLoss/dI: gradients to a, m, n_s at x (through f_d(x)
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(kThreads) void k_ind_gen1(MeshView M, ShadeViews V,
       R.d[1] = sr.df.y;
       R.d[2] = sr.df.z;
       R.tmin = p.tmin;
-      ws.sec_rays[rbase + (int64_t)j * n_cov + below] = R;
+      ws.sec_rays[rbase + (int64_t)below * p.N_b + j] = R;  // a pixel's rays together
     }
   }
   if (__lane_id() == 0) ws.sec_count[region] = n_cov * (uint32_t)p.N_b;
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_ind_gen2(MeshView M, TexView T, En
   const int64_t rbase1 = region * 64 * (int64_t)p.N_b;
   const int64_t rbase2 = rbase1 * (int64_t)p.N_s;
   const uint64_t bal1 = __ballot(f >= 0);
-  const uint32_t below1 = lanes_below(bal1), n_cov = (uint32_t)__popcll(bal1);
+  const uint32_t below1 = lanes_below(bal1);
   const bool diff = !(p.flags & EXM_SPECULAR_ONLY);
   const float invNbNs = (p.N_b > 0 && p.N_s > 0) ? 1.0f / ((float)p.N_b * (float)p.N_s) : 0.0f;
   Surf S;
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(kThreads) void k_ind_gen2(MeshView M, TexView T, En
     float fac[3] = {0.f, 0.f, 0.f};
     exm_sec_rec r{-1, 0.f, 0.f};
     if (f >= 0) {
-      HitRec h = ws.sec_hits[rbase1 + (int64_t)j * n_cov + below1];
+      HitRec h = ws.sec_hits[rbase1 + (int64_t)below1 * p.N_b + j];
       const Draw d = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)j, 1u);
       const SecRay sr = secondary_ray(M, f, b.x, b.y, d.u2, d.u3);
       if (h.id >= 0 && front_facing(M, h.id, sr.df)) {
