@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--workload", default="tori32", choices=["tori32", "sphere", "tori", "small"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-views", type=int, default=8, help="views of the workload the oracle baseline samples")
-    ap.add_argument("--cpu-pixels", type=int, default=196608, help="pixels per view the oracle baseline renders")
+    ap.add_argument("--cpu-pixels", type=int, default=393216, help="pixels per view the oracle baseline renders")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, copy a buffer of this many MiB once (HBM counter calibration)")
     ap.add_argument("--no-extras", dest="extras", action="store_false",
