@@ -448,10 +448,12 @@ def cpu_baseline(sc, p, n_views: int, n_pix: int):
 # (16 B) and 4 bilinear taps of 8 floats (128 B): 300 B. Each env sample reads the two
 # cutpoint entries of its column bucket (8 B), the CDF entry that decides the pick (8 B) and the
 # texel's record (E and 1/pdf, 16 B): 32 B (the row tables are block-shared). Each traced ray
-# reads the nodes it visits (64 B) and the triangles it tests (48 B). An adjoint env sample
-# adds three FP64 read-modify-writes (48 B); a pixel's map adjoint 4 taps x 8 FP32 (256 B).
+# reads the 4-wide nodes it visits (NODE_BYTES) and the triangles it tests (48 B). An adjoint
+# env sample adds three FP64 read-modify-writes (48 B); a pixel's map adjoint 4 taps x 8 FP32
+# (256 B).
 SURF_BYTES = 3 * (12 + 24) + 12 + 12 + 24 + 16 + 4 * 32
 SAMPLE_BYTES = 8 + 8 + 16
+NODE_BYTES = 128.0  # four child boxes (96 B) and four child references (16 B), one cache line
 
 
 def algorithmic_bytes(kernel: str, st: dict, p) -> float:
@@ -462,13 +464,13 @@ def algorithmic_bytes(kernel: str, st: dict, p) -> float:
         return st["He"] * st["We"] * (12 + 8 + 4 + 16 + 4) + 8.0 * st["He"]
     if kernel == "shade_fwd":
         return (32.0 * P + SURF_BYTES * C + SAMPLE_BYTES * st["samples"]
-                + 64.0 * st["shadow_nodes"] + 48.0 * st["shadow_tris"])
+                + NODE_BYTES * st["shadow_nodes"] + 48.0 * st["shadow_tris"])
     if kernel == "shade_bwd":
         return 32.0 * P + (SURF_BYTES + 256.0) * C + (SAMPLE_BYTES + 48) * st["unoccluded"]
     if kernel == "trace_indirect":
         return (12.0 * P + 20.0 * C + st["sec_rays"] * 12.0 + st["sec_hits"] * SURF_BYTES
                 + SAMPLE_BYTES * st["sec_shadow_rays"]
-                + 64.0 * (st["sec_nodes"] + st["sec_shadow_nodes"]) + 48.0 * (st["sec_tris"] + st["sec_shadow_tris"]))
+                + NODE_BYTES * (st["sec_nodes"] + st["sec_shadow_nodes"]) + 48.0 * (st["sec_tris"] + st["sec_shadow_tris"]))
     if kernel == "trace_bwd":
         return (44.0 * P + (SURF_BYTES + 224.0) * C + st["sec_hits"] * (SURF_BYTES + 224.0)
                 + (SAMPLE_BYTES + 48) * st["sec_unoccluded"])
@@ -481,10 +483,10 @@ def kernel_bytes_per_step(kernel: str, st: dict, p) -> float:
     P, C = st["pixels"], st["covered"]
     if kernel == "trace_any":  # direct shadow rays, and the secondary ones where the workload has them
         return (33.0 * (st["shadow_rays"] + st.get("sec_shadow_rays", 0))
-                + 64.0 * (st["shadow_nodes"] + st.get("sec_shadow_nodes", 0))
+                + NODE_BYTES * (st["shadow_nodes"] + st.get("sec_shadow_nodes", 0))
                 + 48.0 * (st["shadow_tris"] + st.get("sec_shadow_tris", 0)))
     if kernel == "trace_closest":  # ray record in, 16 B hit out
-        return 48.0 * st["sec_rays"] + 64.0 * st["sec_nodes"] + 48.0 * st["sec_tris"]
+        return 48.0 * st["sec_rays"] + NODE_BYTES * st["sec_nodes"] + 48.0 * st["sec_tris"]
     if kernel == "dir_gen":
         return 12.0 * P + SURF_BYTES * C + SAMPLE_BYTES * st["samples"]
     if kernel == "dir_finalize":
@@ -497,17 +499,20 @@ def kernel_bytes_per_step(kernel: str, st: dict, p) -> float:
 
 
 # Algorithmic VALU work per unit, one lane operation each (add, mul, fma, min, max, compare,
-# select): a BVH2 node visit tests two child boxes, per child and axis 2 subtractions, 2
+# select): a 4-wide node visit tests four child boxes, per child and axis 2 subtractions, 2
 # multiplications by the inverse direction, a min and a max (18), entry and exit as the max /
-# min of three axes and the ray interval (6) and their comparison (1), plus the child order (1):
-# 51. A watertight ray/triangle test (Woop, Benthin and Wald 2013): vertices relative to the
-# origin (9), shear (6), edge functions U, V, W (9), sign tests (6), determinant (2), scaled
-# distance (8), its reciprocal and product (2), range test (2): 44. The env-map pick and the
+# min of three axes and the ray interval (6) and their comparison (1): 4 x 25; then orders the
+# hit children by entry distance, a compare-exchange of (distance, reference) being a min, a max
+# and two selects (4): the nearest first for an any-hit query (3 exchanges, NODE_OPS = 112), all
+# four sorted for a closest-hit one (5 exchanges, NODE_OPS_CLOSEST = 120). A watertight
+# ray/triangle test (Woop, Benthin and Wald 2013): vertices relative to the origin (9), shear
+# (6), edge functions U, V, W (9), sign tests (6), determinant (2), scaled distance (8), its
+# reciprocal and product (2), range test (2): 44. The env-map pick and the
 # shading of one sample (dir_gen, every sample drawn) and the adjoint of one unoccluded sample
 # (shade_bwd; samples that are occluded or face away contribute nothing and are skipped) take
 # about 150 and 350 lane operations (estimates from the instruction mix of the BRDF and its
 # derivatives). Every count stays below the lane operations the SQ counters show executed.
-NODE_OPS, TRI_OPS, GEN_SAMPLE_OPS, BWD_SAMPLE_OPS = 51.0, 44.0, 150.0, 350.0
+NODE_OPS, NODE_OPS_CLOSEST, TRI_OPS, GEN_SAMPLE_OPS, BWD_SAMPLE_OPS = 112.0, 120.0, 44.0, 150.0, 350.0
 # plain (non-packed) FP32 vector issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 
@@ -517,7 +522,7 @@ def kernel_lane_ops_per_step(kernel: str, st: dict) -> float:
         return (NODE_OPS * (st["shadow_nodes"] + st.get("sec_shadow_nodes", 0))
                 + TRI_OPS * (st["shadow_tris"] + st.get("sec_shadow_tris", 0)))
     if kernel == "trace_closest":
-        return NODE_OPS * st["sec_nodes"] + TRI_OPS * st["sec_tris"]
+        return NODE_OPS_CLOSEST * st["sec_nodes"] + TRI_OPS * st["sec_tris"]
     if kernel == "dir_gen":
         return GEN_SAMPLE_OPS * st["samples"]
     if kernel == "shade_bwd":
@@ -583,7 +588,7 @@ def roofline_objects(workload: str, stats: dict, p) -> dict:
                      "algorithmic_lane_ops_per_launch": round(ops_launch) if ok else None,
                      "executed_lane_ops_per_launch": None if executed is None else round(executed),
                      "avg_launch_ms": round(gk[dom]["avg_ms"], 4)},
-        # the same launches counted in the method's bytes (64 B per node visit, 48 B per triangle
+        # the same launches counted in the method's bytes (128 B per node visit, 48 B per triangle
         # test, the ray in and the answer out): served from L2 and the 256 MB MALL, so no HBM
         # peak applies to this rate
         "cache_bytes": {"kernel": dom, "bytes_per_launch": None if math.isnan(bytes_launch) else round(bytes_launch),

@@ -126,10 +126,11 @@ typedef struct exm_bvh exm_bvh; /* opaque; device resident; owned by the library
  * "interpolated on the current face", Attribute Query). Writes m->vnrm and m->ftan. */
 exm_status exm_mesh_prepare(const exm_mesh* m, hipStream_t stream);
 
-/* Binned-SAH BVH over the fixed triangles, built on the host and uploaded on `stream`
- * (ray queries for visibility and secondary hits: Direct Illumination, One-Bounce Indirect
- * Illumination). Host inputs; *out receives a handle. At most 2^25 triangles: the builder bounds
- * the depth at 24 so that the traversal's stack cannot overflow, which holds up to that size;
+/* Binned-SAH BVH over the fixed triangles, built on the host as a binary tree, collapsed to
+ * 4-wide nodes (128 bytes each) and uploaded on `stream` (ray queries for visibility and
+ * secondary hits: Direct Illumination, One-Bounce Indirect Illumination). Host inputs; *out
+ * receives a handle. At most 2^25 triangles: the builder bounds the binary depth at 24 (the wide
+ * depth at 12) so that the traversal's stack cannot overflow, which holds up to that size;
  * larger meshes return EXM_E_UNSUPPORTED before anything is read. Returns EXM_E_NOMEM if device
  * memory runs out. exm_free_bvh waits for the stream work that uses the BVH to be done by the
  * caller. */

@@ -178,12 +178,15 @@ exm_status exm_build_bvh(const float* pos_host, int32_t nV, const int32_t* tri_h
     free_bvh_host(&hb);
     return fail(EXM_E_UNSUPPORTED, "exm_build_bvh: BVH deeper than the traversal stack");
   }
+  if (hb.depth4 > kMaxDepth4) {  // follows from the binary bound; checked because the stack relies on it
+    free_bvh_host(&hb);
+    return fail(EXM_E_UNSUPPORTED, "exm_build_bvh: 4-wide BVH deeper than the traversal stack");
+  }
   exm_bvh* b = new exm_bvh;
-  b->n_nodes = hb.n_nodes;
+  b->n_nodes = hb.n_nodes4;
   b->n_tris = hb.n_tris;
-  b->root_is_leaf = hb.root_is_leaf;
   b->depth = hb.depth;
-  const size_t nb = sizeof(BvhNode) * (size_t)std::max(1, hb.n_nodes);
+  const size_t nb = sizeof(BvhNode4) * (size_t)std::max(1, hb.n_nodes4);
   const size_t tb = sizeof(BvhTri) * (size_t)std::max(1, hb.n_tris);
   if (hipMalloc(&b->nodes, nb) != hipSuccess || hipMalloc(&b->tris, tb) != hipSuccess) {
     if (b->nodes) (void)hipFree(b->nodes);
@@ -194,7 +197,7 @@ exm_status exm_build_bvh(const float* pos_host, int32_t nV, const int32_t* tri_h
   }
   b->bytes = nb + tb;
   // synchronous copies: the host arrays are freed right after
-  hipError_t e1 = hipMemcpyAsync(b->nodes, hb.nodes, sizeof(BvhNode) * (size_t)hb.n_nodes, hipMemcpyHostToDevice, stream);
+  hipError_t e1 = hipMemcpyAsync(b->nodes, hb.nodes4, sizeof(BvhNode4) * (size_t)hb.n_nodes4, hipMemcpyHostToDevice, stream);
   hipError_t e2 = hipMemcpyAsync(b->tris, hb.tris, sizeof(BvhTri) * (size_t)hb.n_tris, hipMemcpyHostToDevice, stream);
   hipError_t e3 = hipStreamSynchronize(stream);
   free_bvh_host(&hb);

@@ -1,14 +1,15 @@
 // Host builder of the ray-query acceleration structure: a BVH2 over the fixed triangles with
 // binned SAH splits (32 bins per axis), leaves of 2 to 8 triangles (a smaller minimum trades
 // triangle tests for node visits: 10.0 -> 5.5 tests and 26.9 -> 29.4 visits per shadow ray on the
-// displaced sphere, 2% less traversal time), and a depth bound.
+// displaced sphere, 2% less traversal time), and a depth bound; then the 4-wide tree the traversal
+// reads, collapsed from it two levels at a time.
 //
 // Depth bound: with need(N) = smallest k such that 2 * 2^k >= N, every node at depth d holds
 // d + need(N) <= kMaxDepth. A node at the bound is split at the object median of its longest
 // centroid axis (each child gets at most ceil(N/2) triangles, so need drops by one); leaves
-// therefore sit at depth <= kMaxDepth and a traversal stack of kStack entries never overflows
-// (kMaxDepth = 24 deferred references plus the stack's bottom sentinel, kStack = 25: 25 KB of LDS
-// per 256-lane block, which keeps six blocks per CU).
+// therefore sit at depth <= kMaxDepth = 24, the wide tree is at most kMaxDepth4 = 12 levels deep,
+// and the traversal, which defers at most three children per wide level, never holds more than
+// kStack = 37 references (with the bottom sentinel).
 // Subtrees above a size threshold are built on separate threads; node slots come from an
 // atomic counter and each thread partitions its own index range, so the result is
 // deterministic up to node numbering, which does not change any ray query's answer.
@@ -192,6 +193,64 @@ struct Builder {
   }
 };
 
+// The 4-wide tree: each wide node holds the children of a binary node's children (a child that is
+// a leaf stays one slot), so wide nodes are the binary nodes at even depths. Nodes are numbered in
+// depth-first pre-order. Returns the wide depth below `n2` (1 for a node whose slots are all leaves).
+struct Collapser {
+  const BvhNode* n2;
+  std::vector<BvhNode4> out;
+  int32_t emit(int32_t b, int32_t* depth) {
+    const int32_t me = (int32_t)out.size();
+    out.emplace_back();
+    int32_t ref[4];
+    float lo[4][3], hi[4][3];
+    int n = 0;
+    const BvhNode& N = n2[b];
+    for (int c = 0; c < 2; ++c) {
+      const int32_t ci = c == 0 ? N.c0 : N.c1;
+      const float* clo = c == 0 ? N.lo0 : N.lo1;
+      const float* chi = c == 0 ? N.hi0 : N.hi1;
+      if (ci >= 0) {
+        const BvhNode& C = n2[ci];
+        ref[n] = C.c0;
+        std::memcpy(lo[n], C.lo0, 12);
+        std::memcpy(hi[n], C.hi0, 12);
+        ++n;
+        ref[n] = C.c1;
+        std::memcpy(lo[n], C.lo1, 12);
+        std::memcpy(hi[n], C.hi1, 12);
+        ++n;
+      } else if (ci != kEmptyChild) {
+        ref[n] = ci;
+        std::memcpy(lo[n], clo, 12);
+        std::memcpy(hi[n], chi, 12);
+        ++n;
+      }
+    }
+    int32_t sub = 0;
+    for (int k = 0; k < n; ++k)
+      if (ref[k] >= 0) {
+        int32_t d = 0;
+        ref[k] = emit(ref[k], &d);
+        sub = std::max(sub, d);
+      }
+    *depth = sub + 1;
+    BvhNode4& W = out[me];  // after the recursion: `out` may have grown
+    std::memset(&W, 0, sizeof(W));
+    for (int k = 0; k < 4; ++k) {
+      const bool used = k < n;
+      W.lo_x[k] = used ? lo[k][0] : INFINITY;
+      W.lo_y[k] = used ? lo[k][1] : INFINITY;
+      W.lo_z[k] = used ? lo[k][2] : INFINITY;
+      W.hi_x[k] = used ? hi[k][0] : -INFINITY;
+      W.hi_y[k] = used ? hi[k][1] : -INFINITY;
+      W.hi_z[k] = used ? hi[k][2] : -INFINITY;
+      W.child[k] = used ? ref[k] : kEmptyChild;
+    }
+    return me;
+  }
+};
+
 }  // namespace
 
 bool build_bvh_host(const float* pos, int32_t nV, const int32_t* tri, int32_t nF, HostBvh* out, std::string* err) {
@@ -261,13 +320,31 @@ bool build_bvh_host(const float* pos, int32_t nV, const int32_t* tri, int32_t nF
   out->n_nodes = B.n_nodes.load();
   out->n_tris = nF;
   out->depth = B.max_depth.load();
+  Collapser W{B.nodes, {}};
+  W.out.reserve((size_t)out->n_nodes / 2 + 1);
+  int32_t d4 = 0;
+  W.emit(0, &d4);
+  out->nodes4 = static_cast<BvhNode4*>(::operator new[](sizeof(BvhNode4) * W.out.size(), std::align_val_t(128), std::nothrow));
+  if (!out->nodes4) {
+    *err = "host allocation of the wide BVH nodes failed";
+    ::operator delete[](B.nodes, std::align_val_t(64));
+    ::operator delete[](tris, std::align_val_t(64));
+    out->nodes = nullptr;
+    out->tris = nullptr;
+    return false;
+  }
+  std::memcpy(out->nodes4, W.out.data(), sizeof(BvhNode4) * W.out.size());
+  out->n_nodes4 = (int32_t)W.out.size();
+  out->depth4 = d4;
   return true;
 }
 
 void free_bvh_host(HostBvh* b) {
   if (b->nodes) ::operator delete[](b->nodes, std::align_val_t(64));
+  if (b->nodes4) ::operator delete[](b->nodes4, std::align_val_t(128));
   if (b->tris) ::operator delete[](b->tris, std::align_val_t(64));
   b->nodes = nullptr;
+  b->nodes4 = nullptr;
   b->tris = nullptr;
 }
 

@@ -507,12 +507,11 @@ __device__ __forceinline__ Spec spec_terms(f3 n, f3 wi, f3 wo, float ci, float r
 }
 
 // ------------------------------------------------------------------------------------------
-// BVH (binned SAH, 64-byte nodes) and ray queries
+// BVH (binned SAH, collapsed to 128-byte 4-wide nodes) and ray queries
 // ------------------------------------------------------------------------------------------
 struct BvhView {
-  const BvhNode* nodes;
+  const BvhNode4* nodes;  // 4-wide nodes, root at 0
   const BvhTri* tris;
-  int32_t root_is_leaf;
 };
 
 // ray precomputation for the watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013)
@@ -626,8 +625,8 @@ struct TraceCount {
 };
 
 // Resumable traversal state: the node to visit next, one postponed leaf, the depth of the
-// lane's stack of deferred node references (kept in LDS at stack[slot * stride]), and the
-// number of rounds the query has taken.
+// lane's stack of deferred node references (LaneStack), and the number of rounds the query has
+// taken.
 struct TravState {
   int32_t ref;
   int32_t leaf;
@@ -644,12 +643,24 @@ constexpr uint32_t kMaxRounds = 1u << 22;
 
 __device__ __forceinline__ bool is_leaf(int32_t ref) { return ref < 0 && ref != kEmptyRef; }
 
+// The lane's stack: entries [0, kStackLds) in LDS at stack[i * stride], the rest in its private
+// overflow array. The overflow pointer carries the private address space so that the compiler
+// keeps its accesses apart from the LDS ones (as two generic pointers, the two loads of a pop merge
+// into one generic-address load on every pop).
+typedef volatile __attribute__((address_space(5))) int32_t private_i32;  // private (scratch) memory, kept there
+struct LaneStack {
+  int32_t* lds;
+  private_i32* ovf;
+  int stride;
+};
+
 // The lane's stack starts with kEmptyRef as a sentinel in its bottom slot: popping it ends the
 // query, so a pop never needs to test for an empty stack (a query pops nothing after it).
-__device__ __forceinline__ void trav_begin(const BvhView& B, TravState& s, HitRec& h, int32_t* stack) {
-  s.ref = B.root_is_leaf ? B.nodes[0].c0 : 0;
+__device__ __forceinline__ void trav_begin(const BvhView& B, TravState& s, HitRec& h, const LaneStack& st) {
+  (void)B;
+  s.ref = 0;  // the wide root always exists (a mesh in one leaf, or none, hangs from its slots)
   s.leaf = kEmptyRef;
-  stack[0] = kEmptyRef;
+  st.lds[0] = kEmptyRef;
   s.sp = 1;
   s.rounds = 0;
   h.id = -1;
@@ -657,8 +668,35 @@ __device__ __forceinline__ void trav_begin(const BvhView& B, TravState& s, HitRe
   h.b1 = h.b2 = 0.0f;
 }
 
-__device__ __forceinline__ int32_t trav_pop(TravState& s, const int32_t* stack, int stride) {
-  return stack[(--s.sp) * stride];
+__device__ __forceinline__ int32_t trav_pop(TravState& s, const LaneStack& st) {
+  --s.sp;
+  if (s.sp < kStackLds) return st.lds[s.sp * st.stride];
+  return st.ovf[s.sp - kStackLds];
+}
+
+// order in which an any-hit query visits the hit children of a wide node: 0 slot order, 1 nearest
+// first, 2 by distance
+constexpr int kAnyOrder = 1;
+
+// guarded push: the builder's depth bound keeps the stack within kStack entries
+__device__ __forceinline__ void trav_push(TravState& s, const LaneStack& st, int32_t ref) {
+  if (s.sp < kStackLds) {
+    st.lds[(s.sp++) * st.stride] = ref;
+  } else if (s.sp < kStack) {
+    st.ovf[s.sp - kStackLds] = ref;
+    ++s.sp;
+  }
+}
+
+// (ka, ra), (kb, rb) in ascending order of k (ties keep their order)
+__device__ __forceinline__ void sort2(float& ka, int32_t& ra, float& kb, int32_t& rb) {
+  const bool sw = kb < ka;
+  const float k = sw ? kb : ka;
+  const int32_t r = sw ? rb : ra;
+  kb = sw ? ka : kb;
+  rb = sw ? ra : rb;
+  ka = k;
+  ra = r;
 }
 
 // inclusive prefix sum of x over the 64 lanes of the wave (every lane must be active)
@@ -797,8 +835,8 @@ __device__ __forceinline__ bool leaves_any_wave(const BvhView& B, const Ray& r, 
 // any-hit queries test their leaves across the whole wave (leaf_any_wave). Returns true when
 // the lane's query is finished: nothing left to visit, or ANY and a hit was found.
 template <bool ANY, bool COUNT, bool PER_LANE_BVH = false>
-__device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float tmin, int32_t skip, int32_t* stack,
-                                           int stride, TravState& s, HitRec& h, TraceCount* counts,
+__device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float tmin, int32_t skip,
+                                           const LaneStack& st, TravState& s, HitRec& h, TraceCount* counts,
                                            int32_t leaf_gate = 1) {
   bool capped = false;
   if (++s.rounds > kMaxRounds) {  // drop the query (no early return: the leaf phase needs every lane)
@@ -814,42 +852,76 @@ __device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float
       break;
     }
     if (COUNT) counts->nodes++;
-    const BvhNode& N = B.nodes[(uint32_t)s.ref];
-    const float4 a = reinterpret_cast<const float4*>(&N)[0];
-    const float4 b = reinterpret_cast<const float4*>(&N)[1];
-    const float4 c = reinterpret_cast<const float4*>(&N)[2];
-    const int4 e = reinterpret_cast<const int4*>(&N)[3];
-    const float lo0[3] = {a.x, a.y, a.z}, hi0[3] = {a.w, b.x, b.y};
-    const float lo1[3] = {b.z, b.w, c.x}, hi1[3] = {c.y, c.z, c.w};
-    float t0, t1;
-    const bool h0 = box_hit<!ANY>(lo0, hi0, r, h.t, &t0);
-    const bool h1 = box_hit<!ANY>(lo1, hi1, r, h.t, &t1);
-    if (h0 && h1) {
-      const bool first0 = t0 <= t1;
-      s.ref = first0 ? e.x : e.y;
-      if (s.sp < kStack) stack[(s.sp++) * stride] = first0 ? e.y : e.x;
-    } else if (h0 || h1) {
-      s.ref = h0 ? e.x : e.y;
+    // one 4-wide node: the four child boxes by axis, then the child references
+    const float4* q = reinterpret_cast<const float4*>(B.nodes + (uint32_t)s.ref);
+    const float4 lx = q[0], ly = q[1], lz = q[2], hx = q[3], hy = q[4], hz = q[5];
+    const int4 cr = reinterpret_cast<const int4*>(q)[6];
+    constexpr float kMiss = __builtin_huge_valf();
+    float k0, k1, k2, k3;  // entry distance of a hit child, kMiss otherwise
+    int32_t r0 = cr.x, r1 = cr.y, r2 = cr.z, r3 = cr.w;
+    {
+      float t;
+      const float a0[3] = {lx.x, ly.x, lz.x}, b0[3] = {hx.x, hy.x, hz.x};
+      k0 = box_hit<!ANY>(a0, b0, r, h.t, &t) && r0 != kEmptyRef ? t : kMiss;
+      const float a1[3] = {lx.y, ly.y, lz.y}, b1[3] = {hx.y, hy.y, hz.y};
+      k1 = box_hit<!ANY>(a1, b1, r, h.t, &t) && r1 != kEmptyRef ? t : kMiss;
+      const float a2[3] = {lx.z, ly.z, lz.z}, b2[3] = {hx.z, hy.z, hz.z};
+      k2 = box_hit<!ANY>(a2, b2, r, h.t, &t) && r2 != kEmptyRef ? t : kMiss;
+      const float a3[3] = {lx.w, ly.w, lz.w}, b3[3] = {hx.w, hy.w, hz.w};
+      k3 = box_hit<!ANY>(a3, b3, r, h.t, &t) && r3 != kEmptyRef ? t : kMiss;
+    }
+    if (ANY && kAnyOrder == 0) {  // slot order: descend into the first hit child, defer the others
+      int32_t nxt = kEmptyRef;
+      if (k3 != kMiss) nxt = r3;
+      if (k2 != kMiss) {
+        if (nxt != kEmptyRef) trav_push(s, st, nxt);
+        nxt = r2;
+      }
+      if (k1 != kMiss) {
+        if (nxt != kEmptyRef) trav_push(s, st, nxt);
+        nxt = r1;
+      }
+      if (k0 != kMiss) {
+        if (nxt != kEmptyRef) trav_push(s, st, nxt);
+        nxt = r0;
+      }
+      s.ref = nxt != kEmptyRef ? nxt : trav_pop(s, st);
     } else {
-      s.ref = trav_pop(s, stack, stride);
+      // nearest first: a four-input sorting network on (distance, reference), misses last; any-hit
+      // queries with kAnyOrder 1 only bring the nearest to the front (the first three exchanges)
+      sort2(k0, r0, k1, r1);
+      sort2(k2, r2, k3, r3);
+      sort2(k0, r0, k2, r2);
+      if (!(ANY && kAnyOrder == 1)) {
+        sort2(k1, r1, k3, r3);
+        sort2(k1, r1, k2, r2);
+      }
+      if (k0 == kMiss) {
+        s.ref = trav_pop(s, st);
+      } else {  // descend into the nearest, defer the others (farthest first when sorted)
+        s.ref = r0;
+        if (k3 != kMiss) trav_push(s, st, r3);
+        if (k2 != kMiss) trav_push(s, st, r2);
+        if (k1 != kMiss) trav_push(s, st, r1);
+      }
     }
     if (is_leaf(s.ref) && s.leaf == kEmptyRef) {  // postpone the leaf, keep descending
       s.leaf = s.ref;
-      s.ref = trav_pop(s, stack, stride);
+      s.ref = trav_pop(s, st);
     }
     if (__popcll(__ballot(s.leaf == kEmptyRef)) < leaf_gate) break;
   }
   if (s.leaf == kEmptyRef && is_leaf(s.ref)) {  // a round that starts on a leaf (a root leaf, or the
                                                 // second of two leaves met in the last round)
     s.leaf = s.ref;
-    s.ref = trav_pop(s, stack, stride);
+    s.ref = trav_pop(s, st);
   }
   if (ANY) {
     // the postponed leaf and, when the next reference is a leaf as well, that one too, tested
     // across the wave (straight-line code: no lane may leave before the cross-lane reads)
     const bool second = s.leaf != kEmptyRef && is_leaf(s.ref);
     const int32_t leaf_b = second ? s.ref : kEmptyRef;
-    if (second) s.ref = trav_pop(s, stack, stride);
+    if (second) s.ref = trav_pop(s, st);
     const bool hit = leaves_any_wave<COUNT, PER_LANE_BVH>(B, r, tmin, skip, s.leaf, leaf_b, counts);
     s.leaf = kEmptyRef;
     if (hit) h.id = 0;  // any-hit queries report only that something was hit
@@ -883,7 +955,7 @@ __device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float
     s.leaf = kEmptyRef;
     if (is_leaf(s.ref)) {
       s.leaf = s.ref;
-      s.ref = trav_pop(s, stack, stride);
+      s.ref = trav_pop(s, st);
     }
   }
   return capped || s.ref == kEmptyRef;

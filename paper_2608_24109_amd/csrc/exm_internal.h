@@ -20,6 +20,19 @@ struct alignas(64) BvhNode {
 };
 static_assert(sizeof(BvhNode) == 64, "node layout");
 
+// 128-byte 4-wide node (one cache line) for the traversal: the child boxes by axis, so that seven
+// 16-byte loads fetch the node, then the child references (internal: node index; leaf:
+// ~(first * 16 + count) into the triangle records; empty slot: kEmptyChild). Collapsed from the
+// binary tree two levels at a time, so a tree of depth <= kMaxDepth gives 4-wide depth <= 12.
+struct alignas(128) BvhNode4 {
+  float lo_x[4], lo_y[4], lo_z[4];
+  float hi_x[4], hi_y[4], hi_z[4];
+  int32_t child[4];
+  int32_t pad[4];
+};
+static_assert(sizeof(BvhNode4) == 128, "wide node layout");
+constexpr int32_t kEmptyChild = (int32_t)0x80000000;
+
 // 48-byte triangle record in leaf order (vertices copied, original id kept)
 struct alignas(16) BvhTri {
   float v0[3], v1[3], v2[3];
@@ -28,8 +41,14 @@ struct alignas(16) BvhTri {
 };
 static_assert(sizeof(BvhTri) == 48, "triangle layout");
 
-constexpr int kMaxDepth = 24;  // builder guarantee; traversal stack holds <= kMaxDepth refs
-constexpr int kStack = 25;  // 24 deferred references (the depth bound) + the bottom sentinel
+constexpr int kMaxDepth = 24;  // builder guarantee for the binary tree
+constexpr int kMaxDepth4 = (kMaxDepth + 1) / 2;  // of the 4-wide tree collapsed from it
+// the traversal defers at most three children per 4-wide node on its path: 36 references plus the
+// bottom sentinel; the first kStackLds entries live in LDS (25 KB per 256-lane block, so six
+// blocks fit a CU), the rest, which only deep stacks reach, in a per-lane private array
+constexpr int kStack = 3 * kMaxDepth4 + 1;
+constexpr int kStackLds = 25;
+constexpr int kStackOvf = kStack - kStackLds;
 // The builder's depth bound holds while need(nF) <= kMaxDepth, i.e. for at most 2 * 2^kMaxDepth
 // triangles (2^25); larger meshes would put leaves below the bound and overflow the stack.
 constexpr int64_t kMaxBvhTris = (int64_t)2 << kMaxDepth;
@@ -53,11 +72,10 @@ struct ShadeViews {
 }  // namespace exm
 
 struct exm_bvh {
-  exm::BvhNode* nodes = nullptr;
+  exm::BvhNode4* nodes = nullptr;  // 4-wide nodes, root at 0
   exm::BvhTri* tris = nullptr;
   int32_t n_nodes = 0, n_tris = 0;
-  int32_t root_is_leaf = 0;
-  int32_t depth = 0;
+  int32_t depth = 0;  // of the binary tree it was collapsed from
   size_t bytes = 0;
 };
 
@@ -182,9 +200,10 @@ size_t trace_bwd_ws_min(int32_t N_b, int32_t N_s, int32_t He, int32_t We);
 
 // host SAH builder (bvh_build.cpp): fills node/triangle arrays in host memory
 struct HostBvh {
-  BvhNode* nodes;
+  BvhNode* nodes;    // the binary tree (host only)
+  BvhNode4* nodes4;  // the 4-wide tree the traversal reads (root at 0)
   BvhTri* tris;
-  int32_t n_nodes, n_tris, root_is_leaf, depth;
+  int32_t n_nodes, n_nodes4, n_tris, root_is_leaf, depth, depth4;
 };
 bool build_bvh_host(const float* pos, int32_t nV, const int32_t* tri, int32_t nF, HostBvh* out, std::string* err);
 void free_bvh_host(HostBvh* b);

@@ -36,8 +36,9 @@ __global__ __launch_bounds__(kThreads) void k_trace(BvhView B0, BvhTable bt, Ray
                                                     int32_t leaf_gate, HitRec* __restrict__ out_hit,
                                                     uint8_t* __restrict__ out_any,
                                                     unsigned long long* __restrict__ counters) {
-  __shared__ int32_t stack_mem[kStack * kThreads];
-  int32_t* stack = stack_mem + threadIdx.x;
+  __shared__ int32_t stack_mem[kStackLds * kThreads];
+  int32_t ovf[kStackOvf];  // private: only stacks deeper than kStackLds reach it
+  const LaneStack stack{stack_mem + threadIdx.x, (private_i32*)ovf, kThreads};
   BvhView B = B0;        // the BVH of the lane's ray
   BvhView B_region = B0;  // the BVH of the region being handed out (wave-uniform)
   // wave-uniform region cursor
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(kThreads) void k_trace(BvhView B0, BvhTable bt, Ray
     }
     if (__ballot(have_ray) == 0ull) break;
     while (true) {  // every lane of the wave calls trav_round (the any-hit leaf phase spans the wave)
-      const bool fin = trav_round<ANY, COUNT, BATCH>(B, ray, tmin, skip, stack, kThreads, ts, h, &tc, leaf_gate);
+      const bool fin = trav_round<ANY, COUNT, BATCH>(B, ray, tmin, skip, stack, ts, h, &tc, leaf_gate);
       if (have_ray && fin) {
         if (ANY)
           out_any[slot] = h.id >= 0 ? 1 : 0;
@@ -150,7 +151,7 @@ hipError_t launch_impl(const BvhView& B0, const BvhTable& bt, const RayBatch& rb
 
 hipError_t launch_trace_any(const exm_bvh* bvh, const RayBatch& rb, uint8_t* out, unsigned long long* counters,
                             hipStream_t s) {
-  const BvhView B{bvh->nodes, bvh->tris, bvh->root_is_leaf};
+  const BvhView B{bvh->nodes, bvh->tris};
   const BvhTable none{};
   return counters ? launch_impl<true, true, false>(B, none, rb, nullptr, out, counters, s)
                   : launch_impl<true, false, false>(B, none, rb, nullptr, out, nullptr, s);
@@ -164,7 +165,7 @@ hipError_t launch_trace_any_batch(const BvhTable& t, const RayBatch& rb, uint8_t
 
 hipError_t launch_trace_closest(const exm_bvh* bvh, const RayBatch& rb, HitRec* out, unsigned long long* counters,
                                 hipStream_t s) {
-  const BvhView B{bvh->nodes, bvh->tris, bvh->root_is_leaf};
+  const BvhView B{bvh->nodes, bvh->tris};
   const BvhTable none{};
   return counters ? launch_impl<false, true, false>(B, none, rb, out, nullptr, counters, s)
                   : launch_impl<false, false, false>(B, none, rb, out, nullptr, nullptr, s);

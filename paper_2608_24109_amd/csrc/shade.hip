@@ -613,7 +613,7 @@ EnvView env_view(const exm_env* e) {
   return EnvView{e->He,    e->We,    e->env, e->cdf_row, e->cdf_col, e->pdf,
                  e->guide, reinterpret_cast<const float4*>(e->rec), c32, g16, c16};
 }
-BvhView bvh_view(const exm_bvh* b) { return BvhView{b->nodes, b->tris, b->root_is_leaf}; }
+BvhView bvh_view(const exm_bvh* b) { return BvhView{b->nodes, b->tris}; }
 
 hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat, const exm_env* env,
                             const ShadeViews& v, const int32_t* tri_id, const float* bary, const exm_params* p,

@@ -86,7 +86,7 @@ def main() -> int:
         for pos, tri in meshes + [same]:
             pos = np.ascontiguousarray(pos, np.float32)
             tri = np.ascontiguousarray(tri, np.int32)
-            st = np.zeros(4, np.int32)
+            st = np.zeros(6, np.int32)
             rc = lib.bvh_check(pos.ctypes.data, pos.shape[0], tri.ctypes.data, tri.shape[0], st.ctypes.data)
             if rc != 0:
                 print(f"bvh invariant {rc} broken on a mesh of {tri.shape[0]} triangles")

@@ -22,7 +22,9 @@ def test_work_models():
     st = dict(pixels=100, covered=60, samples=3840, shadow_rays=1000, shadow_nodes=30000, shadow_tris=5000,
               sec_rays=200, sec_nodes=7000, sec_tris=1200, sec_shadow_rays=500, sec_shadow_nodes=15000,
               sec_shadow_tris=2500)
-    assert bench.kernel_lane_ops_per_step("trace_any", st) == 51 * (30000 + 15000) + 44 * (5000 + 2500)
-    assert bench.kernel_lane_ops_per_step("trace_closest", st) == 51 * 7000 + 44 * 1200
-    assert bench.kernel_bytes_per_step("trace_any", st, None) == 33 * 1500 + 64 * 45000 + 48 * 7500
+    # a 4-wide node visit: four child slab tests of 25 lane operations, then 3 (any-hit: nearest
+    # first) or 5 (closest hit: sorted) compare-exchanges of 4; 128 B per node, 48 B per triangle
+    assert bench.kernel_lane_ops_per_step("trace_any", st) == (4 * 25 + 3 * 4) * (30000 + 15000) + 44 * (5000 + 2500)
+    assert bench.kernel_lane_ops_per_step("trace_closest", st) == (4 * 25 + 5 * 4) * 7000 + 44 * 1200
+    assert bench.kernel_bytes_per_step("trace_any", st, None) == 33 * 1500 + 128 * 45000 + 48 * 7500
     assert abs(bench.VALU_PEAK_T - 39.3216) < 1e-9

@@ -1,7 +1,9 @@
 """The host SAH builder's output satisfies what the device traversal relies on: a tree whose
 nodes are each reached once, every triangle in exactly one leaf, child boxes inside parent
-boxes and around their triangles, leaves of 1..15 triangles, depth <= 24 (the traversal
-stack holds 24 references)."""
+boxes and around their triangles, leaves of 1..15 triangles, depth <= 24; and the 4-wide tree the
+traversal reads, collapsed from it two levels at a time: every wide node reached once, slot boxes
+nested and around their triangles, every triangle in one leaf slot, depth <= 12 (the traversal
+stack holds three deferred children per wide level)."""
 import ctypes as C
 import os
 import subprocess
@@ -30,12 +32,12 @@ def checker(tmp_path_factory):
 def run(checker, pos, tri):
     pos = np.ascontiguousarray(pos, np.float32)
     tri = np.ascontiguousarray(tri, np.int32)
-    st = np.zeros(4, np.int32)
+    st = np.zeros(6, np.int32)
     rc = checker.bvh_check(pos.ctypes.data, pos.shape[0], tri.ctypes.data, tri.shape[0], st.ctypes.data)
     return rc, st
 
 
-@pytest.mark.parametrize("mesh", ["one", "four", "icosphere", "degenerate", "sphere", "tori"])
+@pytest.mark.parametrize("mesh", ["one", "four", "icosphere", "degenerate", "sphere", "tori", "stack"])
 def test_builder_invariants(checker, mesh):
     if mesh == "one":
         pos, tri = I.quad_mesh(np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0]]), 1, 1)
@@ -48,6 +50,12 @@ def test_builder_invariants(checker, mesh):
         # 5000 copies of the same triangle: centroids coincide, median splits by index
         pos = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32)
         tri = np.tile(np.array([[0, 1, 2]], np.int32), (5000, 1))
+    elif mesh == "stack":
+        # a floor and 2^20 coincident copies of one triangle (the GPU deep-stack test's scene)
+        floor_p, floor_t = I.quad_mesh(np.array([[-2, 0, 2], [2, 0, 2], [2, 0, -2], [-2, 0, -2]]), 1, 1)
+        tv = np.array([[-0.5, 0.5, 0.5], [0.5, 0.5, 0.5], [0.5, 0.5, -0.5]], np.float32)
+        pos = np.concatenate([floor_p, tv])
+        tri = np.concatenate([floor_t, np.tile(np.array([[4, 5, 6]], np.int32), (1 << 20, 1))])
     elif mesh == "sphere":
         pos, tri = I.displaced_cube_sphere(129)
     else:
@@ -55,6 +63,9 @@ def test_builder_invariants(checker, mesh):
     rc, st = run(checker, pos, tri)
     assert rc == 0, f"invariant {rc} broken; stats {st}"
     assert st[1] <= 24 and st[2] <= 15
+    assert 1 <= st[5] <= 12 and st[4] >= 1  # the 4-wide tree: depth <= 12 (stack of 3 x 12 + 1)
+    if mesh == "stack":
+        assert st[5] == 9  # a ray through the shared box defers 3 x 9 + 1 = 28 entries (25 in LDS)
     if mesh == "tori":
         assert st[0] < tri.shape[0]  # internal nodes
         assert st[1] <= 24

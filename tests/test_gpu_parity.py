@@ -437,6 +437,48 @@ def test_full_size_sampled_pixels(name):
         _compare_view(dev, sc.cams[v], p, b, v, v, pix=pix)
 
 
+def _coincident_stack(n_copies: int):
+    """A 4 x 4 floor (y = 0) and n_copies of one triangle at y = 0.5 covering half of the square
+    [-0.5, 0.5]^2: the copies' boxes all coincide."""
+    floor_p, floor_t = I.quad_mesh(np.array([[-2, 0, 2], [2, 0, 2], [2, 0, -2], [-2, 0, -2]]), 1, 1)
+    tri_v = np.array([[-0.5, 0.5, 0.5], [0.5, 0.5, 0.5], [0.5, 0.5, -0.5]], np.float32)
+    pos = np.concatenate([floor_p, tri_v]).astype(np.float32)
+    tri = np.concatenate([floor_t, np.tile(np.array([[4, 5, 6]], np.int32), (n_copies, 1))]).astype(np.int32)
+    return pos, tri
+
+
+def test_deep_traversal_stack_coincident_triangles():
+    """2^20 coincident copies of a triangle above a floor: the builder splits them by index into a
+    binary tree 18 levels deep, whose 4-wide form is 9 levels deep (pinned on the host by
+    tests/test_bvh_builder.py), and every box of it is the same square. A shadow ray through that
+    square (from the floor, or leaving the stack itself) has all four children of every wide node
+    hit, so it defers three per level: 28 stack entries, three past the 25 the traversal keeps in
+    LDS, in the lane's private overflow. The oracle renders the scene with one copy (the copies
+    coincide, so visibility is the same, and the raster keeps the lowest id); ids, visibility
+    bits and radiance match on the whole frame."""
+    from paper_2608_24109_amd import _lib as L
+    from paper_2608_24109_amd.render import PassBuffers, render_forward
+    from paper_2608_24109_amd.scene import DeviceMesh
+    pos, many = _coincident_stack(1 << 20)
+    one = many[:3].copy()
+    cams = I.ring_cameras(1, 3.0, 64, 64, elev_deg=55.0)
+    env = I.env_map(32, 64, 1.0, seed=7)
+    sc1 = I.make_scene("stack_one", pos, one, 64, 64, 32, 64, 1.0, cams, N_d=16, env=env)
+    scN = I.make_scene("stack_many", pos, many, 64, 64, 32, 64, 1.0, cams, N_d=16, tex=sc1.tex, env=env)
+    assert np.array_equal(scN.uv[scN.tri_uv[2]], sc1.uv[sc1.tri_uv[2]]) and scN.tmin == sc1.tmin
+    log("[direct] 2^20 coincident triangles over a floor, 64^2")
+    dev = Dev(sc1)
+    mesh_n = DeviceMesh(scN.pos, scN.tri, scN.uv, scN.tri_uv)
+    p = dev.params()
+    cc = L.cameras(cams, [0])
+    b = PassBuffers(1, 64, 64, 0)
+    render_forward(mesh_n, dev.mat, dev.env, cc, p, b)
+    torch.cuda.synchronize()
+    ids = b.tri_id[0].cpu().numpy()
+    assert (ids == 2).sum() > 50 and (ids == 0).sum() + (ids == 1).sum() > 1000  # stack and floor in view
+    _compare_view(dev, cams[0], p, b, 0, 0)
+
+
 def test_determinism_and_view_batching(small_tori):
     sc = small_tori.sc
     p = small_tori.params()
