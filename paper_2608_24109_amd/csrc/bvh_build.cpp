@@ -1,8 +1,6 @@
 // Host builder of the ray-query acceleration structure: a BVH2 over the fixed triangles with
-// binned SAH splits (32 bins per axis), leaves of 2 to 8 triangles (a smaller minimum trades
-// triangle tests for node visits: 10.0 -> 5.5 tests and 26.9 -> 29.4 visits per shadow ray on the
-// displaced sphere, 2% less traversal time), and a depth bound; then the 4-wide tree the traversal
-// reads, collapsed from it two levels at a time.
+// binned SAH splits (32 bins per axis), leaves of 2 to 8 triangles, and a depth bound; then the
+// 4-wide tree the traversal reads, collapsed from it two levels at a time.
 //
 // Depth bound: with need(N) = smallest k such that 2 * 2^k >= N, every node at depth d holds
 // d + need(N) <= kMaxDepth. A node at the bound is split at the object median of its longest
@@ -140,7 +138,11 @@ struct Builder {
         }
       }
       const float leaf_cost = bb.area() * count;
-      const float trav = bb.area();  // one node visit costs about one triangle test
+      // a wide node visit costs about two triangle tests (the any-hit leaf phase tests triangles
+      // across the whole wave); swept at 1, 2 and 4 with leaves of at least 2 or 4 triangles: 2
+      // took the tori's any-hit traversal 18.7 -> 18.2 ms (closest hit 2.53 -> 2.64 ms), 4 made
+      // it slower (19.1 ms, 16 triangle tests per ray)
+      const float trav = 2.0f * bb.area();
       if (count <= kLeafMax && (axis < 0 || leaf_cost <= trav + best_cost)) return leaf_ref(first, count);
     }
     int32_t mid;
