@@ -517,22 +517,23 @@ struct BvhView {
 // ray precomputation for the watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013)
 struct Ray {
   f3 o, d, inv;
-  f3 off_lo, off_hi;  // slab offsets: o * inv moved outwards per axis (see make_ray)
+  f3 off_n, off_f;    // slab offsets of the entry and exit planes: o * inv moved outwards per axis
+  int32_t nb_x, nb_y, nb_z;  // byte offsets of the entry planes of an axis in a wide node
   int kx, ky, kz;
   float Sx, Sy, Sz;
 };
 
 // Slab offsets for the one-FMA slab distance fma(plane, inv, -off): off approximates o * inv,
 // moved by 2^-21 |o * inv| (at least three ulps after rounding) so that the entry distance of
-// each axis comes out no larger and the exit distance no smaller than (plane - o) * inv would
-// give: the box test stays conservative, and the padding is a few ulps of the coordinates
-// along that axis alone.
-__device__ __forceinline__ void slab_offsets(float o, float inv, float* off_lo, float* off_hi) {
+// each axis comes out no larger (the entry plane's offset, oi + e) and the exit distance no
+// smaller (the exit plane's, oi - e) than (plane - o) * inv would give: the box test stays
+// conservative, and the padding is a few ulps of the coordinates along that axis alone. The entry
+// plane of an axis is its lo plane where inv >= 0 and its hi plane otherwise.
+__device__ __forceinline__ void slab_offsets(float o, float inv, float* off_n, float* off_f) {
   const float oi = o * inv;
   const float e = fabsf(oi) * 0x1p-21f;
-  // the lo plane is the entry when inv >= 0, the hi plane otherwise
-  *off_lo = inv >= 0.0f ? oi + e : oi - e;
-  *off_hi = inv >= 0.0f ? oi - e : oi + e;
+  *off_n = oi + e;
+  *off_f = oi - e;
 }
 
 __device__ __forceinline__ float comp(f3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
@@ -548,9 +549,13 @@ __device__ __forceinline__ Ray make_ray(f3 o, f3 d) {
   r.inv = mk(copysignf(fminf(fabsf(__builtin_amdgcn_rcpf(d.x)), 0x1p64f), d.x),
              copysignf(fminf(fabsf(__builtin_amdgcn_rcpf(d.y)), 0x1p64f), d.y),
              copysignf(fminf(fabsf(__builtin_amdgcn_rcpf(d.z)), 0x1p64f), d.z));
-  slab_offsets(o.x, r.inv.x, &r.off_lo.x, &r.off_hi.x);
-  slab_offsets(o.y, r.inv.y, &r.off_lo.y, &r.off_hi.y);
-  slab_offsets(o.z, r.inv.z, &r.off_lo.z, &r.off_hi.z);
+  slab_offsets(o.x, r.inv.x, &r.off_n.x, &r.off_f.x);
+  slab_offsets(o.y, r.inv.y, &r.off_n.y, &r.off_f.y);
+  slab_offsets(o.z, r.inv.z, &r.off_n.z, &r.off_f.z);
+  // a wide node stores lo x, y, z then hi x, y, z, 16 bytes each (four children)
+  r.nb_x = r.inv.x >= 0.0f ? 0 : 48;
+  r.nb_y = r.inv.y >= 0.0f ? 16 : 64;
+  r.nb_z = r.inv.z >= 0.0f ? 32 : 80;
   const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
   r.kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
   r.kx = r.kz == 2 ? 0 : r.kz + 1;
@@ -598,20 +603,26 @@ __device__ __forceinline__ bool tri_hit(const Ray& r, const BvhTri& T, float tmi
   return true;
 }
 
-// Slab test of one child box: true if the ray's interval [0, tmax] meets it, with the entry
-// distance in *tn. Any-hit queries pass CLAMP = false: their tmax stays +inf for the whole query,
-// and min(x, +inf) = x for every x (a NaN operand included, under the IEEE minimum the clamp
-// would use), so dropping the clamp gives the same answer.
+// Slab test of one child box given its entry planes (nx, ny, nz) and exit planes (fx, fy, fz) for
+// this ray: the entry distance if the ray's interval [0, tmax] meets the box, kSlabMiss otherwise.
+// Taking each axis's entry and exit plane by the sign of 1/d gives the same distances as the
+// minimum and maximum of its two plane distances would for every valid box, and a box with
+// lo = +inf and hi = -inf (an empty slot) always has entry +inf and exit -inf, so it is never
+// met. Any-hit queries pass CLAMP = false: their tmax stays +inf for the whole query, and
+// min(x, +inf) = x for every x (a NaN operand included, under the IEEE minimum the clamp would
+// use), so dropping the clamp gives the same answer.
+constexpr float kSlabMiss = __builtin_huge_valf();
 template <bool CLAMP>
-__device__ __forceinline__ bool box_hit(const float* lo, const float* hi, const Ray& r, float tmax, float* tn) {
-  const float tx0 = fmaf(lo[0], r.inv.x, -r.off_lo.x), tx1 = fmaf(hi[0], r.inv.x, -r.off_hi.x);
-  const float ty0 = fmaf(lo[1], r.inv.y, -r.off_lo.y), ty1 = fmaf(hi[1], r.inv.y, -r.off_hi.y);
-  const float tz0 = fmaf(lo[2], r.inv.z, -r.off_lo.z), tz1 = fmaf(hi[2], r.inv.z, -r.off_hi.z);
-  *tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
-  const float fz = CLAMP ? fminf(fmaxf(tz0, tz1), tmax) : fmaxf(tz0, tz1);
-  const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fz);
+__device__ __forceinline__ float slab_entry(float nx, float ny, float nz, float fx, float fy, float fz, const Ray& r,
+                                            float tmax) {
+  const float tnx = fmaf(nx, r.inv.x, -r.off_n.x), tfx = fmaf(fx, r.inv.x, -r.off_f.x);
+  const float tny = fmaf(ny, r.inv.y, -r.off_n.y), tfy = fmaf(fy, r.inv.y, -r.off_f.y);
+  const float tnz = fmaf(nz, r.inv.z, -r.off_n.z), tfz = fmaf(fz, r.inv.z, -r.off_f.z);
+  const float tn = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, 0.0f));
+  const float fzc = CLAMP ? fminf(tfz, tmax) : tfz;
+  const float tf = fminf(fminf(tfx, tfy), fzc);
   // conservative by a few ulps so rays grazing a box face are not lost
-  return *tn <= tf * 1.00000024f;
+  return tn <= tf * 1.00000024f ? tn : kSlabMiss;
 }
 
 struct HitRec {
@@ -852,24 +863,23 @@ __device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float
       break;
     }
     if (COUNT) counts->nodes++;
-    // one 4-wide node: the four child boxes by axis, then the child references
-    const float4* q = reinterpret_cast<const float4*>(B.nodes + (uint32_t)s.ref);
-    const float4 lx = q[0], ly = q[1], lz = q[2], hx = q[3], hy = q[4], hz = q[5];
-    const int4 cr = reinterpret_cast<const int4*>(q)[6];
-    constexpr float kMiss = __builtin_huge_valf();
-    float k0, k1, k2, k3;  // entry distance of a hit child, kMiss otherwise
+    // one 4-wide node: the entry and exit planes of the four children for this ray's direction
+    // signs (per-lane byte offsets into the node), then the child references
+    const char* nb = reinterpret_cast<const char*>(B.nodes + (uint32_t)s.ref);
+    const float4 nx = *reinterpret_cast<const float4*>(nb + r.nb_x);
+    const float4 fx = *reinterpret_cast<const float4*>(nb + (48 - r.nb_x));
+    const float4 ny = *reinterpret_cast<const float4*>(nb + r.nb_y);
+    const float4 fy = *reinterpret_cast<const float4*>(nb + (80 - r.nb_y));
+    const float4 nz = *reinterpret_cast<const float4*>(nb + r.nb_z);
+    const float4 fz = *reinterpret_cast<const float4*>(nb + (112 - r.nb_z));
+    const int4 cr = *reinterpret_cast<const int4*>(nb + 96);
+    constexpr float kMiss = kSlabMiss;
+    // entry distance of a hit child, kMiss otherwise
+    float k0 = slab_entry<!ANY>(nx.x, ny.x, nz.x, fx.x, fy.x, fz.x, r, h.t);
+    float k1 = slab_entry<!ANY>(nx.y, ny.y, nz.y, fx.y, fy.y, fz.y, r, h.t);
+    float k2 = slab_entry<!ANY>(nx.z, ny.z, nz.z, fx.z, fy.z, fz.z, r, h.t);
+    float k3 = slab_entry<!ANY>(nx.w, ny.w, nz.w, fx.w, fy.w, fz.w, r, h.t);
     int32_t r0 = cr.x, r1 = cr.y, r2 = cr.z, r3 = cr.w;
-    {
-      float t;
-      const float a0[3] = {lx.x, ly.x, lz.x}, b0[3] = {hx.x, hy.x, hz.x};
-      k0 = box_hit<!ANY>(a0, b0, r, h.t, &t) && r0 != kEmptyRef ? t : kMiss;
-      const float a1[3] = {lx.y, ly.y, lz.y}, b1[3] = {hx.y, hy.y, hz.y};
-      k1 = box_hit<!ANY>(a1, b1, r, h.t, &t) && r1 != kEmptyRef ? t : kMiss;
-      const float a2[3] = {lx.z, ly.z, lz.z}, b2[3] = {hx.z, hy.z, hz.z};
-      k2 = box_hit<!ANY>(a2, b2, r, h.t, &t) && r2 != kEmptyRef ? t : kMiss;
-      const float a3[3] = {lx.w, ly.w, lz.w}, b3[3] = {hx.w, hy.w, hz.w};
-      k3 = box_hit<!ANY>(a3, b3, r, h.t, &t) && r3 != kEmptyRef ? t : kMiss;
-    }
     if (ANY && kAnyOrder == 0) {  // slot order: descend into the first hit child, defer the others
       int32_t nxt = kEmptyRef;
       if (k3 != kMiss) nxt = r3;

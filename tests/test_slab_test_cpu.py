@@ -59,20 +59,40 @@ def _exact_hit(o, d, lo, hi):
     return en <= ex
 
 
+def _ray(o, d):
+    inv = _rn(1.0 / d.astype(np.float64))
+    inv = _rn(np.copysign(np.minimum(np.abs(inv), 2.0 ** 64), d))
+    oi = _rn(o.astype(np.float64) * inv)
+    e = _rn(np.abs(oi).astype(np.float64) * 2.0 ** -21).astype(np.float64)
+    pos = inv >= 0
+    off_lo = np.where(pos, _rn(oi + e), _rn(oi - e))
+    off_hi = np.where(pos, _rn(oi - e), _rn(oi + e))
+    return inv, off_lo, off_hi
+
+
+def _interval(tn3, tf3):
+    tn = _fmax(_fmax(tn3[:, 0], tn3[:, 1]), _fmax(tn3[:, 2], np.float32(0)))
+    tf = _fmin(_fmin(tf3[:, 0], tf3[:, 1]), tf3[:, 2])
+    return tn <= _rn(tf.astype(np.float64) * np.float64(np.float32(1.00000024)))
+
+
 def _device_hit(o, d, lo, hi):
+    """The min/max form: both planes of an axis, then the smaller is the entry."""
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
-        inv = _rn(1.0 / d.astype(np.float64))
-        inv = _rn(np.copysign(np.minimum(np.abs(inv), 2.0 ** 64), d))
-        oi = _rn(o.astype(np.float64) * inv)
-        e = _rn(np.abs(oi).astype(np.float64) * 2.0 ** -21).astype(np.float64)
-        pos = inv >= 0
-        off_lo = np.where(pos, _rn(oi + e), _rn(oi - e))
-        off_hi = np.where(pos, _rn(oi - e), _rn(oi + e))
+        inv, off_lo, off_hi = _ray(o, d)
         t0, t1 = _fma32(lo, inv, -off_lo), _fma32(hi, inv, -off_hi)
-        mn, mx = _fmin(t0, t1), _fmax(t0, t1)
-        tn = _fmax(_fmax(mn[:, 0], mn[:, 1]), _fmax(mn[:, 2], np.float32(0)))
-        tf = _fmin(_fmin(mx[:, 0], mx[:, 1]), mx[:, 2])
-        return tn <= _rn(tf.astype(np.float64) * np.float64(np.float32(1.00000024)))
+        return _interval(_fmin(t0, t1), _fmax(t0, t1))
+
+
+def _device_hit_signed(o, d, lo, hi):
+    """The form the traversal runs: the entry plane of an axis is lo where 1/d >= 0 and hi
+    otherwise (chosen per ray), each plane with its own padded offset; no min or max per axis."""
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        inv, off_lo, off_hi = _ray(o, d)
+        pos = inv >= 0
+        near, far = np.where(pos, lo, hi), np.where(pos, hi, lo)
+        on, of = np.where(pos, off_lo, off_hi), np.where(pos, off_hi, off_lo)
+        return _interval(_fma32(near, inv, -on), _fma32(far, inv, -of))
 
 
 def test_padded_fma_slab_test_is_conservative():
@@ -82,3 +102,14 @@ def test_padded_fma_slab_test_is_conservative():
     assert not (ex & ~dev).any()
     # and it stays a test: the boxes it accepts beyond the exact ones are few
     assert (dev & ~ex).sum() < 0.03 * ex.sum()
+
+
+def test_entry_plane_by_ray_sign_equals_min_max():
+    """Picking each axis's entry and exit plane by the sign of 1/d gives the same decisions as the
+    min/max form on every valid box (the padded offsets already follow the sign), and rejects the
+    empty slots of a wide node (lo = +inf, hi = -inf) for every ray, which min/max would accept."""
+    o, d, lo, hi = _cases(300_000, 12)
+    assert np.array_equal(_device_hit_signed(o, d, lo, hi), _device_hit(o, d, lo, hi))
+    inf = np.full(lo.shape, np.inf, np.float32)
+    assert not _device_hit_signed(o, d, inf, -inf).any()
+    assert _device_hit(o, d, inf, -inf).all()
