@@ -418,11 +418,12 @@ def test_ragged_views_direct(small):
         _compare_view(small, cams[v], p, b, v, 5 + v)
 
 
-@pytest.mark.parametrize("name", ["sphere", "tori"])
+@pytest.mark.parametrize("name", ["sphere", "tori", "tori32"])
 def test_full_size_sampled_pixels(name):
-    """The benchmark workload (8 views of 1024^2 in one call), 1024 seeded pixels of two views
-    checked against the oracle one by one."""
-    sc = I.config(name)
+    """The benchmark workloads (8 views of 1024^2 in one call), 1024 seeded pixels of two views
+    checked against the oracle one by one. tori32: the first 8 of the 32-view workload's views (one
+    of its 8-view launches), with its 4096^2 maps and views alternating +-20 degrees of elevation."""
+    sc = I.config(name, views=8) if name == "tori32" else I.config(name)
     log(f"[full] {name}: building device scene")
     dev = Dev(sc)
     p = dev.params()
