@@ -865,14 +865,17 @@ __device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float
     if (COUNT) counts->nodes++;
     // one 4-wide node: the entry and exit planes of the four children for this ray's direction
     // signs (per-lane byte offsets into the node), then the child references
-    const char* nb = reinterpret_cast<const char*>(B.nodes + (uint32_t)s.ref);
-    const float4 nx = *reinterpret_cast<const float4*>(nb + r.nb_x);
-    const float4 fx = *reinterpret_cast<const float4*>(nb + (48 - r.nb_x));
-    const float4 ny = *reinterpret_cast<const float4*>(nb + r.nb_y);
-    const float4 fy = *reinterpret_cast<const float4*>(nb + (80 - r.nb_y));
-    const float4 nz = *reinterpret_cast<const float4*>(nb + r.nb_z);
-    const float4 fz = *reinterpret_cast<const float4*>(nb + (112 - r.nb_z));
-    const int4 cr = *reinterpret_cast<const int4*>(nb + 96);
+    // 32-bit byte offsets from the node array (a wide tree of at most 2^25 triangles stays under
+    // 2^31 bytes), so that each load is a scalar base plus one vector offset
+    const char* nb = reinterpret_cast<const char*>(B.nodes);
+    const uint32_t at = (uint32_t)s.ref * (uint32_t)sizeof(BvhNode4);
+    const float4 nx = *reinterpret_cast<const float4*>(nb + (at + (uint32_t)r.nb_x));
+    const float4 fx = *reinterpret_cast<const float4*>(nb + (at + (uint32_t)(48 - r.nb_x)));
+    const float4 ny = *reinterpret_cast<const float4*>(nb + (at + (uint32_t)r.nb_y));
+    const float4 fy = *reinterpret_cast<const float4*>(nb + (at + (uint32_t)(80 - r.nb_y)));
+    const float4 nz = *reinterpret_cast<const float4*>(nb + (at + (uint32_t)r.nb_z));
+    const float4 fz = *reinterpret_cast<const float4*>(nb + (at + (uint32_t)(112 - r.nb_z)));
+    const int4 cr = *reinterpret_cast<const int4*>(nb + (at + 96u));
     constexpr float kMiss = kSlabMiss;
     // entry distance of a hit child, kMiss otherwise
     float k0 = slab_entry<!ANY>(nx.x, ny.x, nz.x, fx.x, fy.x, fz.x, r, h.t);
@@ -910,9 +913,22 @@ __device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float
         s.ref = trav_pop(s, st);
       } else {  // descend into the nearest, defer the others (farthest first when sorted)
         s.ref = r0;
-        if (k3 != kMiss) trav_push(s, st, r3);
-        if (k2 != kMiss) trav_push(s, st, r2);
-        if (k1 != kMiss) trav_push(s, st, r1);
+        const bool c1 = k1 != kMiss, c2 = k2 != kMiss, c3 = k3 != kMiss;
+        if (s.sp + 3 <= kStackLds) {
+          // room for three in LDS: the deferred ones packed in the order r3, r2, r1 (r1 on top),
+          // all three slots written and the depth advanced by their number (what lies above the
+          // new top is never read)
+          const int32_t e0 = c3 ? r3 : (c2 ? r2 : r1);
+          const int32_t e1 = c3 ? (c2 ? r2 : r1) : r1;
+          st.lds[s.sp * st.stride] = e0;
+          st.lds[(s.sp + 1) * st.stride] = e1;
+          st.lds[(s.sp + 2) * st.stride] = r1;
+          s.sp += (int32_t)c1 + (int32_t)c2 + (int32_t)c3;
+        } else {
+          if (c3) trav_push(s, st, r3);
+          if (c2) trav_push(s, st, r2);
+          if (c1) trav_push(s, st, r1);
+        }
       }
     }
     if (is_leaf(s.ref) && s.leaf == kEmptyRef) {  // postpone the leaf, keep descending
