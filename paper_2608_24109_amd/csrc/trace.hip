@@ -316,6 +316,42 @@ __device__ __forceinline__ void nmap_adjoint(const Surf& S, f3 gn, float gq[3]) 
 
 constexpr int kCacheS = 4;  // secondary light samples per secondary point kept between the adjoint's two passes
 
+// index of the n-th set bit (from 0) of m, which has more than n set bits
+__device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t n) {
+  uint32_t pos = 0, cnt = 0;
+#pragma unroll
+  for (uint32_t step = 32; step > 0; step >>= 1) {
+    const uint32_t c = (uint32_t)__popcll((m >> pos) & ((1ull << step) - 1ull));
+    if (cnt + c <= n) {
+      cnt += c;
+      pos += step;
+    }
+  }
+  return pos;
+}
+
+// Per-wave staging of the indirect adjoint: the pixels' values the secondary points need, the
+// (pixel, secondary ray) pairs of each ray index j (a ballot mask and the index of its first pair),
+// and each pair's contribution to its pixel's x-side gradient (d/d f_d(x), d/d n_s(x)).
+constexpr int kBwdPixWords = 20;
+enum BwdPixField {
+  kBf = 0, kBb1, kBb2, kBpix, kBvid, kBfdx, kBns = kBfdx + 3, kBG = kBns + 3, kBslot = kBG + 3, kBtslot, kBbits,
+  kBvm = kBbits + 2
+};
+static_assert(kBvm + 2 == kBwdPixWords, "staged words");
+struct BwdStage {
+  uint32_t px[kBwdPixWords * 64];
+  float pair[6 * 64];
+  uint64_t bal[64];
+  uint32_t base[65];
+};
+
+// One wave per 64 consecutive pixels. The work of a valid secondary hit (its secondary ray, the
+// query at y, the light samples, the env-map records and the map record of y) runs one lane per
+// (pixel, j) pair, the wave's pairs taken 64 at a time, so that lanes are not left idle by pixels
+// with fewer valid hits; each chunk's contributions to the x side are added by the pixel's lane in
+// order of j, and x's map record is written last. Records go to fixed places in the pixel's
+// reserved ranges (those of a pair whose gradient vanishes are marked unused).
 __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, EnvView E, ShadeViews V,
                                                         const int32_t* __restrict__ tri_id,
                                                         const float* __restrict__ bary, KParams p, float lambda_ind,
@@ -325,14 +361,17 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
                                                         float* __restrict__ dtex, EnvGradWs eg, TexGradWs tg,
                                                         bool tiled, bool use_lds) {
   extern __shared__ __align__(16) char smem[];
+  __shared__ BwdStage stage_all[kThreads / 64];
+  BwdStage& st = stage_all[threadIdx.x >> 6];
   const EnvTabs tb = load_env_tabs(E, smem, use_lds);
   const int64_t HW = (int64_t)V.H * V.W;
   const int64_t gid = p0 + (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  // every lane stays until the wave has reserved its env-gradient records; f_d = 0 at every
-  // point under EXM_SPECULAR_ONLY (no indirect light)
+  const uint32_t lane = __lane_id();
+  // every lane stays to the end (the wave shares its pairs); f_d = 0 at every point under
+  // EXM_SPECULAR_ONLY (no indirect light)
   bool act = gid < p0 + P && gid < HW * V.n && p.N_b > 0 && !(p.flags & EXM_SPECULAR_ONLY);
   int32_t f = -1;
-  uint64_t bits = 0;
+  uint64_t bits = 0, vm = 0;
   float G[3] = {0.f, 0.f, 0.f};
   if (act) {
     f = tri_id[gid];
@@ -343,113 +382,204 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
     act = f >= 0 && (G[0] != 0.0f || G[1] != 0.0f || G[2] != 0.0f);
   }
   const bool y_mat = !(p.flags & EXM_NO_SECONDARY_MATERIAL);
-  // map-gradient records: one for x, one for each secondary hit whose maps are queried
-  uint32_t n_tex = 0;
-  if (act && tiled) {
-    n_tex = 1;
-    if (y_mat)
-      for (int j = 0; j < p.N_b; ++j) n_tex += rec[gid * p.N_b + j].tri >= 0 ? 1u : 0u;
-  }
+  if (act)
+    for (int j = 0; j < p.N_b; ++j)
+      if (rec[gid * p.N_b + j].tri >= 0) vm |= 1ull << j;
+  // map-gradient records: one for each secondary hit whose maps are queried, then one for x
+  const uint32_t n_tex = (act && tiled) ? 1u + (y_mat ? (uint32_t)__popcll(vm) : 0u) : 0u;
   const uint32_t n_rec = act ? (uint32_t)__popcll(bits) : 0u;
-  uint32_t slot = env_grad_reserve(eg.counter, n_rec);
-  uint32_t tslot = tiled ? tex_grad_reserve_n(tg.counter, n_tex) : 0u;
-  if (!act) return;
-  const uint32_t slot_end = slot + n_rec, tslot_end = tslot + n_tex;
-  const int32_t view = (int32_t)(gid / HW);
-  const uint32_t pix = (uint32_t)(gid - view * HW);
-  const float2 b = reinterpret_cast<const float2*>(bary)[gid];
-  const Surf S = query(M, T, f, b.x, b.y, p.flags);
-  const uint32_t vid = (uint32_t)V.view_id[view];
+  const uint32_t slot = env_grad_reserve(eg.counter, n_rec);
+  const uint32_t tslot = tiled ? tex_grad_reserve_n(tg.counter, n_tex) : 0u;
+  if (__ballot(act) == 0ull) return;  // the whole wave
   const float invNb = 1.0f / (float)p.N_b;
   const float invNs = p.N_s > 0 ? 1.0f / (float)p.N_s : 0.0f;
-  const float kdx = (1.0f - S.m) * kInvPi;
-  float gfx[3] = {0.f, 0.f, 0.f};  // d/d f_d(x)
-  f3 gnx = mk(0, 0, 0);             // d/d n_s(x)
-  for (int j = 0; j < p.N_b; ++j) {
-    const exm_sec_rec r = rec[gid * p.N_b + j];
-    if (r.tri < 0) continue;
-    const Draw d = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)j, 1u);
-    const SecRay sr = secondary_ray(M, f, b.x, b.y, d.u2, d.u3);
-    const f3 w = sr.df;
-    const float pb = sr.pb;
-    const float cxr = dot(S.ns, w);
-    const float cx = fmaxf(cxr, 0.0f);
-    const Surf Y = query(M, T, r.tri, r.b1, r.b2, p.flags, y_mat);
-    const float kdy = (1.0f - Y.m) * kInvPi;
-    const float fdy[3] = {kdy * Y.a[0], kdy * Y.a[1], kdy * Y.a[2]};
-    const float fdx[3] = {kdx * S.a[0], kdx * S.a[1], kdx * S.a[2]};
-    // L_sec(y) without the f_d(y) factor, per channel: (1/N_s) sum E c / pdf. The first kCacheS
-    // samples are kept for the second pass below, which would otherwise draw them again.
-    float Es[3] = {0.f, 0.f, 0.f};
-    EnvSample cache[kCacheS];
-#pragma unroll
-    for (int s = 0; s < kCacheS; ++s) {
-      if (s >= p.N_s || !((bits >> (j * p.N_s + s)) & 1ull)) continue;
-      const Draw ds = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s, 2u + (uint32_t)j);
-      cache[s] = env_sample(E, tb, ds);
-      const float c = dot(Y.ns, cache[s].dir);
-      const float* e = cache[s].E;
-      const float wgt = c * cache[s].inv_pdf * invNs;
-      Es[0] += e[0] * wgt;
-      Es[1] += e[1] * wgt;
-      Es[2] += e[2] * wgt;
+  {
+    float fdx[3] = {0.f, 0.f, 0.f};
+    f3 ns = mk(0, 0, 0);
+    float2 b = make_float2(0.f, 0.f);
+    uint32_t pix = 0, vid = 0;
+    if (act) {
+      const int32_t view = (int32_t)(gid / HW);
+      pix = (uint32_t)(gid - view * HW);
+      vid = (uint32_t)V.view_id[view];
+      b = reinterpret_cast<const float2*>(bary)[gid];
+      const Surf S = query(M, T, f, b.x, b.y, p.flags);
+      const float kdx = (1.0f - S.m) * kInvPi;
+      fdx[0] = kdx * S.a[0];
+      fdx[1] = kdx * S.a[1];
+      fdx[2] = kdx * S.a[2];
+      ns = S.ns;
     }
-    for (int s = kCacheS; s < p.N_s; ++s) {
-      if (!((bits >> (j * p.N_s + s)) & 1ull)) continue;
-      const Draw ds = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s, 2u + (uint32_t)j);
-      const EnvSample es = env_sample(E, tb, ds);
-      const float c = dot(Y.ns, es.dir);
-      const float* e = es.E;
-      const float wgt = c * es.inv_pdf * invNs;
-      Es[0] += e[0] * wgt;
-      Es[1] += e[1] * wgt;
-      Es[2] += e[2] * wgt;
-    }
-    const float fac = invNb * cx / pb;  // weight of f_d(x) L_sec(y) in L_ind
-    float H[3];                          // dLoss/dL_sec(y)
-    for (int c = 0; c < 3; ++c) {
-      const float Lsec = fdy[c] * Es[c];
-      gfx[c] += G[c] * Lsec * fac;
-      H[c] = G[c] * fdx[c] * fac;
-    }
-    if (cxr > 0.0f) {
-      const float sc = invNb / pb * (G[0] * fdx[0] * fdy[0] * Es[0] + G[1] * fdx[1] * fdy[1] * Es[1] +
-                                     G[2] * fdx[2] * fdy[2] * Es[2]);
-      gnx = gnx + sc * w;
-    }
-    if (H[0] == 0.0f && H[1] == 0.0f && H[2] == 0.0f) continue;  // its reserved records stay unused
-    // secondary point: env texels, f_d(y) and n_s(y)
-    float gfy[3] = {H[0] * Es[0], H[1] * Es[1], H[2] * Es[2]};
-    f3 gny = mk(0, 0, 0);
-    for (int s = 0; s < p.N_s; ++s) {
-      if (!((bits >> (j * p.N_s + s)) & 1ull)) continue;
-      EnvSample es;
-      if (s < kCacheS) {
-#pragma unroll
-        for (int q = 0; q < kCacheS; ++q)
-          if (q == s) es = cache[q];
-      } else {
-        const Draw ds = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s, 2u + (uint32_t)j);
-        es = env_sample(E, tb, ds);
-      }
-      const float c = dot(Y.ns, es.dir);
-      const float* e = es.E;
-      const float ip = es.inv_pdf * invNs;
-      env_grad_put(eg, slot++, (uint32_t)es.texel, H[0] * fdy[0] * c * ip, H[1] * fdy[1] * c * ip,
-                   H[2] * fdy[2] * c * ip);
-      const float sn = (H[0] * fdy[0] * e[0] + H[1] * fdy[1] * e[1] + H[2] * fdy[2] * e[2]) * ip;
-      gny = gny + sn * es.dir;
-    }
-    float gay[3], gmy = 0.0f, gqy[3];
-    for (int c = 0; c < 3; ++c) {
-      gay[c] = gfy[c] * kdy;
-      gmy -= gfy[c] * Y.a[c] * kInvPi;
-    }
-    if (p.flags & EXM_METALLIC_OFF) gmy = 0.0f;
-    if (!y_mat) continue;  // nothing at y depends on the maps
-    nmap_adjoint(Y, gny, gqy);
-    scatter7(Y, gay, gmy, gqy, dtex, tg, tiled, tslot++);
+    float* fp = reinterpret_cast<float*>(st.px);
+    st.px[kBf * 64 + lane] = (uint32_t)f;
+    fp[kBb1 * 64 + lane] = b.x;
+    fp[kBb2 * 64 + lane] = b.y;
+    st.px[kBpix * 64 + lane] = pix;
+    st.px[kBvid * 64 + lane] = vid;
+    fp[kBfdx * 64 + lane] = fdx[0];
+    fp[(kBfdx + 1) * 64 + lane] = fdx[1];
+    fp[(kBfdx + 2) * 64 + lane] = fdx[2];
+    fp[kBns * 64 + lane] = ns.x;
+    fp[(kBns + 1) * 64 + lane] = ns.y;
+    fp[(kBns + 2) * 64 + lane] = ns.z;
+    fp[kBG * 64 + lane] = G[0];
+    fp[(kBG + 1) * 64 + lane] = G[1];
+    fp[(kBG + 2) * 64 + lane] = G[2];
+    st.px[kBslot * 64 + lane] = slot;
+    st.px[kBtslot * 64 + lane] = tslot;
+    st.px[kBbits * 64 + lane] = (uint32_t)bits;
+    st.px[(kBbits + 1) * 64 + lane] = (uint32_t)(bits >> 32);
+    st.px[kBvm * 64 + lane] = (uint32_t)vm;
+    st.px[(kBvm + 1) * 64 + lane] = (uint32_t)(vm >> 32);
   }
+  uint32_t total = 0;  // wave-uniform
+  for (int j = 0; j < p.N_b; ++j) {
+    const uint64_t bj = __ballot((vm >> j) & 1ull);
+    if (lane == 0) {
+      st.bal[j] = bj;
+      st.base[j] = total;
+    }
+    total += (uint32_t)__popcll(bj);
+  }
+  __builtin_amdgcn_wave_barrier();
+  float gfx[3] = {0.f, 0.f, 0.f};  // d/d f_d(x) of the lane's pixel
+  f3 gnx = mk(0, 0, 0);             // d/d n_s(x)
+  for (uint32_t c0 = 0; c0 < total; c0 += 64) {
+    const uint32_t q = c0 + lane;
+    float pg[3] = {0.f, 0.f, 0.f}, pn[3] = {0.f, 0.f, 0.f};
+    if (q < total) {
+      int j = 0;
+      for (int jj = 1; jj < p.N_b; ++jj)
+        if (st.base[jj] <= q) j = jj;
+      const uint32_t pl = nth_set_bit(st.bal[j], q - st.base[j]);
+      const float* fp = reinterpret_cast<const float*>(st.px);
+      const int32_t pf = (int32_t)st.px[kBf * 64 + pl];
+      const float b1 = fp[kBb1 * 64 + pl], b2 = fp[kBb2 * 64 + pl];
+      const uint32_t ppix = st.px[kBpix * 64 + pl], pvid = st.px[kBvid * 64 + pl];
+      const float fdx[3] = {fp[kBfdx * 64 + pl], fp[(kBfdx + 1) * 64 + pl], fp[(kBfdx + 2) * 64 + pl]};
+      const f3 xns = mk(fp[kBns * 64 + pl], fp[(kBns + 1) * 64 + pl], fp[(kBns + 2) * 64 + pl]);
+      const float Gp[3] = {fp[kBG * 64 + pl], fp[(kBG + 1) * 64 + pl], fp[(kBG + 2) * 64 + pl]};
+      const uint64_t pbits = (uint64_t)st.px[kBbits * 64 + pl] | ((uint64_t)st.px[(kBbits + 1) * 64 + pl] << 32);
+      const uint64_t pvm = (uint64_t)st.px[kBvm * 64 + pl] | ((uint64_t)st.px[(kBvm + 1) * 64 + pl] << 32);
+      // this pair's records: its light samples' env records and (with maps at y) y's map record
+      uint32_t eslot = st.px[kBslot * 64 + pl] + (uint32_t)__popcll(pbits & ((1ull << (j * p.N_s)) - 1ull));
+      const uint32_t yslot = st.px[kBtslot * 64 + pl] + (uint32_t)__popcll(pvm & ((1ull << j) - 1ull));
+      const int64_t pgid = gid - (int64_t)lane + (int64_t)pl;
+      const exm_sec_rec r = rec[pgid * p.N_b + j];
+      const Draw d = philox_draw(p.key.k0, p.key.k1, ppix, pvid, (uint32_t)j, 1u);
+      const SecRay sr = secondary_ray(M, pf, b1, b2, d.u2, d.u3);
+      const f3 w = sr.df;
+      const float pb = sr.pb;
+      const float cxr = dot(xns, w);
+      const float cx = fmaxf(cxr, 0.0f);
+      const Surf Y = query(M, T, r.tri, r.b1, r.b2, p.flags, y_mat);
+      const float kdy = (1.0f - Y.m) * kInvPi;
+      const float fdy[3] = {kdy * Y.a[0], kdy * Y.a[1], kdy * Y.a[2]};
+      // L_sec(y) without the f_d(y) factor, per channel: (1/N_s) sum E c / pdf. The first kCacheS
+      // samples are kept for the second pass below, which would otherwise draw them again.
+      float Es[3] = {0.f, 0.f, 0.f};
+      EnvSample cache[kCacheS];
+#pragma unroll
+      for (int s2 = 0; s2 < kCacheS; ++s2) {
+        if (s2 >= p.N_s || !((pbits >> (j * p.N_s + s2)) & 1ull)) continue;
+        const Draw ds = philox_draw(p.key.k0, p.key.k1, ppix, pvid, (uint32_t)s2, 2u + (uint32_t)j);
+        cache[s2] = env_sample(E, tb, ds);
+        const float c = dot(Y.ns, cache[s2].dir);
+        const float* e = cache[s2].E;
+        const float wgt = c * cache[s2].inv_pdf * invNs;
+        Es[0] += e[0] * wgt;
+        Es[1] += e[1] * wgt;
+        Es[2] += e[2] * wgt;
+      }
+      for (int s2 = kCacheS; s2 < p.N_s; ++s2) {
+        if (!((pbits >> (j * p.N_s + s2)) & 1ull)) continue;
+        const Draw ds = philox_draw(p.key.k0, p.key.k1, ppix, pvid, (uint32_t)s2, 2u + (uint32_t)j);
+        const EnvSample es = env_sample(E, tb, ds);
+        const float c = dot(Y.ns, es.dir);
+        const float* e = es.E;
+        const float wgt = c * es.inv_pdf * invNs;
+        Es[0] += e[0] * wgt;
+        Es[1] += e[1] * wgt;
+        Es[2] += e[2] * wgt;
+      }
+      const float fac = invNb * cx / pb;  // weight of f_d(x) L_sec(y) in L_ind
+      float H[3];                          // dLoss/dL_sec(y)
+      for (int c = 0; c < 3; ++c) {
+        const float Lsec = fdy[c] * Es[c];
+        pg[c] = Gp[c] * Lsec * fac;
+        H[c] = Gp[c] * fdx[c] * fac;
+      }
+      if (cxr > 0.0f) {
+        const float sc = invNb / pb * (Gp[0] * fdx[0] * fdy[0] * Es[0] + Gp[1] * fdx[1] * fdy[1] * Es[1] +
+                                       Gp[2] * fdx[2] * fdy[2] * Es[2]);
+        pn[0] = sc * w.x;
+        pn[1] = sc * w.y;
+        pn[2] = sc * w.z;
+      }
+      if (H[0] == 0.0f && H[1] == 0.0f && H[2] == 0.0f) {  // nothing reaches y: its records stay unused
+        for (int s2 = 0; s2 < p.N_s; ++s2)
+          if ((pbits >> (j * p.N_s + s2)) & 1ull) env_grad_put(eg, eslot++, kNoTexel, 0.f, 0.f, 0.f);
+        if (tiled && y_mat) tex_grad_skip(tg, yslot);
+      } else {
+        // secondary point: env texels, f_d(y) and n_s(y)
+        float gfy[3] = {H[0] * Es[0], H[1] * Es[1], H[2] * Es[2]};
+        f3 gny = mk(0, 0, 0);
+        for (int s2 = 0; s2 < p.N_s; ++s2) {
+          if (!((pbits >> (j * p.N_s + s2)) & 1ull)) continue;
+          EnvSample es;
+          if (s2 < kCacheS) {
+#pragma unroll
+            for (int qq = 0; qq < kCacheS; ++qq)
+              if (qq == s2) es = cache[qq];
+          } else {
+            const Draw ds = philox_draw(p.key.k0, p.key.k1, ppix, pvid, (uint32_t)s2, 2u + (uint32_t)j);
+            es = env_sample(E, tb, ds);
+          }
+          const float c = dot(Y.ns, es.dir);
+          const float* e = es.E;
+          const float ip = es.inv_pdf * invNs;
+          env_grad_put(eg, eslot++, (uint32_t)es.texel, H[0] * fdy[0] * c * ip, H[1] * fdy[1] * c * ip,
+                       H[2] * fdy[2] * c * ip);
+          const float sn = (H[0] * fdy[0] * e[0] + H[1] * fdy[1] * e[1] + H[2] * fdy[2] * e[2]) * ip;
+          gny = gny + sn * es.dir;
+        }
+        if (y_mat) {  // nothing at y depends on the maps otherwise
+          float gay[3], gmy = 0.0f, gqy[3];
+          for (int c = 0; c < 3; ++c) {
+            gay[c] = gfy[c] * kdy;
+            gmy -= gfy[c] * Y.a[c] * kInvPi;
+          }
+          if (p.flags & EXM_METALLIC_OFF) gmy = 0.0f;
+          nmap_adjoint(Y, gny, gqy);
+          scatter7(Y, gay, gmy, gqy, dtex, tg, tiled, yslot);
+        }
+      }
+    }
+    st.pair[0 * 64 + lane] = pg[0];
+    st.pair[1 * 64 + lane] = pg[1];
+    st.pair[2 * 64 + lane] = pg[2];
+    st.pair[3 * 64 + lane] = pn[0];
+    st.pair[4 * 64 + lane] = pn[1];
+    st.pair[5 * 64 + lane] = pn[2];
+    __builtin_amdgcn_wave_barrier();
+    // the pixel's pairs in this chunk, in order of j
+    if (act) {
+      for (int j = 0; j < p.N_b; ++j) {
+        if (!((vm >> j) & 1ull)) continue;
+        const uint32_t qj = st.base[j] + (uint32_t)__popcll(st.bal[j] & ((1ull << lane) - 1ull));
+        if (qj < c0 || qj >= c0 + 64u) continue;
+        const uint32_t i = qj - c0;
+        for (int c = 0; c < 3; ++c) gfx[c] += st.pair[c * 64 + i];
+        gnx = gnx + mk(st.pair[3 * 64 + i], st.pair[4 * 64 + i], st.pair[5 * 64 + i]);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (!act) return;
+  // x: queried again (cheaper than keeping its surface live through the pairs)
+  const float2 b = reinterpret_cast<const float2*>(bary)[gid];
+  const Surf S = query(M, T, f, b.x, b.y, p.flags);
+  const float kdx = (1.0f - S.m) * kInvPi;
   float gax[3], gmx = 0.0f, gqx[3];
   for (int c = 0; c < 3; ++c) {
     gax[c] = gfx[c] * kdx;
@@ -457,10 +587,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_bwd(MeshView M, TexView T, E
   }
   if (p.flags & EXM_METALLIC_OFF) gmx = 0.0f;
   nmap_adjoint(S, gnx, gqx);
-  scatter7(S, gax, gmx, gqx, dtex, tg, tiled, tslot++);
-  while (slot < slot_end) env_grad_put(eg, slot++, kNoTexel, 0.f, 0.f, 0.f);
-  if (tiled)
-    while (tslot < tslot_end) tex_grad_skip(tg, tslot++);
+  scatter7(S, gax, gmx, gqx, dtex, tg, tiled, tslot + n_tex - 1u);
 }
 
 KParams kparams(const exm_params* p) {
