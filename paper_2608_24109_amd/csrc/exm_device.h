@@ -883,6 +883,10 @@ __device__ __forceinline__ bool trav_round(const BvhView& B, const Ray& r, float
     float k2 = slab_entry<!ANY>(nx.z, ny.z, nz.z, fx.z, fy.z, fz.z, r, h.t);
     float k3 = slab_entry<!ANY>(nx.w, ny.w, nz.w, fx.w, fy.w, fz.w, r, h.t);
     int32_t r0 = cr.x, r1 = cr.y, r2 = cr.z, r3 = cr.w;
+    // the child references are needed only when a child is hit, and the compiler would load them
+    // after the test (a second round trip per visit); taking them here keeps the load beside the
+    // six plane loads
+    asm volatile("" ::"v"(r0), "v"(r1), "v"(r2), "v"(r3));
     if (ANY && kAnyOrder == 0) {  // slot order: descend into the first hit child, defer the others
       int32_t nxt = kEmptyRef;
       if (k3 != kMiss) nxt = r3;
