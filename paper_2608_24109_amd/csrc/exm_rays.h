@@ -108,7 +108,8 @@ inline int64_t direct_chunk(size_t ws_bytes, int32_t N_d, int64_t max_px) {
 
 // Indirect pass over a chunk of P pixels (P a multiple of 64): secondary rays (N_b per pixel)
 // with their closest hits, then the light samples of valid hits (N_b * N_s per pixel) with
-// their shadow rays, contributions and hits.
+// their shadow rays, contributions and hits, and for each (pixel, light sample) the slot of its
+// shadow ray in its region (sh_slot[pixel * N_b * N_s + j * N_s + s], set where sh_mask has the bit).
 struct IndirectWs {
   uint32_t* counter;
   uint32_t* sec_count;
@@ -119,12 +120,14 @@ struct IndirectWs {
   RayRec* sh_rays;
   float* sh_contrib;
   uint8_t* sh_hit;
+  uint32_t* sh_slot;
 };
 
 inline size_t indirect_ws_bytes(int64_t P, int32_t N_b, int32_t N_s) {
   const int64_t s1 = P * (int64_t)(N_b > 0 ? N_b : 1), s2 = s1 * (N_s > 0 ? N_s : 1);
   return 256 + 2 * align256((size_t)(P / 64) * 4) + align256((size_t)s1 * 32) + align256((size_t)s1 * 16) +
-         align256((size_t)P * 8) + align256((size_t)s2 * 32) + align256((size_t)s2 * 12) + align256((size_t)s2);
+         align256((size_t)P * 8) + align256((size_t)s2 * 32) + align256((size_t)s2 * 12) + align256((size_t)s2) +
+         align256((size_t)s2 * 4);
 }
 
 inline IndirectWs indirect_ws(void* ws, int64_t P, int32_t N_b, int32_t N_s) {
@@ -148,6 +151,8 @@ inline IndirectWs indirect_ws(void* ws, int64_t P, int32_t N_b, int32_t N_s) {
   w.sh_contrib = reinterpret_cast<float*>(q);
   q += align256((size_t)s2 * 12);
   w.sh_hit = reinterpret_cast<uint8_t*>(q);
+  q += align256((size_t)s2);
+  w.sh_slot = reinterpret_cast<uint32_t*>(q);
   return w;
 }
 

@@ -12,7 +12,8 @@
 // contribution f_d(x) f_d(y) E c / pdf * (n_s(x).w / p_b) / (N_b N_s)) -> any-hit trace ->
 // finalize (sum of the unoccluded contributions in (j, s) order). A covered pixel's N_b secondary
 // rays sit together (the covered pixels of a wave ranked by a ballot), so a traversal wave takes
-// rays of few origins at a time; the light samples' slots come from wave ballots.
+// rays of few origins at a time; gen2 runs one lane per (pixel, secondary ray) pair and then one
+// per valid pair, and keeps each light sample's shadow-ray slot (from wave ballots) for finalize.
 // The hit records and the light-sample visibility bits are stored for the adjoint.
 //
 // Adjoint, for upstream G = lambda_ind dLoss/dI: gradients to a, m, n_s at x (through f_d(x)
@@ -155,130 +156,233 @@ __global__ __launch_bounds__(kThreads) void k_ind_gen1(MeshView M, ShadeViews V,
   if (__lane_id() == 0) ws.sec_count[region] = n_cov * (uint32_t)p.N_b;
 }
 
+// Per-wave staging of the light-sample stage: the covered pixels' values that their secondary
+// points need (indexed by the pixel's rank among the wave's covered pixels), a queue of the valid
+// (pixel, j) pairs in pair order, and each covered pixel's light-sample mask.
+constexpr int kIndPixWords = 12;
+enum IndPixField { kIf = 0, kIb1, kIb2, kIpix, kIvid, kIlane, kIfa, kIns = kIfa + 3 };
+static_assert(kIns + 3 == kIndPixWords, "staged words");
+constexpr int kIndQ = 128;  // queue capacity: fewer than 64 waiting pairs plus one chunk of 64
+constexpr int kIndQWords = 5;
+enum IndQField { kQq = 0, kQhit, kQb1, kQb2, kQw };
+struct IndStage {
+  uint32_t px[kIndPixWords * 64];
+  uint32_t qe[kIndQWords * kIndQ];
+  uint64_t mask[64];
+};
+
+// The queued valid pairs [0, n) of a wave (n <= 64), one lane each: the query at y and the N_s
+// light samples. A sample whose shadow ray is needed gets the region's next slot (in order of
+// sample index, then queue position); the slot is kept per (pixel, sample) for the finalize
+// kernel and the sample's bit is set in the pixel's mask.
+__device__ __forceinline__ void ind_light_samples(const MeshView& M, const TexView& T, const EnvView& E,
+                                                  const EnvTabs& tb, const KParams& p, IndStage& st, uint32_t n,
+                                                  int64_t wave_local0, int64_t rbase2, uint32_t& running,
+                                                  const IndirectWs& ws) {
+  const uint32_t lane = __lane_id();
+  const bool act = lane < n;
+  const bool diff = !(p.flags & EXM_SPECULAR_ONLY);
+  const int n_slots = p.N_b * p.N_s;
+  uint32_t below = 0, j = 0, pix = 0, vid = 0, plane = 0;
+  int32_t hid = -1;
+  float fac[3] = {0.f, 0.f, 0.f};
+  Surf Y;
+  uint64_t bits = 0;
+  if (act) {
+    const float* qf = reinterpret_cast<const float*>(st.qe);
+    const uint32_t q = st.qe[kQq * kIndQ + lane];
+    hid = (int32_t)st.qe[kQhit * kIndQ + lane];
+    const float b1 = qf[kQb1 * kIndQ + lane], b2 = qf[kQb2 * kIndQ + lane], w = qf[kQw * kIndQ + lane];
+    below = q / (uint32_t)p.N_b;
+    j = q - below * (uint32_t)p.N_b;
+    pix = st.px[kIpix * 64 + below];
+    vid = st.px[kIvid * 64 + below];
+    plane = st.px[kIlane * 64 + below];
+    const float* pf = reinterpret_cast<const float*>(st.px);
+    Y = query(M, T, hid, b1, b2, p.flags, !(p.flags & EXM_NO_SECONDARY_MATERIAL));
+    const float kdy = diff ? (1.0f - Y.m) * kInvPi : 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fac[c] = pf[(kIfa + c) * 64 + below] * (kdy * Y.a[c]) * w;
+  }
+  for (int s2 = 0; s2 < p.N_s; ++s2) {
+    bool need = false;
+    EnvSample es;
+    float c = 0.0f;
+    if (act) {
+      es = env_sample(E, tb, philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s2, 2u + j));
+      c = dot(Y.ns, es.dir);
+      need = c > 0.0f;
+    }
+    const uint64_t bal = __ballot(need);
+    if (need) {
+      const uint32_t rel = running + lanes_below(bal);
+      const int64_t slot = rbase2 + rel;
+      RayRec R;
+      R.o[0] = Y.x.x;
+      R.o[1] = Y.x.y;
+      R.o[2] = Y.x.z;
+      R.skip = hid;
+      R.d[0] = es.dir.x;
+      R.d[1] = es.dir.y;
+      R.d[2] = es.dir.z;
+      R.tmin = p.tmin;
+      ws.sh_rays[slot] = R;
+      const float* e = es.E;
+      const float wgt = c * es.inv_pdf;
+      ws.sh_contrib[3 * slot] = fac[0] * e[0] * wgt;
+      ws.sh_contrib[3 * slot + 1] = fac[1] * e[1] * wgt;
+      ws.sh_contrib[3 * slot + 2] = fac[2] * e[2] * wgt;
+      const uint32_t t = j * (uint32_t)p.N_s + (uint32_t)s2;
+      ws.sh_slot[(wave_local0 + plane) * n_slots + t] = rel;
+      bits |= 1ull << t;
+    }
+    running += (uint32_t)__popcll(bal);
+  }
+  if (bits) atomicOr(&st.mask[below], bits);
+}
+
+// One wave per 64 consecutive pixels. The covered pixels' secondary rays lie together in pixel
+// order (k_ind_gen1), so pair q of the wave is ray q % N_b of its (q / N_b)-th covered pixel. One
+// lane per pair tests the hit (validity, FP64 refinement, the record for the adjoint), 64 pairs at a
+// time; the valid pairs wait in LDS and their light samples run 64 pairs at a time as well, so
+// lanes are idle neither for uncovered pixels nor for missed or back-facing secondary rays.
 __global__ __launch_bounds__(kThreads) void k_ind_gen2(MeshView M, TexView T, EnvView E, ShadeViews V,
                                                        const int32_t* __restrict__ tri_id,
                                                        const float* __restrict__ bary, KParams p, int64_t p0,
                                                        int64_t P, IndirectWs ws, exm_sec_rec* __restrict__ rec,
                                                        bool use_lds) {
   extern __shared__ __align__(16) char smem[];
+  __shared__ IndStage stage_all[kThreads / 64];
+  IndStage& st = stage_all[threadIdx.x >> 6];
   const EnvTabs tb = load_env_tabs(E, smem, use_lds);
   const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if ((local & ~(int64_t)63) >= P) return;
+  const uint32_t lane = __lane_id();
   const int64_t HW = (int64_t)V.H * V.W;
   const int64_t gid = p0 + local;
+  const int64_t gid0 = gid - (int64_t)lane, wave_local0 = local - (int64_t)lane;
   const bool in_range = gid < HW * V.n;
   const int32_t f = in_range ? tri_id[gid] : -1;
   const int64_t region = local >> 6;
   const int64_t rbase1 = region * 64 * (int64_t)p.N_b;
   const int64_t rbase2 = rbase1 * (int64_t)p.N_s;
   const uint64_t bal1 = __ballot(f >= 0);
-  const uint32_t below1 = lanes_below(bal1);
+  const uint32_t below1 = lanes_below(bal1), n_cov = (uint32_t)__popcll(bal1);
   const bool diff = !(p.flags & EXM_SPECULAR_ONLY);
   const float invNbNs = (p.N_b > 0 && p.N_s > 0) ? 1.0f / ((float)p.N_b * (float)p.N_s) : 0.0f;
-  Surf S;
-  float2 b = make_float2(0.f, 0.f);
-  uint32_t pix = 0, vid = 0;
-  float kdx = 0.0f;
+  st.mask[lane] = 0ull;
   if (f >= 0) {
     const int32_t view = (int32_t)(gid / HW);
-    pix = (uint32_t)(gid - view * HW);
-    vid = (uint32_t)V.view_id[view];
-    b = reinterpret_cast<const float2*>(bary)[gid];
-    S = query(M, T, f, b.x, b.y, p.flags);
-    kdx = diff ? (1.0f - S.m) * kInvPi : 0.0f;
+    const uint32_t pix = (uint32_t)(gid - view * HW);
+    const float2 b = reinterpret_cast<const float2*>(bary)[gid];
+    const Surf S = query(M, T, f, b.x, b.y, p.flags);
+    const float kdx = diff ? (1.0f - S.m) * kInvPi : 0.0f;
+    float* pf = reinterpret_cast<float*>(st.px);
+    st.px[kIf * 64 + below1] = (uint32_t)f;
+    pf[kIb1 * 64 + below1] = b.x;
+    pf[kIb2 * 64 + below1] = b.y;
+    st.px[kIpix * 64 + below1] = pix;
+    st.px[kIvid * 64 + below1] = (uint32_t)V.view_id[view];
+    st.px[kIlane * 64 + below1] = lane;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pf[(kIfa + c) * 64 + below1] = kdx * S.a[c];
+    pf[kIns * 64 + below1] = S.ns.x;
+    pf[(kIns + 1) * 64 + below1] = S.ns.y;
+    pf[(kIns + 2) * 64 + below1] = S.ns.z;
+  } else if (in_range) {
+    for (int j = 0; j < p.N_b; ++j) rec[gid * p.N_b + j] = exm_sec_rec{-1, 0.f, 0.f};
   }
-  uint64_t mask = 0;
-  uint32_t running = 0;
-  for (int j = 0; j < p.N_b; ++j) {
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t total = n_cov * (uint32_t)max(p.N_b, 0);  // wave-uniform
+  uint32_t qn = 0, running = 0;                             // wave-uniform
+  for (uint32_t c0 = 0; c0 < total; c0 += 64) {
+    const uint32_t q = c0 + lane;
     bool valid = false;
-    Surf Y;
     int32_t hid = -1;
-    float fac[3] = {0.f, 0.f, 0.f};
-    exm_sec_rec r{-1, 0.f, 0.f};
-    if (f >= 0) {
-      HitRec h = ws.sec_hits[rbase1 + (int64_t)below1 * p.N_b + j];
-      const Draw d = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)j, 1u);
-      const SecRay sr = secondary_ray(M, f, b.x, b.y, d.u2, d.u3);
+    float hb1 = 0.0f, hb2 = 0.0f, w = 0.0f;
+    if (q < total) {
+      const uint32_t below = q / (uint32_t)p.N_b, j = q - below * (uint32_t)p.N_b;
+      const float* pf = reinterpret_cast<const float*>(st.px);
+      const int32_t pf_tri = (int32_t)st.px[kIf * 64 + below];
+      const float b1 = pf[kIb1 * 64 + below], b2 = pf[kIb2 * 64 + below];
+      const uint32_t pix = st.px[kIpix * 64 + below], vid = st.px[kIvid * 64 + below];
+      const uint32_t plane = st.px[kIlane * 64 + below];
+      const f3 ns = mk(pf[kIns * 64 + below], pf[(kIns + 1) * 64 + below], pf[(kIns + 2) * 64 + below]);
+      HitRec h = ws.sec_hits[rbase1 + q];
+      const Draw d = philox_draw(p.key.k0, p.key.k1, pix, vid, j, 1u);
+      const SecRay sr = secondary_ray(M, pf_tri, b1, b2, d.u2, d.u3);
+      exm_sec_rec r{-1, 0.f, 0.f};
       if (h.id >= 0 && front_facing(M, h.id, sr.df)) {
         refine_hit(M, h.id, sr, &h.b1, &h.b2);
         r = exm_sec_rec{h.id, h.b1, h.b2};
+        const float cx = fmaxf(dot(ns, sr.df), 0.0f);
+        w = cx / sr.pb * invNbNs;
         hid = h.id;
-        Y = query(M, T, h.id, h.b1, h.b2, p.flags, !(p.flags & EXM_NO_SECONDARY_MATERIAL));
-        const float kdy = diff ? (1.0f - Y.m) * kInvPi : 0.0f;
-        const float cx = fmaxf(dot(S.ns, sr.df), 0.0f);
-        const float w = cx / sr.pb * invNbNs;
-        fac[0] = kdx * S.a[0] * (kdy * Y.a[0]) * w;
-        fac[1] = kdx * S.a[1] * (kdy * Y.a[1]) * w;
-        fac[2] = kdx * S.a[2] * (kdy * Y.a[2]) * w;
+        hb1 = h.b1;
+        hb2 = h.b2;
         valid = true;
       }
+      rec[(gid0 + (int64_t)plane) * p.N_b + j] = r;
     }
-    if (in_range) rec[gid * p.N_b + j] = r;
-    for (int s2 = 0; s2 < p.N_s; ++s2) {
-      bool need = false;
-      EnvSample es;
-      float c = 0.0f;
-      if (valid) {
-        es = env_sample(E, tb, philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)s2, 2u + (uint32_t)j));
-        c = dot(Y.ns, es.dir);
-        need = c > 0.0f;
+    const uint64_t vb = __ballot(valid);
+    if (valid) {
+      const uint32_t at = qn + lanes_below(vb);
+      float* qf = reinterpret_cast<float*>(st.qe);
+      st.qe[kQq * kIndQ + at] = q;
+      st.qe[kQhit * kIndQ + at] = (uint32_t)hid;
+      qf[kQb1 * kIndQ + at] = hb1;
+      qf[kQb2 * kIndQ + at] = hb2;
+      qf[kQw * kIndQ + at] = w;
+    }
+    qn += (uint32_t)__popcll(vb);
+    __builtin_amdgcn_wave_barrier();
+    if (qn >= 64) {
+      ind_light_samples(M, T, E, tb, p, st, 64u, wave_local0, rbase2, running, ws);
+      // the waiting pairs (fewer than 64) move to the front of the queue
+      const bool mv = lane + 64u < qn;
+      uint32_t e[kIndQWords];
+#pragma unroll
+      for (int k = 0; k < kIndQWords; ++k) e[k] = mv ? st.qe[k * kIndQ + 64 + lane] : 0u;
+      __builtin_amdgcn_wave_barrier();
+      if (mv) {
+#pragma unroll
+        for (int k = 0; k < kIndQWords; ++k) st.qe[k * kIndQ + lane] = e[k];
       }
-      const uint64_t bal = __ballot(need);
-      if (need) {
-        const int64_t slot = rbase2 + running + lanes_below(bal);
-        RayRec R;
-        R.o[0] = Y.x.x;
-        R.o[1] = Y.x.y;
-        R.o[2] = Y.x.z;
-        R.skip = hid;
-        R.d[0] = es.dir.x;
-        R.d[1] = es.dir.y;
-        R.d[2] = es.dir.z;
-        R.tmin = p.tmin;
-        ws.sh_rays[slot] = R;
-        const float* e = es.E;
-        const float wgt = c * es.inv_pdf;
-        ws.sh_contrib[3 * slot] = fac[0] * e[0] * wgt;
-        ws.sh_contrib[3 * slot + 1] = fac[1] * e[1] * wgt;
-        ws.sh_contrib[3 * slot + 2] = fac[2] * e[2] * wgt;
-        mask |= 1ull << (j * p.N_s + s2);
-      }
-      running += (uint32_t)__popcll(bal);
+      qn -= 64u;
+      __builtin_amdgcn_wave_barrier();
     }
   }
-  ws.sh_mask[local] = mask;
-  if (__lane_id() == 0) ws.sh_count[region] = running;
+  if (qn > 0) ind_light_samples(M, T, E, tb, p, st, qn, wave_local0, rbase2, running, ws);
+  __builtin_amdgcn_wave_barrier();
+  ws.sh_mask[local] = f >= 0 ? st.mask[below1] : 0ull;
+  if (lane == 0) ws.sh_count[region] = running;
 }
 
+// Per pixel: the unoccluded light samples' contributions summed in (j, s) order, their bits kept
+// for the adjoint.
 __global__ __launch_bounds__(kThreads) void k_ind_finalize(ShadeViews V, KParams p, int64_t p0, int64_t P,
                                                            IndirectWs ws, float* __restrict__ L_ind,
                                                            uint64_t* __restrict__ sec_vis) {
   const int64_t local = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if ((local & ~(int64_t)63) >= P) return;
+  if (local >= P) return;
   const int64_t gid = p0 + local;
-  const bool valid = gid < (int64_t)V.H * V.W * V.n;
+  if (gid >= (int64_t)V.H * V.W * V.n) return;
   const uint64_t mask = ws.sh_mask[local];
   const bool novis = (p.flags & EXM_NO_VIS) != 0;
   const int64_t rbase = (local >> 6) * 64 * (int64_t)p.N_b * p.N_s;
-  const int n_slots = p.N_b * p.N_s;
-  uint32_t running = 0;
+  const int64_t n_slots = (int64_t)p.N_b * p.N_s;
   float L[3] = {0.f, 0.f, 0.f};
   uint64_t bits = 0;
-  for (int t = 0; t < n_slots; ++t) {
-    const bool have = (mask >> t) & 1ull;
-    const uint64_t bal = __ballot(have);
-    if (have) {
-      const int64_t slot = rbase + running + lanes_below(bal);
-      if (novis || ws.sh_hit[slot] == 0) {
-        bits |= 1ull << t;
-        L[0] += ws.sh_contrib[3 * slot];
-        L[1] += ws.sh_contrib[3 * slot + 1];
-        L[2] += ws.sh_contrib[3 * slot + 2];
-      }
+  for (uint64_t m = mask; m != 0ull; m &= m - 1ull) {
+    const int t = __ffsll((long long)m) - 1;
+    const int64_t slot = rbase + ws.sh_slot[local * n_slots + t];
+    if (novis || ws.sh_hit[slot] == 0) {
+      bits |= 1ull << t;
+      L[0] += ws.sh_contrib[3 * slot];
+      L[1] += ws.sh_contrib[3 * slot + 1];
+      L[2] += ws.sh_contrib[3 * slot + 2];
     }
-    running += (uint32_t)__popcll(bal);
   }
-  if (!valid) return;
   L_ind[3 * gid] = L[0];
   L_ind[3 * gid + 1] = L[1];
   L_ind[3 * gid + 2] = L[2];
