@@ -118,10 +118,27 @@ __device__ __forceinline__ bool front_facing(const MeshView& M, int32_t f, f3 w)
   return dot(w, cross(P1 - P0, P2 - P0)) < 0.0f;
 }
 
+// index of the n-th set bit (from 0) of m, which has more than n set bits
+__device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t n) {
+  uint32_t pos = 0, cnt = 0;
+#pragma unroll
+  for (uint32_t step = 32; step > 0; step >>= 1) {
+    const uint32_t c = (uint32_t)__popcll((m >> pos) & ((1ull << step) - 1ull));
+    if (cnt + c <= n) {
+      cnt += c;
+      pos += step;
+    }
+  }
+  return pos;
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return (uint32_t)__popcll(mask & ((1ull << __lane_id()) - 1ull));
 }
 
+// One wave per 64 consecutive pixels, one lane per (covered pixel, secondary ray) pair: pair q is
+// ray q % N_b of the wave's (q / N_b)-th covered pixel, and its ray goes to slot q of the region,
+// so a pixel's rays lie together.
 __global__ __launch_bounds__(kThreads) void k_ind_gen1(MeshView M, ShadeViews V, const int32_t* __restrict__ tri_id,
                                                        const float* __restrict__ bary, KParams p, int64_t p0,
                                                        int64_t P, IndirectWs ws) {
@@ -129,31 +146,34 @@ __global__ __launch_bounds__(kThreads) void k_ind_gen1(MeshView M, ShadeViews V,
   if ((local & ~(int64_t)63) >= P) return;  // whole waves only
   const int64_t HW = (int64_t)V.H * V.W;
   const int64_t gid = p0 + local;
+  const int64_t gid0 = gid - (int64_t)__lane_id();
   const int32_t f = gid < HW * V.n ? tri_id[gid] : -1;
   const int64_t region = local >> 6;
   const int64_t rbase = region * 64 * (int64_t)p.N_b;
   const uint64_t bal = __ballot(f >= 0);
-  const uint32_t below = lanes_below(bal), n_cov = (uint32_t)__popcll(bal);
-  if (f >= 0) {
-    const int32_t view = (int32_t)(gid / HW);
-    const uint32_t pix = (uint32_t)(gid - view * HW), vid = (uint32_t)V.view_id[view];
-    const float2 b = reinterpret_cast<const float2*>(bary)[gid];
-    for (int j = 0; j < p.N_b; ++j) {
-      const Draw d = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)j, 1u);
-      const SecRay sr = secondary_ray(M, f, b.x, b.y, d.u2, d.u3);
-      RayRec R;
-      R.o[0] = sr.of.x;
-      R.o[1] = sr.of.y;
-      R.o[2] = sr.of.z;
-      R.skip = f;
-      R.d[0] = sr.df.x;
-      R.d[1] = sr.df.y;
-      R.d[2] = sr.df.z;
-      R.tmin = p.tmin;
-      ws.sec_rays[rbase + (int64_t)below * p.N_b + j] = R;  // a pixel's rays together
-    }
+  const uint32_t n_cov = (uint32_t)__popcll(bal);
+  const uint32_t total = n_cov * (uint32_t)max(p.N_b, 0);
+  for (uint32_t q = __lane_id(); q < total; q += 64) {
+    const uint32_t below = q / (uint32_t)p.N_b, j = q - below * (uint32_t)p.N_b;
+    const int64_t pg = gid0 + (int64_t)nth_set_bit(bal, below);
+    const int32_t pf = tri_id[pg];
+    const int32_t view = (int32_t)(pg / HW);
+    const uint32_t pix = (uint32_t)(pg - view * HW), vid = (uint32_t)V.view_id[view];
+    const float2 b = reinterpret_cast<const float2*>(bary)[pg];
+    const Draw d = philox_draw(p.key.k0, p.key.k1, pix, vid, j, 1u);
+    const SecRay sr = secondary_ray(M, pf, b.x, b.y, d.u2, d.u3);
+    RayRec R;
+    R.o[0] = sr.of.x;
+    R.o[1] = sr.of.y;
+    R.o[2] = sr.of.z;
+    R.skip = pf;
+    R.d[0] = sr.df.x;
+    R.d[1] = sr.df.y;
+    R.d[2] = sr.df.z;
+    R.tmin = p.tmin;
+    ws.sec_rays[rbase + q] = R;
   }
-  if (__lane_id() == 0) ws.sec_count[region] = n_cov * (uint32_t)p.N_b;
+  if (__lane_id() == 0) ws.sec_count[region] = total;
 }
 
 // Per-wave staging of the light-sample stage: the covered pixels' values that their secondary
@@ -420,19 +440,6 @@ __device__ __forceinline__ void nmap_adjoint(const Surf& S, f3 gn, float gq[3]) 
 
 constexpr int kCacheS = 4;  // secondary light samples per secondary point kept between the adjoint's two passes
 
-// index of the n-th set bit (from 0) of m, which has more than n set bits
-__device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t n) {
-  uint32_t pos = 0, cnt = 0;
-#pragma unroll
-  for (uint32_t step = 32; step > 0; step >>= 1) {
-    const uint32_t c = (uint32_t)__popcll((m >> pos) & ((1ull << step) - 1ull));
-    if (cnt + c <= n) {
-      cnt += c;
-      pos += step;
-    }
-  }
-  return pos;
-}
 
 // Per-wave staging of the indirect adjoint: the pixels' values the secondary points need, the
 // (pixel, secondary ray) pairs of each ray index j (a ballot mask and the index of its first pair),
