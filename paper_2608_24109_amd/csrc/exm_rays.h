@@ -8,21 +8,29 @@
 
 namespace exm {
 
-// 32-byte ray record: origin, the triangle the ray leaves from (skipped), direction, t_min
+// 16-byte ray record: direction and the index of its origin record. The rays that leave one
+// point (a pixel's shadow or secondary rays, a secondary point's light samples) share that record:
+// the point and the triangle it lies on, which they skip.
 struct alignas(16) RayRec {
+  float d[3];
+  uint32_t org;
+};
+static_assert(sizeof(RayRec) == 16, "ray layout");
+struct alignas(16) RayOrg {
   float o[3];
   int32_t skip;
-  float d[3];
-  float tmin;
 };
-static_assert(sizeof(RayRec) == 32, "ray layout");
+static_assert(sizeof(RayOrg) == 16, "origin layout");
 
-// Region r holds count[r] rays at slots [r * region_stride, r * region_stride + count[r]).
+// Region r holds count[r] rays at slots [r * region_stride, r * region_stride + count[r]); a hit
+// counts at t >= tmin (for batches over several assets, the tmin of the region's asset).
 struct RayBatch {
   const RayRec* rays;
+  const RayOrg* orgs;
   const uint32_t* count;
   int32_t n_regions;
   int64_t region_stride;
+  float tmin;
   uint32_t* region_counter;  // workspace word, reset by the launcher
 };
 
@@ -41,6 +49,7 @@ constexpr int64_t kWideRegion = 2048;
 // belong to asset f, region_start[f] <= r < region_start[f + 1].
 struct BvhTable {
   BvhView b[kMaxFrames];
+  float tmin[kMaxFrames];
   int32_t region_start[kMaxFrames + 1];
   int32_t n;
 };
@@ -59,20 +68,22 @@ hipError_t launch_trace_closest(const exm_bvh* bvh, const RayBatch& rb, HitRec* 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Direct pass over a chunk of P pixels (P a multiple of 64; one region per 64 pixels, N_d slots
-// per pixel): counter, per-region counts, per-pixel sample masks, rays, contributions, hits.
+// per pixel): counter, per-region counts, per-pixel sample masks, rays, the covered pixels' origin
+// records (region * 64 + the pixel's rank among the region's covered pixels), contributions, hits.
 struct DirectWs {
   uint32_t* counter;
   uint32_t* count;
   uint64_t* mask;
   RayRec* rays;
+  RayOrg* orgs;
   float* contrib;
   uint8_t* hit;
 };
 
 inline size_t direct_ws_bytes(int64_t P, int32_t N_d) {
   const int64_t slots = P * (int64_t)(N_d > 0 ? N_d : 1);
-  return 256 + align256((size_t)(P / 64) * 4) + align256((size_t)P * 8) + align256((size_t)slots * 32) +
-         align256((size_t)slots * 12) + align256((size_t)slots);
+  return 256 + align256((size_t)(P / 64) * 4) + align256((size_t)P * 8) + align256((size_t)slots * 16) +
+         align256((size_t)P * 16) + align256((size_t)slots * 12) + align256((size_t)slots);
 }
 
 inline DirectWs direct_ws(void* ws, int64_t P, int32_t N_d) {
@@ -86,7 +97,9 @@ inline DirectWs direct_ws(void* ws, int64_t P, int32_t N_d) {
   w.mask = reinterpret_cast<uint64_t*>(q);
   q += align256((size_t)P * 8);
   w.rays = reinterpret_cast<RayRec*>(q);
-  q += align256((size_t)slots * 32);
+  q += align256((size_t)slots * 16);
+  w.orgs = reinterpret_cast<RayOrg*>(q);
+  q += align256((size_t)P * 16);
   w.contrib = reinterpret_cast<float*>(q);
   q += align256((size_t)slots * 12);
   w.hit = reinterpret_cast<uint8_t*>(q);
@@ -107,17 +120,21 @@ inline int64_t direct_chunk(size_t ws_bytes, int32_t N_d, int64_t max_px) {
 }
 
 // Indirect pass over a chunk of P pixels (P a multiple of 64): secondary rays (N_b per pixel)
-// with their closest hits, then the light samples of valid hits (N_b * N_s per pixel) with
-// their shadow rays, contributions and hits, and for each (pixel, light sample) the slot of its
-// shadow ray in its region (sh_slot[pixel * N_b * N_s + j * N_s + s], set where sh_mask has the bit).
+// with their closest hits and the covered pixels' origin records (as in the direct pass), then the
+// light samples of valid hits (N_b * N_s per pixel) with their shadow rays, the origin records of the
+// valid hits (at the secondary ray's slot), contributions and hits, and for each (pixel, light
+// sample) the slot of its shadow ray in its region (sh_slot[pixel * N_b * N_s + j * N_s + s], set
+// where sh_mask has the bit).
 struct IndirectWs {
   uint32_t* counter;
   uint32_t* sec_count;
   RayRec* sec_rays;
+  RayOrg* sec_orgs;
   HitRec* sec_hits;
   uint32_t* sh_count;
   uint64_t* sh_mask;
   RayRec* sh_rays;
+  RayOrg* sh_orgs;
   float* sh_contrib;
   uint8_t* sh_hit;
   uint32_t* sh_slot;
@@ -125,9 +142,9 @@ struct IndirectWs {
 
 inline size_t indirect_ws_bytes(int64_t P, int32_t N_b, int32_t N_s) {
   const int64_t s1 = P * (int64_t)(N_b > 0 ? N_b : 1), s2 = s1 * (N_s > 0 ? N_s : 1);
-  return 256 + 2 * align256((size_t)(P / 64) * 4) + align256((size_t)s1 * 32) + align256((size_t)s1 * 16) +
-         align256((size_t)P * 8) + align256((size_t)s2 * 32) + align256((size_t)s2 * 12) + align256((size_t)s2) +
-         align256((size_t)s2 * 4);
+  return 256 + 2 * align256((size_t)(P / 64) * 4) + align256((size_t)s1 * 16) + align256((size_t)P * 16) +
+         align256((size_t)s1 * 16) + align256((size_t)P * 8) + align256((size_t)s2 * 16) + align256((size_t)s1 * 16) +
+         align256((size_t)s2 * 12) + align256((size_t)s2) + align256((size_t)s2 * 4);
 }
 
 inline IndirectWs indirect_ws(void* ws, int64_t P, int32_t N_b, int32_t N_s) {
@@ -141,13 +158,17 @@ inline IndirectWs indirect_ws(void* ws, int64_t P, int32_t N_b, int32_t N_s) {
   w.sh_count = reinterpret_cast<uint32_t*>(q);
   q += align256((size_t)(P / 64) * 4);
   w.sec_rays = reinterpret_cast<RayRec*>(q);
-  q += align256((size_t)s1 * 32);
+  q += align256((size_t)s1 * 16);
+  w.sec_orgs = reinterpret_cast<RayOrg*>(q);
+  q += align256((size_t)P * 16);
   w.sec_hits = reinterpret_cast<HitRec*>(q);
   q += align256((size_t)s1 * 16);
   w.sh_mask = reinterpret_cast<uint64_t*>(q);
   q += align256((size_t)P * 8);
   w.sh_rays = reinterpret_cast<RayRec*>(q);
-  q += align256((size_t)s2 * 32);
+  q += align256((size_t)s2 * 16);
+  w.sh_orgs = reinterpret_cast<RayOrg*>(q);
+  q += align256((size_t)s1 * 16);
   w.sh_contrib = reinterpret_cast<float*>(q);
   q += align256((size_t)s2 * 12);
   w.sh_hit = reinterpret_cast<uint8_t*>(q);

@@ -44,6 +44,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6, 6))
   const LaneStack stack{stack_mem + threadIdx.x, (private_i32*)ovf, kThreads};
   BvhView B = B0;        // the BVH of the lane's ray
   BvhView B_region = B0;  // the BVH of the region being handed out (wave-uniform)
+  float tmin_region = rb.tmin;
   // wave-uniform region cursor
   int32_t region = -1;
   uint32_t next = 0, count = 0;
@@ -84,6 +85,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6, 6))
           int32_t f = 0;
           while (f + 1 < bt.n && region >= bt.region_start[f + 1]) ++f;
           B_region = bt.b[f];
+          tmin_region = bt.tmin[f];
         }
         base = (int64_t)region * rb.region_stride;
         continue;
@@ -94,9 +96,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6, 6))
         slot = base + next + rank;
         if (BATCH) B = B_region;
         const RayRec R = rb.rays[slot];
-        ray = make_ray(mk(R.o[0], R.o[1], R.o[2]), mk(R.d[0], R.d[1], R.d[2]));
-        tmin = R.tmin;
-        skip = R.skip;
+        const RayOrg O = rb.orgs[R.org];
+        ray = make_ray(mk(O.o[0], O.o[1], O.o[2]), mk(R.d[0], R.d[1], R.d[2]));
+        tmin = BATCH ? tmin_region : rb.tmin;
+        skip = O.skip;
         trav_begin(B, ts, h, stack);
         have_ray = true;
         if (COUNT) ++n_rays;

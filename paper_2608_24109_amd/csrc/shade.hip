@@ -149,6 +149,12 @@ __device__ __forceinline__ void dir_gen_wave(const MeshView& M, const TexView& T
     rec[kRpix * 64 + c] = pix;
     rec[kRvid * 64 + c] = (uint32_t)V.view_id[view];
     rec[kRlane * 64 + c] = lane;
+    RayOrg O;
+    O.o[0] = S.x.x;
+    O.o[1] = S.x.y;
+    O.o[2] = S.x.z;
+    O.skip = f;
+    ws.orgs[region * 64 + c] = O;
   } else {
     ws.mask[local] = 0ull;
   }
@@ -198,14 +204,10 @@ __device__ __forceinline__ void dir_gen_wave(const MeshView& M, const TexView& T
         if (need[j]) {
           const int64_t slot = rbase + running + lanes_below(bal);
           RayRec R;
-          R.o[0] = q[j].x.x;
-          R.o[1] = q[j].x.y;
-          R.o[2] = q[j].x.z;
-          R.skip = q[j].f;
           R.d[0] = es[j].dir.x;
           R.d[1] = es[j].dir.y;
           R.d[2] = es[j].dir.z;
-          R.tmin = p.tmin;
+          R.org = (uint32_t)(region * 64 + (int64_t)(c0 + (uint32_t)j * G + sub));
           ws.rays[slot] = R;
           float fr[3];
           brdf_eval(q[j], es[j].dir, q[j].wo, cs[j], p, fr);
@@ -641,7 +643,7 @@ hipError_t launch_shade_fwd(const exm_mesh* m, const exm_bvh* bvh, const exm_mat
                                                                 p0, Pc, ws, nullptr, use_lds);
     }
     if (trace) {
-      const RayBatch rb{ws.rays, ws.count, (int32_t)(Pc / 64), 64 * (int64_t)p->N_d, ws.counter};
+      const RayBatch rb{ws.rays, ws.orgs, ws.count, (int32_t)(Pc / 64), 64 * (int64_t)p->N_d, p->tmin, ws.counter};
       const hipError_t e = launch_trace_any(bvh, rb, ws.hit, counters, s);
       if (e != hipSuccess) return e;
     }
@@ -682,6 +684,7 @@ hipError_t launch_shade_fwd_batch(const exm_request* r, int32_t n, const exm_par
     F.L_dir = r[i].L_dir;
     F.vis = r[i].vis;
     F.tmin = r[i].tmin;
+    tt.tmin[i] = r[i].tmin;
     const size_t b = env_tabs_bytes(r[i].env->He, r[i].env->We);
     F.use_lds = b <= kEnvTabsMaxBytes;
     if (F.use_lds) lds = std::max(lds, b);
@@ -701,7 +704,7 @@ hipError_t launch_shade_fwd_batch(const exm_request* r, int32_t n, const exm_par
       k_dir_gen_batch<false><<<nb, kThreads, lds, s>>>(bt, kp, ws, nullptr);
   }
   if (p->N_d > 0 && !(p->flags & EXM_NO_VIS)) {
-    const RayBatch rb{ws.rays, ws.count, (int32_t)(P / 64), 64 * (int64_t)p->N_d, ws.counter};
+    const RayBatch rb{ws.rays, ws.orgs, ws.count, (int32_t)(P / 64), 64 * (int64_t)p->N_d, p->tmin, ws.counter};
     const hipError_t e = launch_trace_any_batch(tt, rb, ws.hit, counters, s);
     if (e != hipSuccess) return e;
   }

@@ -162,15 +162,20 @@ __global__ __launch_bounds__(kThreads) void k_ind_gen1(MeshView M, ShadeViews V,
     const float2 b = reinterpret_cast<const float2*>(bary)[pg];
     const Draw d = philox_draw(p.key.k0, p.key.k1, pix, vid, j, 1u);
     const SecRay sr = secondary_ray(M, pf, b.x, b.y, d.u2, d.u3);
+    const int64_t org = region * 64 + (int64_t)below;
+    if (j == 0) {  // the origin does not depend on the ray: written by the pixel's first pair
+      RayOrg O;
+      O.o[0] = sr.of.x;
+      O.o[1] = sr.of.y;
+      O.o[2] = sr.of.z;
+      O.skip = pf;
+      ws.sec_orgs[org] = O;
+    }
     RayRec R;
-    R.o[0] = sr.of.x;
-    R.o[1] = sr.of.y;
-    R.o[2] = sr.of.z;
-    R.skip = pf;
     R.d[0] = sr.df.x;
     R.d[1] = sr.df.y;
     R.d[2] = sr.df.z;
-    R.tmin = p.tmin;
+    R.org = (uint32_t)org;
     ws.sec_rays[rbase + q] = R;
   }
   if (__lane_id() == 0) ws.sec_count[region] = total;
@@ -197,13 +202,13 @@ struct IndStage {
 // kernel and the sample's bit is set in the pixel's mask.
 __device__ __forceinline__ void ind_light_samples(const MeshView& M, const TexView& T, const EnvView& E,
                                                   const EnvTabs& tb, const KParams& p, IndStage& st, uint32_t n,
-                                                  int64_t wave_local0, int64_t rbase2, uint32_t& running,
+                                                  int64_t wave_local0, int64_t rbase1, int64_t rbase2, uint32_t& running,
                                                   const IndirectWs& ws) {
   const uint32_t lane = __lane_id();
   const bool act = lane < n;
   const bool diff = !(p.flags & EXM_SPECULAR_ONLY);
   const int n_slots = p.N_b * p.N_s;
-  uint32_t below = 0, j = 0, pix = 0, vid = 0, plane = 0;
+  uint32_t below = 0, j = 0, pix = 0, vid = 0, plane = 0, org = 0;
   int32_t hid = -1;
   float fac[3] = {0.f, 0.f, 0.f};
   Surf Y;
@@ -211,6 +216,7 @@ __device__ __forceinline__ void ind_light_samples(const MeshView& M, const TexVi
   if (act) {
     const float* qf = reinterpret_cast<const float*>(st.qe);
     const uint32_t q = st.qe[kQq * kIndQ + lane];
+    org = (uint32_t)(rbase1 + (int64_t)q);  // the pair's secondary-ray slot
     hid = (int32_t)st.qe[kQhit * kIndQ + lane];
     const float b1 = qf[kQb1 * kIndQ + lane], b2 = qf[kQb2 * kIndQ + lane], w = qf[kQw * kIndQ + lane];
     below = q / (uint32_t)p.N_b;
@@ -223,6 +229,12 @@ __device__ __forceinline__ void ind_light_samples(const MeshView& M, const TexVi
     const float kdy = diff ? (1.0f - Y.m) * kInvPi : 0.0f;
 #pragma unroll
     for (int c = 0; c < 3; ++c) fac[c] = pf[(kIfa + c) * 64 + below] * (kdy * Y.a[c]) * w;
+    RayOrg O;
+    O.o[0] = Y.x.x;
+    O.o[1] = Y.x.y;
+    O.o[2] = Y.x.z;
+    O.skip = hid;
+    ws.sh_orgs[org] = O;
   }
   for (int s2 = 0; s2 < p.N_s; ++s2) {
     bool need = false;
@@ -238,14 +250,10 @@ __device__ __forceinline__ void ind_light_samples(const MeshView& M, const TexVi
       const uint32_t rel = running + lanes_below(bal);
       const int64_t slot = rbase2 + rel;
       RayRec R;
-      R.o[0] = Y.x.x;
-      R.o[1] = Y.x.y;
-      R.o[2] = Y.x.z;
-      R.skip = hid;
       R.d[0] = es.dir.x;
       R.d[1] = es.dir.y;
       R.d[2] = es.dir.z;
-      R.tmin = p.tmin;
+      R.org = org;
       ws.sh_rays[slot] = R;
       const float* e = es.E;
       const float wgt = c * es.inv_pdf;
@@ -357,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void k_ind_gen2(MeshView M, TexView T, En
     qn += (uint32_t)__popcll(vb);
     __builtin_amdgcn_wave_barrier();
     if (qn >= 64) {
-      ind_light_samples(M, T, E, tb, p, st, 64u, wave_local0, rbase2, running, ws);
+      ind_light_samples(M, T, E, tb, p, st, 64u, wave_local0, rbase1, rbase2, running, ws);
       // the waiting pairs (fewer than 64) move to the front of the queue
       const bool mv = lane + 64u < qn;
       uint32_t e[kIndQWords];
@@ -372,7 +380,7 @@ __global__ __launch_bounds__(kThreads) void k_ind_gen2(MeshView M, TexView T, En
       __builtin_amdgcn_wave_barrier();
     }
   }
-  if (qn > 0) ind_light_samples(M, T, E, tb, p, st, qn, wave_local0, rbase2, running, ws);
+  if (qn > 0) ind_light_samples(M, T, E, tb, p, st, qn, wave_local0, rbase1, rbase2, running, ws);
   __builtin_amdgcn_wave_barrier();
   ws.sh_mask[local] = f >= 0 ? st.mask[below1] : 0ull;
   if (lane == 0) ws.sh_count[region] = running;
@@ -735,7 +743,8 @@ hipError_t launch_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const ex
         EXM_TIMED("ind_gen1", s);
         k_ind_gen1<<<nb, kThreads, 0, s>>>(mesh_view(m), v, tri_id, bary, kp, p0, Pc, ws);
       }
-      const RayBatch rb1{ws.sec_rays, ws.sec_count, (int32_t)(Pc / 64), 64 * (int64_t)p->N_b, ws.counter};
+      const RayBatch rb1{ws.sec_rays, ws.sec_orgs, ws.sec_count, (int32_t)(Pc / 64), 64 * (int64_t)p->N_b, p->tmin,
+                         ws.counter};
       hipError_t e = launch_trace_closest(bvh, rb1, ws.sec_hits, counters, s);
       if (e != hipSuccess) return e;
     }
@@ -745,7 +754,8 @@ hipError_t launch_trace_indirect(const exm_mesh* m, const exm_bvh* bvh, const ex
                                                          Pc, ws, sec_rec, use_lds);
     }
     if (vis_rays && p->N_b > 0) {
-      const RayBatch rb2{ws.sh_rays, ws.sh_count, (int32_t)(Pc / 64), 64 * (int64_t)p->N_b * p->N_s, ws.counter};
+      const RayBatch rb2{ws.sh_rays,  ws.sh_orgs, ws.sh_count, (int32_t)(Pc / 64), 64 * (int64_t)p->N_b * p->N_s,
+                         p->tmin, ws.counter};
       hipError_t e = launch_trace_any(bvh, rb2, ws.sh_hit, counters ? counters + 3 : nullptr, s);
       if (e != hipSuccess) return e;
     }
