@@ -481,12 +481,13 @@ def kernel_bytes_per_step(kernel: str, st: dict, p) -> float:
     """Algorithmic bytes of one GPU kernel over one step (same per-unit figures as above; the
     ray workspace that links the wavefront kernels is this design's own traffic, not counted)."""
     P, C = st["pixels"], st["covered"]
-    if kernel == "trace_any":  # direct shadow rays, and the secondary ones where the workload has them
-        return (33.0 * (st["shadow_rays"] + st.get("sec_shadow_rays", 0))
+    if kernel == "trace_any":  # direct shadow rays, and the secondary ones where the workload has them:
+        # a 16 B ray record in and 1 B out per ray, a 16 B origin record per covered pixel or secondary point
+        return (17.0 * (st["shadow_rays"] + st.get("sec_shadow_rays", 0)) + 16.0 * (C + st.get("sec_hits", 0))
                 + NODE_BYTES * (st["shadow_nodes"] + st.get("sec_shadow_nodes", 0))
                 + 48.0 * (st["shadow_tris"] + st.get("sec_shadow_tris", 0)))
-    if kernel == "trace_closest":  # ray record in, 16 B hit out
-        return 48.0 * st["sec_rays"] + NODE_BYTES * st["sec_nodes"] + 48.0 * st["sec_tris"]
+    if kernel == "trace_closest":  # 16 B ray record in, 16 B hit out, a 16 B origin per covered pixel
+        return 32.0 * st["sec_rays"] + 16.0 * C + NODE_BYTES * st["sec_nodes"] + 48.0 * st["sec_tris"]
     if kernel == "dir_gen":
         return 12.0 * P + SURF_BYTES * C + SAMPLE_BYTES * st["samples"]
     if kernel == "dir_finalize":

@@ -210,7 +210,7 @@ exm_status exm_shade_fwd_batch(const exm_request* reqs_host, int32_t n_req, cons
  * outputs, bit for bit, computed in a device scratch array of 64 MiB that the library holds on
  * each GPU it runs on until the process ends (looked up on the first call on a device). It
  * allocates nothing: any image size works, the pixels run in chunks of what fits in the
- * scratch (at N_d = 64 about 23,000 pixels per chunk, at N_d = 8 about 180,000). Every call on
+ * scratch (at N_d = 64 about 35,000 pixels per chunk, at N_d = 8 about 260,000). Every call on
  * one GPU shares that GPU's scratch: calls that overlap on one GPU (on different streams or
  * from several threads) race; order them on one stream. */
 exm_status exm_shade_fwd_noalloc(const exm_mesh* m, const exm_bvh* bvh, const exm_material* mat,

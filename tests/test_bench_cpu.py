@@ -26,5 +26,7 @@ def test_work_models():
     # first) or 5 (closest hit: sorted) compare-exchanges of 4; 128 B per node, 48 B per triangle
     assert bench.kernel_lane_ops_per_step("trace_any", st) == (4 * 25 + 3 * 4) * (30000 + 15000) + 44 * (5000 + 2500)
     assert bench.kernel_lane_ops_per_step("trace_closest", st) == (4 * 25 + 5 * 4) * 7000 + 44 * 1200
-    assert bench.kernel_bytes_per_step("trace_any", st, None) == 33 * 1500 + 128 * 45000 + 48 * 7500
+    # 16 B ray record in and 1 B out per ray; one 16 B origin record per covered pixel
+    assert bench.kernel_bytes_per_step("trace_any", st, None) == 17 * 1500 + 16 * 60 + 128 * 45000 + 48 * 7500
+    assert bench.kernel_bytes_per_step("trace_closest", st, None) == 32 * 200 + 16 * 60 + 128 * 7000 + 48 * 1200
     assert abs(bench.VALU_PEAK_T - 39.3216) < 1e-9
