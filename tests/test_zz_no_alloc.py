@@ -36,7 +36,7 @@ def _direct_both_ways(sc, nviews):
 
 
 def test_shade_fwd_noalloc_equals_workspace_call():
-    # 1) the displaced sphere, 2 views of 512^2 at N_d 64: 524,288 pixels in about 23 chunks of the scratch
+    # 1) the displaced sphere, 2 views of 512^2 at N_d 64: 524,288 pixels in about 15 chunks of the scratch
     sc = I.config("sphere", views=2, res=512)
     print("[noalloc] sphere 2 x 512^2, N_d 64", flush=True)
     b, L_na, vis_na = _direct_both_ways(sc, 2)
