@@ -22,6 +22,20 @@ struct alignas(16) RayOrg {
 };
 static_assert(sizeof(RayOrg) == 16, "origin layout");
 
+// The wavefront records (rays, contributions) are written once and read once by a later kernel,
+// after far more data than the caches hold has passed: nontemporal stores keep them from displacing
+// the sampling tables and the BVH that the kernels reuse.
+__device__ __forceinline__ void store_ray(RayRec* rays, int64_t slot, const float d[3], uint32_t org) {
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  const f4v v = {d[0], d[1], d[2], __uint_as_float(org)};
+  __builtin_nontemporal_store(v, reinterpret_cast<f4v*>(rays) + slot);
+}
+__device__ __forceinline__ void store_contrib(float* contrib, int64_t slot, float r, float g, float b) {
+  __builtin_nontemporal_store(r, contrib + 3 * slot);
+  __builtin_nontemporal_store(g, contrib + 3 * slot + 1);
+  __builtin_nontemporal_store(b, contrib + 3 * slot + 2);
+}
+
 // Region r holds count[r] rays at slots [r * region_stride, r * region_stride + count[r]); a hit
 // counts at t >= tmin (for batches over several assets, the tmin of the region's asset).
 struct RayBatch {

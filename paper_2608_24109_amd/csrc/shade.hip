@@ -203,18 +203,12 @@ __device__ __forceinline__ void dir_gen_wave(const MeshView& M, const TexView& T
         const uint64_t bal = __ballot(need[j]);
         if (need[j]) {
           const int64_t slot = rbase + running + lanes_below(bal);
-          RayRec R;
-          R.d[0] = es[j].dir.x;
-          R.d[1] = es[j].dir.y;
-          R.d[2] = es[j].dir.z;
-          R.org = (uint32_t)(region * 64 + (int64_t)(c0 + (uint32_t)j * G + sub));
-          ws.rays[slot] = R;
+          const float d[3] = {es[j].dir.x, es[j].dir.y, es[j].dir.z};
+          store_ray(ws.rays, slot, d, (uint32_t)(region * 64 + (int64_t)(c0 + (uint32_t)j * G + sub)));
           float fr[3];
           brdf_eval(q[j], es[j].dir, q[j].wo, cs[j], p, fr);
           const float wgt = cs[j] * es[j].inv_pdf;
-          ws.contrib[3 * slot] = es[j].E[0] * fr[0] * wgt;
-          ws.contrib[3 * slot + 1] = es[j].E[1] * fr[1] * wgt;
-          ws.contrib[3 * slot + 2] = es[j].E[2] * fr[2] * wgt;
+          store_contrib(ws.contrib, slot, es[j].E[0] * fr[0] * wgt, es[j].E[1] * fr[1] * wgt, es[j].E[2] * fr[2] * wgt);
         }
         // the pixel's sample mask: its group's bits of the ballot, written by the group's first lane
         if (ok[j] && k == 0u) ws.mask[mbase + q[j].lane] = (bal >> (sub * Nd)) & group;

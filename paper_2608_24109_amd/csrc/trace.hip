@@ -171,12 +171,8 @@ __global__ __launch_bounds__(kThreads) void k_ind_gen1(MeshView M, ShadeViews V,
       O.skip = pf;
       ws.sec_orgs[org] = O;
     }
-    RayRec R;
-    R.d[0] = sr.df.x;
-    R.d[1] = sr.df.y;
-    R.d[2] = sr.df.z;
-    R.org = (uint32_t)org;
-    ws.sec_rays[rbase + q] = R;
+    const float d3[3] = {sr.df.x, sr.df.y, sr.df.z};
+    store_ray(ws.sec_rays, rbase + q, d3, (uint32_t)org);
   }
   if (__lane_id() == 0) ws.sec_count[region] = total;
 }
@@ -249,17 +245,11 @@ __device__ __forceinline__ void ind_light_samples(const MeshView& M, const TexVi
     if (need) {
       const uint32_t rel = running + lanes_below(bal);
       const int64_t slot = rbase2 + rel;
-      RayRec R;
-      R.d[0] = es.dir.x;
-      R.d[1] = es.dir.y;
-      R.d[2] = es.dir.z;
-      R.org = org;
-      ws.sh_rays[slot] = R;
+      const float d3[3] = {es.dir.x, es.dir.y, es.dir.z};
+      store_ray(ws.sh_rays, slot, d3, org);
       const float* e = es.E;
       const float wgt = c * es.inv_pdf;
-      ws.sh_contrib[3 * slot] = fac[0] * e[0] * wgt;
-      ws.sh_contrib[3 * slot + 1] = fac[1] * e[1] * wgt;
-      ws.sh_contrib[3 * slot + 2] = fac[2] * e[2] * wgt;
+      store_contrib(ws.sh_contrib, slot, fac[0] * e[0] * wgt, fac[1] * e[1] * wgt, fac[2] * e[2] * wgt);
       const uint32_t t = j * (uint32_t)p.N_s + (uint32_t)s2;
       ws.sh_slot[(wave_local0 + plane) * n_slots + t] = rel;
       bits |= 1ull << t;
