@@ -535,7 +535,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     }
     act = f >= 0 && bits != 0 && (g[0] != 0.0f || g[1] != 0.0f || g[2] != 0.0f);
   }
-  uint32_t slot = env_grad_reserve(eg.counter, act ? (uint32_t)__popcll(bits) : 0u);
+  // the wave's env-gradient records fill one range; they are handed out in pick order, lane order
+  // within a pick, so that each store of the wave writes whole lines
+  const uint32_t slot0 = env_grad_reserve(eg.counter, act ? (uint32_t)__popcll(bits) : 0u);
+  const uint32_t wslot = __shfl(slot0, 0, 64);
   const uint32_t tslot = tiled ? tex_grad_reserve(tg.counter, act || extra) : 0u;
   if (!act && !extra) return;
   if (!act) bits = 0;
@@ -549,6 +552,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   SurfGrad G;
   G.a[0] = G.a[1] = G.a[2] = G.r = G.m = 0.0f;
   G.n = mk(0, 0, 0);
+  uint32_t running = 0;  // records handed out so far (the same in every lane still in the loop)
   while (bits) {  // set bits in increasing order, kBwdPicks at a time
     Draw dr[kBwdPicks];
     bool ok[kBwdPicks];
@@ -565,6 +569,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     env_sample_k<kBwdPicks>(E, tb, dr, ok, es);
 #pragma unroll
     for (int j = 0; j < kBwdPicks; ++j) {
+      const uint64_t have = __ballot(ok[j]);  // the lanes still picking
+      const uint32_t slot = wslot + running + lanes_below(have);
+      running += (uint32_t)__popcll(have);
       if (!ok[j]) break;
       const float c = dot(S.ns, es[j].dir);
       const float s = invN * es[j].inv_pdf;
@@ -572,7 +579,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       float fr[3];
       brdf_adjoint(S, es[j].dir, wo, c, p, W, fr, G);
       const float cs = c * s;
-      env_grad_put(eg, slot++, (uint32_t)es[j].texel, g[0] * fr[0] * cs, g[1] * fr[1] * cs, g[2] * fr[2] * cs);
+      env_grad_put(eg, slot, (uint32_t)es[j].texel, g[0] * fr[0] * cs, g[1] * fr[1] * cs, g[2] * fr[2] * cs);
     }
   }
   float gq[3];
