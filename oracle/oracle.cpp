@@ -656,7 +656,9 @@ void shade_pixel(const Scene& S, const ora_camera* cam, uint32_t pixel, int32_t 
     }
     T cx = max0(dot(A.ns, lift<T>(w)));
     for (int ch = 0; ch < 3; ++ch) {
-      T ls = Lsec[ch] / T((double)p->N_s);
+      // Eq. 18's average over the N_s light samples; with none (N_s = 0) the empty estimator is zero,
+      // as Eq. 17's is above for N_d = 0
+      T ls = p->N_s > 0 ? Lsec[ch] / T((double)p->N_s) : T(0.0);
       Lind[ch] = Lind[ch] + fdx[ch] * ls * cx / T(pb);
     }
   }

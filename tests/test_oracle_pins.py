@@ -546,14 +546,9 @@ def test_convex_mesh_has_no_indirect_light():
     assert np.all(r.sec_tri == -1)
 
 
-@pytest.mark.parametrize("no_sec_mat", [False, True])
-def test_floor_and_wall_interreflection_closed_form(no_sec_mat):
-    """Floor (albedo a_x) meeting a perpendicular wall (albedo a_w), both 1000x the viewed
-    distances, under constant L: a floor point sees the wall over half of its hemisphere (also
-    half of the cosine-weighted measure), so L_dir(floor) = a_x L / 2; a wall point likewise
-    sees half sky, L_sec(wall) = a_w L / 2; hence L_ind(floor) = a_x a_w L / 4 (Eq. 18-19).
-    With the no-secondary-material ablation the wall is shaded as the grey Lambertian
-    (albedo 0.5) whatever its maps hold: L_ind(floor) = a_x 0.5 L / 4."""
+def _floor_and_wall():
+    """Floor (albedo a_x = 0.8) meeting a perpendicular wall (albedo a_w = 0.9), both 1000x the
+    viewed distances, under a constant env of 1; a camera looking down at the floor by the wall."""
     S = 500.0
     floor_p, floor_t = I.quad_mesh(np.array([[-S, 0, S], [S, 0, S], [S, 0, -0.5], [-S, 0, -0.5]]), 1, 1)
     wall_p, wall_t = I.quad_mesh(np.array([[-S, 0, -0.5], [S, 0, -0.5], [S, 2 * S, -0.5], [-S, 2 * S, -0.5]]), 1, 1)
@@ -576,6 +571,17 @@ def test_floor_and_wall_interreflection_closed_form(no_sec_mat):
     eye = np.array([0.0, 1.5, 0.3])  # looking straight down at the floor next to the wall
     cam = I.Camera(mvp=I.perspective(60, 1, 0.01, 50) @ I.look_at(eye, [0, 0, 0.3], [0, 0, -1]),
                    eye=eye, H=40, W=40)
+    return m, cam, t, tex, env, ax, aw, L
+
+
+@pytest.mark.parametrize("no_sec_mat", [False, True])
+def test_floor_and_wall_interreflection_closed_form(no_sec_mat):
+    """A floor point sees the wall over half of its hemisphere (also half of the cosine-weighted
+    measure), so L_dir(floor) = a_x L / 2; a wall point likewise sees half sky, L_sec(wall) =
+    a_w L / 2; hence L_ind(floor) = a_x a_w L / 4 (Eq. 18-19). With the no-secondary-material
+    ablation the wall is shaded as the grey Lambertian (albedo 0.5) whatever its maps hold:
+    L_ind(floor) = a_x 0.5 L / 4."""
+    m, cam, t, tex, env, ax, aw, L = _floor_and_wall()
     flags = O.DIFFUSE_ONLY | (O.NO_SECONDARY_MATERIAL if no_sec_mat else 0)
     r = O.render(m, cam, t, tex, env, N_d=64, N_b=32, N_s=2, tmin=1e-5, flags=flags)
     fl = (r.tri_id >= 0) & (r.tri_id < 2)
@@ -584,6 +590,21 @@ def test_floor_and_wall_interreflection_closed_form(no_sec_mat):
     assert abs(Ld.mean() - ax * L / 2) < 4 * Ld.std() / math.sqrt(Ld.size) + 2e-3
     ay = 0.5 if no_sec_mat else aw
     assert abs(Li.mean() - ax * ay * L / 4) < 4 * Li.std() / math.sqrt(Li.size) + 2e-3
+
+
+def test_no_light_samples_give_no_indirect_light():
+    """With N_s = 0 the light-sample average of Eq. 18 is empty and taken as zero (as Eq. 17's is for
+    N_d = 0): L_ind is exactly zero, no light-sample bit is set, and the secondary hits, which do not
+    depend on N_s, are those of a render with light samples."""
+    m, cam, t, tex, env, _, _, _ = _floor_and_wall()
+    r0 = O.render(m, cam, t, tex, env, N_d=4, N_b=8, N_s=0, tmin=1e-5, flags=O.DIFFUSE_ONLY)
+    r2 = O.render(m, cam, t, tex, env, N_d=4, N_b=8, N_s=2, tmin=1e-5, flags=O.DIFFUSE_ONLY)
+    assert np.all(r0.L_ind == 0.0)
+    assert np.all(r0.sec_vis == 0)
+    assert (r0.sec_tri >= 0).sum() > 1000
+    assert np.array_equal(r0.sec_tri, r2.sec_tri)
+    assert np.array_equal(r0.sec_bary, r2.sec_bary)
+    assert np.array_equal(r0.L_dir, r2.L_dir)
 
 
 # ------------------------------------------------------------------------------------------
