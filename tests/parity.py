@@ -27,6 +27,8 @@ def bits_set(x: np.ndarray) -> np.ndarray:
 
 def flipped_pairs(a: np.ndarray, b: np.ndarray, nbits: int):
     """(row, bit) of every bit where the u64 arrays a and b differ."""
+    if nbits <= 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
     x = (a.astype(np.uint64) ^ b.astype(np.uint64))
     rows, ks = [], []
     for k in range(nbits):

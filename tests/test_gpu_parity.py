@@ -376,6 +376,21 @@ def test_indirect_small_tori_full_frame(small_tori, lib, no_sec_mat):
         _compare_view(small_tori, sc.cams[v], p, b, v, v)
 
 
+@pytest.mark.parametrize("N_b,N_s", [(1, 1), (3, 5), (16, 4), (8, 8), (4, 0)])
+def test_indirect_sample_counts(small_tori, N_b, N_s):
+    """The indirect pass at other sample counts than the default: one secondary ray per pixel, counts
+    that are not powers of two, more pairs than a wave's lanes (N_b 16: up to 1024 pairs per wave, so
+    valid pairs wait in the queue across chunks), the 64 light samples the visibility mask holds, and
+    no light samples at all."""
+    sc = small_tori.sc
+    p = small_tori.params(N_d=4, N_b=N_b, N_s=N_s)
+    log(f"[indirect] small tori view 0, N_b {N_b} N_s {N_s}")
+    _, b = small_tori.forward(sc.cams[:1], p)
+    if N_s == 0:
+        assert float(b.L_ind.abs().max()) == 0.0 and int(b.sec_vis.cpu().numpy().max()) == 0
+    _compare_view(small_tori, sc.cams[0], p, b, 0, 0)
+
+
 def test_direct_smooth_env_both_column_paths():
     """A nearly constant env map: its equator rows have column shifts near 20 (their probes read
     the 32-bit column CDF) and its polar rows small ones (probes decided by the 16-bit residues);
