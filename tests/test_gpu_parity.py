@@ -693,6 +693,16 @@ def test_gradients_indirect_small_tori(small_tori):
     _check_grads(small_tori, small_tori.sc.cams[:1], small_tori.params(), lam=0.7, n_texels=32, n_dirs=3)
 
 
+@pytest.mark.parametrize("N_b,N_s", [(16, 4), (3, 5), (4, 0)])
+def test_gradients_indirect_sample_counts(small_tori, N_b, N_s):
+    """The indirect adjoint at other sample counts: N_b 16 gives up to 1024 (pixel, secondary ray)
+    pairs per wave, taken 64 at a time; 3 x 5 counts that are not powers of two; N_s 0 has no light
+    samples (no env records, and nothing reaches the maps through L_ind)."""
+    log(f"[grad] small tori direct + indirect, N_b {N_b} N_s {N_s}")
+    _check_grads(small_tori, small_tori.sc.cams[:1], small_tori.params(N_d=4, N_b=N_b, N_s=N_s), lam=0.7,
+                 n_texels=8, n_dirs=2, seed=2)
+
+
 def test_gradients_indirect_no_secondary_material(small_tori, lib):
     """The ablation that does not query the maps at secondary hits: the adjoint sends nothing
     to the maps at y, and what it sends to x and to E matches the oracle's derivative."""
