@@ -74,20 +74,18 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
 // The shading point of a covered pixel, staged in LDS between the two phases of dir_gen: kRecWords
 // words per pixel, structure of arrays over the wave's 64 pixels (the lanes reading one pixel's
 // record read the same word: a broadcast).
-constexpr int kRecWords = 18;
-enum RecField { kRx = 0, kRns = 3, kRwo = 6, kRa = 9, kRr = 12, kRm = 13, kRf = 14, kRpix = 15, kRvid = 16, kRlane = 17 };
+constexpr int kRecWords = 14;
+enum RecField { kRns = 0, kRwo = 3, kRa = 6, kRr = 9, kRm = 10, kRpix = 11, kRvid = 12, kRlane = 13 };
 
 struct ShadePt {
-  f3 x, ns, wo;
+  f3 ns, wo;
   float a[3], r, m;
-  int32_t f;
   uint32_t pix, vid, lane;
 };
 
 __device__ __forceinline__ ShadePt load_pt(const uint32_t* rec, uint32_t c) {
   const float* rf = reinterpret_cast<const float*>(rec);
   ShadePt q;
-  q.x = mk(rf[kRx * 64 + c], rf[(kRx + 1) * 64 + c], rf[(kRx + 2) * 64 + c]);
   q.ns = mk(rf[kRns * 64 + c], rf[(kRns + 1) * 64 + c], rf[(kRns + 2) * 64 + c]);
   q.wo = mk(rf[kRwo * 64 + c], rf[(kRwo + 1) * 64 + c], rf[(kRwo + 2) * 64 + c]);
   q.a[0] = rf[kRa * 64 + c];
@@ -95,7 +93,6 @@ __device__ __forceinline__ ShadePt load_pt(const uint32_t* rec, uint32_t c) {
   q.a[2] = rf[(kRa + 2) * 64 + c];
   q.r = rf[kRr * 64 + c];
   q.m = rf[kRm * 64 + c];
-  q.f = (int32_t)rec[kRf * 64 + c];
   q.pix = rec[kRpix * 64 + c];
   q.vid = rec[kRvid * 64 + c];
   q.lane = rec[kRlane * 64 + c];
@@ -131,9 +128,6 @@ __device__ __forceinline__ void dir_gen_wave(const MeshView& M, const TexView& T
     const f3 wo = normalize(mk(V.eye[view][0], V.eye[view][1], V.eye[view][2]) - S.x);
     const uint32_t c = lanes_below(cov);
     float* rf = reinterpret_cast<float*>(rec);
-    rf[kRx * 64 + c] = S.x.x;
-    rf[(kRx + 1) * 64 + c] = S.x.y;
-    rf[(kRx + 2) * 64 + c] = S.x.z;
     rf[kRns * 64 + c] = S.ns.x;
     rf[(kRns + 1) * 64 + c] = S.ns.y;
     rf[(kRns + 2) * 64 + c] = S.ns.z;
@@ -145,7 +139,6 @@ __device__ __forceinline__ void dir_gen_wave(const MeshView& M, const TexView& T
     rf[(kRa + 2) * 64 + c] = S.a[2];
     rf[kRr * 64 + c] = S.r;
     rf[kRm * 64 + c] = S.m;
-    rec[kRf * 64 + c] = (uint32_t)f;
     rec[kRpix * 64 + c] = pix;
     rec[kRvid * 64 + c] = (uint32_t)V.view_id[view];
     rec[kRlane * 64 + c] = lane;
