@@ -463,9 +463,11 @@ struct BwdStage {
 // (pixel, j) pair, the wave's pairs taken 64 at a time, so that lanes are not left idle by pixels
 // with fewer valid hits; each chunk's contributions to the x side are added by the pixel's lane in
 // order of j, and x's map record is written last. Records go to fixed places in the pixel's
-// reserved ranges (those of a pair whose gradient vanishes are marked unused). Held to three waves
-// per SIMD (213 -> 168 VGPRs: 1.63 -> 1.58 ms on the tori).
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_trace_bwd(MeshView M, TexView T, EnvView E, ShadeViews V,
+// reserved ranges (those of a pair whose gradient vanishes are marked unused). Blocks of eight
+// waves share one copy of the env tables in LDS; held to four waves per SIMD (128 VGPRs with some
+// spilled: 1.57 -> 1.49 ms on the tori against three waves of 256-lane blocks at 168 VGPRs).
+constexpr int kTbThreads = 512;
+__global__ __launch_bounds__(kTbThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_trace_bwd(MeshView M, TexView T, EnvView E, ShadeViews V,
                                                         const int32_t* __restrict__ tri_id,
                                                         const float* __restrict__ bary, KParams p, float lambda_ind,
                                                         const float* __restrict__ dI,
@@ -474,11 +476,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3))
                                                         float* __restrict__ dtex, EnvGradWs eg, TexGradWs tg,
                                                         bool tiled, bool use_lds) {
   extern __shared__ __align__(16) char smem[];
-  __shared__ BwdStage stage_all[kThreads / 64];
+  __shared__ BwdStage stage_all[kTbThreads / 64];
   BwdStage& st = stage_all[threadIdx.x >> 6];
   const EnvTabs tb = load_env_tabs(E, smem, use_lds);
   const int64_t HW = (int64_t)V.H * V.W;
-  const int64_t gid = p0 + (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t gid = p0 + (int64_t)blockIdx.x * kTbThreads + threadIdx.x;
   const uint32_t lane = __lane_id();
   // every lane stays to the end (the wave shares its pairs); f_d = 0 at every point under
   // EXM_SPECULAR_ONLY (no indirect light)
@@ -791,7 +793,7 @@ hipError_t launch_trace_bwd(const exm_mesh* m, const exm_material* mat, const ex
     }
     {
       EXM_TIMED("trace_bwd", s);
-      k_trace_bwd<<<(unsigned)((Pc + kThreads - 1) / kThreads), kThreads, use_lds ? lds : 0, s>>>(
+      k_trace_bwd<<<(unsigned)((Pc + kTbThreads - 1) / kTbThreads), kTbThreads, use_lds ? lds : 0, s>>>(
           mesh_view(m), TexView{mat->Ht, mat->Wt, mat->tex}, env_view(env), v, tri_id, bary, kp, lambda_ind, dI,
           sec_rec, sec_vis, p0, Pc, dtex, eg, tg, tiled, use_lds);
     }
