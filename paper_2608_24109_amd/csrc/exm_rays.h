@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "exm_device.h"
 
 namespace exm {
@@ -192,6 +194,8 @@ inline IndirectWs indirect_ws(void* ws, int64_t P, int32_t N_b, int32_t N_s) {
 }
 
 inline int64_t indirect_chunk(size_t ws_bytes, int32_t N_b, int32_t N_s, int64_t max_px) {
+  // a chunk's origin records (one per secondary ray slot) are indexed by 32-bit fields of the rays
+  max_px = std::min<int64_t>(max_px, (((int64_t)1 << 31) - 64) / (N_b > 0 ? N_b : 1));
   int64_t lo = 0, hi = (max_px + 63) / 64;
   while (lo < hi) {
     const int64_t mid = (lo + hi + 1) / 2;
