@@ -38,9 +38,10 @@ namespace {
 
 constexpr int kThreads = 256;
 // env picks in flight per thread in dir_gen and in the adjoint (on the displaced sphere, 3 or 4 in
-// dir_gen took 7.0 -> 7.5 / 8.6 ms, 4 in the adjoint 5.6 -> 9.8 ms)
+// dir_gen took 7.0 -> 7.5 / 8.6 ms, 4 in the adjoint 5.6 -> 9.8 ms; once the adjoint's records were
+// written in pick order, one pick in flight beat two: 4.55 -> 4.41 ms)
 constexpr int kGenPicks = 2;
-constexpr int kBwdPicks = 2;
+constexpr int kBwdPicks = 1;
 
 struct KParams {
   int32_t N_d;
