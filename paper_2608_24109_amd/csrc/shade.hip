@@ -38,9 +38,10 @@ namespace {
 
 constexpr int kThreads = 256;
 // env picks in flight per thread in dir_gen and in the adjoint (on the displaced sphere, 3 or 4 in
-// dir_gen took 7.0 -> 7.5 / 8.6 ms, 4 in the adjoint 5.6 -> 9.8 ms; once the adjoint's records were
-// written in pick order, one pick in flight beat two: 4.55 -> 4.41 ms)
-constexpr int kGenPicks = 2;
+// dir_gen took 7.0 -> 7.5 / 8.6 ms, 4 in the adjoint 5.6 -> 9.8 ms). Since the 16-byte ray records,
+// the adjoint's records written in pick order and the eight-wave blocks, one pick beats two in both:
+// dir_gen 6.39 -> 5.26 ms (74 VGPRs, more waves per SIMD), the adjoint 4.55 -> 4.41 ms.
+constexpr int kGenPicks = 1;
 constexpr int kBwdPicks = 1;
 
 struct KParams {
@@ -219,12 +220,12 @@ __device__ __forceinline__ void dir_gen_wave(const MeshView& M, const TexView& T
 }
 
 // Chunk [p0, p0 + P) of the launch's pixels; P is a multiple of 64 and waves past it exit whole.
-// Blocks of eight waves share one copy of the env tables in LDS; held to five waves per SIMD (96
-// VGPRs, a few bytes spilled): tori 5.02 -> 4.62 ms, sphere 6.68 -> 6.35 ms against four waves of
-// 256-lane blocks.
+// Blocks of eight waves share one copy of the env tables in LDS, so that six waves per SIMD fit
+// (with two picks in flight, held to five waves at 96 VGPRs: tori 5.02 -> 4.62 ms, sphere 6.68 ->
+// 6.35 ms against four waves of 256-lane blocks).
 constexpr int kGenThreads = 512;
 template <bool COUNT>
-__global__ __launch_bounds__(kGenThreads) __attribute__((amdgpu_waves_per_eu(5, 5))) void k_dir_gen(MeshView M, TexView T, EnvView E, ShadeViews V,
+__global__ __launch_bounds__(kGenThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_dir_gen(MeshView M, TexView T, EnvView E, ShadeViews V,
                                                       const int32_t* __restrict__ tri_id,
                                                       const float* __restrict__ bary, KParams p, int64_t p0,
                                                       int64_t P, DirectWs ws, unsigned long long* __restrict__ counters,
