@@ -128,8 +128,9 @@ __global__ __launch_bounds__(kThreads) void k_raster(int32_t nF, const float* __
   const int64_t nx = x1 - x0 + 1, ny = y1 - y0 + 1;
   const int64_t npix = (P.ok && nx > 0 && ny > 0) ? nx * ny : 0;
   const bool big = npix > kSmallPixels;
-  if (!big) {
-    for (int64_t k = 0; k < npix; ++k) fragment(P, f, x0 + k % nx, y0 + k / nx, W, keys);
+  if (!big && npix > 0) {  // row by row: no 64-bit division per pixel
+    for (int64_t yy = y0; yy <= y1; ++yy)
+      for (int64_t xx = x0; xx <= x1; ++xx) fragment(P, f, xx, yy, W, keys);
   }
   // large triangles: the whole wave walks one triangle's pixels at a time
   unsigned long long mask = __ballot(big);
@@ -147,7 +148,12 @@ __global__ __launch_bounds__(kThreads) void k_raster(int32_t nF, const float* __
     const int32_t qf = __shfl(f, src, 64);
     const int64_t qx0 = __shfl(x0, src, 64), qy0 = __shfl(y0, src, 64);
     const int64_t qnx = __shfl(nx, src, 64), qn = __shfl(npix, src, 64);
-    for (int64_t k = lane; k < qn; k += 64) fragment(Q, qf, qx0 + k % qnx, qy0 + k / qnx, W, keys);
+    if (qn < ((int64_t)1 << 31)) {  // 32-bit division for the pixel of index k
+      const uint32_t n32 = (uint32_t)qn, nx32 = (uint32_t)qnx;
+      for (uint32_t k = lane; k < n32; k += 64) fragment(Q, qf, qx0 + k % nx32, qy0 + k / nx32, W, keys);
+    } else {
+      for (int64_t k = lane; k < qn; k += 64) fragment(Q, qf, qx0 + k % qnx, qy0 + k / qnx, W, keys);
+    }
   }
 }
 
@@ -155,11 +161,12 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const float* __restrict__ 
                                                       RasterViews V, int32_t* __restrict__ tri_id,
                                                       float* __restrict__ bary) {
 #pragma clang fp contract(off)
-  const int64_t HW = (int64_t)V.H * V.W;
-  const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (gid >= HW * V.n) return;
-  const int32_t view = (int32_t)(gid / HW);
-  const int64_t p = gid - view * HW;
+  // 32-bit pixel indices: the boundary holds nViews * H * W below 2^31
+  const uint32_t HW = (uint32_t)V.H * (uint32_t)V.W;
+  const uint32_t gid = blockIdx.x * kThreads + threadIdx.x;
+  if (gid >= HW * (uint32_t)V.n) return;
+  const uint32_t view = gid / HW;
+  const uint32_t p = gid - view * HW, px = p % (uint32_t)V.W, py = p / (uint32_t)V.W;
   const unsigned long long key = reinterpret_cast<const unsigned long long*>(bary)[gid];
   float2 out = make_float2(0.f, 0.f);
   int32_t f = -1;
@@ -167,7 +174,7 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const float* __restrict__ 
     f = (int32_t)(uint32_t)key;
     const Proj P = project(pos, tri, f, V.mvp[view], V.H, V.W);
     int64_t E[3], A2;
-    cover(P, 256 * (p % V.W) + 128, 256 * (p / V.W) + 128, E, &A2);
+    cover(P, 256 * (int64_t)px + 128, 256 * (int64_t)py + 128, E, &A2);
     const double q0 = (double)E[0] / P.w[0], q1 = (double)E[1] / P.w[1], q2 = (double)E[2] / P.w[2];
     const double s = (q0 + q1) + q2;
     out = make_float2((float)(q1 / s), (float)(q2 / s));
