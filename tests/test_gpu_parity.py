@@ -256,6 +256,34 @@ def test_raster_triangle_order_and_large_triangles(lib):
     assert np.array_equal(perm[ids2[0]], ids[0])
 
 
+def test_raster_mixed_box_sizes_past_the_screen_edges(lib):
+    """Jittered fine grid reaching past all four screen edges, mixed windings: clamped pixel boxes
+    of 1 to 16 pixels (walked row by row by one lane) next to larger ones (wave-cooperative)."""
+    nx, ny = 40, 30
+    pos, tri = I.quad_mesh(np.array([[-1.4, -1.4, 0], [1.4, -1.4, 0], [1.4, 1.4, 0], [-1.4, 1.4, 0]]), nx, ny)
+    rng = np.random.default_rng(7)
+    idx = np.arange((nx + 1) * (ny + 1)).reshape(nx + 1, ny + 1)[1:-1, 1:-1].ravel()
+    pos[idx, 0] += (rng.random(idx.size) - 0.5) * 0.6 * (2.8 / nx)  # < 0.3 cell: no fold-overs
+    pos[idx, 1] += (rng.random(idx.size) - 0.5) * 0.6 * (2.8 / ny)
+    flip = rng.random(tri.shape[0]) < 0.5
+    tri[flip, 1], tri[flip, 2] = tri[flip, 2].copy(), tri[flip, 1].copy()
+    cam = I.Camera(mvp=np.eye(4), eye=np.array([0, 0, 10.0]), H=70, W=90)
+    sc = I.make_scene("jgrid", pos, tri, 16, 16, 8, 16, 1.0, [cam], N_d=4)
+    log("[raster] jittered grid 40x30 cells on 70x90")
+    dev = Dev(sc)
+    # pixel boxes on both sides of the one-lane limit, as the kernel clamps them to the screen
+    X = (pos[:, 0].astype(np.float64) + 1) * 0.5 * 90 * 256
+    Y = (1 - pos[:, 1].astype(np.float64)) * 0.5 * 70 * 256
+    nxp = np.clip(np.floor((X[tri].max(1) - 128) / 256), -1, 89) - np.clip(np.ceil((X[tri].min(1) - 128) / 256), 0, 90) + 1
+    nyp = np.clip(np.floor((Y[tri].max(1) - 128) / 256), -1, 69) - np.clip(np.ceil((Y[tri].min(1) - 128) / 256), 0, 70) + 1
+    box = np.maximum(nxp, 0) * np.maximum(nyp, 0)
+    assert ((box >= 1) & (box <= 16)).sum() > 100 and (box > 16).sum() > 100
+    ids, bary = _raster_gpu(dev, [cam])
+    _check_raster(dev, [cam], ids, bary, [0])
+    cnt = O.coverage_count(dev.om, cam)
+    assert cnt.min() == 1 and cnt.max() == 1 and (ids[0] >= 0).all()
+
+
 def test_raster_empty_mesh_is_background(lib):
     from paper_2608_24109_amd.scene import DeviceMesh
     from paper_2608_24109_amd.render import PassBuffers, raster
