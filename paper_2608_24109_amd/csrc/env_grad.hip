@@ -43,6 +43,10 @@ __global__ __launch_bounds__(kThreads) void k_eg_hist(EnvGradWs w) {
     if (h[b]) atomicAdd(&w.bucket_count[b], h[b]);
 }
 
+// records in flight per thread in the histogram and reduction loops (indices stay below 2^32:
+// a chunk holds fewer than 2^31 records)
+constexpr int kLoads = 8;
+
 // Contiguous record range of block g of a G-block tiled pass (the histogram and the scatter split
 // the records the same way).
 __device__ __forceinline__ void block_range(uint32_t n, uint32_t g, uint32_t G, uint32_t* r0, uint32_t* r1) {
@@ -59,7 +63,18 @@ __global__ __launch_bounds__(kThreads) void k_eg_hist_blocks(EnvGradWs w) {
   __syncthreads();
   uint32_t r0, r1;
   block_range(n_records(w), blockIdx.x, gridDim.x, &r0, &r1);
-  for (uint32_t i = r0 + threadIdx.x; i < r1; i += kThreads) {
+  // kLoads records per thread loaded together before their LDS atomics (a load followed by its
+  // atomic waits for memory once per record)
+  uint32_t i = r0 + threadIdx.x;
+  for (; i + (kLoads - 1) * kThreads < r1; i += kLoads * kThreads) {
+    uint32_t t[kLoads];
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k) t[k] = w.rec[i + k * kThreads].texel;
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k)
+      if (valid(w, t[k])) atomicAdd(&h[t[k] >> kBucketShift], 1u);
+  }
+  for (; i < r1; i += kThreads) {
     const uint32_t t = w.rec[i].texel;
     if (valid(w, t)) atomicAdd(&h[t >> kBucketShift], 1u);
   }
@@ -260,7 +275,20 @@ __global__ __launch_bounds__(kThreads) void k_eg_reduce(EnvGradWs w, int64_t n_t
   const uint32_t r1 = (uint32_t)min((int64_t)w.bucket_off[b + 1], (int64_t)r0 + kReduceChunk);
   for (int32_t k = threadIdx.x; k < 3 * kBucketTexels; k += kThreads) acc[k] = 0.0;
   __syncthreads();
-  for (uint32_t i = r0 + threadIdx.x; i < r1; i += kThreads) {
+  uint32_t i = r0 + threadIdx.x;
+  for (; i + (kLoads - 1) * kThreads < r1; i += kLoads * kThreads) {
+    EnvRec r[kLoads];
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k) r[k] = w.sorted[i + k * kThreads];
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k) {
+      const uint32_t t = r[k].texel & (kBucketTexels - 1);
+      atomicAdd(&acc[3 * t], (double)r[k].w[0]);
+      atomicAdd(&acc[3 * t + 1], (double)r[k].w[1]);
+      atomicAdd(&acc[3 * t + 2], (double)r[k].w[2]);
+    }
+  }
+  for (; i < r1; i += kThreads) {
     const EnvRec r = w.sorted[i];
     const uint32_t t = r.texel & (kBucketTexels - 1);
     atomicAdd(&acc[3 * t], (double)r.w[0]);
