@@ -621,7 +621,7 @@ def roofline_objects(workload: str, stats: dict, p) -> dict:
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU: the render pass would shard views across GPUs "
+        print(json.dumps({"error": "the benchmark runs on one GPU: the render pass would shard views across GPUs "
                                    "with one all-reduce of the gradient maps, which is not built; run --gpus 1"}))
         sys.exit(2)
     import torch
