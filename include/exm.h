@@ -44,6 +44,13 @@ typedef enum {
 /* Thread-local text of the last non-OK status returned on this thread. */
 const char* exm_last_error(void);
 
+/* Test hook for failure handling (not a paper operation): the next n calls that would reach the
+ * device fail with EXM_E_HIP and the message "injected failure (exm_inject_failures)" after
+ * validating their arguments, enqueuing nothing; n <= 0 clears the count. Process-wide, taken
+ * by whichever thread calls first. Lets a caller exercise its error paths (a failed request in
+ * the relight service) without a faulty device. */
+void exm_inject_failures(int32_t n);
+
 /* Shading flags (exm_params.flags). METALLIC_OFF fixes m = 0 (dielectric model; UV-PBR Asset
  * Decomposition section, and the Implementation details of the Experiments). DIFFUSE_ONLY /
  * SPECULAR_ONLY drop f_s / f_d of Eq. 13 (tests). NO_VIS sets Vis = 1 (tests).

@@ -100,6 +100,7 @@ def _load() -> C.CDLL:
     vp, i32, st = C.c_void_p, C.c_int32, C.c_int
     sig = {
         "exm_last_error": (C.c_char_p, []),
+        "exm_inject_failures": (None, [i32]),
         "exm_mesh_prepare": (st, [vp, vp]),
         "exm_build_bvh": (st, [vp, i32, vp, i32, C.POINTER(vp), vp]),
         "exm_free_bvh": (st, [vp]),
@@ -160,6 +161,12 @@ lib = _load()
 
 def last_error() -> str:
     return lib.exm_last_error().decode()
+
+
+def inject_failures(n: int) -> None:
+    """The next n library calls that would reach the device fail with EXM_E_HIP (a test hook for
+    error paths); 0 clears."""
+    lib.exm_inject_failures(int(n))
 
 
 def _check(status: int, where: str) -> None:

@@ -3,6 +3,7 @@
 // work on the caller's stream.
 #include <hip/hip_runtime_api.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -24,7 +25,14 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 std::mutex g_dev_mu;
 std::vector<int> g_dev_ok;  // -1 unknown, 0 no, 1 yes
 
+// calls still to fail on purpose (exm_inject_failures), process-wide
+std::atomic<int32_t> g_inject{0};
+
 exm_status check_device() {
+  // an injected failure is taken by the first call that reaches this point, after its
+  // arguments were validated and before anything is enqueued
+  for (int32_t n = g_inject.load(); n > 0;)
+    if (g_inject.compare_exchange_weak(n, n - 1)) return fail(EXM_E_HIP, "injected failure (exm_inject_failures)");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0) return fail(EXM_E_HIP, "no current HIP device");
   std::lock_guard<std::mutex> lk(g_dev_mu);
@@ -149,6 +157,8 @@ using namespace exm;
 extern "C" {
 
 const char* exm_last_error(void) { return g_last_error.c_str(); }
+
+void exm_inject_failures(int32_t n) { g_inject.store(n > 0 ? n : 0); }
 
 exm_status exm_mesh_prepare(const exm_mesh* m, hipStream_t stream) {
   EXM_TRY(check_mesh(m, true));

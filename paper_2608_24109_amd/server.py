@@ -16,6 +16,9 @@ Device memory is admitted by footprint against a budget:
             and its ray workspace (capped; the passes run in pixel chunks beyond the cap).
 Admission is first-come first-served: a request that does not fit after evicting every idle
 map waits for in-flight requests to finish; one larger than the whole budget is rejected.
+A launch that raises (a library error) fails its request, or every request of its batch: they
+retire with status "failed" and the error, their slot and memory are returned, and the service
+goes on with the others.
 
 The scheduler holds no device code and runs against any backend with the DeviceBackend
 interface (the tests drive it with a simulated one on the CPU).
@@ -41,7 +44,7 @@ class Request:
     arrival: float                 # scheduled arrival (seconds on the service clock)
     t_admit: float = math.nan
     t_done: float = math.nan
-    status: str = "queued"         # queued | running | done | rejected
+    status: str = "queued"         # queued | running | done | rejected | failed
     result: object = None
 
     @property
@@ -75,6 +78,7 @@ class Scheduler:
         self.batch_max = max(1, int(batch_max)) if hasattr(backend, "launch_batch") else 1
         self.batch_res = int(batch_res)
         self.batches = 0
+        self.failures = 0
         if self.fixed > self.budget:
             raise ValueError(f"resident geometry and env tables ({self.fixed} B) exceed the budget")
 
@@ -137,7 +141,8 @@ class Scheduler:
         return need
 
     def admit(self, clock) -> list[Request]:
-        """Admit queued requests in order while a slot is free and their footprint fits."""
+        """Admit queued requests in order while a slot is free and their footprint fits; returns
+        the requests started, rejected or failed at launch."""
         started, rejected = [], []
         while self.queue and self.free:
             req = self.queue[0]
@@ -165,11 +170,24 @@ class Scheduler:
             for r in batch:
                 r.t_admit = t
                 r.status = "running"
-            if len(batch) > 1:
-                tok = self.b.launch_batch(batch, slot)
-                self.batches += 1
-            else:
-                tok = self.b.launch(req, slot)
+            try:
+                if len(batch) > 1:
+                    tok = self.b.launch_batch(batch, slot)
+                    self.batches += 1
+                else:
+                    tok = self.b.launch(req, slot)
+            except RuntimeError as e:  # the library's errors (ExmError) and the backend's own
+                t = clock()
+                for r in batch:
+                    r.status = "failed"
+                    r.t_done = t
+                    r.result = e
+                    self.pins[r.asset] -= 1
+                self.failures += len(batch)
+                self.free.append(slot)
+                self.used -= total
+                rejected.extend(batch)
+                continue
             self.inflight[slot] = (batch, tok, total)
             started.extend(batch)
         return started + rejected
@@ -195,7 +213,7 @@ def serve(sched: Scheduler, requests: list[Request], clock=time.monotonic, idle_
             i += 1
         done = sched.poll(rel)
         out = sched.admit(rel)
-        finished = done + [r for r in out if r.status == "rejected"]
+        finished = done + [r for r in out if r.status in ("rejected", "failed")]
         left -= len(finished)
         if not keep_results:
             for r in finished:
@@ -214,6 +232,7 @@ def latency_stats(reqs: list[Request], window: float | None = None) -> dict:
     span = window if window is not None else max((r.t_done for r in ok), default=float("nan"))
     px = float(sum(r.res * r.res for r in ok))
     return {"requests": len(reqs), "completed": len(ok), "rejected": sum(r.status == "rejected" for r in reqs),
+            "failed": sum(r.status == "failed" for r in reqs),
             "p50_ms": float(np.percentile(lat, 50)) if len(ok) else None,
             "p99_ms": float(np.percentile(lat, 99)) if len(ok) else None,
             "mean_ms": float(lat.mean()) if len(ok) else None,

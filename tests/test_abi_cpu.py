@@ -65,6 +65,32 @@ def test_raster_validation(L):
     assert _status(L, f, C.byref(m), huge, 1, 0x1000, 0x1000, None)[0] == L.EXM_E_INVAL
 
 
+def test_injected_failures_are_counted_and_taken_after_validation(L):
+    """exm_inject_failures(n): the next n calls that pass validation return EXM_E_HIP with the
+    injected message; invalid calls still return EXM_E_INVAL and leave the count alone. (Every
+    call here fails before any launch, so the test never touches a device.)"""
+    f = L.lib.exm_raster_gbuffer
+    m = _mesh(L)
+    cams = _cams(L)
+    L.inject_failures(3)
+    try:
+        assert _status(L, f, None, cams, 1, 0x1000, 0x1000, None)[0] == L.EXM_E_INVAL
+        assert _status(L, f, C.byref(m), cams, 1, 0x1000, 0x1004, None)[0] == L.EXM_E_INVAL
+        for _ in range(3):
+            s, msg = _status(L, f, C.byref(m), cams, 1, 0x1000, 0x1000, None)
+            assert s == L.EXM_E_HIP and "injected failure" in msg
+        L.inject_failures(1)
+        assert L.lib.exm_env_guide_len(4, 8) > 0  # a size query reaches no device, takes nothing
+        s, msg = _status(L, f, C.byref(m), cams, 1, 0x1000, 0x1000, None)
+        assert s == L.EXM_E_HIP and "injected failure" in msg
+        L.inject_failures(-5)  # clears; a negative count injects nothing
+        L.inject_failures(1)
+    finally:
+        L.inject_failures(0)
+    s, msg = _status(L, f, None, cams, 1, 0x1000, 0x1000, None)
+    assert s == L.EXM_E_INVAL and "injected" not in msg
+
+
 def test_shade_validation(L):
     m = _mesh(L)
     cams = _cams(L)

@@ -60,3 +60,37 @@ def test_alone_equals_mix():
         assert torch.isfinite(ra).all() and float(ra.max()) > 0
         assert torch.equal(ra, rb), f"request {a.rid} differs alone and in the mix"
         assert torch.equal(rc, rb), f"request {a.rid} differs alone and in a batch"
+
+
+def test_injected_failure_fails_only_its_request():
+    """A library call that fails (forced with exm_inject_failures before the first launch) fails
+    that request alone: it retires as failed with the library's error, and every other request of
+    the stream is served with the image it has when rendered alone."""
+    from paper_2608_24109_amd import _lib as L
+    from paper_2608_24109_amd.server import (DeviceBackend, Scheduler, build_host_assets, latency_stats,
+                                             requests_from_specs, serve)
+    specs = I.relight_asset_specs(n=3, lo=10_000, hi=40_000, sizes=(512,))
+    log("[server] building 3 assets")
+    be = DeviceBackend(build_host_assets(specs), I.relight_envs(n=2), slots=2)
+    stream = I.relight_stream(rate=400.0, seconds=0.03, n_assets=3, n_envs=2, resolutions=(64, 128))
+    assert len(stream) >= 4
+    budget = be.fixed_bytes() + 3 * be.map_bytes(0) + 4 * 128 * 128 * 400
+    reqs = requests_from_specs(stream)
+    torch.cuda.synchronize()
+    L.inject_failures(1)
+    try:
+        serve(Scheduler(be, budget, slots=2), reqs)
+    finally:
+        L.inject_failures(0)
+    st = latency_stats(reqs)
+    log(f"[server] with one injected failure: {st}")
+    first = min(reqs, key=lambda r: r.t_admit)
+    assert first.status == "failed" and isinstance(first.result, L.ExmError)
+    assert "injected failure" in str(first.result)
+    assert st["failed"] == 1 and st["completed"] == len(reqs) - 1
+    solo = Scheduler(be, budget, slots=1)
+    for r, b in zip(reqs, requests_from_specs(stream)):
+        if r.status == "failed":
+            continue
+        serve(solo, [b])
+        assert torch.equal(r.result, b.result), f"request {r.rid} differs alone and beside a failed one"

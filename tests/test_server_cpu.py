@@ -219,3 +219,60 @@ def test_batch_waits_for_memory_like_single_requests():
     s.admit(clk)
     assert rs[2].status == "running"
     _check(s)
+
+
+class FailingBackend(FakeBatchBackend):
+    """Raises in the launch of the requests (or batches holding a request) whose rid is in `bad`."""
+
+    def __init__(self, *a, bad=(), **k):
+        super().__init__(*a, **k)
+        self.bad = set(bad)
+
+    def launch(self, r, slot):
+        if r.rid in self.bad:
+            raise RuntimeError(f"launch of request {r.rid} failed")
+        return super().launch(r, slot)
+
+    def launch_batch(self, rs, slot):
+        if any(r.rid in self.bad for r in rs):
+            raise RuntimeError("batch launch failed")
+        return super().launch_batch(rs, slot)
+
+
+def test_failed_launch_fails_only_its_requests():
+    """A launch that raises retires its request (or its whole batch) as failed with the error and
+    returns the slot and the request memory; the requests around it are served as usual, the map
+    stays resident and evictable, and the serving loop ends."""
+    clk = FakeClock()
+    b = FailingBackend({a: 50 for a in range(4)}, clock=clk, bad={2, 5})
+    s = Scheduler(b, budget=100 + 4 * 50 + 3 * 100, slots=2, batch_max=2, batch_res=16)
+    reqs = [_req(i, i % 4) for i in range(8)]
+    for r in (reqs[2], reqs[3], reqs[6]):
+        r.indirect = True  # 2 fails alone; 5 fails inside the batch (4, 5)
+    for r in reqs:
+        s.submit(r)
+    while not s.idle():
+        s.admit(clk)
+        _check(s)
+        clk.t += 1.0
+        s.poll(clk)
+        _check(s)
+    failed = [r.rid for r in reqs if r.status == "failed"]
+    assert failed == [2, 4, 5] and s.failures == 3
+    assert all(isinstance(reqs[i].result, RuntimeError) for i in failed)
+    assert all(r.status == "done" for r in reqs if r.rid not in failed)
+    assert s.used == s.fixed + sum(s.resident.values()) and sorted(s.free) == [0, 1]
+    assert all(s.pins[a] == 0 for a in range(4))
+    st = latency_stats(reqs)
+    assert st["failed"] == 3 and st["completed"] == 5
+
+
+def test_serve_ends_with_failed_requests():
+    import time
+    clk = time.monotonic
+    b = FailingBackend({a: 100 for a in range(3)}, clock=clk, bad={0, 7})
+    s = Scheduler(b, budget=100 + 3 * 100 + 2 * 32 * 32, slots=2)
+    reqs = [_req(i, i % 3, res=32, arrival=0.001 * i) for i in range(12)]
+    serve(s, reqs, clock=clk, idle_sleep=1e-4)
+    assert [r.rid for r in reqs if r.status == "failed"] == [0, 7]
+    assert sum(r.status == "done" for r in reqs) == 10
