@@ -186,12 +186,25 @@ __device__ __forceinline__ EnvTabs load_env_tabs(const EnvView& e, void* lds, bo
   return t;
 }
 
+// sin(pi x) and cos(pi x) for |x| <= 1/32 by their Taylor series (terms to t^5 and t^6, t = pi x;
+// the first omitted terms, t^7/5040 and t^8/40320, stay below 2e-11 and 3e-13: far under a float's
+// rounding), in place of the general range-reduced evaluation
+__device__ __forceinline__ void sincospi_small(float x, float* s, float* c) {
+  const float t = x * kPi;
+  const float t2 = t * t;
+  *s = t * fmaf(t2, fmaf(t2, 1.0f / 120.0f, -1.0f / 6.0f), 1.0f);
+  *c = fmaf(t2, fmaf(t2, fmaf(t2, -1.0f / 720.0f, 1.0f / 24.0f), -0.5f), 1.0f);
+}
+
 // K independent picks advanced stage by stage (rows in LDS, then the K cutpoint pairs, a
 // lockstep column search, the K records), so that each thread has K loads in flight at every
 // stage; every pick is the one a lone search returns. Picks with valid[j] false read nothing
 // and leave out[j] untouched. REC false skips the record loads: out[j].E and out[j].inv_pdf are
 // then left unset, for the caller to fetch with env_rec only for the picks it keeps.
-template <int K, bool REC = true>
+// SMALL_PHI: the in-texel azimuth of maps at least 64 texels wide through sincospi_small (the
+// direct pass, forward and adjoint; in the indirect kernels the second code path cost spills).
+// A forward pass and its adjoint take the same path, so they draw identical directions.
+template <int K, bool REC = true, bool SMALL_PHI = false>
 __device__ __forceinline__ void env_sample_k(const EnvView& e, const EnvTabs& tb, const Draw (&d)[K],
                                              const bool (&valid)[K], EnvSample (&out)[K]) {
   const uint64_t Q = tb.cdf_row[e.He - 1];
@@ -270,6 +283,7 @@ __device__ __forceinline__ void env_sample_k(const EnvView& e, const EnvTabs& tb
   for (int j = 0; j < K; ++j)
     if (REC && valid[j]) rec[j] = e.rec[row[j] * e.We + min(lo[j], e.We - 1)];
   const float two_over_We = 2.0f / (float)e.We;  // one division per call instead of one per pick
+  const bool small_phi = SMALL_PHI && e.We >= 64;  // the in-texel angle is then at most pi/32
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     if (!valid[j]) continue;
@@ -292,7 +306,10 @@ __device__ __forceinline__ void env_sample_k(const EnvView& e, const EnvTabs& tb
     // phi = 2 pi (col + u2) / We by angle addition (keeps u2's resolution at large col)
     const float2 cj = tb.colc ? tb.colc[col] : env_col_consts(col, e.We);
     float sd, cd;
-    sincospif(d[j].u2 * two_over_We, &sd, &cd);
+    if (small_phi)
+      sincospi_small(d[j].u2 * two_over_We, &sd, &cd);
+    else
+      sincospif(d[j].u2 * two_over_We, &sd, &cd);
     const float cphi = cj.y * cd - cj.x * sd, sphi = cj.x * cd + cj.y * sd;
     s.dir = mk(st * cphi, ct, st * sphi);
     if (REC) {

@@ -177,7 +177,7 @@ __device__ __forceinline__ void dir_gen_wave(const MeshView& M, const TexView& T
       }
       // records are read only for the picks above the shading hemisphere: the others are dropped
       // whatever their records hold (half of all picks on the displaced sphere)
-      env_sample_k<kGenPicks, false>(E, tb, dr, ok, es);
+      env_sample_k<kGenPicks, false, true>(E, tb, dr, ok, es);
       bool need[kGenPicks];
       float cs[kGenPicks];
 #pragma unroll
@@ -565,7 +565,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         dr[j] = philox_draw(p.key.k0, p.key.k1, pix, vid, (uint32_t)k, 0u);
       }
     }
-    env_sample_k<kBwdPicks>(E, tb, dr, ok, es);
+    env_sample_k<kBwdPicks, true, true>(E, tb, dr, ok, es);
 #pragma unroll
     for (int j = 0; j < kBwdPicks; ++j) {
       const uint64_t have = __ballot(ok[j]);  // the lanes still picking
