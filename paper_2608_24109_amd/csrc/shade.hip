@@ -51,24 +51,6 @@ struct KParams {
   RngKey key;
 };
 
-// f_r of a surface point (S: n_s, albedo a, roughness r, metallic m)
-template <class SURF>
-__device__ __forceinline__ void brdf_eval(const SURF& S, f3 wi, f3 wo, float ci, const KParams& p, float fr[3]) {
-  const float kd = (p.flags & EXM_SPECULAR_ONLY) ? 0.0f : (1.0f - S.m) * kInvPi;
-  fr[0] = kd * S.a[0];
-  fr[1] = kd * S.a[1];
-  fr[2] = kd * S.a[2];
-  if (p.flags & EXM_DIFFUSE_ONLY) return;
-  const Spec s = spec_terms(S.ns, wi, wo, ci, S.r, p.eps);
-  if (!s.on) return;
-  const float k = s.D * s.G1i * s.G1o * __builtin_amdgcn_rcpf(s.den);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const float F0 = (1.0f - S.m) * p.f_diel + S.m * S.a[c];
-    fr[c] += k * (F0 + (1.0f - F0) * s.x5);
-  }
-}
-
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return (uint32_t)__popcll(mask & ((1ull << __lane_id()) - 1ull));
 }
@@ -76,12 +58,12 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
 // The shading point of a covered pixel, staged in LDS between the two phases of dir_gen: kRecWords
 // words per pixel, structure of arrays over the wave's 64 pixels (the lanes reading one pixel's
 // record read the same word: a broadcast).
-constexpr int kRecWords = 14;
-enum RecField { kRns = 0, kRwo = 3, kRa = 6, kRr = 9, kRm = 10, kRpix = 11, kRvid = 12, kRlane = 13 };
+constexpr int kRecWords = 15;
+enum RecField { kRns = 0, kRwo = 3, kRa = 6, kRal2 = 9, kRm = 10, kRpix = 11, kRvid = 12, kRlane = 13, kRg1o = 14 };
 
 struct ShadePt {
   f3 ns, wo;
-  float a[3], r, m;
+  float a[3], alpha2, m, g1o;  // alpha^2 and G1(wo) from spec_pixel
   uint32_t pix, vid, lane;
 };
 
@@ -93,12 +75,56 @@ __device__ __forceinline__ ShadePt load_pt(const uint32_t* rec, uint32_t c) {
   q.a[0] = rf[kRa * 64 + c];
   q.a[1] = rf[(kRa + 1) * 64 + c];
   q.a[2] = rf[(kRa + 2) * 64 + c];
-  q.r = rf[kRr * 64 + c];
+  q.alpha2 = rf[kRal2 * 64 + c];
   q.m = rf[kRm * 64 + c];
+  q.g1o = rf[kRg1o * 64 + c];
   q.pix = rec[kRpix * 64 + c];
   q.vid = rec[kRvid * 64 + c];
   q.lane = rec[kRlane * 64 + c];
   return q;
+}
+
+// alpha^2 (clamped) and G1(wo) of a shading point: they depend on the pixel only, so the forward
+// pass computes them once per pixel; the same expressions and order as spec_terms
+__device__ __forceinline__ void spec_pixel(f3 n, f3 wo, float r, float* alpha2, float* g1o) {
+  const float alpha = r * r;
+  float a2 = alpha * alpha;
+  if (a2 < 1e-12f) a2 = 1e-12f;
+  const float co = dot(n, wo);
+  const float so = sqrtf(a2 + (1.0f - a2) * co * co);
+  *alpha2 = a2;
+  *g1o = 2.0f * co * __builtin_amdgcn_rcpf(co + so);
+}
+
+// f_r(wi, wo) of Eq. 13 at a staged shading point (alpha^2 and G1(wo) from spec_pixel): the values
+// spec_terms gives, without the per-sample square root of G1(wo)
+__device__ __forceinline__ void brdf_eval(const ShadePt& S, f3 wi, f3 wo, float ci, const KParams& p, float fr[3]) {
+  const float kd = (p.flags & EXM_SPECULAR_ONLY) ? 0.0f : (1.0f - S.m) * kInvPi;
+  fr[0] = kd * S.a[0];
+  fr[1] = kd * S.a[1];
+  fr[2] = kd * S.a[2];
+  if (p.flags & EXM_DIFFUSE_ONLY) return;
+  const f3 hs = wi + wo;
+  const float hl = len(hs);
+  const float co = dot(S.ns, wo);
+  if (!(hl >= 1e-12f) || !(co > 0.0f) || !(ci > 0.0f)) return;
+  const f3 h = __builtin_amdgcn_rcpf(hl) * hs;
+  const float chh = dot(S.ns, h);
+  const f3 nx = cross(S.ns, h);
+  const float d = dot(nx, nx) + S.alpha2 * chh * chh;
+  const float D = S.alpha2 * __builtin_amdgcn_rcpf(kPi * d * d);
+  const float si = sqrtf(S.alpha2 + (1.0f - S.alpha2) * ci * ci);
+  const float G1i = 2.0f * ci * __builtin_amdgcn_rcpf(ci + si);
+  const float x = 1.0f - fmaxf(dot(wi, h), 0.0f);
+  const float x2 = x * x;
+  const float x5 = x2 * x2 * x;
+  const float den = 4.0f * ci * co + p.eps;
+  const float k = D * G1i * S.g1o * __builtin_amdgcn_rcpf(den);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float F0 = (1.0f - S.m) * p.f_diel + S.m * S.a[c];
+    fr[c] += k * (F0 + (1.0f - F0) * x5);
+  }
 }
 
 // One wave, 64 consecutive pixels (pixel gid of the views V at workspace position `local`; the
@@ -139,8 +165,11 @@ __device__ __forceinline__ void dir_gen_wave(const MeshView& M, const TexView& T
     rf[kRa * 64 + c] = S.a[0];
     rf[(kRa + 1) * 64 + c] = S.a[1];
     rf[(kRa + 2) * 64 + c] = S.a[2];
-    rf[kRr * 64 + c] = S.r;
+    float alpha2, g1o;
+    spec_pixel(S.ns, wo, S.r, &alpha2, &g1o);
+    rf[kRal2 * 64 + c] = alpha2;
     rf[kRm * 64 + c] = S.m;
+    rf[kRg1o * 64 + c] = g1o;
     rec[kRpix * 64 + c] = pix;
     rec[kRvid * 64 + c] = (uint32_t)V.view_id[view];
     rec[kRlane * 64 + c] = lane;
